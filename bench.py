@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the SEM elastic time step on one MI355X.
+
+Workload: layered elastic cube on 64^3 hexahedra (262,144 elements, NGLL 5,
+16,974,593 unique GLL points), interior vertices jittered by +-10% of h,
+three flat layers (vp 6000/4000/2500 m/s, vp/vs 1.73, rho 2500) with a +-5%
+Gaussian random field (correlation length 4 elements), vertical Ricker point
+force (10 Hz) at the centre vertex, 8 receivers on the top face, dt from
+Courant number 0.4.  FP32 storage and arithmetic, graph-coloured assembly.
+
+A step is one explicit Newmark step: correct/predict update, the element
+force operator f = -K u over every element (the hot path), source injection
+and receiver recording.  ``value`` is element-local GLL-point force
+evaluations per second over the timed steps (E n^3 per step).
+
+Prints ONE JSON line.  Also reports the force kernel's roofline (HIP events
+on the library stream), the force apply alone with coloured and with atomic
+assembly, and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+NE, NGLL = 64, 5
+
+
+def bytes_per_element(n: int, nglob: int, nspec: int, irregular: bool = True) -> float:
+    """Algorithmic HBM bytes per element per force apply (FP32, this library's layout):
+    ibool 4 n^3, Gamma 9*4 n^3 (irregular) or 9*4 per element (regular),
+    lambda*W and mu*W 2*4 n^3, u read once and f written once per unique node
+    (3*4*G/E each)."""
+    n3 = n ** 3
+    geo = 36 * n3 if irregular else 36
+    return 4 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
+
+
+def traffic_from_profiles(src_hash: str):
+    """HBM bytes per launch measured with rocprofv3 PMC counters, if they were
+    taken on the current force kernel source."""
+    p = os.path.join(ROOT, "profiles", "force_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
+    """FP64 oracle force apply on the first 8 element layers of the same mesh."""
+    import numpy as np
+    from oracle import oracle as O
+    n = mesh.n
+    nsub = mesh.nex * mesh.ney * 8
+    ibool = mesh.ibool[:nsub]
+    gam, jac, _ = O.geometry(n, mesh.elem_vert[:nsub], mesh.vert)
+    u = np.random.default_rng(0).uniform(-1, 1, (mesh.nglob, 3))
+    O.force(n, ibool, gam, jac, lam[:nsub], mu[:nsub], u, mesh.nglob)  # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.force(n, ibool, gam, jac, lam[:nsub], mu[:nsub], u, mesh.nglob)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 200:
+            break
+    return {"value": nsub * n ** 3 * reps / el, "unit": "GLL-pt force evals/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle force apply on the first 8 of 64 element layers "
+                      f"({nsub} elements, {nsub * n ** 3} GLL points), {reps} applies in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--assembly", choices=["colored", "atomic"], default="colored")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
+              "multi-GPU path; the operator would shard by mesh blocks with a halo exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    nt_total = args.warmup + args.steps
+    wl = W.layered_jittered(ne=NE, n=NGLL, nt=nt_total, dt=1.0, jitter=0.10, seed=2606,
+                            grf_seed=12850, grf_amp=0.05, nrec=8)
+    mesh = wl.mesh
+    s = P.Solver(NGLL)
+    info = s.upload_mesh(mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    asm = P.SEMX_ASM_COLORED if args.assembly == "colored" else P.SEMX_ASM_ATOMIC
+    s.set_mode(P.SEMX_C_F32, asm)
+    dt = P.semx_cfl_dt(s.ctx, 0.4)
+    wl.dt = dt
+    wl.stf = W.ricker(10.0, 0.12, dt, nt_total + 1)[None, :]
+    s.setup_run(wl)
+    setup_s = time.perf_counter() - t_setup
+    stream = s.stream
+    E, n3 = mesh.nspec, NGLL ** 3
+    b_elem = bytes_per_element(NGLL, mesh.nglob, E, irregular=info["nirregular"] > 0)
+
+    # ---- force apply alone (coloured and atomic), event-timed on the library stream
+    u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
+    f = torch.empty_like(u)
+    apply = {}
+    for name, mode in (("colored", P.SEMX_ASM_COLORED), ("atomic", P.SEMX_ASM_ATOMIC)):
+        P.semx_set_mode(s.ctx, P.SEMX_C_F32, mode)
+        for _ in range(5):
+            P.semx_apply_force(s.ctx, u, f)
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.apply_reps):
+            P.semx_apply_force(s.ctx, u, f)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.apply_reps
+        apply[name] = {"ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3),
+                       "hbm_frac_alg": (b_elem * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)}
+    P.semx_set_mode(s.ctx, P.SEMX_C_F32, asm)
+
+    # ---- time loop: warmup, then exactly `steps` timed steps
+    P.semx_reset(s.ctx)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    P.semx_set_timing(s.ctx, True)
+    P.semx_force_timing(s.ctx)  # clear
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    launches, force_ms = P.semx_force_timing(s.ctx)
+    P.semx_set_timing(s.ctx, False)
+    step_ms = e0.elapsed_time(e1) / args.steps
+    seis = s.seismograms()
+    assert np.all(np.isfinite(seis)), "non-finite seismograms"
+
+    # ---- roofline of the force kernel (per launch)
+    launches_per_apply = launches / args.steps
+    avg_launch_ms = force_ms / launches
+    bytes_per_launch = b_elem * E / launches_per_apply
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    src = open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", "force_f32.hip"), "rb").read()
+    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+
+    out = {
+        "metric": "GLL-point force evals/s (FP32 vs mixed) + % HBM roofline; adjoint/fwd time",
+        "value": E * n3 / (step_ms * 1e-3),
+        "unit": "GLL-pt force evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "layered elastic cube 64^3 hex, NGLL 5, jittered +-10% h, 3 layers + 5% GRF, "
+                               f"Ricker 10 Hz, Courant 0.4, {args.assembly} assembly, FP32",
+                   "nspec": E, "nglob": mesh.nglob, "ngll": NGLL, "dt": dt,
+                   "assembly": args.assembly, "contraction": "f32",
+                   "nregular": info["nregular"], "nirregular": info["nirregular"], "ncolors": info["ncolors"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "force_f32_kernel<5, irregular, colored>",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
+                     "launches": launches, "bytes_per_element": b_elem},
+        "force_apply": apply,
+        "wall_s_timed": round(wall, 3),
+        "setup_s": round(setup_s, 1),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

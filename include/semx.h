@@ -1,0 +1,194 @@
+/*
+ * semx -- spectral-element elastic wave operator for AMD Instinct MI355X (gfx950).
+ *
+ * C interface of libsemx.so.  The library implements the matrix-free
+ * element internal-force operator of the spectral-element method (SEM) for
+ * isotropic elasticity and the explicit, diagonal-mass Newmark time loop
+ * around it, following "High-Order Spectral Element Methods for Wave
+ * Propagation on ARM Multicore CPU with SME" (Sec. II-B: GLL tensor-product
+ * basis, elastic wave equation and weak form, diagonal mass, stiffness
+ * applied as three forward and three transpose batched small contractions;
+ * Sec. IV-C: graph-coloured assembly versus atomic updates; Sec. IV-D: fused
+ * derivative/strain/stress traversal, regular/irregular element paths,
+ * flattened gather/scatter; Sec. V-C: second-order Newmark, Ricker source).
+ *
+ * Conventions
+ *   - Every function returns an int status: SEMX_OK (0) or a negative code.
+ *     semx_last_error() returns a per-context text for the last failure.
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership.  Device pointers passed in (u_dev, f_dev, ...) stay
+ *     owned by the caller and must hold at least the stated number of
+ *     elements; the library never frees them.  Buffers the library allocates
+ *     are freed by semx_destroy().
+ *   - All GPU work is ordered on the HIP stream given to semx_create(); a
+ *     call that returns data to host memory synchronises that stream.
+ *     A context is not thread-safe; use one context per host thread.
+ *   - ngll = n = N+1 GLL points per direction, 2 <= n <= 10 (N = polynomial
+ *     degree).  Element-local point q = i + n*(j + n*k), i fastest (i along
+ *     xi, j along eta, k along zeta).
+ *   - Corner v = a + 2b + 4c of an 8-node hexahedron sits at reference
+ *     coordinates (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the geometry is the
+ *     trilinear map of the 8 corners.
+ *   - Vectors over global nodes are FP32 [nmodels][nglob][3], component
+ *     fastest.  f = -K u is the internal force (the negative stiffness
+ *     action), the right-hand-side term of the weak form.
+ */
+#ifndef SEMX_H
+#define SEMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct semx_ctx semx_ctx;
+
+/* status codes */
+#define SEMX_OK 0
+#define SEMX_EINVAL -1     /* bad argument, size or shape */
+#define SEMX_ESTATE -2     /* call out of order (e.g. step before upload) */
+#define SEMX_EGEOM -3      /* det J <= 0 at some GLL point */
+#define SEMX_EUNSTABLE -4  /* dt above the stability bound of the operator */
+#define SEMX_EHIP -5       /* HIP runtime error; the text names the HIP call */
+#define SEMX_ENOMEM -6     /* device allocation failed */
+#define SEMX_ENUMERIC -7   /* NaN/Inf or energy blow-up detected by the watchdog */
+
+/* contraction arithmetic of the force operator (mixed precision keeps the
+ * geometry map, stress and assembly in FP32) */
+#define SEMX_C_F32 0       /* FP32 VALU contractions through LDS */
+#define SEMX_C_BF16 1      /* BF16-operand MFMA contractions, FP32 accumulation */
+#define SEMX_C_F16 2       /* FP16-operand MFMA contractions, FP32 accumulation */
+
+/* assembly of element forces into the global vector (Sec. IV-C) */
+#define SEMX_ASM_COLORED 0 /* colour by colour, plain read-modify-write, deterministic */
+#define SEMX_ASM_ATOMIC 1  /* one launch, FP32 global atomic adds */
+
+/* Create a context for n = ngll GLL points per direction whose GPU work runs
+ * on hip_stream (a hipStream_t; NULL = the default stream) of the current
+ * device.  Defaults: SEMX_C_F32, SEMX_ASM_COLORED. */
+int semx_create(semx_ctx **out, int ngll, void *hip_stream);
+
+/* Free every buffer of the context.  NULL is accepted. */
+int semx_destroy(semx_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *semx_last_error(const semx_ctx *ctx);
+
+/* Mesh (Sec. II-B; global-to-local map of Sec. IV-C).
+ *   ibool     [nspec][n^3]  global node of each element-local point, 0 <= g < nglob;
+ *   vert_xyz  [nvert][3]    FP64 corner coordinates;
+ *   elem_vert [nspec][8]    corner vertex indices, order above.
+ * The library computes J, det J and Gamma = J^{-1} at every GLL point in FP64
+ * on the device, stores Gamma in FP32, classifies each element as regular
+ * (affine map: Gamma constant) or irregular, and colours the elements by
+ * greedy first-fit in element order so that no two elements of a colour share
+ * a global node.  Returns SEMX_EGEOM if det J <= 0 anywhere.  Invalidates any
+ * uploaded model and time-loop state. */
+int semx_upload_mesh(semx_ctx *ctx, int64_t nspec, int64_t nglob, const int32_t *ibool,
+                     int64_t nvert, const double *vert_xyz, const int32_t *elem_vert);
+
+/* Replace the colouring: elem_order [nspec] lists the elements colour by
+ * colour, colour c owning elem_order[color_ptr[c] .. color_ptr[c+1]-1].
+ * Rejected (SEMX_EINVAL) unless it is a permutation and no two elements of a
+ * colour share a global node. */
+int semx_set_coloring(semx_ctx *ctx, int ncolors, const int32_t *color_ptr, const int32_t *elem_order);
+
+/* Read the current colouring.  color_ptr needs ncolors+1 entries and
+ * elem_order nspec entries; either may be NULL to query ncolors only. */
+int semx_get_coloring(semx_ctx *ctx, int *ncolors, int32_t *color_ptr, int32_t *elem_order);
+
+/* Counts of the mesh: regular and irregular elements and colours. */
+int semx_mesh_info(semx_ctx *ctx, int64_t *nregular, int64_t *nirregular, int *ncolors);
+
+/* Isotropic elastic model per element-local point (Sec. II-B, T = C : grad s
+ * with C isotropic), FP64 host arrays [nmodels][nspec][n^3]: Lame lambda,
+ * mu and density rho.  nmodels > 1 uploads a batch of models sharing the
+ * mesh; state vectors then hold nmodels stacked fields.  The library forms
+ * lambda*w_i w_j w_k det J and mu*w_i w_j w_k det J (FP32) and the lumped
+ * GLL mass M_g = sum rho w_i w_j w_k det J (FP64 accumulate, FP32 M^{-1}).
+ * Requires rho > 0, mu > 0, lambda + 2 mu/3 > 0.  Resets the time loop. */
+int semx_upload_model(semx_ctx *ctx, int nmodels, const double *lambda, const double *mu,
+                      const double *rho);
+
+/* Select the contraction arithmetic and the assembly (constants above). */
+int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
+
+/* f = -K u for every model: u_dev, f_dev device FP32 [nmodels][nglob][3].
+ * f_dev is overwritten (not accumulated).  u_dev and f_dev must not overlap. */
+int semx_apply_force(semx_ctx *ctx, const float *u_dev, float *f_dev);
+
+/* Time step of the explicit Newmark loop (Sec. V-C).  Rejected with
+ * SEMX_EUNSTABLE if dt exceeds 2/sqrt(lambda_max(M^{-1}K)) as estimated by
+ * semx_max_eigenvalue() when that estimate has been made. */
+int semx_set_dt(semx_ctx *ctx, double dt);
+
+/* dt = courant * (min distance between adjacent GLL points) / (max P speed),
+ * P speed sqrt((lambda + 2 mu)/rho) over all points of all models. */
+int semx_cfl_dt(semx_ctx *ctx, double courant, double *dt_out);
+
+/* Largest eigenvalue of M^{-1}K (model 0) by `iters` power iterations on the
+ * device; the explicit scheme is stable for dt < 2/sqrt(lambda_max). */
+int semx_max_eigenvalue(semx_ctx *ctx, int iters, double *lambda_max);
+
+/* Point forces (Sec. V-C: Ricker source).  Source s acts at reference
+ * coordinates xi[s][0..2] in [-1,1]^3 of element elem[s] with unit direction
+ * dir[s][0..2] and time function stf[s][m], m = 0..nstf-1, sample m at
+ * t_m = m dt (samples beyond nstf are 0).  It adds
+ * stf[s][m] dir[s][c] l_i(xi) l_j(eta) l_k(zeta) to node (i,j,k) of elem[s]
+ * (tensor-product interpolation weights, Sec. II-B).  With nmodels > 1 the
+ * same sources act on every model.  nsrc = 0 removes all sources. */
+int semx_set_sources(semx_ctx *ctx, int nsrc, const int32_t *elem, const double *xi,
+                     const double *dir, int64_t nstf, const float *stf);
+
+/* Receivers: displacement interpolated at reference coordinates xi[r] of
+ * element elem[r] (Sec. II-B interpolation) recorded after every step into
+ * a device buffer [nmodels][nrec][3][nt_max]; steps beyond nt_max are not
+ * recorded.  Clears earlier recordings. */
+int semx_set_receivers(semx_ctx *ctx, int nrec, const int32_t *elem, const double *xi, int64_t nt_max);
+
+/* u = v = 0, time index 0, a = M^{-1} f_src(t_0); clears seismograms. */
+int semx_reset(semx_ctx *ctx);
+
+/* Advance nsteps explicit Newmark steps (beta = 0, gamma = 1/2):
+ *   u += dt v + dt^2/2 a;  v += dt/2 a;  f = -K u + f_src(t_{n+1});
+ *   a = M^{-1} f;  v += dt/2 a;  record u at the receivers.
+ * Requires mesh, model and dt.  If the watchdog interval is set, checks
+ * every that many steps that the state is finite (SEMX_ENUMERIC otherwise). */
+int semx_step(semx_ctx *ctx, int64_t nsteps);
+
+/* Current time index (number of steps taken since reset). */
+int semx_time_index(semx_ctx *ctx, int64_t *it);
+
+/* Copy the seismograms [nmodels][nrec][3][nt_max] (FP32) to out, which is a
+ * device pointer if out_on_device != 0, else host memory (stream synchronised). */
+int semx_read_seismograms(semx_ctx *ctx, float *out, int out_on_device);
+
+/* Checkpoint: copy u, v, a ([nmodels][nglob][3] FP32, device pointers; any
+ * may be NULL) and the time index out of / into the context.  Restoring a
+ * state and stepping reproduces the uninterrupted run bitwise with
+ * SEMX_ASM_COLORED. */
+int semx_get_state(semx_ctx *ctx, float *u_dev, float *v_dev, float *a_dev, int64_t *it);
+int semx_set_state(semx_ctx *ctx, const float *u_dev, const float *v_dev, const float *a_dev, int64_t it);
+
+/* Energy of model 0 in FP64 accumulation: kinetic 1/2 v^T M v and
+ * potential 1/2 u^T K u of the current state. */
+int semx_energy(semx_ctx *ctx, double *kinetic, double *potential);
+
+/* Watchdog: every `interval` steps (0 = off) semx_step checks that u and v
+ * are finite, and that the total energy (if max_energy > 0) stays below
+ * max_energy; a violation stops stepping and returns SEMX_ENUMERIC. */
+int semx_set_watchdog(semx_ctx *ctx, int64_t interval, double max_energy);
+
+/* Kernel timing.  While enabled, every force-kernel launch is bracketed by a
+ * pair of HIP events recorded on the context stream.  semx_force_timing()
+ * synchronises the stream, returns the number of force launches and their
+ * summed event-measured duration in milliseconds since the last read, and
+ * clears the record. */
+int semx_set_timing(semx_ctx *ctx, int enable);
+int semx_force_timing(semx_ctx *ctx, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEMX_H */

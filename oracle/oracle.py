@@ -43,6 +43,7 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB)
         i64 = ctypes.c_int64
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_gll.argtypes = [ctypes.c_int, _dp, _dp]
         L.orc_gll.restype = ctypes.c_int
         L.orc_lagrange.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp]
@@ -68,6 +69,11 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's element loops."""
+    return int(lib().orc_num_threads())
 
 
 def gll(n: int):

@@ -30,6 +30,20 @@
 
 #define ORC_MAXN 16
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------------------
  * Legendre polynomial P_N(x) and its first derivative by the three-term
  * recurrence (k+1)P_{k+1} = (2k+1) x P_k - k P_{k-1}.

@@ -1,0 +1,1262 @@
+// libsemx C interface: context, mesh/model upload, force apply, explicit
+// Newmark time loop, sources, receivers, checkpoints, energy.
+//
+// Everything here is either host bookkeeping (validation, colouring, launch
+// lists) or a small HIP kernel; the hot operator lives in force_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "semx_internal.hpp"
+
+namespace semx {
+
+int fail(semx_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(semx_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) +
+                  ") in " + what;
+  return fail(c, SEMX_EHIP, m);
+}
+
+int dev_alloc(semx_ctx* c, DevBuf& b, size_t bytes) {
+  dev_free(b);
+  if (bytes == 0) return SEMX_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, SEMX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return SEMX_OK;
+}
+
+void dev_free(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int cap = 1 << 16) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (FP64): J = dx/dxi of the trilinear map at every GLL point,
+// det J, Gamma = J^{-1} (rows: gradients of the reference coordinates), and
+// W = w_i w_j w_k det J.  Gamma goes out in FP32 when requested.
+// ---------------------------------------------------------------------------
+__global__ void geom_kernel(int n, int64_t nspec, const double* __restrict__ vert,
+                            const int32_t* __restrict__ ev, const double* __restrict__ xi,
+                            const double* __restrict__ w, float* __restrict__ gam_pt,
+                            double* __restrict__ wdet, int* __restrict__ bad) {
+  const int n3 = n * n * n;
+  const int64_t total = nspec * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / n3;
+    const int q = (int)(t - e * n3);
+    const int i = q % n, j = (q / n) % n, k = q / (n * n);
+    const double r0 = xi[i], r1 = xi[j], r2 = xi[k];
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double sa = (v & 1) ? 1.0 : -1.0, sb = (v & 2) ? 1.0 : -1.0, sc = (v & 4) ? 1.0 : -1.0;
+      const double fa = 1.0 + sa * r0, fb = 1.0 + sb * r1, fc = 1.0 + sc * r2;
+      const double d0 = 0.125 * sa * fb * fc, d1 = 0.125 * fa * sb * fc, d2 = 0.125 * fa * fb * sc;
+      const double* x = vert + 3 * (int64_t)ev[8 * e + v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        J[c][0] += x[c] * d0;
+        J[c][1] += x[c] * d1;
+        J[c][2] += x[c] * d2;
+      }
+    }
+    // cofactor matrix C[a][b]; det = sum_b J[0][b] C[0][b]; J^{-1} = C^T / det
+    double C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    if (!(det > 0.0)) atomicOr(bad, 1);
+    const double inv = 1.0 / det;
+    wdet[t] = w[i] * w[j] * w[k] * det;
+    if (gam_pt) {
+      float* gp = gam_pt + e * 9 * n3 + q;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gp[(d * 3 + b) * n3] = (float)(C[b][d] * inv);
+    }
+  }
+}
+
+// Smallest distance between GLL points adjacent along xi, eta or zeta (FP64),
+// reduced with an integer atomicMin on the bit pattern (positive doubles
+// order like their bits).
+__global__ void spacing_kernel(int n, int64_t nspec, const double* __restrict__ vert,
+                               const int32_t* __restrict__ ev, const double* __restrict__ xi,
+                               unsigned long long* __restrict__ out) {
+  const int n3 = n * n * n;
+  const int64_t total = nspec * n3;
+  double best = 1e300;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = t / n3;
+    const int q = (int)(t - e * n3);
+    const int ijk[3] = {q % n, (q / n) % n, q / (n * n)};
+    double x0[3];
+    auto map = [&](int a, int b, int c, double* x) {
+      const double r[3] = {xi[a], xi[b], xi[c]};
+      x[0] = x[1] = x[2] = 0.0;
+      for (int v = 0; v < 8; ++v) {
+        const double Nv = 0.125 * (1.0 + ((v & 1) ? 1.0 : -1.0) * r[0]) *
+                          (1.0 + ((v & 2) ? 1.0 : -1.0) * r[1]) * (1.0 + ((v & 4) ? 1.0 : -1.0) * r[2]);
+        const double* xv = vert + 3 * (int64_t)ev[8 * e + v];
+        x[0] += Nv * xv[0];
+        x[1] += Nv * xv[1];
+        x[2] += Nv * xv[2];
+      }
+    };
+    map(ijk[0], ijk[1], ijk[2], x0);
+    for (int d = 0; d < 3; ++d) {
+      if (ijk[d] + 1 >= n) continue;
+      int m[3] = {ijk[0], ijk[1], ijk[2]};
+      m[d] += 1;
+      double x1[3];
+      map(m[0], m[1], m[2], x1);
+      const double dist = sqrt((x1[0] - x0[0]) * (x1[0] - x0[0]) + (x1[1] - x0[1]) * (x1[1] - x0[1]) +
+                               (x1[2] - x0[2]) * (x1[2] - x0[2]));
+      best = fmin(best, dist);
+    }
+  }
+  if (best < 1e300) atomicMin(out, (unsigned long long)__double_as_longlong(best));
+}
+
+// lambda W, mu W (FP32) and rho W per element-local point for every model.
+__global__ void material_kernel(int n3, int64_t nspec, int nmodels, const double* __restrict__ lam,
+                                const double* __restrict__ mu, const double* __restrict__ rho,
+                                const double* __restrict__ wdet, float* __restrict__ mat,
+                                float* __restrict__ wrho) {
+  const int64_t total = (int64_t)nmodels * nspec * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t me = t / n3;  // model * nspec + e
+    const int q = (int)(t - me * n3);
+    const int64_t e = me % nspec;
+    const double W = wdet[e * n3 + q];
+    mat[me * 2 * n3 + q] = (float)(lam[t] * W);
+    mat[me * 2 * n3 + n3 + q] = (float)(mu[t] * W);
+    wrho[t] = (float)(rho[t] * W);
+  }
+}
+
+// Lumped mass, one colour at a time (no two elements of a colour share a
+// node, so plain read-modify-write in FP64 is race free and deterministic).
+__global__ void mass_color_kernel(int n3, int64_t nspec, int64_t nglob, int nmodels,
+                                  const int32_t* __restrict__ elems, int64_t count,
+                                  const int32_t* __restrict__ ibool, const double* __restrict__ rho,
+                                  const double* __restrict__ wdet, double* __restrict__ mass) {
+  const int64_t total = (int64_t)nmodels * count * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t mp = t / n3;
+    const int q = (int)(t - mp * n3);
+    const int model = (int)(mp / count);
+    const int64_t e = elems[mp - (int64_t)model * count];
+    const int64_t pt = e * n3 + q;
+    mass[(int64_t)model * nglob + ibool[pt]] += rho[(int64_t)model * nspec * n3 + pt] * wdet[pt];
+  }
+}
+
+__global__ void mass_serial_kernel(int n3, int64_t nspec, int64_t nglob, int nmodels,
+                                   const int32_t* __restrict__ ibool, const double* __restrict__ rho,
+                                   const double* __restrict__ wdet, double* __restrict__ mass) {
+  for (int model = 0; model < nmodels; ++model)
+    for (int64_t pt = 0; pt < nspec * n3; ++pt)
+      mass[(int64_t)model * nglob + ibool[pt]] += rho[(int64_t)model * nspec * n3 + pt] * wdet[pt];
+}
+
+__global__ void minv_kernel(int64_t n, const double* __restrict__ mass, float* __restrict__ minv) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    minv[t] = (float)(1.0 / mass[t]);
+}
+
+__global__ void fill_f32(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+__global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Explicit Newmark (beta = 0, gamma = 1/2) update, one thread per global node
+// and model.  mode bit 1 (kCorrect): acc = M^{-1} f, v += dt/2 acc, and acc
+// is stored to a if kStoreA; without it acc is read from a.  Bit 2
+// (kPredict): u += dt v + dt^2/2 acc, v += dt/2 acc, f = 0.  A step is
+// "correct then predict" in one pass, so a never has to be written.
+// ---------------------------------------------------------------------------
+constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4;
+
+template <int MODE>
+__global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
+                               float* __restrict__ u, float* __restrict__ v, float* __restrict__ a,
+                               float* __restrict__ f) {
+  const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    float acc, vv = v[t];
+    if constexpr ((MODE & kCorrect) != 0) {
+      acc = minv[t / 3] * f[t];
+      vv = vv + hdt * acc;
+      if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+    } else {
+      acc = a[t];
+    }
+    if constexpr ((MODE & kPredict) != 0) {
+      u[t] = u[t] + dt * vv + hdt2 * acc;
+      vv = vv + hdt * acc;
+      f[t] = 0.0f;
+    }
+    v[t] = vv;
+  }
+}
+
+// a = M^{-1} f without touching v (initial acceleration).
+__global__ void accel_kernel(int64_t nnodes, const float* __restrict__ minv, const float* __restrict__ f,
+                             float* __restrict__ a) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+       t += (int64_t)gridDim.x * blockDim.x)
+    a[t] = minv[t / 3] * f[t];
+}
+
+// Point forces at sample m: f[node] += stf[s][m] * l_q(x_s) dir_c, all models.
+__global__ void source_kernel(int nsrc, int n3, int64_t nstf, int64_t m, int nmodels, int64_t nglob,
+                              const int32_t* __restrict__ nodes, const float* __restrict__ wdir,
+                              const float* __restrict__ stf, float* __restrict__ f) {
+  const int64_t total = (int64_t)nmodels * nsrc * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sq = t % ((int64_t)nsrc * n3);
+    const int model = (int)(t / ((int64_t)nsrc * n3));
+    const int s = (int)(sq / n3);
+    const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)s * nstf + m] : 0.0f;
+    if (amp == 0.0f) continue;
+    float* fg = f + ((int64_t)model * nglob + nodes[sq]) * 3;
+    unsafeAtomicAdd(fg + 0, amp * wdir[3 * sq + 0]);
+    unsafeAtomicAdd(fg + 1, amp * wdir[3 * sq + 1]);
+    unsafeAtomicAdd(fg + 2, amp * wdir[3 * sq + 2]);
+  }
+}
+
+// Receivers: one block per (model, receiver); sum_q l_q(x_r) u[node_q] per component.
+__global__ void receiver_kernel(int nrec, int n3, int64_t nglob, int64_t nt_max, int64_t it,
+                                const int32_t* __restrict__ nodes, const float* __restrict__ wts,
+                                const float* __restrict__ u, float* __restrict__ seis) {
+  __shared__ float red[3][256];
+  const int r = blockIdx.x, model = blockIdx.y;
+  const float* um = u + (int64_t)model * nglob * 3;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    const float wq = wts[(int64_t)r * n3 + q];
+    const int64_t g = nodes[(int64_t)r * n3 + q];
+    s0 += wq * um[3 * g + 0];
+    s1 += wq * um[3 * g + 1];
+    s2 += wq * um[3 * g + 2];
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3)
+    seis[(((int64_t)model * nrec + r) * 3 + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
+}
+
+// FP64 block reductions accumulated with a double atomic into out[slot].
+__device__ inline void block_sum_to(double v, double* out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// out[0] += sum_g mass_g |x_g|^2 (FP64), over one model's nodes.
+__global__ void mnorm_kernel(int64_t nglob, const double* __restrict__ mass, const float* __restrict__ x,
+                             double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nglob;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double xv = x[t];
+    s += mass[t / 3] * xv * xv;
+  }
+  block_sum_to(s, out);
+}
+
+// out[0] += sum x.y (FP64)
+__global__ void dot_kernel(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
+                           double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[t] * (double)y[t];
+  block_sum_to(s, out);
+}
+
+// flag[0] = 1 if any entry is NaN or Inf
+__global__ void finite_kernel(int64_t n, const float* __restrict__ x, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[t]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// power iteration helpers: y = -M^{-1} f (f = -K x), so y = M^{-1} K x
+__global__ void neg_minv_kernel(int64_t nglob, const float* __restrict__ minv, const float* __restrict__ f,
+                                float* __restrict__ y, float scale) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nglob;
+       t += (int64_t)gridDim.x * blockDim.x)
+    y[t] = -minv[t / 3] * f[t] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+int check_ctx(semx_ctx* c) {
+  if (!c) return SEMX_EINVAL;
+  return SEMX_OK;
+}
+
+int set_device(semx_ctx* c) {
+  SEMX_HIP(c, hipSetDevice(c->device));
+  return SEMX_OK;
+}
+
+int grid_cap_force(semx_ctx* c) {
+  // enough resident blocks to fill every CU several times over
+  return c->num_cu * 8;
+}
+
+// Greedy first-fit colouring in element order (Sec. IV-C: element adjacency
+// from the global-to-local map, colour by colour execution).  Two elements
+// conflict when they share a global node; with `corners_only` the conflict
+// test uses the 8 corner nodes (enough for a conforming hexahedral mesh,
+// where shared edges and faces imply shared corners).
+void greedy_color(int n, int64_t nspec, int64_t nglob, const int32_t* ibool, bool corners_only,
+                  std::vector<int32_t>& color) {
+  const int n3 = n * n * n;
+  const int N = n - 1;
+  std::vector<int> qs;
+  if (corners_only) {
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) qs.push_back(a * N + n * (b * N + n * c * N));
+  } else {
+    for (int q = 0; q < n3; ++q) qs.push_back(q);
+  }
+  // node -> elements (CSR) over the selected local points
+  std::vector<int64_t> cnt(nglob + 1, 0);
+  for (int64_t e = 0; e < nspec; ++e)
+    for (int q : qs) cnt[ibool[e * n3 + q] + 1]++;
+  for (int64_t g = 0; g < nglob; ++g) cnt[g + 1] += cnt[g];
+  std::vector<int32_t> adj(cnt[nglob]);
+  std::vector<int64_t> fillp(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < nspec; ++e)
+    for (int q : qs) adj[fillp[ibool[e * n3 + q]]++] = (int32_t)e;
+  color.assign(nspec, -1);
+  std::vector<int64_t> stamp(1024, -1);
+  for (int64_t e = 0; e < nspec; ++e) {
+    for (int q : qs) {
+      const int64_t g = ibool[e * n3 + q];
+      for (int64_t t = cnt[g]; t < cnt[g + 1]; ++t) {
+        const int32_t o = adj[t];
+        if (o != e && color[o] >= 0) stamp[color[o]] = e;
+      }
+    }
+    int c = 0;
+    while (c < (int)stamp.size() && stamp[c] == e) ++c;
+    if (c >= (int)stamp.size()) stamp.resize(stamp.size() * 2, -1);
+    color[e] = c;
+  }
+}
+
+// True if no two elements of a colour share a global node and every element
+// has distinct nodes.
+bool coloring_valid(int n3, int64_t nspec, int64_t nglob, const int32_t* ibool, int ncolors,
+                    const int32_t* cptr, const int32_t* order) {
+  std::vector<int64_t> stamp(nglob, -1);
+  for (int c = 0; c < ncolors; ++c) {
+    for (int32_t t = cptr[c]; t < cptr[c + 1]; ++t) {
+      const int64_t e = order[t];
+      for (int q = 0; q < n3; ++q) {
+        const int64_t g = ibool[e * n3 + q];
+        if (stamp[g] == c) return false;
+        stamp[g] = c;
+      }
+    }
+  }
+  return true;
+}
+
+int build_launch_lists(semx_ctx* c) {
+  // per colour: regular list then irregular list; then the two atomic lists
+  std::vector<int32_t> lists;
+  lists.reserve(2 * c->nspec);
+  struct Range { int64_t off, cnt; bool irr; };
+  std::vector<Range> col, atom;
+  for (int k = 0; k < c->ncolors; ++k) {
+    for (int irr = 0; irr < 2; ++irr) {
+      Range r{(int64_t)lists.size(), 0, irr == 1};
+      for (int32_t t = c->color_ptr[k]; t < c->color_ptr[k + 1]; ++t) {
+        const int32_t e = c->elem_order[t];
+        if ((c->h_regular[e] == 0) == (irr == 1)) lists.push_back(e);
+      }
+      r.cnt = (int64_t)lists.size() - r.off;
+      if (r.cnt) col.push_back(r);
+    }
+  }
+  for (int irr = 0; irr < 2; ++irr) {
+    Range r{(int64_t)lists.size(), 0, irr == 1};
+    for (int64_t e = 0; e < c->nspec; ++e)
+      if ((c->h_regular[e] == 0) == (irr == 1)) lists.push_back((int32_t)e);
+    r.cnt = (int64_t)lists.size() - r.off;
+    if (r.cnt) atom.push_back(r);
+  }
+  int rc = dev_alloc(c, c->d_lists, lists.size() * sizeof(int32_t));
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->d_lists.p, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  c->colored_launches.clear();
+  c->atomic_launches.clear();
+  for (auto& r : col) c->colored_launches.push_back({c->d_lists.as<int32_t>() + r.off, r.cnt, r.irr});
+  for (auto& r : atom) c->atomic_launches.push_back({c->d_lists.as<int32_t>() + r.off, r.cnt, r.irr});
+  return SEMX_OK;
+}
+
+// f = -K u accumulated into f (f must already hold zeros or earlier sums).
+int force_accumulate(semx_ctx* c, const float* u, float* f) {
+  ForceArgs a{};
+  a.ibool = c->d_ibool.as<int32_t>();
+  a.gam_pt = c->d_gam_pt.as<float>();
+  a.gam_el = c->d_gam_el.as<float>();
+  a.mat = c->d_mat.as<float>();
+  a.u = u;
+  a.f = f;
+  a.D = c->d_D.as<float>();
+  a.Dh = c->d_Dh.p;
+  a.nspec = c->nspec;
+  a.nglob = c->nglob;
+  a.nmodels = c->nmodels;
+  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
+  const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
+  for (const auto& L : launches) {
+    a.elems = L.elems;
+    a.count = L.count;
+    hipError_t e;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t ev;
+        SEMX_HIP(c, hipEventCreate(&ev));
+        c->ev_pool.push_back(ev);
+      }
+      e0 = c->ev_pool[c->ev_used];
+      e1 = c->ev_pool[c->ev_used + 1];
+      c->ev_used += 2;
+      SEMX_HIP(c, hipEventRecord(e0, c->stream));
+    }
+    if (c->contraction == SEMX_C_F32)
+      e = launch_force_f32(c->n, L.irregular, atomic, a, grid_cap_force(c), c->stream);
+    else
+      e = launch_force_mfma(c->n, c->contraction, L.irregular, atomic, a, grid_cap_force(c), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
+    if (c->timing) SEMX_HIP(c, hipEventRecord(e1, c->stream));
+  }
+  return SEMX_OK;
+}
+
+int zero_f32(semx_ctx* c, float* p, int64_t n) {
+  fill_f32<<<grid_for(n), kThreads, 0, c->stream>>>(p, n, 0.0f);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int64_t state_len(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * 3; }
+
+int inject_sources(semx_ctx* c, int64_t m, float* f) {
+  if (c->src.nsrc == 0) return SEMX_OK;
+  const int64_t total = (int64_t)c->nmodels * c->src.nsrc * c->n3;
+  source_kernel<<<grid_for(total), kThreads, 0, c->stream>>>(
+      c->src.nsrc, c->n3, c->src.nstf, m, c->nmodels, c->nglob, c->src.nodes.as<int32_t>(),
+      c->src.wdir.as<float>(), c->src.stf.as<float>(), f);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int finalize_state(semx_ctx* c) {
+  if (!c->pending_correct) return SEMX_OK;
+  const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  newmark_kernel<kCorrect | kStoreA><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(
+      nn, c->nglob, (float)c->dt, c->d_minv.as<float>(), c->d_u.as<float>(), c->d_v.as<float>(),
+      c->d_a.as<float>(), c->d_f.as<float>());
+  SEMX_HIP(c, hipGetLastError());
+  c->pending_correct = false;
+  return SEMX_OK;
+}
+
+int do_reset(semx_ctx* c) {
+  const int64_t len = state_len(c);
+  for (auto* b : {&c->d_u, &c->d_v, &c->d_a, &c->d_f}) {
+    int rc = zero_f32(c, b->as<float>(), len);
+    if (rc) return rc;
+  }
+  c->it = 0;
+  c->pending_correct = false;
+  if (c->rec.nrec > 0 && c->rec.seis.p) {
+    int rc = zero_f32(c, c->rec.seis.as<float>(), c->rec.seis.bytes / sizeof(float));
+    if (rc) return rc;
+  }
+  if (c->src.nsrc > 0) {
+    int rc = inject_sources(c, 0, c->d_f.as<float>());
+    if (rc) return rc;
+    const int64_t nn = (int64_t)c->nmodels * c->nglob;
+    accel_kernel<<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->d_minv.as<float>(),
+                                                               c->d_f.as<float>(), c->d_a.as<float>());
+    SEMX_HIP(c, hipGetLastError());
+    rc = zero_f32(c, c->d_f.as<float>(), len);
+    if (rc) return rc;
+  }
+  return SEMX_OK;
+}
+
+int record_receivers(semx_ctx* c, int64_t idx) {
+  if (c->rec.nrec == 0 || idx < 0 || idx >= c->rec.nt_max) return SEMX_OK;
+  dim3 grid(c->rec.nrec, c->nmodels);
+  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->nglob, c->rec.nt_max, idx,
+                                               c->rec.nodes.as<int32_t>(), c->rec.wts.as<float>(),
+                                               c->d_u.as<float>(), c->rec.seis.as<float>());
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+// scratch layout: [0..7] doubles for reductions, then int flags
+double* scratch_d(semx_ctx* c) { return c->d_scratch.as<double>(); }
+int* scratch_i(semx_ctx* c) { return reinterpret_cast<int*>(c->d_scratch.as<double>() + 8); }
+
+int energy_model0(semx_ctx* c, double* kin, double* pot) {
+  int rc = finalize_state(c);
+  if (rc) return rc;
+  const int64_t n3g = 3 * c->nglob;
+  fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
+  // kinetic: 1/2 sum M v^2
+  mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(),
+                                                                c->d_v.as<float>(), scratch_d(c));
+  SEMX_HIP(c, hipGetLastError());
+  // potential: 1/2 u^T K u = -1/2 u . f(u), f(u) computed into the work vector
+  DevBuf& tmp = c->d_work;
+  rc = zero_f32(c, tmp.as<float>(), state_len(c));
+  if (!rc) rc = force_accumulate(c, c->d_u.as<float>(), tmp.as<float>());
+  if (!rc) {
+    dot_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(n3g, c->d_u.as<float>(), tmp.as<float>(),
+                                                               scratch_d(c) + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(c, e, "dot_kernel");
+  }
+  double h[2] = {0, 0};
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(h, scratch_d(c), 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(c, e, "energy readback");
+  }
+  if (rc) return rc;
+  *kin = 0.5 * h[0];
+  *pot = -0.5 * h[1];
+  return SEMX_OK;
+}
+
+int check_finite(semx_ctx* c, bool* ok) {
+  int* flag = scratch_i(c);
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync flag");
+  const int64_t len = state_len(c);
+  finite_kernel<<<grid_for(len, 4096), kThreads, 0, c->stream>>>(len, c->d_u.as<float>(), flag);
+  finite_kernel<<<grid_for(len, 4096), kThreads, 0, c->stream>>>(len, c->d_v.as<float>(), flag);
+  int h = 0;
+  e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "finite check");
+  *ok = (h == 0);
+  return SEMX_OK;
+}
+
+}  // namespace
+}  // namespace semx
+
+using namespace semx;
+
+extern "C" {
+
+int semx_create(semx_ctx** out, int ngll, void* hip_stream) {
+  if (!out) return SEMX_EINVAL;
+  *out = nullptr;
+  if (ngll < 2 || ngll > kMaxN) return SEMX_EINVAL;
+  semx_ctx* c = new semx_ctx();
+  c->n = ngll;
+  c->n3 = ngll * ngll * ngll;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, c->device);
+    if (e == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return SEMX_EHIP;
+  }
+  gll_nodes_weights(ngll, c->xi, c->w);
+  deriv_matrix(ngll, c->xi, c->D);
+  std::vector<float> Df(c->D.begin(), c->D.end());
+  int rc = dev_alloc(c, c->d_D, Df.size() * sizeof(float));
+  if (!rc) rc = dev_alloc(c, c->d_xi64, ngll * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->d_w64, ngll * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->d_scratch, 8 * sizeof(double) + 64);
+  if (rc) {
+    semx_destroy(c);
+    return rc;
+  }
+  e = hipMemcpy(c->d_D.p, Df.data(), Df.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_xi64.p, c->xi.data(), ngll * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_w64.p, c->w.data(), ngll * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    semx_destroy(c);
+    return SEMX_EHIP;
+  }
+  *out = c;
+  return SEMX_OK;
+}
+
+int semx_destroy(semx_ctx* c) {
+  if (!c) return SEMX_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
+  for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
+                    &c->d_gam_pt, &c->d_gam_el, &c->d_wdet, &c->d_lists, &c->d_mat, &c->d_minv,
+                    &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
+                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis})
+    dev_free(*b);
+  delete c;
+  return SEMX_OK;
+}
+
+const char* semx_last_error(const semx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int semx_upload_mesh(semx_ctx* c, int64_t nspec, int64_t nglob, const int32_t* ibool, int64_t nvert,
+                     const double* vert_xyz, const int32_t* elem_vert) {
+  if (!c) return SEMX_EINVAL;
+  c->err.clear();
+  if (nspec <= 0 || nglob <= 0 || nvert <= 0 || !ibool || !vert_xyz || !elem_vert)
+    return fail(c, SEMX_EINVAL, "upload_mesh: empty mesh or null array");
+  if (nspec * c->n3 >= ((int64_t)1 << 31) || 3 * nglob >= ((int64_t)1 << 31))
+    return fail(c, SEMX_EINVAL, "upload_mesh: mesh exceeds 2^31 element-local points or 2^31/3 nodes");
+  const int n = c->n, n3 = c->n3;
+  for (int64_t t = 0; t < nspec * n3; ++t)
+    if (ibool[t] < 0 || ibool[t] >= nglob)
+      return fail(c, SEMX_EINVAL, "upload_mesh: ibool entry outside [0, nglob)");
+  for (int64_t t = 0; t < nspec * 8; ++t)
+    if (elem_vert[t] < 0 || elem_vert[t] >= nvert)
+      return fail(c, SEMX_EINVAL, "upload_mesh: elem_vert entry outside [0, nvert)");
+  for (int64_t t = 0; t < 3 * nvert; ++t)
+    if (!std::isfinite(vert_xyz[t])) return fail(c, SEMX_EINVAL, "upload_mesh: non-finite vertex coordinate");
+  int rc = set_device(c);
+  if (rc) return rc;
+  c->have_mesh = c->have_model = false;
+  c->nspec = nspec;
+  c->nglob = nglob;
+  c->nvert = nvert;
+  c->h_ibool.assign(ibool, ibool + nspec * n3);
+  c->h_elem_vert.assign(elem_vert, elem_vert + nspec * 8);
+  c->h_vert.assign(vert_xyz, vert_xyz + 3 * nvert);
+
+  // regular (affine) elements: x_v - x_0 = a e1 + b e2 + c e3 for corner v = a + 2b + 4c
+  c->h_regular.assign(nspec, 0);
+  c->nregular = 0;
+  std::vector<float> gam_el(9 * nspec, 0.0f);
+  for (int64_t e = 0; e < nspec; ++e) {
+    const double* x0 = vert_xyz + 3 * (int64_t)elem_vert[8 * e];
+    double E[3][3];
+    double scale = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double* xd = vert_xyz + 3 * (int64_t)elem_vert[8 * e + (1 << d)];
+      for (int a = 0; a < 3; ++a) {
+        E[a][d] = xd[a] - x0[a];
+        scale = std::max(scale, std::fabs(E[a][d]));
+      }
+    }
+    bool affine = true;
+    for (int v = 0; v < 8 && affine; ++v) {
+      const double* xv = vert_xyz + 3 * (int64_t)elem_vert[8 * e + v];
+      for (int a = 0; a < 3; ++a) {
+        const double pred = x0[a] + ((v & 1) ? E[a][0] : 0.0) + ((v & 2) ? E[a][1] : 0.0) + ((v & 4) ? E[a][2] : 0.0);
+        if (std::fabs(xv[a] - pred) > 1e-12 * scale) affine = false;
+      }
+    }
+    if (!affine) continue;
+    // J = E/2 (reference cube has side 2); Gamma = J^{-1}
+    double J[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int d = 0; d < 3; ++d) J[a][d] = 0.5 * E[a][d];
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(det > 0.0)) continue;  // left to the device check, which reports it
+    double G[3][3];
+    G[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    G[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    G[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    G[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    G[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    G[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    G[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    G[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    G[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < 3; ++b) gam_el[9 * e + 3 * d + b] = (float)G[d][b];
+    c->h_regular[e] = 1;
+    c->nregular++;
+  }
+  c->nirregular = nspec - c->nregular;
+
+  rc = dev_alloc(c, c->d_ibool, sizeof(int32_t) * nspec * n3);
+  if (!rc) rc = dev_alloc(c, c->d_vert, sizeof(double) * 3 * nvert);
+  if (!rc) rc = dev_alloc(c, c->d_elem_vert, sizeof(int32_t) * 8 * nspec);
+  if (!rc) rc = dev_alloc(c, c->d_gam_el, sizeof(float) * 9 * nspec);
+  if (!rc) rc = dev_alloc(c, c->d_wdet, sizeof(double) * nspec * n3);
+  if (!rc && c->nirregular > 0) rc = dev_alloc(c, c->d_gam_pt, sizeof(float) * 9 * nspec * n3);
+  if (!rc && c->nirregular == 0) dev_free(c->d_gam_pt);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->d_ibool.p, ibool, sizeof(int32_t) * nspec * n3, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_vert.p, vert_xyz, sizeof(double) * 3 * nvert, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_elem_vert.p, elem_vert, sizeof(int32_t) * 8 * nspec, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gam_el.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
+
+  int* bad = scratch_i(c);
+  unsigned long long* hmin_bits = reinterpret_cast<unsigned long long*>(scratch_d(c));
+  SEMX_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+  const unsigned long long big = 0x7FEFFFFFFFFFFFFFull;
+  SEMX_HIP(c, hipMemcpyAsync(hmin_bits, &big, sizeof(big), hipMemcpyHostToDevice, c->stream));
+  geom_kernel<<<grid_for(nspec * n3, 8192), kThreads, 0, c->stream>>>(
+      n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_xi64.as<double>(),
+      c->d_w64.as<double>(), c->d_gam_pt.as<float>(), c->d_wdet.as<double>(), bad);
+  SEMX_HIP(c, hipGetLastError());
+  spacing_kernel<<<grid_for(nspec * n3, 4096), kThreads, 0, c->stream>>>(
+      n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_xi64.as<double>(), hmin_bits);
+  SEMX_HIP(c, hipGetLastError());
+  int hbad = 0;
+  unsigned long long hbits = 0;
+  SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipMemcpyAsync(&hbits, hmin_bits, sizeof(hbits), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  if (hbad) return fail(c, SEMX_EGEOM, "upload_mesh: det J <= 0 at some GLL point");
+  std::memcpy(&c->hmin, &hbits, sizeof(double));
+
+  // colouring: corners first, full-node conflicts if that is not valid
+  std::vector<int32_t> color;
+  greedy_color(n, nspec, nglob, ibool, true, color);
+  auto to_lists = [&](const std::vector<int32_t>& col) {
+    int nc = 0;
+    for (auto v : col) nc = std::max(nc, v + 1);
+    c->ncolors = nc;
+    c->color_ptr.assign(nc + 1, 0);
+    for (auto v : col) c->color_ptr[v + 1]++;
+    for (int k = 0; k < nc; ++k) c->color_ptr[k + 1] += c->color_ptr[k];
+    c->elem_order.assign(nspec, 0);
+    std::vector<int32_t> pos(c->color_ptr.begin(), c->color_ptr.end() - 1);
+    for (int64_t e = 0; e < nspec; ++e) c->elem_order[pos[col[e]]++] = (int32_t)e;
+  };
+  to_lists(color);
+  if (!coloring_valid(n3, nspec, nglob, ibool, c->ncolors, c->color_ptr.data(), c->elem_order.data())) {
+    greedy_color(n, nspec, nglob, ibool, false, color);
+    to_lists(color);
+    if (!coloring_valid(n3, nspec, nglob, ibool, c->ncolors, c->color_ptr.data(), c->elem_order.data())) {
+      // an element repeats a node (e.g. a periodic mesh one element wide): only atomics are exact
+      c->ncolors = 0;
+      c->assembly = SEMX_ASM_ATOMIC;
+    }
+  }
+  rc = build_launch_lists(c);
+  if (rc) return rc;
+  c->have_mesh = true;
+  return SEMX_OK;
+}
+
+int semx_set_coloring(semx_ctx* c, int ncolors, const int32_t* color_ptr, const int32_t* elem_order) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "set_coloring: no mesh");
+  if (ncolors <= 0 || !color_ptr || !elem_order) return fail(c, SEMX_EINVAL, "set_coloring: bad arguments");
+  if (color_ptr[0] != 0 || color_ptr[ncolors] != c->nspec)
+    return fail(c, SEMX_EINVAL, "set_coloring: color_ptr must run from 0 to nspec");
+  for (int k = 0; k < ncolors; ++k)
+    if (color_ptr[k + 1] < color_ptr[k]) return fail(c, SEMX_EINVAL, "set_coloring: color_ptr decreasing");
+  std::vector<char> seen(c->nspec, 0);
+  for (int64_t t = 0; t < c->nspec; ++t) {
+    const int32_t e = elem_order[t];
+    if (e < 0 || e >= c->nspec || seen[e]) return fail(c, SEMX_EINVAL, "set_coloring: not a permutation");
+    seen[e] = 1;
+  }
+  if (!coloring_valid(c->n3, c->nspec, c->nglob, c->h_ibool.data(), ncolors, color_ptr, elem_order))
+    return fail(c, SEMX_EINVAL, "set_coloring: two elements of a colour share a node");
+  c->ncolors = ncolors;
+  c->color_ptr.assign(color_ptr, color_ptr + ncolors + 1);
+  c->elem_order.assign(elem_order, elem_order + c->nspec);
+  return build_launch_lists(c);
+}
+
+int semx_get_coloring(semx_ctx* c, int* ncolors, int32_t* color_ptr, int32_t* elem_order) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "get_coloring: no mesh");
+  if (ncolors) *ncolors = c->ncolors;
+  if (color_ptr && c->ncolors) std::copy(c->color_ptr.begin(), c->color_ptr.end(), color_ptr);
+  if (elem_order && c->ncolors) std::copy(c->elem_order.begin(), c->elem_order.end(), elem_order);
+  return SEMX_OK;
+}
+
+int semx_mesh_info(semx_ctx* c, int64_t* nregular, int64_t* nirregular, int* ncolors) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "mesh_info: no mesh");
+  if (nregular) *nregular = c->nregular;
+  if (nirregular) *nirregular = c->nirregular;
+  if (ncolors) *ncolors = c->ncolors;
+  return SEMX_OK;
+}
+
+int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const double* mu, const double* rho) {
+  if (!c) return SEMX_EINVAL;
+  c->err.clear();
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "upload_model: no mesh");
+  if (nmodels <= 0 || !lambda || !mu || !rho) return fail(c, SEMX_EINVAL, "upload_model: bad arguments");
+  const int64_t npt = (int64_t)nmodels * c->nspec * c->n3;
+  if (npt >= ((int64_t)1 << 31) || 3 * (int64_t)nmodels * c->nglob >= ((int64_t)1 << 31))
+    return fail(c, SEMX_EINVAL, "upload_model: batch too large");
+  double vpmax = 0.0;
+  for (int64_t t = 0; t < npt; ++t) {
+    const double l = lambda[t], m = mu[t], r = rho[t];
+    if (!(r > 0.0) || !(m > 0.0) || !(l + 2.0 * m / 3.0 > 0.0) || !std::isfinite(l) || !std::isfinite(m) ||
+        !std::isfinite(r))
+      return fail(c, SEMX_EINVAL, "upload_model: need rho > 0, mu > 0, lambda + 2 mu/3 > 0");
+    vpmax = std::max(vpmax, std::sqrt((l + 2.0 * m) / r));
+  }
+  int rc = set_device(c);
+  if (rc) return rc;
+  c->have_model = false;
+  c->nmodels = nmodels;
+  c->vp_max = vpmax;
+  DevBuf dl, dm, dr;
+  rc = dev_alloc(c, dl, sizeof(double) * npt);
+  if (!rc) rc = dev_alloc(c, dm, sizeof(double) * npt);
+  if (!rc) rc = dev_alloc(c, dr, sizeof(double) * npt);
+  if (!rc) rc = dev_alloc(c, c->d_mat, sizeof(float) * 2 * npt);
+  if (!rc) rc = dev_alloc(c, c->d_wrho, sizeof(float) * npt);
+  if (!rc) rc = dev_alloc(c, c->d_mass64, sizeof(double) * nmodels * c->nglob);
+  if (!rc) rc = dev_alloc(c, c->d_minv, sizeof(float) * nmodels * c->nglob);
+  const int64_t len = 3 * (int64_t)nmodels * c->nglob;
+  if (!rc) rc = dev_alloc(c, c->d_u, sizeof(float) * len);
+  if (!rc) rc = dev_alloc(c, c->d_v, sizeof(float) * len);
+  if (!rc) rc = dev_alloc(c, c->d_a, sizeof(float) * len);
+  if (!rc) rc = dev_alloc(c, c->d_f, sizeof(float) * len);
+  if (!rc) rc = dev_alloc(c, c->d_work, sizeof(float) * len);
+  auto cleanup = [&]() { dev_free(dl); dev_free(dm); dev_free(dr); };
+  if (rc) { cleanup(); return rc; }
+  hipError_t e = hipMemcpy(dl.p, lambda, sizeof(double) * npt, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dm.p, mu, sizeof(double) * npt, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dr.p, rho, sizeof(double) * npt, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { cleanup(); return hip_fail(c, e, "upload_model copies"); }
+  material_kernel<<<grid_for(npt, 8192), kThreads, 0, c->stream>>>(
+      c->n3, c->nspec, nmodels, dl.as<double>(), dm.as<double>(), dr.as<double>(), c->d_wdet.as<double>(),
+      c->d_mat.as<float>(), c->d_wrho.as<float>());
+  fill_f64<<<grid_for(nmodels * c->nglob), kThreads, 0, c->stream>>>(c->d_mass64.as<double>(),
+                                                                     nmodels * c->nglob, 0.0);
+  // deterministic mass assembly, colour by colour (element order if uncoloured)
+  std::vector<int32_t> order;
+  std::vector<int32_t> cptr;
+  if (c->ncolors > 0) {
+    order = c->elem_order;
+    cptr = c->color_ptr;
+  }
+  DevBuf dorder;
+  if (c->ncolors > 0) {
+    rc = dev_alloc(c, dorder, sizeof(int32_t) * c->nspec);
+    if (rc) { cleanup(); return rc; }
+    e = hipMemcpy(dorder.p, order.data(), sizeof(int32_t) * c->nspec, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { cleanup(); dev_free(dorder); return hip_fail(c, e, "mass order copy"); }
+    for (int k = 0; k < c->ncolors; ++k) {
+      const int64_t cnt = cptr[k + 1] - cptr[k];
+      if (!cnt) continue;
+      mass_color_kernel<<<grid_for((int64_t)nmodels * cnt * c->n3, 8192), kThreads, 0, c->stream>>>(
+          c->n3, c->nspec, c->nglob, nmodels, dorder.as<int32_t>() + cptr[k], cnt, c->d_ibool.as<int32_t>(),
+          dr.as<double>(), c->d_wdet.as<double>(), c->d_mass64.as<double>());
+    }
+  } else {
+    // no valid colouring (an element repeats a node): one thread walks the
+    // elements in order, which keeps the sum deterministic (tiny meshes only)
+    mass_serial_kernel<<<1, 1, 0, c->stream>>>(c->n3, c->nspec, c->nglob, nmodels, c->d_ibool.as<int32_t>(),
+                                               dr.as<double>(), c->d_wdet.as<double>(), c->d_mass64.as<double>());
+  }
+  minv_kernel<<<grid_for(nmodels * c->nglob), kThreads, 0, c->stream>>>(nmodels * c->nglob,
+                                                                        c->d_mass64.as<double>(),
+                                                                        c->d_minv.as<float>());
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  dev_free(dorder);
+  if (e != hipSuccess) return hip_fail(c, e, "upload_model kernels");
+  c->have_model = true;
+  c->lambda_max = 0.0;
+  // receivers depend on nmodels
+  if (c->rec.nrec > 0) {
+    rc = dev_alloc(c, c->rec.seis, sizeof(float) * nmodels * c->rec.nrec * 3 * c->rec.nt_max);
+    if (rc) return rc;
+  }
+  return do_reset(c);
+}
+
+int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
+  if (!c) return SEMX_EINVAL;
+  if (contraction != SEMX_C_F32 && contraction != SEMX_C_BF16 && contraction != SEMX_C_F16)
+    return fail(c, SEMX_EINVAL, "set_mode: unknown contraction");
+  if (assembly != SEMX_ASM_COLORED && assembly != SEMX_ASM_ATOMIC)
+    return fail(c, SEMX_EINVAL, "set_mode: unknown assembly");
+  if (contraction != SEMX_C_F32 && !mfma_supported(c->n))
+    return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8");
+  if (assembly == SEMX_ASM_COLORED && c->have_mesh && c->ncolors == 0)
+    return fail(c, SEMX_EINVAL, "set_mode: mesh has elements with repeated nodes; only atomic assembly is exact");
+  c->contraction = contraction;
+  c->assembly = assembly;
+  return SEMX_OK;
+}
+
+int semx_apply_force(semx_ctx* c, const float* u_dev, float* f_dev) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "apply_force: mesh and model required");
+  if (!u_dev || !f_dev) return fail(c, SEMX_EINVAL, "apply_force: null pointer");
+  const int64_t len = state_len(c);
+  if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "apply_force: u and f overlap");
+  int rc = zero_f32(c, f_dev, len);
+  if (rc) return rc;
+  return force_accumulate(c, u_dev, f_dev);
+}
+
+int semx_set_dt(semx_ctx* c, double dt) {
+  if (!c) return SEMX_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SEMX_EINVAL, "set_dt: dt must be positive");
+  if (c->lambda_max > 0.0 && dt * std::sqrt(c->lambda_max) >= 2.0)
+    return fail(c, SEMX_EUNSTABLE, "set_dt: dt above the stability bound 2/sqrt(lambda_max)");
+  c->dt = dt;
+  c->have_dt = true;
+  return SEMX_OK;
+}
+
+int semx_cfl_dt(semx_ctx* c, double courant, double* dt_out) {
+  if (!c || !dt_out) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "cfl_dt: mesh and model required");
+  if (!(courant > 0.0)) return fail(c, SEMX_EINVAL, "cfl_dt: courant must be positive");
+  *dt_out = courant * c->hmin / c->vp_max;
+  return SEMX_OK;
+}
+
+int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
+  if (!c || !lambda_max) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "max_eigenvalue: mesh and model required");
+  if (iters <= 0) return fail(c, SEMX_EINVAL, "max_eigenvalue: iters must be positive");
+  // power iteration on M^{-1} K for model 0 (nmodels entries are independent)
+  const int saved_models = c->nmodels;
+  const int64_t n3g = 3 * c->nglob;
+  DevBuf x, y;
+  int rc = dev_alloc(c, x, sizeof(float) * n3g * saved_models);
+  if (!rc) rc = dev_alloc(c, y, sizeof(float) * n3g * saved_models);
+  if (rc) { dev_free(x); dev_free(y); return rc; }
+  // deterministic pseudo-random start vector (hash of the index)
+  std::vector<float> h(n3g * saved_models, 0.0f);
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  for (int64_t t = 0; t < n3g; ++t) {
+    s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+    h[t] = (float)((s >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+  }
+  hipError_t e = hipMemcpy(x.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { dev_free(x); dev_free(y); return hip_fail(c, e, "power iteration init"); }
+  double lam = 0.0;
+  for (int k = 0; k < iters && !rc; ++k) {
+    rc = zero_f32(c, y.as<float>(), n3g * saved_models);
+    if (!rc) rc = force_accumulate(c, x.as<float>(), y.as<float>());  // y = -K x
+    if (rc) break;
+    fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
+    // Rayleigh quotient lam = (x^T K x)/(x^T M x) = -(x.y)/(x^T M x)
+    dot_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(n3g, x.as<float>(), y.as<float>(), scratch_d(c));
+    mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(), x.as<float>(),
+                                                                  scratch_d(c) + 1);
+    double hd[2];
+    e = hipMemcpyAsync(hd, scratch_d(c), 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { rc = hip_fail(c, e, "power iteration"); break; }
+    lam = -hd[0] / hd[1];
+    // x <- M^{-1} K x, normalised to unit M-norm scale
+    const double nrm = std::sqrt(hd[1]);
+    neg_minv_kernel<<<grid_for(n3g), kThreads, 0, c->stream>>>(c->nglob, c->d_minv.as<float>(), y.as<float>(),
+                                                               x.as<float>(), (float)(1.0 / (lam * nrm)));
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(c, e, "power iteration update");
+  }
+  dev_free(x);
+  dev_free(y);
+  if (rc) return rc;
+  c->lambda_max = lam;
+  *lambda_max = lam;
+  return SEMX_OK;
+}
+
+int semx_set_sources(semx_ctx* c, int nsrc, const int32_t* elem, const double* xi, const double* dir,
+                     int64_t nstf, const float* stf) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "set_sources: no mesh");
+  if (nsrc < 0) return fail(c, SEMX_EINVAL, "set_sources: nsrc < 0");
+  if (nsrc == 0) {
+    c->src.nsrc = 0;
+    return SEMX_OK;
+  }
+  if (!elem || !xi || !dir || !stf || nstf <= 0) return fail(c, SEMX_EINVAL, "set_sources: bad arguments");
+  const int n = c->n, n3 = c->n3;
+  std::vector<int32_t> nodes((size_t)nsrc * n3);
+  std::vector<float> wdir((size_t)nsrc * n3 * 3);
+  for (int s = 0; s < nsrc; ++s) {
+    if (elem[s] < 0 || elem[s] >= c->nspec) return fail(c, SEMX_EINVAL, "set_sources: element out of range");
+    for (int d = 0; d < 3; ++d)
+      if (!(xi[3 * s + d] >= -1.0 && xi[3 * s + d] <= 1.0))
+        return fail(c, SEMX_EINVAL, "set_sources: reference coordinate outside [-1, 1]");
+    double lx[kMaxN], ly[kMaxN], lz[kMaxN];
+    lagrange_at(n, c->xi, xi[3 * s + 0], lx);
+    lagrange_at(n, c->xi, xi[3 * s + 1], ly);
+    lagrange_at(n, c->xi, xi[3 * s + 2], lz);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const int q = i + n * (j + n * k);
+          nodes[(size_t)s * n3 + q] = c->h_ibool[(size_t)elem[s] * n3 + q];
+          const double wq = lx[i] * ly[j] * lz[k];
+          for (int d = 0; d < 3; ++d) wdir[((size_t)s * n3 + q) * 3 + d] = (float)(wq * dir[3 * s + d]);
+        }
+  }
+  int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
+  if (!rc) rc = dev_alloc(c, c->src.wdir, wdir.size() * sizeof(float));
+  if (!rc) rc = dev_alloc(c, c->src.stf, sizeof(float) * nsrc * nstf);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->src.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.wdir.p, wdir.data(), wdir.size() * sizeof(float), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.stf.p, stf, sizeof(float) * nsrc * nstf, hipMemcpyHostToDevice));
+  c->src.nsrc = nsrc;
+  c->src.nstf = nstf;
+  return SEMX_OK;
+}
+
+int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double* xi, int64_t nt_max) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "set_receivers: no mesh");
+  if (nrec < 0 || nt_max < 0) return fail(c, SEMX_EINVAL, "set_receivers: negative count");
+  if (nrec == 0) {
+    c->rec.nrec = 0;
+    return SEMX_OK;
+  }
+  if (!elem || !xi || nt_max == 0) return fail(c, SEMX_EINVAL, "set_receivers: bad arguments");
+  const int n = c->n, n3 = c->n3;
+  std::vector<int32_t> nodes((size_t)nrec * n3);
+  std::vector<float> wts((size_t)nrec * n3);
+  for (int r = 0; r < nrec; ++r) {
+    if (elem[r] < 0 || elem[r] >= c->nspec) return fail(c, SEMX_EINVAL, "set_receivers: element out of range");
+    for (int d = 0; d < 3; ++d)
+      if (!(xi[3 * r + d] >= -1.0 && xi[3 * r + d] <= 1.0))
+        return fail(c, SEMX_EINVAL, "set_receivers: reference coordinate outside [-1, 1]");
+    double lx[kMaxN], ly[kMaxN], lz[kMaxN];
+    lagrange_at(n, c->xi, xi[3 * r + 0], lx);
+    lagrange_at(n, c->xi, xi[3 * r + 1], ly);
+    lagrange_at(n, c->xi, xi[3 * r + 2], lz);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const int q = i + n * (j + n * k);
+          nodes[(size_t)r * n3 + q] = c->h_ibool[(size_t)elem[r] * n3 + q];
+          wts[(size_t)r * n3 + q] = (float)(lx[i] * ly[j] * lz[k]);
+        }
+  }
+  const int nm = c->nmodels > 0 ? c->nmodels : 1;
+  int rc = dev_alloc(c, c->rec.nodes, nodes.size() * sizeof(int32_t));
+  if (!rc) rc = dev_alloc(c, c->rec.wts, wts.size() * sizeof(float));
+  if (!rc) rc = dev_alloc(c, c->rec.seis, sizeof(float) * nm * nrec * 3 * nt_max);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->rec.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->rec.wts.p, wts.data(), wts.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->rec.nrec = nrec;
+  c->rec.nt_max = nt_max;
+  return zero_f32(c, c->rec.seis.as<float>(), (int64_t)nm * nrec * 3 * nt_max);
+}
+
+int semx_reset(semx_ctx* c) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "reset: mesh and model required");
+  return do_reset(c);
+}
+
+int semx_step(semx_ctx* c, int64_t nsteps) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "step: mesh and model required");
+  if (!c->have_dt) return fail(c, SEMX_ESTATE, "step: dt not set");
+  if (nsteps < 0) return fail(c, SEMX_EINVAL, "step: nsteps < 0");
+  const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  const float dt = (float)c->dt;
+  float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
+  const float* minv = c->d_minv.as<float>();
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (c->pending_correct)
+      newmark_kernel<kCorrect | kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v,
+                                                                                     a, f);
+    else
+      newmark_kernel<kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+    SEMX_HIP(c, hipGetLastError());
+    int rc = force_accumulate(c, u, f);
+    if (!rc) rc = inject_sources(c, c->it + 1, f);
+    if (!rc) rc = record_receivers(c, c->it);
+    if (rc) return rc;
+    c->it++;
+    c->pending_correct = true;
+    if (c->watchdog_every > 0 && c->it % c->watchdog_every == 0) {
+      bool ok = true;
+      rc = check_finite(c, &ok);
+      if (rc) return rc;
+      if (!ok) return fail(c, SEMX_ENUMERIC, "watchdog: non-finite displacement or velocity at step " + std::to_string(c->it));
+      if (c->watchdog_emax > 0.0) {
+        double k = 0, p = 0;
+        rc = energy_model0(c, &k, &p);
+        if (rc) return rc;
+        if (!(k + p <= c->watchdog_emax))
+          return fail(c, SEMX_ENUMERIC, "watchdog: energy above the limit at step " + std::to_string(c->it));
+      }
+    }
+  }
+  return SEMX_OK;
+}
+
+int semx_time_index(semx_ctx* c, int64_t* it) {
+  if (!c || !it) return SEMX_EINVAL;
+  *it = c->it;
+  return SEMX_OK;
+}
+
+int semx_read_seismograms(semx_ctx* c, float* out, int out_on_device) {
+  if (!c || !out) return SEMX_EINVAL;
+  if (c->rec.nrec == 0 || !c->rec.seis.p) return fail(c, SEMX_ESTATE, "read_seismograms: no receivers");
+  SEMX_HIP(c, hipMemcpyAsync(out, c->rec.seis.p, c->rec.seis.bytes,
+                             out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  if (!out_on_device) SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  return SEMX_OK;
+}
+
+int semx_get_state(semx_ctx* c, float* u_dev, float* v_dev, float* a_dev, int64_t* it) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_model) return fail(c, SEMX_ESTATE, "get_state: no model");
+  int rc = finalize_state(c);
+  if (rc) return rc;
+  const size_t bytes = sizeof(float) * state_len(c);
+  if (u_dev) SEMX_HIP(c, hipMemcpyAsync(u_dev, c->d_u.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (v_dev) SEMX_HIP(c, hipMemcpyAsync(v_dev, c->d_v.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (a_dev) SEMX_HIP(c, hipMemcpyAsync(a_dev, c->d_a.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (it) *it = c->it;
+  return SEMX_OK;
+}
+
+int semx_set_state(semx_ctx* c, const float* u_dev, const float* v_dev, const float* a_dev, int64_t it) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_model) return fail(c, SEMX_ESTATE, "set_state: no model");
+  if (!u_dev || !v_dev || !a_dev || it < 0) return fail(c, SEMX_EINVAL, "set_state: null pointer or negative index");
+  const size_t bytes = sizeof(float) * state_len(c);
+  SEMX_HIP(c, hipMemcpyAsync(c->d_u.p, u_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  SEMX_HIP(c, hipMemcpyAsync(c->d_v.p, v_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  SEMX_HIP(c, hipMemcpyAsync(c->d_a.p, a_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  int rc = zero_f32(c, c->d_f.as<float>(), state_len(c));
+  if (rc) return rc;
+  c->it = it;
+  c->pending_correct = false;
+  return SEMX_OK;
+}
+
+int semx_energy(semx_ctx* c, double* kinetic, double* potential) {
+  if (!c || !kinetic || !potential) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "energy: mesh and model required");
+  return energy_model0(c, kinetic, potential);
+}
+
+int semx_set_watchdog(semx_ctx* c, int64_t interval, double max_energy) {
+  if (!c) return SEMX_EINVAL;
+  if (interval < 0) return fail(c, SEMX_EINVAL, "set_watchdog: negative interval");
+  c->watchdog_every = interval;
+  c->watchdog_emax = max_energy;
+  return SEMX_OK;
+}
+
+int semx_set_timing(semx_ctx* c, int enable) {
+  if (!c) return SEMX_EINVAL;
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return SEMX_OK;
+}
+
+int semx_force_timing(semx_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return SEMX_EINVAL;
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.0f;
+    SEMX_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+    tot += ms;
+  }
+  *launches = (int64_t)(c->ev_used / 2);
+  *total_ms = tot;
+  c->ev_used = 0;
+  return SEMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of libsemx (not installed).  Context layout, error
+// helpers and the launchers each kernel translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/semx.h"
+
+namespace semx {
+
+constexpr int kMaxN = 10;   // largest supported NGLL
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin block dispatch
+
+// Device buffer owned by the library.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Element list of one launch: elements of one colour and one geometry kind.
+struct Launch {
+  int32_t* elems = nullptr;  // device pointer into ctx->d_lists
+  int64_t count = 0;
+  bool irregular = false;
+};
+
+struct SourceSet {
+  int nsrc = 0;
+  int64_t nstf = 0;
+  DevBuf nodes;   // int32 [nsrc][n3]
+  DevBuf wdir;    // float [nsrc][n3][3]: l_q(x_s) * dir_c
+  DevBuf stf;     // float [nsrc][nstf]
+};
+
+struct ReceiverSet {
+  int nrec = 0;
+  int64_t nt_max = 0;
+  DevBuf nodes;   // int32 [nrec][n3]
+  DevBuf wts;     // float [nrec][n3]
+  DevBuf seis;    // float [nmodels][nrec][3][nt_max]
+};
+
+}  // namespace semx
+
+struct semx_ctx {
+  int n = 0, n3 = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 256;
+  std::string err;
+
+  int contraction = SEMX_C_F32;
+  int assembly = SEMX_ASM_COLORED;
+
+  // GLL data (library's own, FP64 on host)
+  std::vector<double> xi, w, D;  // D[a*n+b] = l'_b(xi_a)
+  semx::DevBuf d_D;              // float [n][n]
+  semx::DevBuf d_Dh;             // packed half/bfloat D tables for the MFMA paths
+  semx::DevBuf d_xi64, d_w64;    // double [n]
+
+  // mesh
+  bool have_mesh = false;
+  int64_t nspec = 0, nglob = 0, nvert = 0;
+  std::vector<int32_t> h_ibool;     // kept for colouring checks and sources
+  std::vector<int32_t> h_elem_vert;
+  std::vector<double> h_vert;
+  semx::DevBuf d_ibool;     // int32 [nspec][n3]
+  semx::DevBuf d_vert;      // double [nvert][3]
+  semx::DevBuf d_elem_vert; // int32 [nspec][8]
+  semx::DevBuf d_gam_pt;    // float [nspec][9][n3] (allocated if any irregular element)
+  semx::DevBuf d_gam_el;    // float [nspec][9]     (per-element Gamma of regular elements)
+  semx::DevBuf d_wdet;      // double [nspec][n3]   w_i w_j w_k det J
+  std::vector<uint8_t> h_regular;  // per element
+  int64_t nregular = 0, nirregular = 0;
+  double hmin = 0.0;               // min distance between adjacent GLL points
+
+  // colouring
+  int ncolors = 0;
+  std::vector<int32_t> color_ptr, elem_order;
+  semx::DevBuf d_lists;            // int32: lists of all launches, back to back
+  std::vector<semx::Launch> colored_launches;  // per colour: regular then irregular
+  std::vector<semx::Launch> atomic_launches;   // regular list, irregular list
+
+  // model
+  bool have_model = false;
+  int nmodels = 0;
+  semx::DevBuf d_mat;      // float [nmodels][nspec][2][n3]: lambda*W, mu*W
+  semx::DevBuf d_minv;     // float [nmodels][nglob]
+  semx::DevBuf d_mass64;   // double [nmodels][nglob]
+  semx::DevBuf d_wrho;     // float [nmodels][nspec][n3] rho * W (adjoint density kernel)
+  double vp_max = 0.0;
+
+  // time loop state, [nmodels][nglob][3]
+  semx::DevBuf d_u, d_v, d_a, d_f;
+  semx::DevBuf d_work;     // scratch vector of the same shape (energy, power iteration)
+  semx::DevBuf d_scratch;  // double reduction scratch + flags
+  double dt = 0.0;
+  bool have_dt = false;
+  double lambda_max = 0.0;  // power-iteration estimate (0 = unknown)
+  int64_t it = 0;
+  bool pending_correct = false;  // f holds -K u^n + f_src^n, a/v not yet corrected
+  int64_t watchdog_every = 0;
+  double watchdog_emax = 0.0;
+
+  semx::SourceSet src;
+  semx::ReceiverSet rec;
+
+  // optional event timing of force launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;  // 2 per recorded launch, reused
+  size_t ev_used = 0;
+};
+
+namespace semx {
+
+// ---- error helpers -------------------------------------------------------
+int fail(semx_ctx* c, int code, const std::string& msg);
+int hip_fail(semx_ctx* c, hipError_t e, const char* what);
+#define SEMX_HIP(ctx, call)                                   \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return semx::hip_fail(ctx, e_, #call); \
+  } while (0)
+
+int dev_alloc(semx_ctx* c, DevBuf& b, size_t bytes);
+void dev_free(DevBuf& b);
+
+// ---- GLL basis (host, FP64) ---------------------------------------------
+void gll_nodes_weights(int n, std::vector<double>& xi, std::vector<double>& w);
+void deriv_matrix(int n, const std::vector<double>& xi, std::vector<double>& D);
+void lagrange_at(int n, const std::vector<double>& xi, double x, double* l);
+
+// ---- launchers (force.hip, force_mfma.hip) --------------------------------
+struct ForceArgs {
+  const int32_t* ibool;
+  const float* gam_pt;   // [nspec][9][n3]
+  const float* gam_el;   // [nspec][9]
+  const float* mat;      // [nmodels][nspec][2][n3]
+  const float* u;        // [nmodels][nglob][3]
+  float* f;              // [nmodels][nglob][3]
+  const float* D;        // [n][n] FP32
+  const void* Dh;        // packed low-precision D tables (MFMA paths)
+  const int32_t* elems;
+  int64_t count;
+  int64_t nspec, nglob;
+  int nmodels;
+};
+hipError_t launch_force_f32(int n, bool irregular, bool atomic, const ForceArgs& a, int grid_cap,
+                            hipStream_t s);
+hipError_t launch_force_mfma(int n, int prec, bool irregular, bool atomic, const ForceArgs& a,
+                             int grid_cap, hipStream_t s);
+bool mfma_supported(int n);
+
+}  // namespace semx

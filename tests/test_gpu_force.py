@@ -1,0 +1,174 @@
+"""GPU parity of the FP32 force operator f = -K u against the FP64 oracle.
+
+Bar: relative L2 error <= 1e-5 over all degrees of freedom for the FP32
+path (the stated tolerance of the FP32 force apply), on random and smooth
+displacements, for every NGLL, both assembly modes and both geometry paths.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import gpu_force, make_solver, oracle_geometry, rel_l2, smooth_field
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+def _hetero_model(mesh, seed):
+    lam, mu, rho = W.layered_model(mesh, grf_amp=0.05, grf_seed=seed, grf_corr_elems=1.5)
+    return lam, mu, rho
+
+
+CASES = [
+    # (name, ne, n, jitter)
+    ("regular_cube_n5", 4, 5, 0.0),
+    ("jittered_ragged_n5", (7, 5, 3), 5, 0.1),
+    ("jittered_n4", (5, 4, 3), 4, 0.1),
+    ("jittered_n3", (4, 3, 5), 3, 0.1),
+    ("jittered_n6", (3, 4, 3), 6, 0.1),
+    ("jittered_n7", (3, 3, 2), 7, 0.1),
+    ("jittered_n8", (2, 3, 2), 8, 0.1),
+    ("jittered_n9", (2, 2, 2), 9, 0.1),
+    ("regular_n9", (3, 2, 2), 9, 0.0),
+    ("jittered_n10", (2, 2, 2), 10, 0.1),
+    ("regular_n2", (5, 3, 4), 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("assembly", ["colored", "atomic"])
+@pytest.mark.parametrize("name,ne,n,jitter", CASES, ids=[c[0] for c in CASES])
+def test_force_parity(orc, name, ne, n, jitter, assembly):
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh(ne, n, 4000.0, jitter=jitter, seed=17)
+    lam, mu, rho = _hetero_model(mesh, 5)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    s = make_solver(n)
+    info = s.upload_mesh(mesh)
+    if jitter == 0.0:
+        assert info["nirregular"] == 0
+    else:
+        assert info["nregular"] == 0
+    s.upload_model(lam, mu, rho)
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED if assembly == "colored" else P.SEMX_ASM_ATOMIC)
+    rng = np.random.default_rng(3)
+    for u in (rng.uniform(-1, 1, (mesh.nglob, 3)), smooth_field(orc, mesh)):
+        u32 = u.astype(np.float32).astype(np.float64)   # both sides see the same FP32 input
+        f_ref = orc.force(n, mesh.ibool, gam, jac, lam, mu, u32, mesh.nglob)
+        f_gpu = gpu_force(s, u32)
+        err = rel_l2(f_gpu, f_ref)
+        print(f"{name} {assembly} n={n}: rel L2 = {err:.3e}")
+        assert err <= TOL_F32, err
+    s.close()
+
+
+def test_force_mixed_regular_irregular(orc):
+    """A mesh with both element kinds runs the two specialised paths."""
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((4, 3, 3), 5, 4000.0)
+    # move one interior vertex: the 8 elements around it become irregular
+    mesh.vert[1 + 5 * (1 + 4 * 1)] += np.array([60.0, -40.0, 30.0])
+    lam, mu, rho = _hetero_model(mesh, 9)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    s = make_solver(5)
+    info = s.upload_mesh(mesh)
+    assert info["nirregular"] == 8 and info["nregular"] == mesh.nspec - 8
+    s.upload_model(lam, mu, rho)
+    u = np.random.default_rng(4).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+    f_ref = orc.force(5, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        s.set_mode(P.SEMX_C_F32, asm)
+        assert rel_l2(gpu_force(s, u), f_ref) <= TOL_F32
+    s.close()
+
+
+def test_rigid_modes_and_symmetry_on_gpu(orc):
+    mesh = W.box_mesh((4, 4, 3), 5, 4000.0, jitter=0.1, seed=3)
+    lam, mu, rho = _hetero_model(mesh, 2)
+    gam, jac, xyz = oracle_geometry(orc, mesh)
+    s = make_solver(5)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    rng = np.random.default_rng(5)
+    ur = rng.uniform(-1, 1, (mesh.nglob, 3))
+    fr = gpu_force(s, ur)
+    kscale = np.linalg.norm(fr) / np.linalg.norm(ur)
+    f = gpu_force(s, np.ones((mesh.nglob, 3)))
+    # FP32 rounding of the contraction only: D 1 = 0 is not exact in FP32
+    assert np.linalg.norm(f) <= 1e-5 * kscale * np.sqrt(3 * mesh.nglob)
+    u = rng.uniform(-1, 1, (mesh.nglob, 3)); v = rng.uniform(-1, 1, (mesh.nglob, 3))
+    fu, fv = gpu_force(s, u), gpu_force(s, v)
+    a, b = np.sum(u * fv), np.sum(v * fu)
+    assert abs(a - b) <= 1e-5 * np.linalg.norm(fu) * np.linalg.norm(v)
+    s.close()
+
+
+def test_colored_is_deterministic_atomic_within_tolerance():
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((6, 5, 4), 5, 4000.0, jitter=0.1, seed=8)
+    lam, mu, rho = _hetero_model(mesh, 1)
+    s = make_solver(5)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    u = torch.rand((mesh.nglob, 3), device=s.device) - 0.5
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED)
+    f1 = s.apply_force(u).clone(); f2 = s.apply_force(u).clone()
+    assert torch.equal(f1, f2)
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_ATOMIC)
+    fa = s.apply_force(u)
+    torch.cuda.synchronize()
+    assert (torch.linalg.norm(fa - f1) / torch.linalg.norm(f1)).item() < 1e-6
+    s.close()
+
+
+def test_empty_and_error_paths():
+    import paper_2606_12850_amd as P
+    s = make_solver(5)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_apply_force(s.ctx, None, None)
+    assert ei.value.code == P.SEMX_ESTATE
+    mesh = W.box_mesh(2, 5, 1000.0)
+    bad = mesh.ibool.copy(); bad[0, 0] = mesh.nglob
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_upload_mesh(s.ctx, bad, mesh.vert, mesh.elem_vert, mesh.nglob)
+    assert ei.value.code == P.SEMX_EINVAL
+    ev = mesh.elem_vert.copy(); ev[:, [0, 1]] = ev[:, [1, 0]]
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_upload_mesh(s.ctx, mesh.ibool, mesh.vert, ev, mesh.nglob)
+    assert ei.value.code == P.SEMX_EGEOM
+    s.upload_mesh(mesh)
+    lam, mu, rho = W.homogeneous_model(mesh)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_upload_model(s.ctx, lam, -mu, rho)
+    assert ei.value.code == P.SEMX_EINVAL
+    s.upload_model(lam, mu, rho)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_step(s.ctx, 1)  # no dt yet
+    assert ei.value.code == P.SEMX_ESTATE
+    with pytest.raises(P.SemxError):
+        P.semx_set_dt(s.ctx, -1.0)
+    # an element repeating a node (periodic, one element wide) cannot be coloured
+    pm = W.box_mesh((1, 2, 2), 3, 1000.0, periodic=True)
+    s3 = make_solver(3)
+    s3.upload_mesh(pm)
+    with pytest.raises(P.SemxError):
+        P.semx_set_mode(s3.ctx, P.SEMX_C_F32, P.SEMX_ASM_COLORED)
+    s3.close()
+    s.close()
+
+
+def test_periodic_atomic_matches_oracle(orc):
+    """Wrap-around numbering (a periodic box) through the atomic path."""
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((1, 3, 2), 4, 1200.0, periodic=True)
+    lam, mu, rho = W.homogeneous_model(mesh)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    s = make_solver(4)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    P.semx_set_mode(s.ctx, P.SEMX_C_F32, P.SEMX_ASM_ATOMIC)
+    u = np.random.default_rng(0).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+    f_ref = orc.force(4, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+    assert rel_l2(gpu_force(s, u), f_ref) <= TOL_F32
+    s.close()

@@ -1,0 +1,252 @@
+"""GPU parity of the explicit Newmark time loop (sources, receivers,
+checkpoints, energy, watchdog, batched models) against the FP64 oracle.
+
+Bar: receiver seismograms within 1e-4 relative L2 of the oracle after up to
+1000 FP32 steps."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import make_solver, oracle_geometry, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_SEIS = 1e-4
+
+
+def cfl_dt(orc, mesh, lam, mu, rho, courant=0.4):
+    """dt = courant * (min adjacent GLL distance) / (max P speed), from oracle geometry."""
+    n = mesh.n
+    _, _, xyz = oracle_geometry(orc, mesh)
+    x = xyz.reshape(mesh.nspec, n, n, n, 3)
+    d = min(np.linalg.norm(np.diff(x, axis=ax), axis=-1).min() for ax in (1, 2, 3))
+    vp = np.sqrt((lam + 2 * mu) / rho).max()
+    return courant * d / vp
+
+
+def run_oracle(orc, wl, dt=None):
+    m = wl.mesh
+    gam, jac, _ = oracle_geometry(orc, m)
+    return orc.forward(m.n, m.ibool, gam, jac, wl.lam, wl.mu, wl.rho, m.nglob, wl.dt if dt is None else dt,
+                       wl.nt, wl.src_elem, wl.src_xi, wl.src_dir, wl.stf, wl.rec_elem, wl.rec_xi)["seis"]
+
+
+def run_gpu(wl, assembly=None):
+    import paper_2606_12850_amd as P
+    s = make_solver(wl.mesh.n)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    if assembly is not None:
+        s.set_mode(P.SEMX_C_F32, assembly)
+    s.setup_run(wl)
+    s.step(wl.nt)
+    out = s.seismograms()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("nt", [200, 1000])
+def test_cube_seismograms(orc, nt):
+    """Homogeneous 4 km cube, 4^3 elements, NGLL 5, Ricker 10 Hz, Courant 0.4."""
+    import paper_2606_12850_amd as P
+    wl = W.cube_homogeneous(ne=4, n=5, nt=nt)
+    ref = run_oracle(orc, wl)
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        got = run_gpu(wl, asm)
+        err = rel_l2(got, ref)
+        print(f"cube nt={nt} asm={asm}: seismogram rel L2 = {err:.3e}")
+        assert err <= TOL_SEIS
+
+
+@pytest.mark.parametrize("ne,nt", [(6, 1000), (8, 300)])
+def test_layered_jittered_seismograms(orc, ne, nt):
+    wl = W.layered_jittered(ne=ne, n=5, nt=nt, dt=1.0, jitter=0.1, nrec=8)
+    wl.dt = cfl_dt(orc, wl.mesh, wl.lam, wl.mu, wl.rho)
+    wl.stf = W.ricker(10.0, 0.12, wl.dt, nt + 1)[None, :]
+    ref = run_oracle(orc, wl)
+    got = run_gpu(wl)
+    err = rel_l2(got, ref)
+    print(f"layered jittered {ne}^3 nt={nt}: rel L2 = {err:.3e}")
+    assert err <= TOL_SEIS
+
+
+def test_cfl_dt_matches_oracle_geometry(orc):
+    import paper_2606_12850_amd as P
+    wl = W.layered_jittered(ne=5, n=5, nt=10, dt=1.0, jitter=0.1)
+    s = make_solver(5)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    dt = P.semx_cfl_dt(s.ctx, 0.4)
+    assert abs(dt / cfl_dt(orc, wl.mesh, wl.lam, wl.mu, wl.rho) - 1) < 1e-12
+    # the cube of the reference workload: 0.4 * 172.673 m / 3000 m/s
+    wl1 = W.cube_homogeneous()
+    s1 = make_solver(5)
+    s1.upload_mesh(wl1.mesh)
+    s1.upload_model(wl1.lam, wl1.mu, wl1.rho)
+    assert abs(P.semx_cfl_dt(s1.ctx, 0.4) - 0.0230231) < 1e-6
+    # stability: dt * sqrt(lambda_max) < 2 at Courant 0.4
+    lmax = P.semx_max_eigenvalue(s1.ctx, 300)
+    assert 0.0230231 * np.sqrt(lmax) < 2.0
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_set_dt(s1.ctx, 2.05 / np.sqrt(lmax))
+    assert ei.value.code == P.SEMX_EUNSTABLE
+    s.close(); s1.close()
+
+
+def test_max_eigenvalue_vs_dense(orc):
+    import paper_2606_12850_amd as P
+    from tests import indep
+    mesh = W.box_mesh((2, 2, 1), 3, (2000.0, 2000.0, 1000.0), jitter=0.0)
+    lam, mu, rho = W.homogeneous_model(mesh)
+    K = indep.dense_stiffness(3, mesh.ibool, mesh.elem_vert, mesh.vert, lam, mu, mesh.nglob)
+    M = np.repeat(indep.mass_numpy(3, mesh.ibool, mesh.elem_vert, mesh.vert, rho, mesh.nglob), 3)
+    ev = np.linalg.eigvalsh(K / np.sqrt(M)[:, None] / np.sqrt(M)[None, :])
+    s = make_solver(3)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    lm = P.semx_max_eigenvalue(s.ctx, 2000)
+    assert lm <= ev[-1] * (1 + 1e-5)
+    assert lm >= 0.98 * ev[-1]
+    s.close()
+
+
+def test_checkpoint_restart_bitwise():
+    import torch
+    import paper_2606_12850_amd as P
+    wl = W.cube_homogeneous(ne=4, n=5, nt=120)
+    s = make_solver(5)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    s.setup_run(wl)
+    s.step(60)
+    u = s.empty_field(); v = s.empty_field(); a = s.empty_field()
+    it = P.semx_get_state(s.ctx, u, v, a)
+    assert it == 60
+    s.step(60)
+    full = s.seismograms().copy()
+    # restart from the checkpoint (fresh context)
+    s2 = make_solver(5)
+    s2.upload_mesh(wl.mesh)
+    s2.upload_model(wl.lam, wl.mu, wl.rho)
+    s2.setup_run(wl)
+    P.semx_set_state(s2.ctx, u, v, a, it)
+    s2.step(60)
+    torch.cuda.synchronize()
+    rest = s2.seismograms()
+    np.testing.assert_array_equal(rest[:, :, 60:], full[:, :, 60:])
+    s.close(); s2.close()
+
+
+def test_energy_matches_oracle_evaluation(orc):
+    import torch
+    import paper_2606_12850_amd as P
+    wl = W.layered_jittered(ne=4, n=5, nt=80, dt=1.0, jitter=0.1)
+    wl.dt = cfl_dt(orc, wl.mesh, wl.lam, wl.mu, wl.rho)
+    wl.stf = W.ricker(10.0, 0.12, wl.dt, wl.nt + 1)[None, :] * 1e9
+    s = make_solver(5)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    s.setup_run(wl)
+    s.step(wl.nt)
+    kin, pot = P.semx_energy(s.ctx)
+    u = s.empty_field(); v = s.empty_field()
+    P.semx_get_state(s.ctx, u, v, None)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().astype(np.float64); v = v.cpu().numpy().astype(np.float64)
+    m = wl.mesh
+    gam, jac, _ = oracle_geometry(orc, m)
+    M = orc.mass(5, m.ibool, jac, wl.rho, m.nglob)
+    kin_ref = 0.5 * np.sum(M[:, None] * v * v)
+    pot_ref = -0.5 * np.sum(u * orc.force(5, m.ibool, gam, jac, wl.lam, wl.mu, u, m.nglob))
+    assert kin > 0 and pot > 0
+    assert abs(kin / kin_ref - 1) < 1e-5
+    assert abs(pot / pot_ref - 1) < 1e-4
+    s.close()
+
+
+def test_energy_conserved_after_source(orc):
+    """Once the wavelet has passed, the FP32 run conserves the scheme's
+    discrete energy E^{n+1/2} = 1/2 |u^{n+1}-u^n|_M^2/dt^2 + 1/2 (u^{n+1})^T K u^n
+    (exact for central differences) up to FP32 rounding; the instantaneous
+    energy 1/2 v^T M v + 1/2 u^T K u only up to its O((omega dt)^2) wobble."""
+    import torch
+    import paper_2606_12850_amd as P
+    wl = W.cube_homogeneous(ne=4, n=5, nt=400)
+    m = wl.mesh
+    gam, jac, _ = oracle_geometry(orc, m)
+    M = orc.mass(5, m.ibool, jac, wl.rho, m.nglob)
+    s = make_solver(5)
+    s.upload_mesh(m)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    s.setup_run(wl)
+    s.step(40)  # wavelet over at t = 0.24 s < 40 dt
+    E, Einst = [], []
+    u0 = s.empty_field(); u1 = s.empty_field()
+    for _ in range(8):
+        s.step(39)
+        P.semx_get_state(s.ctx, u0, None, None)
+        s.step(1)
+        P.semx_get_state(s.ctx, u1, None, None)
+        k, p = P.semx_energy(s.ctx)
+        Einst.append(k + p)
+        torch.cuda.synchronize()
+        a = u0.cpu().numpy().astype(np.float64); b = u1.cpu().numpy().astype(np.float64)
+        kin = 0.5 * np.sum(M[:, None] * (b - a) ** 2) / wl.dt ** 2
+        pot = -0.5 * np.sum(b * orc.force(5, m.ibool, gam, jac, wl.lam, wl.mu, a, m.nglob))
+        E.append(kin + pot)
+    E = np.array(E); Einst = np.array(Einst)
+    assert np.all(E > 0) and np.all(Einst > 0)
+    assert (E.max() - E.min()) / E.mean() < 1e-4
+    assert (Einst.max() - Einst.min()) / Einst.mean() < 0.2
+    s.close()
+
+
+def test_watchdog_trips_on_nan():
+    import torch
+    import paper_2606_12850_amd as P
+    wl = W.cube_homogeneous(ne=3, n=4, nt=50)
+    s = make_solver(4)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(wl.lam, wl.mu, wl.rho)
+    s.setup_run(wl)
+    s.step(10)
+    u = s.empty_field(); v = s.empty_field(); a = s.empty_field()
+    it = P.semx_get_state(s.ctx, u, v, a)
+    u[5, 1] = float("nan")
+    P.semx_set_state(s.ctx, u, v, a, it)
+    P.semx_set_watchdog(s.ctx, 5)
+    with pytest.raises(P.SemxError) as ei:
+        s.step(20)
+    assert ei.value.code == P.SEMX_ENUMERIC
+    # energy limit: a tiny ceiling trips at once
+    P.semx_reset(s.ctx)
+    P.semx_set_watchdog(s.ctx, 2, 1e-30)
+    with pytest.raises(P.SemxError) as ei:
+        s.step(20)
+    assert ei.value.code == P.SEMX_ENUMERIC
+    s.close()
+
+
+def test_batched_models_equal_single_runs(orc):
+    """nmodels > 1: each model of the batch reproduces its single-model run."""
+    import paper_2606_12850_amd as P
+    wl = W.cube_homogeneous(ne=4, n=5, nt=100)
+    rng = np.random.default_rng(0)
+    lams, mus, rhos = [], [], []
+    for b in range(3):
+        f = 1.0 + 0.1 * rng.uniform(-1, 1)
+        lams.append(wl.lam * f); mus.append(wl.mu * (2 - f)); rhos.append(wl.rho)
+    s = make_solver(5)
+    s.upload_mesh(wl.mesh)
+    s.upload_model(np.stack(lams), np.stack(mus), np.stack(rhos))
+    s.setup_run(wl)
+    s.step(wl.nt)
+    batch = s.seismograms()
+    s.close()
+    for b in range(3):
+        wb = W.Workload(wl.name, wl.mesh, lams[b], mus[b], rhos[b], wl.dt, wl.nt, wl.src_elem, wl.src_xi,
+                        wl.src_dir, wl.stf, wl.rec_elem, wl.rec_xi)
+        single = run_gpu(wb)
+        np.testing.assert_array_equal(batch[b], single)
+        if b == 0:
+            assert rel_l2(batch[b], run_oracle(orc, wb)) <= TOL_SEIS

@@ -146,7 +146,7 @@ def gaussian_random_field(shape, corr_len: float, seed: int) -> np.ndarray:
         K2 = K2 + (2 * np.pi * kk.reshape(sh)) ** 2
     # Fourier transform of exp(-r^2/l^2) ~ exp(-k^2 l^2 / 4); amplitude filter is its sqrt
     F *= np.exp(-K2 * corr_len ** 2 / 8.0)
-    out = np.fft.irfftn(F, s=shape)
+    out = np.fft.irfftn(F, s=shape, axes=list(range(len(shape))))
     return out / np.max(np.abs(out))
 
 
