@@ -114,6 +114,19 @@ int semx_upload_model(semx_ctx *ctx, int nmodels, const double *lambda, const do
 /* Select the contraction arithmetic and the assembly (constants above). */
 int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 
+/* Geometry path of irregular (non-affine) elements (Sec. IV-D keeps the
+ * regular and irregular cases in separate code paths):
+ *   SEMX_GEOM_STORED     Gamma = J^{-1} at every GLL point precomputed in FP64
+ *                        and streamed from memory (9 floats per point);
+ *   SEMX_GEOM_TRILINEAR  J rebuilt at every point inside the kernel from the
+ *                        element's trilinear-map coefficients (computed in
+ *                        FP64, stored FP32): the same operator with no
+ *                        per-point geometry traffic.
+ * Regular (affine) elements always use one Gamma per element.  Default STORED. */
+#define SEMX_GEOM_STORED 0
+#define SEMX_GEOM_TRILINEAR 1
+int semx_set_geometry(semx_ctx *ctx, int mode);
+
 /* f = -K u for every model: u_dev, f_dev device FP32 [nmodels][nglob][3].
  * f_dev is overwritten (not accumulated).  u_dev and f_dev must not overlap. */
 int semx_apply_force(semx_ctx *ctx, const float *u_dev, float *f_dev);

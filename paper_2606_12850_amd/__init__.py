@@ -33,6 +33,8 @@ SEMX_C_BF16 = 1
 SEMX_C_F16 = 2
 SEMX_ASM_COLORED = 0
 SEMX_ASM_ATOMIC = 1
+SEMX_GEOM_STORED = 0
+SEMX_GEOM_TRILINEAR = 1
 
 _ERRNAMES = {-1: "EINVAL", -2: "ESTATE", -3: "EGEOM", -4: "EUNSTABLE", -5: "EHIP", -6: "ENOMEM",
              -7: "ENUMERIC"}
@@ -69,6 +71,7 @@ _SIGS = {
     "semx_set_state": [_vp, _vp, _vp, _vp, _i64],
     "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
     "semx_set_watchdog": [_vp, _i64, _f64],
+    "semx_set_geometry": [_vp, _i32],
     "semx_set_timing": [_vp, _i32],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
@@ -254,6 +257,10 @@ def semx_energy(ctx):
 
 def semx_set_watchdog(ctx, interval: int, max_energy: float = 0.0):
     return _check(ctx, lib().semx_set_watchdog(ctx, int(interval), float(max_energy)))
+
+
+def semx_set_geometry(ctx, mode: int):
+    return _check(ctx, lib().semx_set_geometry(ctx, int(mode)))
 
 
 def semx_set_timing(ctx, enable: bool):

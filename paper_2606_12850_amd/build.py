@@ -13,14 +13,17 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libsemx.so")
+# SEMX_BUILD_DIR / SEMX_LIB_OUT / SEMX_EXTRA_FLAGS redirect a build (e.g. to
+# compare compile-time options) without touching the in-tree library.
+BUILD = os.environ.get("SEMX_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("SEMX_LIB_OUT", os.path.join(HERE, "libsemx.so"))
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+COMMON += os.environ.get("SEMX_EXTRA_FLAGS", "").split()
 
 
 def sources():

@@ -60,18 +60,20 @@ inline unsigned grid_for(int64_t n, int cap = 1 << 16) {
 // ---------------------------------------------------------------------------
 // Geometry (FP64): J = dx/dxi of the trilinear map at every GLL point,
 // det J, Gamma = J^{-1} (rows: gradients of the reference coordinates), and
-// W = w_i w_j w_k det J.  Gamma goes out in FP32 when requested.
+// W = w_i w_j w_k det J.  Gamma goes out in FP32 when requested.  Outputs
+// are stored at the element's launch position (order[pos] = element).
 // ---------------------------------------------------------------------------
 __global__ void geom_kernel(int n, int64_t nspec, const double* __restrict__ vert,
-                            const int32_t* __restrict__ ev, const double* __restrict__ xi,
-                            const double* __restrict__ w, float* __restrict__ gam_pt,
-                            double* __restrict__ wdet, int* __restrict__ bad) {
+                            const int32_t* __restrict__ ev, const int32_t* __restrict__ order,
+                            const double* __restrict__ xi, const double* __restrict__ w,
+                            float* __restrict__ gam_pt, double* __restrict__ wdet, int* __restrict__ bad) {
   const int n3 = n * n * n;
   const int64_t total = nspec * n3;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = t / n3;
-    const int q = (int)(t - e * n3);
+    const int64_t pos = t / n3;
+    const int q = (int)(t - pos * n3);
+    const int64_t e = order[pos];
     const int i = q % n, j = (q / n) % n, k = q / (n * n);
     const double r0 = xi[i], r1 = xi[j], r2 = xi[k];
     double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -104,7 +106,7 @@ __global__ void geom_kernel(int n, int64_t nspec, const double* __restrict__ ver
     const double inv = 1.0 / det;
     wdet[t] = w[i] * w[j] * w[k] * det;
     if (gam_pt) {
-      float* gp = gam_pt + e * 9 * n3 + q;
+      float* gp = gam_pt + pos * 9 * n3 + q;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -155,28 +157,33 @@ __global__ void spacing_kernel(int n, int64_t nspec, const double* __restrict__ 
   if (best < 1e300) atomicMin(out, (unsigned long long)__double_as_longlong(best));
 }
 
-// lambda W, mu W (FP32) and rho W per element-local point for every model.
-__global__ void material_kernel(int n3, int64_t nspec, int nmodels, const double* __restrict__ lam,
-                                const double* __restrict__ mu, const double* __restrict__ rho,
-                                const double* __restrict__ wdet, float* __restrict__ mat,
-                                float* __restrict__ wrho) {
+// lambda W, mu W (FP32) and rho W per element-local point for every model,
+// in launch order: position pos holds element order[pos] of the user arrays.
+__global__ void material_kernel(int n3, int64_t nspec, int nmodels, const int32_t* __restrict__ order,
+                                const double* __restrict__ lam, const double* __restrict__ mu,
+                                const double* __restrict__ rho, const double* __restrict__ wdet,
+                                float* __restrict__ mat, float* __restrict__ wrho) {
   const int64_t total = (int64_t)nmodels * nspec * n3;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t me = t / n3;  // model * nspec + e
-    const int q = (int)(t - me * n3);
-    const int64_t e = me % nspec;
-    const double W = wdet[e * n3 + q];
-    mat[me * 2 * n3 + q] = (float)(lam[t] * W);
-    mat[me * 2 * n3 + n3 + q] = (float)(mu[t] * W);
-    wrho[t] = (float)(rho[t] * W);
+    const int64_t mp = t / n3;  // model * nspec + pos
+    const int q = (int)(t - mp * n3);
+    const int64_t model = mp / nspec;
+    const int64_t pos = mp - model * nspec;
+    const int64_t src = (model * nspec + order[pos]) * n3 + q;
+    const double W = wdet[pos * n3 + q];
+    mat[mp * 2 * n3 + q] = (float)(lam[src] * W);
+    mat[mp * 2 * n3 + n3 + q] = (float)(mu[src] * W);
+    wrho[t] = (float)(rho[src] * W);
   }
 }
 
-// Lumped mass, one colour at a time (no two elements of a colour share a
-// node, so plain read-modify-write in FP64 is race free and deterministic).
-__global__ void mass_color_kernel(int n3, int64_t nspec, int64_t nglob, int nmodels,
-                                  const int32_t* __restrict__ elems, int64_t count,
+// Lumped mass over the launch positions [pbeg, pbeg + count) of one colour
+// (no two elements of a colour share a node, so plain read-modify-write in
+// FP64 is race free and deterministic).  ibool and wdet are in launch order,
+// rho in user order.
+__global__ void mass_color_kernel(int n3, int64_t nspec, int64_t nglob, int nmodels, int64_t pbeg,
+                                  int64_t count, const int32_t* __restrict__ order,
                                   const int32_t* __restrict__ ibool, const double* __restrict__ rho,
                                   const double* __restrict__ wdet, double* __restrict__ mass) {
   const int64_t total = (int64_t)nmodels * count * n3;
@@ -185,18 +192,24 @@ __global__ void mass_color_kernel(int n3, int64_t nspec, int64_t nglob, int nmod
     const int64_t mp = t / n3;
     const int q = (int)(t - mp * n3);
     const int model = (int)(mp / count);
-    const int64_t e = elems[mp - (int64_t)model * count];
-    const int64_t pt = e * n3 + q;
-    mass[(int64_t)model * nglob + ibool[pt]] += rho[(int64_t)model * nspec * n3 + pt] * wdet[pt];
+    const int64_t pos = pbeg + (mp - (int64_t)model * count);
+    const int64_t pt = pos * n3 + q;
+    mass[(int64_t)model * nglob + ibool[pt]] +=
+        rho[((int64_t)model * nspec + order[pos]) * n3 + q] * wdet[pt];
   }
 }
 
+// Same sum by one thread in position order (meshes without a valid colouring).
 __global__ void mass_serial_kernel(int n3, int64_t nspec, int64_t nglob, int nmodels,
-                                   const int32_t* __restrict__ ibool, const double* __restrict__ rho,
-                                   const double* __restrict__ wdet, double* __restrict__ mass) {
+                                   const int32_t* __restrict__ order, const int32_t* __restrict__ ibool,
+                                   const double* __restrict__ rho, const double* __restrict__ wdet,
+                                   double* __restrict__ mass) {
   for (int model = 0; model < nmodels; ++model)
-    for (int64_t pt = 0; pt < nspec * n3; ++pt)
-      mass[(int64_t)model * nglob + ibool[pt]] += rho[(int64_t)model * nspec * n3 + pt] * wdet[pt];
+    for (int64_t pt = 0; pt < nspec * n3; ++pt) {
+      const int64_t pos = pt / n3;
+      mass[(int64_t)model * nglob + ibool[pt]] +=
+          rho[((int64_t)model * nspec + order[pos]) * n3 + (pt - pos * n3)] * wdet[pt];
+    }
 }
 
 __global__ void minv_kernel(int64_t n, const double* __restrict__ mass, float* __restrict__ minv) {
@@ -369,10 +382,10 @@ int set_device(semx_ctx* c) {
   return SEMX_OK;
 }
 
-int grid_cap_force(semx_ctx* c) {
-  // enough resident blocks to fill every CU several times over
-  return c->num_cu * 8;
-}
+// scratch layout: [0..7] doubles for reductions, then int flags
+double* scratch_d(semx_ctx* c) { return c->d_scratch.as<double>(); }
+int* scratch_i(semx_ctx* c) { return reinterpret_cast<int*>(c->d_scratch.as<double>() + 8); }
+
 
 // Greedy first-fit colouring in element order (Sec. IV-C: element adjacency
 // from the global-to-local map, colour by colour execution).  Two elements
@@ -435,37 +448,91 @@ bool coloring_valid(int n3, int64_t nspec, int64_t nglob, const int32_t* ibool, 
   return true;
 }
 
-int build_launch_lists(semx_ctx* c) {
-  // per colour: regular list then irregular list; then the two atomic lists
-  std::vector<int32_t> lists;
-  lists.reserve(2 * c->nspec);
-  struct Range { int64_t off, cnt; bool irr; };
-  std::vector<Range> col, atom;
-  for (int k = 0; k < c->ncolors; ++k) {
-    for (int irr = 0; irr < 2; ++irr) {
-      Range r{(int64_t)lists.size(), 0, irr == 1};
-      for (int32_t t = c->color_ptr[k]; t < c->color_ptr[k + 1]; ++t) {
-        const int32_t e = c->elem_order[t];
-        if ((c->h_regular[e] == 0) == (irr == 1)) lists.push_back(e);
+// Launch-ordered layout: every per-element array on the device is stored by
+// launch position, positions sorted by (geometry kind, colour, element), so
+// that each launch (one colour of one kind, or one kind for atomic assembly)
+// streams one contiguous range with no element-list indirection.  Then the
+// FP64 geometry kernel fills Gamma and W det J in that order.
+int build_layout(semx_ctx* c) {
+  const int n3 = c->n3;
+  const int64_t nspec = c->nspec;
+  std::vector<int32_t> order;
+  order.reserve(nspec);
+  struct Range { int64_t beg, cnt; bool irr; int color; };
+  std::vector<Range> col;
+  const int nc = c->ncolors > 0 ? c->ncolors : 1;
+  std::vector<int64_t> kind_beg(3, 0);
+  for (int irr = 0; irr < 2; ++irr) {
+    kind_beg[irr] = (int64_t)order.size();
+    for (int k = 0; k < nc; ++k) {
+      Range r{(int64_t)order.size(), 0, irr == 1, k};
+      if (c->ncolors > 0) {
+        for (int32_t t = c->color_ptr[k]; t < c->color_ptr[k + 1]; ++t) {
+          const int32_t e = c->elem_order[t];
+          if ((c->h_regular[e] == 0) == (irr == 1)) order.push_back(e);
+        }
+      } else {
+        for (int64_t e = 0; e < nspec; ++e)
+          if ((c->h_regular[e] == 0) == (irr == 1)) order.push_back((int32_t)e);
       }
-      r.cnt = (int64_t)lists.size() - r.off;
+      r.cnt = (int64_t)order.size() - r.beg;
       if (r.cnt) col.push_back(r);
     }
   }
-  for (int irr = 0; irr < 2; ++irr) {
-    Range r{(int64_t)lists.size(), 0, irr == 1};
-    for (int64_t e = 0; e < c->nspec; ++e)
-      if ((c->h_regular[e] == 0) == (irr == 1)) lists.push_back((int32_t)e);
-    r.cnt = (int64_t)lists.size() - r.off;
-    if (r.cnt) atom.push_back(r);
-  }
-  int rc = dev_alloc(c, c->d_lists, lists.size() * sizeof(int32_t));
-  if (rc) return rc;
-  SEMX_HIP(c, hipMemcpy(c->d_lists.p, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  kind_beg[2] = (int64_t)order.size();
+  c->h_order = order;
   c->colored_launches.clear();
   c->atomic_launches.clear();
-  for (auto& r : col) c->colored_launches.push_back({c->d_lists.as<int32_t>() + r.off, r.cnt, r.irr});
-  for (auto& r : atom) c->atomic_launches.push_back({c->d_lists.as<int32_t>() + r.off, r.cnt, r.irr});
+  // coloured: colour-major execution order, regular before irregular in a colour
+  for (int k = 0; k < nc; ++k)
+    for (const auto& r : col)
+      if (r.color == k) c->colored_launches.push_back({r.beg, r.cnt, r.irr});
+  for (int irr = 0; irr < 2; ++irr)
+    if (kind_beg[irr + 1] > kind_beg[irr])
+      c->atomic_launches.push_back({kind_beg[irr], kind_beg[irr + 1] - kind_beg[irr], irr == 1});
+
+  std::vector<int32_t> ib((size_t)nspec * n3);
+  std::vector<float> gel((size_t)nspec * 9);
+  // trilinear map x_a = sum_m c_m[a] b_m(r) with monomials
+  // b = (1, rx, ry, rz, rx ry, rx rz, ry rz, rx ry rz); c_m[a] = 1/8 sum_v x_v[a] b_m(s_v)
+  std::vector<float> tri((size_t)nspec * 24, 0.0f);
+  for (int64_t pos = 0; pos < nspec; ++pos) {
+    const int64_t e = order[pos];
+    std::memcpy(&ib[pos * n3], &c->h_ibool[e * n3], sizeof(int32_t) * n3);
+    std::memcpy(&gel[pos * 9], &c->h_gam_el[e * 9], sizeof(float) * 9);
+    double cm[3][8] = {{0}};
+    for (int v = 0; v < 8; ++v) {
+      const double sx = (v & 1) ? 1.0 : -1.0, sy = (v & 2) ? 1.0 : -1.0, sz = (v & 4) ? 1.0 : -1.0;
+      const double b[8] = {1.0, sx, sy, sz, sx * sy, sx * sz, sy * sz, sx * sy * sz};
+      const double* x = &c->h_vert[3 * (int64_t)c->h_elem_vert[8 * e + v]];
+      for (int a = 0; a < 3; ++a)
+        for (int m = 0; m < 8; ++m) cm[a][m] += 0.125 * x[a] * b[m];
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int m = 0; m < 8; ++m) tri[pos * 24 + 8 * a + m] = (float)cm[a][m];
+  }
+  int rc = dev_alloc(c, c->d_order, sizeof(int32_t) * nspec);
+  if (!rc) rc = dev_alloc(c, c->d_ibool, sizeof(int32_t) * nspec * n3);
+  if (!rc) rc = dev_alloc(c, c->d_gam_el, sizeof(float) * 9 * nspec);
+  if (!rc) rc = dev_alloc(c, c->d_tri, sizeof(float) * 24 * nspec);
+  if (!rc) rc = dev_alloc(c, c->d_wdet, sizeof(double) * nspec * n3);
+  if (!rc && c->nirregular > 0) rc = dev_alloc(c, c->d_gam_pt, sizeof(float) * 9 * nspec * n3);
+  if (!rc && c->nirregular == 0) dev_free(c->d_gam_pt);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->d_order.p, order.data(), sizeof(int32_t) * nspec, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_ibool.p, ib.data(), sizeof(int32_t) * nspec * n3, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gel.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_tri.p, tri.data(), sizeof(float) * 24 * nspec, hipMemcpyHostToDevice));
+  int* bad = scratch_i(c);
+  SEMX_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+  geom_kernel<<<grid_for(nspec * n3, 8192), kThreads, 0, c->stream>>>(
+      c->n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_order.as<int32_t>(),
+      c->d_xi64.as<double>(), c->d_w64.as<double>(), c->d_gam_pt.as<float>(), c->d_wdet.as<double>(), bad);
+  SEMX_HIP(c, hipGetLastError());
+  int hbad = 0;
+  SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  if (hbad) return fail(c, SEMX_EGEOM, "upload_mesh: det J <= 0 at some GLL point");
   return SEMX_OK;
 }
 
@@ -475,6 +542,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f) {
   a.ibool = c->d_ibool.as<int32_t>();
   a.gam_pt = c->d_gam_pt.as<float>();
   a.gam_el = c->d_gam_el.as<float>();
+  a.tri = c->d_tri.as<float>();
+  a.xi = c->d_xi32.as<float>();
   a.mat = c->d_mat.as<float>();
   a.u = u;
   a.f = f;
@@ -486,7 +555,7 @@ int force_accumulate(semx_ctx* c, const float* u, float* f) {
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
   const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
   for (const auto& L : launches) {
-    a.elems = L.elems;
+    a.pos0 = L.pos0;
     a.count = L.count;
     hipError_t e;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -501,10 +570,11 @@ int force_accumulate(semx_ctx* c, const float* u, float* f) {
       c->ev_used += 2;
       SEMX_HIP(c, hipEventRecord(e0, c->stream));
     }
+    const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->contraction == SEMX_C_F32)
-      e = launch_force_f32(c->n, L.irregular, atomic, a, grid_cap_force(c), c->stream);
+      e = launch_force_f32(c->n, geo, atomic, a, c->stream);
     else
-      e = launch_force_mfma(c->n, c->contraction, L.irregular, atomic, a, grid_cap_force(c), c->stream);
+      e = launch_force_mfma(c->n, c->contraction, geo, atomic, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
     if (c->timing) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   }
@@ -575,9 +645,6 @@ int record_receivers(semx_ctx* c, int64_t idx) {
   return SEMX_OK;
 }
 
-// scratch layout: [0..7] doubles for reductions, then int flags
-double* scratch_d(semx_ctx* c) { return c->d_scratch.as<double>(); }
-int* scratch_i(semx_ctx* c) { return reinterpret_cast<int*>(c->d_scratch.as<double>() + 8); }
 
 int energy_model0(semx_ctx* c, double* kin, double* pot) {
   int rc = finalize_state(c);
@@ -656,6 +723,7 @@ int semx_create(semx_ctx** out, int ngll, void* hip_stream) {
   int rc = dev_alloc(c, c->d_D, Df.size() * sizeof(float));
   if (!rc) rc = dev_alloc(c, c->d_xi64, ngll * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->d_w64, ngll * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->d_xi32, ngll * sizeof(float));
   if (!rc) rc = dev_alloc(c, c->d_scratch, 8 * sizeof(double) + 64);
   if (rc) {
     semx_destroy(c);
@@ -664,6 +732,8 @@ int semx_create(semx_ctx** out, int ngll, void* hip_stream) {
   e = hipMemcpy(c->d_D.p, Df.data(), Df.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_xi64.p, c->xi.data(), ngll * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_w64.p, c->w.data(), ngll * sizeof(double), hipMemcpyHostToDevice);
+  std::vector<float> xi32(c->xi.begin(), c->xi.end());
+  if (e == hipSuccess) e = hipMemcpy(c->d_xi32.p, xi32.data(), ngll * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     semx_destroy(c);
     return SEMX_EHIP;
@@ -678,7 +748,7 @@ int semx_destroy(semx_ctx* c) {
   else (void)hipDeviceSynchronize();
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
-                    &c->d_gam_pt, &c->d_gam_el, &c->d_wdet, &c->d_lists, &c->d_mat, &c->d_minv,
+                    &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
                     &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis})
     dev_free(*b);
@@ -764,37 +834,21 @@ int semx_upload_mesh(semx_ctx* c, int64_t nspec, int64_t nglob, const int32_t* i
   }
   c->nirregular = nspec - c->nregular;
 
-  rc = dev_alloc(c, c->d_ibool, sizeof(int32_t) * nspec * n3);
-  if (!rc) rc = dev_alloc(c, c->d_vert, sizeof(double) * 3 * nvert);
+  c->h_gam_el = std::move(gam_el);
+  rc = dev_alloc(c, c->d_vert, sizeof(double) * 3 * nvert);
   if (!rc) rc = dev_alloc(c, c->d_elem_vert, sizeof(int32_t) * 8 * nspec);
-  if (!rc) rc = dev_alloc(c, c->d_gam_el, sizeof(float) * 9 * nspec);
-  if (!rc) rc = dev_alloc(c, c->d_wdet, sizeof(double) * nspec * n3);
-  if (!rc && c->nirregular > 0) rc = dev_alloc(c, c->d_gam_pt, sizeof(float) * 9 * nspec * n3);
-  if (!rc && c->nirregular == 0) dev_free(c->d_gam_pt);
   if (rc) return rc;
-  SEMX_HIP(c, hipMemcpy(c->d_ibool.p, ibool, sizeof(int32_t) * nspec * n3, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_vert.p, vert_xyz, sizeof(double) * 3 * nvert, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_elem_vert.p, elem_vert, sizeof(int32_t) * 8 * nspec, hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gam_el.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
-
-  int* bad = scratch_i(c);
   unsigned long long* hmin_bits = reinterpret_cast<unsigned long long*>(scratch_d(c));
-  SEMX_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
   const unsigned long long big = 0x7FEFFFFFFFFFFFFFull;
   SEMX_HIP(c, hipMemcpyAsync(hmin_bits, &big, sizeof(big), hipMemcpyHostToDevice, c->stream));
-  geom_kernel<<<grid_for(nspec * n3, 8192), kThreads, 0, c->stream>>>(
-      n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_xi64.as<double>(),
-      c->d_w64.as<double>(), c->d_gam_pt.as<float>(), c->d_wdet.as<double>(), bad);
-  SEMX_HIP(c, hipGetLastError());
   spacing_kernel<<<grid_for(nspec * n3, 4096), kThreads, 0, c->stream>>>(
       n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_xi64.as<double>(), hmin_bits);
   SEMX_HIP(c, hipGetLastError());
-  int hbad = 0;
   unsigned long long hbits = 0;
-  SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SEMX_HIP(c, hipMemcpyAsync(&hbits, hmin_bits, sizeof(hbits), hipMemcpyDeviceToHost, c->stream));
   SEMX_HIP(c, hipStreamSynchronize(c->stream));
-  if (hbad) return fail(c, SEMX_EGEOM, "upload_mesh: det J <= 0 at some GLL point");
   std::memcpy(&c->hmin, &hbits, sizeof(double));
 
   // colouring: corners first, full-node conflicts if that is not valid
@@ -821,7 +875,7 @@ int semx_upload_mesh(semx_ctx* c, int64_t nspec, int64_t nglob, const int32_t* i
       c->assembly = SEMX_ASM_ATOMIC;
     }
   }
-  rc = build_launch_lists(c);
+  rc = build_layout(c);
   if (rc) return rc;
   c->have_mesh = true;
   return SEMX_OK;
@@ -846,7 +900,9 @@ int semx_set_coloring(semx_ctx* c, int ncolors, const int32_t* color_ptr, const 
   c->ncolors = ncolors;
   c->color_ptr.assign(color_ptr, color_ptr + ncolors + 1);
   c->elem_order.assign(elem_order, elem_order + c->nspec);
-  return build_launch_lists(c);
+  // the device layout follows the colouring: rebuild it; the model must be uploaded again
+  c->have_model = false;
+  return build_layout(c);
 }
 
 int semx_get_coloring(semx_ctx* c, int* ncolors, int32_t* color_ptr, int32_t* elem_order) {
@@ -909,35 +965,22 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
   if (e == hipSuccess) e = hipMemcpy(dr.p, rho, sizeof(double) * npt, hipMemcpyHostToDevice);
   if (e != hipSuccess) { cleanup(); return hip_fail(c, e, "upload_model copies"); }
   material_kernel<<<grid_for(npt, 8192), kThreads, 0, c->stream>>>(
-      c->n3, c->nspec, nmodels, dl.as<double>(), dm.as<double>(), dr.as<double>(), c->d_wdet.as<double>(),
-      c->d_mat.as<float>(), c->d_wrho.as<float>());
+      c->n3, c->nspec, nmodels, c->d_order.as<int32_t>(), dl.as<double>(), dm.as<double>(), dr.as<double>(),
+      c->d_wdet.as<double>(), c->d_mat.as<float>(), c->d_wrho.as<float>());
   fill_f64<<<grid_for(nmodels * c->nglob), kThreads, 0, c->stream>>>(c->d_mass64.as<double>(),
                                                                      nmodels * c->nglob, 0.0);
-  // deterministic mass assembly, colour by colour (element order if uncoloured)
-  std::vector<int32_t> order;
-  std::vector<int32_t> cptr;
+  // deterministic mass assembly, one coloured launch range at a time
   if (c->ncolors > 0) {
-    order = c->elem_order;
-    cptr = c->color_ptr;
-  }
-  DevBuf dorder;
-  if (c->ncolors > 0) {
-    rc = dev_alloc(c, dorder, sizeof(int32_t) * c->nspec);
-    if (rc) { cleanup(); return rc; }
-    e = hipMemcpy(dorder.p, order.data(), sizeof(int32_t) * c->nspec, hipMemcpyHostToDevice);
-    if (e != hipSuccess) { cleanup(); dev_free(dorder); return hip_fail(c, e, "mass order copy"); }
-    for (int k = 0; k < c->ncolors; ++k) {
-      const int64_t cnt = cptr[k + 1] - cptr[k];
-      if (!cnt) continue;
-      mass_color_kernel<<<grid_for((int64_t)nmodels * cnt * c->n3, 8192), kThreads, 0, c->stream>>>(
-          c->n3, c->nspec, c->nglob, nmodels, dorder.as<int32_t>() + cptr[k], cnt, c->d_ibool.as<int32_t>(),
-          dr.as<double>(), c->d_wdet.as<double>(), c->d_mass64.as<double>());
-    }
+    for (const auto& L : c->colored_launches)
+      mass_color_kernel<<<grid_for((int64_t)nmodels * L.count * c->n3, 8192), kThreads, 0, c->stream>>>(
+          c->n3, c->nspec, c->nglob, nmodels, L.pos0, L.count, c->d_order.as<int32_t>(),
+          c->d_ibool.as<int32_t>(), dr.as<double>(), c->d_wdet.as<double>(), c->d_mass64.as<double>());
   } else {
     // no valid colouring (an element repeats a node): one thread walks the
-    // elements in order, which keeps the sum deterministic (tiny meshes only)
-    mass_serial_kernel<<<1, 1, 0, c->stream>>>(c->n3, c->nspec, c->nglob, nmodels, c->d_ibool.as<int32_t>(),
-                                               dr.as<double>(), c->d_wdet.as<double>(), c->d_mass64.as<double>());
+    // positions in order, which keeps the sum deterministic (tiny meshes only)
+    mass_serial_kernel<<<1, 1, 0, c->stream>>>(c->n3, c->nspec, c->nglob, nmodels, c->d_order.as<int32_t>(),
+                                               c->d_ibool.as<int32_t>(), dr.as<double>(), c->d_wdet.as<double>(),
+                                               c->d_mass64.as<double>());
   }
   minv_kernel<<<grid_for(nmodels * c->nglob), kThreads, 0, c->stream>>>(nmodels * c->nglob,
                                                                         c->d_mass64.as<double>(),
@@ -945,7 +988,6 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
-  dev_free(dorder);
   if (e != hipSuccess) return hip_fail(c, e, "upload_model kernels");
   c->have_model = true;
   c->lambda_max = 0.0;
@@ -1234,6 +1276,14 @@ int semx_set_watchdog(semx_ctx* c, int64_t interval, double max_energy) {
   if (interval < 0) return fail(c, SEMX_EINVAL, "set_watchdog: negative interval");
   c->watchdog_every = interval;
   c->watchdog_emax = max_energy;
+  return SEMX_OK;
+}
+
+int semx_set_geometry(semx_ctx* c, int mode) {
+  if (!c) return SEMX_EINVAL;
+  if (mode == SEMX_GEOM_STORED) c->irregular_geo = kStored;
+  else if (mode == SEMX_GEOM_TRILINEAR) c->irregular_geo = kTrilinear;
+  else return fail(c, SEMX_EINVAL, "set_geometry: unknown mode");
   return SEMX_OK;
 }
 

@@ -1,16 +1,28 @@
 // FP32 element internal-force kernel f = -K u (VALU contractions through LDS).
 //
-// One workgroup owns one element at a time (one lane per GLL point, the
-// n^3 points padded to whole 64-lane wavefronts) and walks a contiguous slice
-// of the launch's element list.  Per element, in one fused traversal
-// (the paper's Sec. IV-D "single grid-point traversal" with scalar
+// One workgroup owns one element at a time, one lane per GLL point (the n^3
+// points padded to whole 64-lane wavefronts).  Per element, in one fused
+// traversal (the paper's Sec. IV-D single grid-point traversal with scalar
 // intermediates):
 //   gather u[ibool] -> LDS,
 //   three forward contractions with D along xi/eta/zeta (Sec. II-B),
 //   inverse-Jacobian map, isotropic stress, weighted fluxes in registers,
 //   fluxes -> LDS, three transpose contractions with D^T (Sec. II-B, weak form),
 //   scatter-add to f (plain read-modify-write inside a colour, or atomics).
-// The per-lane rows and columns of D stay in registers for the whole kernel.
+//
+// Geometry paths (the paper's Sec. IV-D regular/irregular specialisation,
+// chosen per launch, never per point):
+//   kRegular   affine element: one Gamma per element (scalar loads);
+//   kStored    per-point Gamma = J^{-1} streamed from memory (9 floats/point);
+//   kTrilinear J rebuilt at each point from the 7x3 coefficients of the
+//              element's trilinear map (scalar loads), no per-point geometry
+//              traffic.  With C the cofactor matrix of J (J^{-1} = C^T/det J)
+//              and lambda' = lambda w det J, mu' = mu w det J as stored:
+//              g' = du C^T, sigma'' = lambda' tr(g') I + mu' (g' + g'^T),
+//              Phi = sigma'' C / det^2  (equal to w det J sigma J^{-T}).
+//
+// The streaming inputs (node numbers, Gamma, lambda', mu') use non-temporal
+// loads so they do not evict u and f from the caches.
 #include "semx_internal.hpp"
 
 namespace semx {
@@ -22,66 +34,106 @@ struct Shape {
   static constexpr int BLK = ((N3 + 63) / 64) * 64;
 };
 
-template <int NG, bool IRREG, bool ATOMIC>
+template <class T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Per-lane inputs of one element.
+struct PointIn {
+  int g;
+  float G[9];  // Gamma (kStored); unused otherwise
+  float lw, mw;
+  float u[3];
+  float f[3];
+};
+
+template <int NG, int GEO, bool ATOMIC>
+__device__ __forceinline__ void load_point(const ForceArgs& a, const float* __restrict__ mat,
+                                           const float* __restrict__ u, const float* f, int pos, int pp,
+                                           int g, PointIn& P) {
+  constexpr int N3 = Shape<NG>::N3;
+  P.g = g;
+  if constexpr (GEO == kStored) {
+    const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) P.G[d] = ldnt(gp + d * N3);
+  }
+  P.lw = ldnt(mat + (size_t)pos * 2 * N3 + pp);
+  P.mw = ldnt(mat + (size_t)pos * 2 * N3 + N3 + pp);
+  P.u[0] = u[3 * (size_t)g + 0];
+  P.u[1] = u[3 * (size_t)g + 1];
+  P.u[2] = u[3 * (size_t)g + 2];
+  if constexpr (!ATOMIC) {
+    P.f[0] = f[3 * (size_t)g + 0];
+    P.f[1] = f[3 * (size_t)g + 1];
+    P.f[2] = f[3 * (size_t)g + 2];
+  }
+}
+
+// One workgroup handles R consecutive launch positions (elements) in
+// straight-line code: the inputs of element m+1 are loaded while element m
+// computes.  Straight-line code (no loop) lets the compiler count outstanding
+// memory operations exactly, so waits for prefetched data never wait for the
+// scatter stores issued after them.
+template <int NG, int GEO, bool ATOMIC, int R>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
   __shared__ float s_u[3 * N3];
   __shared__ float s_q[9 * N3];
+  __shared__ float s_D[NG * NG];
+
+  // XCD-aware grouping: blocks are dispatched round-robin over the XCDs, so
+  // block b runs on XCD b % 8; the groups of R elements are dealt so that
+  // each XCD walks one contiguous eighth of the range, keeping elements that
+  // share nodes within one L2.
+  const int ngrp = (int)((a.count + R - 1) / R);
+  const int gpx = (ngrp + kNumXcd - 1) / kNumXcd;
+  const int grp = (blockIdx.x % kNumXcd) * gpx + blockIdx.x / kNumXcd;
+  if (grp >= ngrp) return;  // uniform over the block
+  const int r0 = grp * R;
+  const int nr = min(R, (int)a.count - r0);
+  const int P0 = (int)a.pos0 + r0;
 
   const int p = threadIdx.x;
   const bool act = p < N3;
   const int pp = act ? p : 0;
   const int i = pp % NG, j = (pp / NG) % NG, k = pp / (NG * NG);
 
-  // D rows (forward) and columns (transpose) needed by this lane.
-  float Di[NG], Dj[NG], Dk[NG], Ti[NG], Tj[NG], Tk[NG];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    Di[q] = a.D[i * NG + q];
-    Dj[q] = a.D[j * NG + q];
-    Dk[q] = a.D[k * NG + q];
-    Ti[q] = a.D[q * NG + i];
-    Tj[q] = a.D[q * NG + j];
-    Tk[q] = a.D[q * NG + k];
-  }
-
   const int model = blockIdx.y;
   const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
-  float* __restrict__ f = a.f + (size_t)model * a.nglob * 3;
+  float* f = a.f + (size_t)model * a.nglob * 3;
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
 
-  // XCD-aware slicing: blocks are dispatched round-robin over the XCDs, so
-  // block b runs on XCD b % 8; each XCD walks one contiguous eighth of the
-  // list, keeping elements that share nodes within one L2.
-  const int bpx = gridDim.x / kNumXcd;
-  const int xcd = blockIdx.x % kNumXcd;
-  const int lb = blockIdx.x / kNumXcd;
-  const int64_t chunk = (a.count + kNumXcd - 1) / kNumXcd;
-  const int64_t beg = xcd * chunk;
-  const int64_t end = (beg + chunk < a.count) ? beg + chunk : a.count;
+  PointIn P[2];
+  int g_next = (nr > 1) ? ldnt(a.ibool + (size_t)(P0 + 1) * N3 + pp) : 0;
+  load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0, pp, ldnt(a.ibool + (size_t)P0 * N3 + pp), P[0]);
 
-  for (int64_t pos = beg + lb; pos < end; pos += bpx) {
-    const int e = a.elems[pos];
-    const size_t eb = (size_t)e * N3;
-    const int g = a.ibool[eb + pp];
-    float G[9];
-    if constexpr (IRREG) {
-      const float* gp = a.gam_pt + (size_t)e * 9 * N3 + pp;
+  // D in LDS: the lane's rows and columns are read per contraction step,
+  // which keeps the register count low enough for 8 waves per SIMD.
+  if (p < NG * NG) s_D[p] = a.D[p];
+  // reference coordinates of this lane's node (trilinear path)
+  float rx = 0.f, ry = 0.f, rz = 0.f;
+  if constexpr (GEO == kTrilinear) {
+    rx = a.xi[i];
+    ry = a.xi[j];
+    rz = a.xi[k];
+  }
+
 #pragma unroll
-      for (int d = 0; d < 9; ++d) G[d] = gp[d * N3];
-    } else {
-#pragma unroll
-      for (int d = 0; d < 9; ++d) G[d] = a.gam_el[(size_t)e * 9 + d];
-    }
-    const float lamw = mat[(size_t)e * 2 * N3 + pp];
-    const float muw = mat[(size_t)e * 2 * N3 + N3 + pp];
-    const float ux = u[3 * (size_t)g + 0];
-    const float uy = u[3 * (size_t)g + 1];
-    const float uz = u[3 * (size_t)g + 2];
+  for (int m = 0; m < R; ++m) {
+    if (m >= nr) break;  // uniform over the block
+    PointIn& cur = P[m & 1];
+    PointIn& nxt = P[(m + 1) & 1];
+    if (m > 0) __syncthreads();  // the previous element has finished reading s_q / s_u
     if (act) {
-      s_u[pp] = ux;
-      s_u[N3 + pp] = uy;
-      s_u[2 * N3 + pp] = uz;
+      s_u[pp] = cur.u[0];
+      s_u[N3 + pp] = cur.u[1];
+      s_u[2 * N3 + pp] = cur.u[2];
+    }
+    if (m + 1 < nr) {
+      load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0 + m + 1, pp, g_next, nxt);
+      if (m + 2 < nr) g_next = ldnt(a.ibool + (size_t)(P0 + m + 2) * N3 + pp);
     }
     __syncthreads();
 
@@ -91,21 +143,62 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     for (int c = 0; c < 3; ++c) du[c][0] = du[c][1] = du[c][2] = 0.0f;
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
+      const float di = s_D[i * NG + q], dj = s_D[j * NG + q], dk = s_D[k * NG + q];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        du[c][0] += Di[q] * s_u[c * N3 + q + NG * (j + NG * k)];
-        du[c][1] += Dj[q] * s_u[c * N3 + i + NG * (q + NG * k)];
-        du[c][2] += Dk[q] * s_u[c * N3 + i + NG * (j + NG * q)];
+        du[c][0] += di * s_u[c * N3 + q + NG * (j + NG * k)];
+        du[c][1] += dj * s_u[c * N3 + i + NG * (q + NG * k)];
+        du[c][2] += dk * s_u[c * N3 + i + NG * (j + NG * q)];
       }
     }
-    // physical gradient gr[c][b] = sum_d du[c][d] Gamma[d][b]
+
+    // geometry map M (Gamma, or the cofactor matrix on the trilinear path):
+    // gr[c][b] = sum_d du[c][d] M[d][b]
+    float Mg[9];
+    float scale = 1.0f;  // applied to the fluxes
+    if constexpr (GEO == kStored) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d) Mg[d] = cur.G[d];
+    } else if constexpr (GEO == kRegular) {
+      const float* ge = a.gam_el + (size_t)(P0 + m) * 9;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) Mg[d] = ge[d];
+    } else {
+      // x_a(r) = c0 + c1 rx + c2 ry + c3 rz + c4 rx ry + c5 rx rz + c6 ry rz + c7 rx ry rz
+      const float* cf = a.tri + (size_t)(P0 + m) * 24;  // [a][c1..c7], 3 x 8 with padding
+      float J[3][3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const float* c = cf + 8 * ax;
+        J[ax][0] = c[1] + c[4] * ry + c[5] * rz + c[7] * (ry * rz);
+        J[ax][1] = c[2] + c[4] * rx + c[6] * rz + c[7] * (rx * rz);
+        J[ax][2] = c[3] + c[5] * rx + c[6] * ry + c[7] * (rx * ry);
+      }
+      // cofactors C[a][b]; J^{-1}[d][b] = C[b][d] / det, so M[d][b] = C[b][d]
+      const float C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const float C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const float C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      const float C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      const float C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      const float C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      const float C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      const float C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      const float C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const float det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
+      Mg[0] = C00; Mg[1] = C10; Mg[2] = C20;
+      Mg[3] = C01; Mg[4] = C11; Mg[5] = C21;
+      Mg[6] = C02; Mg[7] = C12; Mg[8] = C22;
+      const float id = 1.0f / det;
+      scale = id * id;
+    }
     float gr[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int b = 0; b < 3; ++b)
-        gr[c][b] = du[c][0] * G[0 * 3 + b] + du[c][1] * G[1 * 3 + b] + du[c][2] * G[2 * 3 + b];
-    // isotropic stress (already weighted by w_i w_j w_k det J)
+        gr[c][b] = du[c][0] * Mg[0 * 3 + b] + du[c][1] * Mg[1 * 3 + b] + du[c][2] * Mg[2 * 3 + b];
+    // isotropic stress (lambda' and mu' carry w_i w_j w_k det J)
+    const float lamw = cur.lw, muw = cur.mw;
     const float ltr = lamw * (gr[0][0] + gr[1][1] + gr[2][2]);
     float sg[3][3];
     sg[0][0] = ltr + 2.0f * muw * gr[0][0];
@@ -114,14 +207,20 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     sg[0][1] = sg[1][0] = muw * (gr[0][1] + gr[1][0]);
     sg[0][2] = sg[2][0] = muw * (gr[0][2] + gr[2][0]);
     sg[1][2] = sg[2][1] = muw * (gr[1][2] + gr[2][1]);
-    // fluxes Phi[c][d] = sum_b sigma[c][b] Gamma[d][b]
+    if constexpr (GEO == kTrilinear) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) sg[c][b] *= scale;
+    }
+    // fluxes Phi[c][d] = sum_b sigma[c][b] M[d][b]
     if (act) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
           s_q[(c * 3 + d) * N3 + pp] =
-              sg[c][0] * G[d * 3 + 0] + sg[c][1] * G[d * 3 + 1] + sg[c][2] * G[d * 3 + 2];
+              sg[c][0] * Mg[d * 3 + 0] + sg[c][1] * Mg[d * 3 + 1] + sg[c][2] * Mg[d * 3 + 2];
     }
     __syncthreads();
 
@@ -131,57 +230,69 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
       float s = 0.0f;
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
-        s += Ti[q] * s_q[(c * 3 + 0) * N3 + q + NG * (j + NG * k)];
-        s += Tj[q] * s_q[(c * 3 + 1) * N3 + i + NG * (q + NG * k)];
-        s += Tk[q] * s_q[(c * 3 + 2) * N3 + i + NG * (j + NG * q)];
+        s += s_D[q * NG + i] * s_q[(c * 3 + 0) * N3 + q + NG * (j + NG * k)];
+        s += s_D[q * NG + j] * s_q[(c * 3 + 1) * N3 + i + NG * (q + NG * k)];
+        s += s_D[q * NG + k] * s_q[(c * 3 + 2) * N3 + i + NG * (j + NG * q)];
       }
       F[c] = -s;
     }
     if (act) {
-      float* fg = f + 3 * (size_t)g;
+      float* fg = f + 3 * (size_t)cur.g;
       if constexpr (ATOMIC) {
         unsafeAtomicAdd(fg + 0, F[0]);
         unsafeAtomicAdd(fg + 1, F[1]);
         unsafeAtomicAdd(fg + 2, F[2]);
       } else {
-        fg[0] += F[0];
-        fg[1] += F[1];
-        fg[2] += F[2];
+        fg[0] = cur.f[0] + F[0];
+        fg[1] = cur.f[1] + F[1];
+        fg[2] = cur.f[2] + F[2];
       }
     }
   }
 }
 
-template <int NG>
-hipError_t launch_n(bool irregular, bool atomic, const ForceArgs& a, int grid_cap, hipStream_t s) {
-  if (a.count <= 0) return hipSuccess;
-  int64_t nb = a.count < grid_cap ? a.count : grid_cap;
-  nb = ((nb + kNumXcd - 1) / kNumXcd) * kNumXcd;
+#ifndef SEMX_F32_ELEMS_PER_BLOCK
+#define SEMX_F32_ELEMS_PER_BLOCK 1
+#endif
+
+template <int NG, int GEO, bool ATOMIC>
+hipError_t launch_one(const ForceArgs& a, hipStream_t s) {
+  constexpr int R = SEMX_F32_ELEMS_PER_BLOCK;
+  const int64_t ngrp = (a.count + R - 1) / R;
+  const int64_t nb = ((ngrp + kNumXcd - 1) / kNumXcd) * kNumXcd;
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
-  if (irregular) {
-    if (atomic) force_f32_kernel<NG, true, true><<<grid, block, 0, s>>>(a);
-    else force_f32_kernel<NG, true, false><<<grid, block, 0, s>>>(a);
-  } else {
-    if (atomic) force_f32_kernel<NG, false, true><<<grid, block, 0, s>>>(a);
-    else force_f32_kernel<NG, false, false><<<grid, block, 0, s>>>(a);
-  }
+  force_f32_kernel<NG, GEO, ATOMIC, R><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
+}
+
+template <int NG>
+hipError_t launch_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  switch (geo) {
+    case kRegular:
+      return atomic ? launch_one<NG, kRegular, true>(a, s) : launch_one<NG, kRegular, false>(a, s);
+    case kStored:
+      return atomic ? launch_one<NG, kStored, true>(a, s) : launch_one<NG, kStored, false>(a, s);
+    case kTrilinear:
+      return atomic ? launch_one<NG, kTrilinear, true>(a, s) : launch_one<NG, kTrilinear, false>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_force_f32(int n, bool irregular, bool atomic, const ForceArgs& a, int grid_cap,
-                            hipStream_t s) {
+hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   switch (n) {
-    case 2: return launch_n<2>(irregular, atomic, a, grid_cap, s);
-    case 3: return launch_n<3>(irregular, atomic, a, grid_cap, s);
-    case 4: return launch_n<4>(irregular, atomic, a, grid_cap, s);
-    case 5: return launch_n<5>(irregular, atomic, a, grid_cap, s);
-    case 6: return launch_n<6>(irregular, atomic, a, grid_cap, s);
-    case 7: return launch_n<7>(irregular, atomic, a, grid_cap, s);
-    case 8: return launch_n<8>(irregular, atomic, a, grid_cap, s);
-    case 9: return launch_n<9>(irregular, atomic, a, grid_cap, s);
-    case 10: return launch_n<10>(irregular, atomic, a, grid_cap, s);
+    case 2: return launch_n<2>(geo, atomic, a, s);
+    case 3: return launch_n<3>(geo, atomic, a, s);
+    case 4: return launch_n<4>(geo, atomic, a, s);
+    case 5: return launch_n<5>(geo, atomic, a, s);
+    case 6: return launch_n<6>(geo, atomic, a, s);
+    case 7: return launch_n<7>(geo, atomic, a, s);
+    case 8: return launch_n<8>(geo, atomic, a, s);
+    case 9: return launch_n<9>(geo, atomic, a, s);
+    case 10: return launch_n<10>(geo, atomic, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -3,7 +3,7 @@
 
 namespace semx {
 bool mfma_supported(int) { return false; }
-hipError_t launch_force_mfma(int, int, bool, bool, const ForceArgs&, int, hipStream_t) {
+hipError_t launch_force_mfma(int, int, int, bool, const ForceArgs&, hipStream_t) {
   return hipErrorNotSupported;
 }
 }  // namespace semx

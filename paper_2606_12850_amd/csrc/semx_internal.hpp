@@ -14,6 +14,11 @@ namespace semx {
 constexpr int kMaxN = 10;   // largest supported NGLL
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin block dispatch
 
+// geometry path of a force launch
+constexpr int kRegular = 0;    // affine element: one Gamma per element
+constexpr int kStored = 1;     // per-point Gamma streamed from memory
+constexpr int kTrilinear = 2;  // J rebuilt per point from the trilinear map coefficients
+
 // Device buffer owned by the library.
 struct DevBuf {
   void* p = nullptr;
@@ -21,11 +26,12 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Element list of one launch: elements of one colour and one geometry kind.
+// One force launch: a contiguous range of launch positions (elements of one
+// colour and one geometry kind, or of one kind for atomic assembly).
 struct Launch {
-  int32_t* elems = nullptr;  // device pointer into ctx->d_lists
+  int64_t pos0 = 0;
   int64_t count = 0;
-  bool irregular = false;
+  bool irregular = false;  // geometry path: kRegular, else the context's irregular path
 };
 
 struct SourceSet {
@@ -68,10 +74,18 @@ struct semx_ctx {
   std::vector<int32_t> h_ibool;     // kept for colouring checks and sources
   std::vector<int32_t> h_elem_vert;
   std::vector<double> h_vert;
+  // per-element device arrays are stored by launch position; h_order[pos] =
+  // element, positions sorted by (geometry kind, colour, element)
+  std::vector<int32_t> h_order;
+  semx::DevBuf d_order;     // int32 [nspec]
+  std::vector<float> h_gam_el;  // [nspec][9] per-element Gamma of regular elements (user order)
   semx::DevBuf d_ibool;     // int32 [nspec][n3]
   semx::DevBuf d_vert;      // double [nvert][3]
   semx::DevBuf d_elem_vert; // int32 [nspec][8]
   semx::DevBuf d_gam_pt;    // float [nspec][9][n3] (allocated if any irregular element)
+  semx::DevBuf d_tri;       // float [nspec][3][8] trilinear map coefficients (irregular elements)
+  semx::DevBuf d_xi32;      // float [n] GLL nodes
+  int irregular_geo = semx::kStored;  // path for irregular elements (semx_set_geometry)
   semx::DevBuf d_gam_el;    // float [nspec][9]     (per-element Gamma of regular elements)
   semx::DevBuf d_wdet;      // double [nspec][n3]   w_i w_j w_k det J
   std::vector<uint8_t> h_regular;  // per element
@@ -81,7 +95,6 @@ struct semx_ctx {
   // colouring
   int ncolors = 0;
   std::vector<int32_t> color_ptr, elem_order;
-  semx::DevBuf d_lists;            // int32: lists of all launches, back to back
   std::vector<semx::Launch> colored_launches;  // per colour: regular then irregular
   std::vector<semx::Launch> atomic_launches;   // regular list, irregular list
 
@@ -134,25 +147,26 @@ void gll_nodes_weights(int n, std::vector<double>& xi, std::vector<double>& w);
 void deriv_matrix(int n, const std::vector<double>& xi, std::vector<double>& D);
 void lagrange_at(int n, const std::vector<double>& xi, double x, double* l);
 
-// ---- launchers (force.hip, force_mfma.hip) --------------------------------
+// ---- launchers (force_f32.hip, force_mfma.hip) -----------------------------
+
 struct ForceArgs {
   const int32_t* ibool;
-  const float* gam_pt;   // [nspec][9][n3]
-  const float* gam_el;   // [nspec][9]
+  const float* gam_pt;   // [nspec][9][n3]   (kStored)
+  const float* gam_el;   // [nspec][9]       (kRegular)
+  const float* tri;      // [nspec][3][8]    (kTrilinear: c0..c7 of each coordinate)
+  const float* xi;       // [n] GLL nodes, FP32
   const float* mat;      // [nmodels][nspec][2][n3]
   const float* u;        // [nmodels][nglob][3]
   float* f;              // [nmodels][nglob][3]
   const float* D;        // [n][n] FP32
   const void* Dh;        // packed low-precision D tables (MFMA paths)
-  const int32_t* elems;
+  int64_t pos0;          // first launch position of this launch
   int64_t count;
   int64_t nspec, nglob;
   int nmodels;
 };
-hipError_t launch_force_f32(int n, bool irregular, bool atomic, const ForceArgs& a, int grid_cap,
-                            hipStream_t s);
-hipError_t launch_force_mfma(int n, int prec, bool irregular, bool atomic, const ForceArgs& a,
-                             int grid_cap, hipStream_t s);
+hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);
 
 }  // namespace semx

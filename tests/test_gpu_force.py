@@ -36,10 +36,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("geometry", ["stored", "trilinear"])
 @pytest.mark.parametrize("assembly", ["colored", "atomic"])
 @pytest.mark.parametrize("name,ne,n,jitter", CASES, ids=[c[0] for c in CASES])
-def test_force_parity(orc, name, ne, n, jitter, assembly):
+def test_force_parity(orc, name, ne, n, jitter, assembly, geometry):
     import paper_2606_12850_amd as P
+    if jitter == 0.0 and geometry == "trilinear":
+        pytest.skip("regular meshes use the per-element path in both geometry modes")
     mesh = W.box_mesh(ne, n, 4000.0, jitter=jitter, seed=17)
     lam, mu, rho = _hetero_model(mesh, 5)
     gam, jac, _ = oracle_geometry(orc, mesh)
@@ -51,6 +54,7 @@ def test_force_parity(orc, name, ne, n, jitter, assembly):
         assert info["nregular"] == 0
     s.upload_model(lam, mu, rho)
     s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED if assembly == "colored" else P.SEMX_ASM_ATOMIC)
+    P.semx_set_geometry(s.ctx, P.SEMX_GEOM_STORED if geometry == "stored" else P.SEMX_GEOM_TRILINEAR)
     rng = np.random.default_rng(3)
     for u in (rng.uniform(-1, 1, (mesh.nglob, 3)), smooth_field(orc, mesh)):
         u32 = u.astype(np.float32).astype(np.float64)   # both sides see the same FP32 input

@@ -36,13 +36,15 @@ def _sampled_reference(orc, wl, u, sample):
     return nodes, f[nodes]
 
 
+@pytest.mark.parametrize("geometry", ["stored", "trilinear"])
 @pytest.mark.parametrize("assembly", ["colored", "atomic"])
-def test_fullsize_force_sampled(orc, big, assembly):
+def test_fullsize_force_sampled(orc, big, assembly, geometry):
     import torch
     import paper_2606_12850_amd as P
     wl, s, info = big
     assert info["nirregular"] == wl.mesh.nspec and info["ncolors"] == 8
     s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED if assembly == "colored" else P.SEMX_ASM_ATOMIC)
+    P.semx_set_geometry(s.ctx, P.SEMX_GEOM_STORED if geometry == "stored" else P.SEMX_GEOM_TRILINEAR)
     rng = np.random.default_rng(11)
     u = rng.uniform(-1, 1, (wl.mesh.nglob, 3)).astype(np.float32)
     f = s.apply_force(torch.from_numpy(u).cuda())
@@ -53,7 +55,7 @@ def test_fullsize_force_sampled(orc, big, assembly):
     sample = np.unique(np.concatenate([rng.choice(E, 48, replace=False), [0, 63, E - 64, E - 1, E // 2]]))
     nodes, ref = _sampled_reference(orc, wl, u.astype(np.float64), sample)
     err = rel_l2(f[nodes], ref)
-    print(f"full-size {assembly}: sampled rel L2 = {err:.3e} over {len(nodes)} nodes")
+    print(f"full-size {assembly} {geometry}: sampled rel L2 = {err:.3e} over {len(nodes)} nodes")
     assert err <= 1e-5
 
 
