@@ -172,3 +172,39 @@ def forward(n: int, ibool, gam, jac, lam, mu, rho, nglob: int, dt: float, nt: in
     if want_history:
         out["uhist"] = uhist.reshape(nt + 1, nglob, 3)
     return out
+
+
+def adjoint(n: int, ibool, gam, jac, lam, mu, rho, nglob: int, dt: float, nt: int,
+            src_elem, src_xi, src_dir, stf, rec_elem, rec_xi, gseis):
+    """Exact discrete-adjoint gradient of a seismogram functional chi through
+    the Newmark run of :func:`forward`, given gseis = d chi / d seis
+    [nrec, 3, nt].  Returns (d chi/d lambda, d chi/d mu, d chi/d rho), each
+    [nspec, n^3] per element-local point."""
+    L = lib()
+    if not getattr(L, "_adj_sig", False):
+        i64 = ctypes.c_int64
+        L.orc_adjoint.argtypes = [ctypes.c_int, i64, i64, _ip, _dp, _dp, _dp, _dp, _dp,
+                                  ctypes.c_double, i64,
+                                  ctypes.c_int, _ip, _dp, _dp, _dp,
+                                  ctypes.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
+        L.orc_adjoint.restype = ctypes.c_int
+        L._adj_sig = True
+    ib = _i32(ibool)
+    nspec = ib.shape[0]
+    n3 = n ** 3
+    nsrc = len(src_elem); nrec = len(rec_elem)
+    stf = _f64(stf).reshape(nsrc, nt + 1)
+    gl = np.zeros(nspec * n3); gm = np.zeros(nspec * n3); gr = np.zeros(nspec * n3)
+    rc = L.orc_adjoint(n, nspec, nglob, ib.ravel(), _f64(gam).ravel(), _f64(jac).ravel(),
+                       _f64(lam).ravel(), _f64(mu).ravel(), _f64(rho).ravel(), float(dt), int(nt),
+                       nsrc, _i32(src_elem).ravel(), _f64(src_xi).ravel(), _f64(src_dir).ravel(),
+                       stf.ravel(), nrec, _i32(rec_elem).ravel(), _f64(rec_xi).ravel(),
+                       _f64(gseis).ravel(), gl, gm, gr)
+    if rc != 0:
+        raise RuntimeError(f"orc_adjoint failed ({rc})")
+    return gl.reshape(nspec, n3), gm.reshape(nspec, n3), gr.reshape(nspec, n3)
+
+
+def misfit(seis, data, dt: float) -> float:
+    """L2 seismogram misfit chi = 1/2 dt sum (s - d)^2."""
+    return 0.5 * dt * float(np.sum((np.asarray(seis) - np.asarray(data)) ** 2))

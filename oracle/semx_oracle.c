@@ -454,3 +454,150 @@ int orc_forward(int n, int64_t nspec, int64_t nglob, const int32_t *ibool,
     free(fsrc); free(swt); free(rwt); free(unew_minus_uold);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of the Newmark run above (exact gradient of a seismogram
+ * misfit with respect to lambda, mu and rho at every element-local point).
+ *
+ * The run is, for n >= 1, the central-difference recursion
+ *   r^{n+1} = M (u^{n+1} - 2u^n + u^{n-1}) + dt^2 K u^n - dt^2 f_src^n = 0,
+ * started by r^1 = M u^1 - dt^2/2 f_src^0 = 0 (u^0 = 0), and seis[.][.][n-1]
+ * = R u^n.  Given gseis = d chi / d seis ([nrec][3][nt]), the adjoint fields
+ * psi^m solve, for m = nt .. 1 with psi^{nt+1} = psi^{nt+2} = 0,
+ *   M psi^m = R^T gseis(m) + M (2 psi^{m+1} - psi^{m+2}) - dt^2 K psi^{m+1},
+ * and since K is linear in (lambda, mu) and M in rho (Sec. II-B weak form
+ * with the lumped GLL mass), with W_q = w_i w_j w_k det J:
+ *   dchi/dlambda_q = -dt^2 sum_{n=1}^{nt-1} W_q div psi^{n+1} div u^n,
+ *   dchi/dmu_q     = -dt^2 sum_{n=1}^{nt-1} 2 W_q eps(psi^{n+1}) : eps(u^n),
+ *   dchi/drho_q    = - sum_{n=1}^{nt-1} W_q psi^{n+1}.(u^{n+1} - 2u^n + u^{n-1})
+ *                    - W_q psi^1 . u^1            (all at node ibool(q)).
+ * The forward history is recomputed here in full (small problems only).
+ * ------------------------------------------------------------------------- */
+
+/* grad[q][c][b] = d u_c / d x_b at every local point of element e */
+static void element_grad(int n, const double *D, int64_t e, const int32_t *ibool,
+                         const double *gam, const double *u, double *ue, double *grad)
+{
+    const int n3 = n * n * n;
+    for (int q = 0; q < n3; ++q)
+        for (int c = 0; c < 3; ++c) ue[3 * q + c] = u[3 * (int64_t)ibool[e * n3 + q] + c];
+    for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+        int q = i + n * (j + n * k);
+        const double *G = gam + 9 * (e * n3 + q);
+        for (int c = 0; c < 3; ++c) {
+            double d0 = 0, d1 = 0, d2 = 0;
+            for (int a = 0; a < n; ++a) {
+                d0 += D[i * n + a] * ue[3 * (a + n * (j + n * k)) + c];
+                d1 += D[j * n + a] * ue[3 * (i + n * (a + n * k)) + c];
+                d2 += D[k * n + a] * ue[3 * (i + n * (j + n * a)) + c];
+            }
+            for (int b = 0; b < 3; ++b)
+                grad[9 * q + 3 * c + b] = d0 * G[b] + d1 * G[3 + b] + d2 * G[6 + b];
+        }
+    }
+}
+
+int orc_adjoint(int n, int64_t nspec, int64_t nglob, const int32_t *ibool,
+                const double *gam, const double *jac, const double *lam, const double *mu,
+                const double *rho, double dt, int64_t nt,
+                int nsrc, const int32_t *src_elem, const double *src_xi, const double *src_dir,
+                const double *stf, int nrec, const int32_t *rec_elem, const double *rec_xi,
+                const double *gseis, double *g_lam, double *g_mu, double *g_rho)
+{
+    double xi[ORC_MAXN], w[ORC_MAXN], D[ORC_MAXN * ORC_MAXN];
+    if (orc_gll(n, xi, w)) return -2;
+    orc_dmatrix(n, xi, D);
+    const int n3 = n * n * n;
+    const size_t nv = 3 * (size_t)nglob;
+    double *seis = (double *)malloc(sizeof(double) * (nrec > 0 ? nrec : 1) * 3 * nt);
+    double *uh = (double *)malloc(sizeof(double) * nv * (nt + 1));
+    int rc = orc_forward(n, nspec, nglob, ibool, gam, jac, lam, mu, rho, dt, nt, nsrc, src_elem,
+                         src_xi, src_dir, stf, nrec, rec_elem, rec_xi, seis, NULL, NULL, uh);
+    free(seis);
+    if (rc) { free(uh); return rc; }
+    double *mass = (double *)malloc(sizeof(double) * nglob);
+    orc_mass(n, nspec, nglob, ibool, jac, rho, mass);
+    double *rwt = (double *)malloc(sizeof(double) * n3 * (nrec > 0 ? nrec : 1));
+    for (int r = 0; r < nrec; ++r) point_weights(n, xi, rec_xi + 3 * r, rwt + n3 * r);
+    double *p0 = (double *)calloc(nv, sizeof(double)); /* psi^{m+2} */
+    double *p1 = (double *)calloc(nv, sizeof(double)); /* psi^{m+1} */
+    double *p2 = (double *)calloc(nv, sizeof(double)); /* psi^m */
+    double *kf = (double *)calloc(nv, sizeof(double)); /* -K psi^{m+1} */
+    double *gsrc = (double *)calloc(nv, sizeof(double));
+    memset(g_lam, 0, sizeof(double) * nspec * n3);
+    memset(g_mu, 0, sizeof(double) * nspec * n3);
+    memset(g_rho, 0, sizeof(double) * nspec * n3);
+    for (int64_t m = nt; m >= 1; --m) {
+        /* adjoint source R^T gseis(m), seismogram sample m-1 */
+        memset(gsrc, 0, sizeof(double) * nv);
+        for (int r = 0; r < nrec; ++r)
+            for (int q = 0; q < n3; ++q)
+                for (int c = 0; c < 3; ++c)
+                    gsrc[3 * (int64_t)ibool[(int64_t)rec_elem[r] * n3 + q] + c] +=
+                        rwt[n3 * r + q] * gseis[((size_t)r * 3 + c) * nt + (m - 1)];
+        orc_force(n, nspec, nglob, ibool, gam, jac, lam, mu, p1, kf);
+        for (int64_t g = 0; g < nglob; ++g)
+            for (int c = 0; c < 3; ++c) {
+                size_t t = 3 * g + c;
+                p2[t] = 2.0 * p1[t] - p0[t] + (dt * dt * kf[t] + gsrc[t]) / mass[g];
+            }
+        /* gradient terms pairing psi^{m+1} (p1) with u^m, for 1 <= m <= nt-1 */
+        if (m <= nt - 1) {
+            const double *um = uh + nv * m;
+            const double *up = uh + nv * (m + 1);
+            const double *uo = uh + nv * (m - 1);
+#pragma omp parallel
+            {
+                double *ue = (double *)malloc(sizeof(double) * 3 * n3);
+                double *gp = (double *)malloc(sizeof(double) * 9 * n3);
+                double *gu = (double *)malloc(sizeof(double) * 9 * n3);
+#pragma omp for schedule(static)
+                for (int64_t e = 0; e < nspec; ++e) {
+                    element_grad(n, D, e, ibool, gam, p1, ue, gp);
+                    element_grad(n, D, e, ibool, gam, um, ue, gu);
+                    for (int k = 0; k < n; ++k)
+                    for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        int q = i + n * (j + n * k);
+                        int64_t p = e * n3 + q;
+                        double W = w[i] * w[j] * w[k] * jac[p];
+                        const double *A = gp + 9 * q, *B = gu + 9 * q;
+                        double divp = A[0] + A[4] + A[8], divu = B[0] + B[4] + B[8];
+                        double ee = 0.0;
+                        for (int c = 0; c < 3; ++c)
+                            for (int b = 0; b < 3; ++b)
+                                ee += 0.5 * (A[3 * c + b] + A[3 * b + c]) * 0.5 * (B[3 * c + b] + B[3 * b + c]);
+                        g_lam[p] += -dt * dt * W * divp * divu;
+                        g_mu[p] += -dt * dt * 2.0 * W * ee;
+                        int64_t gq = ibool[p];
+                        double acc = 0.0;
+                        for (int c = 0; c < 3; ++c)
+                            acc += p1[3 * gq + c] * (up[3 * gq + c] - 2.0 * um[3 * gq + c] + uo[3 * gq + c]);
+                        g_rho[p] += -W * acc;
+                    }
+                }
+                free(ue); free(gp); free(gu);
+            }
+        }
+        double *tmp = p0; p0 = p1; p1 = p2; p2 = tmp;
+    }
+    /* p1 now holds psi^1: the start-up term -W psi^1 . u^1 */
+    {
+        const double *u1 = uh + nv * 1;
+        for (int64_t e = 0; e < nspec; ++e)
+            for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int64_t p = e * n3 + i + n * (j + n * k);
+                double W = w[i] * w[j] * w[k] * jac[p];
+                int64_t gq = ibool[p];
+                double acc = 0.0;
+                for (int c = 0; c < 3; ++c) acc += p1[3 * gq + c] * u1[3 * gq + c];
+                g_rho[p] += -W * acc;
+            }
+    }
+    free(uh); free(mass); free(rwt); free(p0); free(p1); free(p2); free(kf); free(gsrc);
+    return 0;
+}
