@@ -193,6 +193,30 @@ int semx_energy(semx_ctx *ctx, double *kinetic, double *potential);
  * max_energy; a violation stops stepping and returns SEMX_ENUMERIC. */
 int semx_set_watchdog(semx_ctx *ctx, int64_t interval, double max_energy);
 
+/* Forward checkpoints for the adjoint: with every > 0, semx_reset() and every
+ * `every`-th semx_step() keep a copy of (u, v, a) on the device (3 vectors
+ * per checkpoint, owned by the library).  0 turns checkpointing off and
+ * frees the copies. */
+int semx_set_checkpointing(semx_ctx *ctx, int64_t every);
+
+/* Discrete adjoint of the explicit Newmark run (exact gradient of a
+ * seismogram functional chi; the paper's weak form gives K linear in
+ * lambda, mu and the lumped mass linear in rho).  gseis_dev holds
+ * d chi / d seismogram, device FP32 [nmodels][nrec][3][nt_max] laid out like
+ * semx_read_seismograms(); the first nt samples (steps 1..nt since reset)
+ * are used, nt <= steps taken.  Writes d chi / d lambda, d chi / d mu and
+ * d chi / d rho per element-local point to device FP64 arrays
+ * [nmodels][nspec][n^3] (user element order, overwritten).  The adjoint runs
+ * in FP32 with exact power-of-two normalisation of the adjoint source and of
+ * the forward field; only the final rescaling is FP64, so gradients of
+ * physically tiny misfits do not underflow.  Recomputes the
+ * forward segment by segment from the checkpoints (coloured assembly makes
+ * the recomputation bitwise equal to the first pass); the context's own
+ * state is restored before return.  Needs semx_set_checkpointing() before the
+ * semx_reset() that started the forward run. */
+int semx_adjoint(semx_ctx *ctx, const float *gseis_dev, int64_t nt, double *g_lambda_dev,
+                 double *g_mu_dev, double *g_rho_dev);
+
 /* Kernel timing.  While enabled, every force-kernel launch is bracketed by a
  * pair of HIP events recorded on the context stream.  semx_force_timing()
  * synchronises the stream, returns the number of force launches and their

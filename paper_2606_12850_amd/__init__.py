@@ -72,6 +72,8 @@ _SIGS = {
     "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
     "semx_set_watchdog": [_vp, _i64, _f64],
     "semx_set_geometry": [_vp, _i32],
+    "semx_set_checkpointing": [_vp, _i64],
+    "semx_adjoint": [_vp, _vp, _i64, _vp, _vp, _vp],
     "semx_set_timing": [_vp, _i32],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
@@ -261,6 +263,15 @@ def semx_set_watchdog(ctx, interval: int, max_energy: float = 0.0):
 
 def semx_set_geometry(ctx, mode: int):
     return _check(ctx, lib().semx_set_geometry(ctx, int(mode)))
+
+
+def semx_set_checkpointing(ctx, every: int):
+    return _check(ctx, lib().semx_set_checkpointing(ctx, int(every)))
+
+
+def semx_adjoint(ctx, gseis, nt: int, g_lambda, g_mu, g_rho):
+    """d chi/d (lambda, mu, rho) into the three device arrays, from d chi/d seis."""
+    return _check(ctx, lib().semx_adjoint(ctx, _ptr(gseis), int(nt), _ptr(g_lambda), _ptr(g_mu), _ptr(g_rho)))
 
 
 def semx_set_timing(ctx, enable: bool):

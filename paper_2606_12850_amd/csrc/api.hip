@@ -693,6 +693,33 @@ int check_finite(semx_ctx* c, bool* ok) {
 }
 
 }  // namespace
+
+// One explicit Newmark step (correct the pending step, predict, force,
+// sources; optionally record receivers).  Leaves f = -K u + f_src pending.
+int step_once(semx_ctx* c, bool record) {
+  const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  const float dt = (float)c->dt;
+  float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
+  const float* minv = c->d_minv.as<float>();
+  if (c->pending_correct)
+    newmark_kernel<kCorrect | kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+  else
+    newmark_kernel<kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+  SEMX_HIP(c, hipGetLastError());
+  int rc = force_accumulate(c, u, f);
+  if (!rc) rc = inject_sources(c, c->it + 1, f);
+  if (!rc && record) rc = record_receivers(c, c->it);
+  if (rc) return rc;
+  c->it++;
+  c->pending_correct = true;
+  return SEMX_OK;
+}
+
+int apply_force_accumulate(semx_ctx* c, const float* u, float* f) { return force_accumulate(c, u, f); }
+int fill_zero(semx_ctx* c, float* p, int64_t n) { return zero_f32(c, p, n); }
+int complete_step(semx_ctx* c) { return finalize_state(c); }
+unsigned grid_1d(int64_t n, int cap) { return grid_for(n, cap); }
+
 }  // namespace semx
 
 using namespace semx;
@@ -747,6 +774,7 @@ int semx_destroy(semx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
+  for (DevBuf& b : c->ckpts) dev_free(b);
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
@@ -1180,7 +1208,12 @@ int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double*
 int semx_reset(semx_ctx* c) {
   if (!c) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "reset: mesh and model required");
-  return do_reset(c);
+  int rc = do_reset(c);
+  if (!rc && c->ckpt_every > 0) {
+    c->ckpt_count = 0;
+    rc = save_checkpoint(c);
+  }
+  return rc;
 }
 
 int semx_step(semx_ctx* c, int64_t nsteps) {
@@ -1188,23 +1221,13 @@ int semx_step(semx_ctx* c, int64_t nsteps) {
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "step: mesh and model required");
   if (!c->have_dt) return fail(c, SEMX_ESTATE, "step: dt not set");
   if (nsteps < 0) return fail(c, SEMX_EINVAL, "step: nsteps < 0");
-  const int64_t nn = (int64_t)c->nmodels * c->nglob;
-  const float dt = (float)c->dt;
-  float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
-  const float* minv = c->d_minv.as<float>();
   for (int64_t s = 0; s < nsteps; ++s) {
-    if (c->pending_correct)
-      newmark_kernel<kCorrect | kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v,
-                                                                                     a, f);
-    else
-      newmark_kernel<kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
-    SEMX_HIP(c, hipGetLastError());
-    int rc = force_accumulate(c, u, f);
-    if (!rc) rc = inject_sources(c, c->it + 1, f);
-    if (!rc) rc = record_receivers(c, c->it);
+    int rc = step_once(c, true);
     if (rc) return rc;
-    c->it++;
-    c->pending_correct = true;
+    if (c->ckpt_every > 0 && c->it % c->ckpt_every == 0) {
+      rc = save_checkpoint(c);
+      if (rc) return rc;
+    }
     if (c->watchdog_every > 0 && c->it % c->watchdog_every == 0) {
       bool ok = true;
       rc = check_finite(c, &ok);

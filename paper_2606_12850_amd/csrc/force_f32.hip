@@ -14,7 +14,7 @@
 // chosen per launch, never per point):
 //   kRegular   affine element: one Gamma per element (scalar loads);
 //   kStored    per-point Gamma = J^{-1} streamed from memory (9 floats/point);
-//   kTrilinear J rebuilt at each point from the 7x3 coefficients of the
+//   kTrilinear J rebuilt at each point from the 8x3 coefficients of the
 //              element's trilinear map (scalar loads), no per-point geometry
 //              traffic.  With C the cofactor matrix of J (J^{-1} = C^T/det J)
 //              and lambda' = lambda w det J, mu' = mu w det J as stored:
@@ -23,21 +23,10 @@
 //
 // The streaming inputs (node numbers, Gamma, lambda', mu') use non-temporal
 // loads so they do not evict u and f from the caches.
-#include "semx_internal.hpp"
+#include "elem_common.hpp"
 
 namespace semx {
 namespace {
-
-template <int NG>
-struct Shape {
-  static constexpr int N3 = NG * NG * NG;
-  static constexpr int BLK = ((N3 + 63) / 64) * 64;
-};
-
-template <class T>
-__device__ __forceinline__ T ldnt(const T* p) {
-  return __builtin_nontemporal_load(p);
-}
 
 // Per-lane inputs of one element.
 struct PointIn {
@@ -83,13 +72,8 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   __shared__ float s_q[9 * N3];
   __shared__ float s_D[NG * NG];
 
-  // XCD-aware grouping: blocks are dispatched round-robin over the XCDs, so
-  // block b runs on XCD b % 8; the groups of R elements are dealt so that
-  // each XCD walks one contiguous eighth of the range, keeping elements that
-  // share nodes within one L2.
   const int ngrp = (int)((a.count + R - 1) / R);
-  const int gpx = (ngrp + kNumXcd - 1) / kNumXcd;
-  const int grp = (blockIdx.x % kNumXcd) * gpx + blockIdx.x / kNumXcd;
+  const int grp = xcd_group(ngrp);
   if (grp >= ngrp) return;  // uniform over the block
   const int r0 = grp * R;
   const int nr = min(R, (int)a.count - r0);
@@ -112,8 +96,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   // D in LDS: the lane's rows and columns are read per contraction step,
   // which keeps the register count low enough for 8 waves per SIMD.
   if (p < NG * NG) s_D[p] = a.D[p];
-  // reference coordinates of this lane's node (trilinear path)
-  float rx = 0.f, ry = 0.f, rz = 0.f;
+  float rx = 0.f, ry = 0.f, rz = 0.f;  // reference coordinates (trilinear path)
   if constexpr (GEO == kTrilinear) {
     rx = a.xi[i];
     ry = a.xi[j];
@@ -137,105 +120,17 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     }
     __syncthreads();
 
-    // reference derivatives du[c][d] = d u_c / d xi_d
     float du[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) du[c][0] = du[c][1] = du[c][2] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const float di = s_D[i * NG + q], dj = s_D[j * NG + q], dk = s_D[k * NG + q];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        du[c][0] += di * s_u[c * N3 + q + NG * (j + NG * k)];
-        du[c][1] += dj * s_u[c * N3 + i + NG * (q + NG * k)];
-        du[c][2] += dk * s_u[c * N3 + i + NG * (j + NG * q)];
-      }
-    }
-
-    // geometry map M (Gamma, or the cofactor matrix on the trilinear path):
-    // gr[c][b] = sum_d du[c][d] M[d][b]
-    float Mg[9];
-    float scale = 1.0f;  // applied to the fluxes
-    if constexpr (GEO == kStored) {
-#pragma unroll
-      for (int d = 0; d < 9; ++d) Mg[d] = cur.G[d];
-    } else if constexpr (GEO == kRegular) {
-      const float* ge = a.gam_el + (size_t)(P0 + m) * 9;
-#pragma unroll
-      for (int d = 0; d < 9; ++d) Mg[d] = ge[d];
-    } else {
-      // x_a(r) = c0 + c1 rx + c2 ry + c3 rz + c4 rx ry + c5 rx rz + c6 ry rz + c7 rx ry rz
-      const float* cf = a.tri + (size_t)(P0 + m) * 24;  // [a][c1..c7], 3 x 8 with padding
-      float J[3][3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const float* c = cf + 8 * ax;
-        J[ax][0] = c[1] + c[4] * ry + c[5] * rz + c[7] * (ry * rz);
-        J[ax][1] = c[2] + c[4] * rx + c[6] * rz + c[7] * (rx * rz);
-        J[ax][2] = c[3] + c[5] * rx + c[6] * ry + c[7] * (rx * ry);
-      }
-      // cofactors C[a][b]; J^{-1}[d][b] = C[b][d] / det, so M[d][b] = C[b][d]
-      const float C00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-      const float C01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-      const float C02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-      const float C10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-      const float C11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-      const float C12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-      const float C20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-      const float C21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-      const float C22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-      const float det = J[0][0] * C00 + J[0][1] * C01 + J[0][2] * C02;
-      Mg[0] = C00; Mg[1] = C10; Mg[2] = C20;
-      Mg[3] = C01; Mg[4] = C11; Mg[5] = C21;
-      Mg[6] = C02; Mg[7] = C12; Mg[8] = C22;
-      const float id = 1.0f / det;
-      scale = id * id;
-    }
+    ref_grad<NG>(s_u, s_D, i, j, k, du);
+    float Mg[9], scale, det;
+    geom_map<GEO>(a, P0 + m, cur.G, rx, ry, rz, Mg, scale, det);
     float gr[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        gr[c][b] = du[c][0] * Mg[0 * 3 + b] + du[c][1] * Mg[1 * 3 + b] + du[c][2] * Mg[2 * 3 + b];
-    // isotropic stress (lambda' and mu' carry w_i w_j w_k det J)
-    const float lamw = cur.lw, muw = cur.mw;
-    const float ltr = lamw * (gr[0][0] + gr[1][1] + gr[2][2]);
-    float sg[3][3];
-    sg[0][0] = ltr + 2.0f * muw * gr[0][0];
-    sg[1][1] = ltr + 2.0f * muw * gr[1][1];
-    sg[2][2] = ltr + 2.0f * muw * gr[2][2];
-    sg[0][1] = sg[1][0] = muw * (gr[0][1] + gr[1][0]);
-    sg[0][2] = sg[2][0] = muw * (gr[0][2] + gr[2][0]);
-    sg[1][2] = sg[2][1] = muw * (gr[1][2] + gr[2][1]);
-    if constexpr (GEO == kTrilinear) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) sg[c][b] *= scale;
-    }
-    // fluxes Phi[c][d] = sum_b sigma[c][b] M[d][b]
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-          s_q[(c * 3 + d) * N3 + pp] =
-              sg[c][0] * Mg[d * 3 + 0] + sg[c][1] * Mg[d * 3 + 1] + sg[c][2] * Mg[d * 3 + 2];
-    }
+    apply_map(du, Mg, gr);
+    stress_flux(gr, cur.lw, cur.mw, scale, Mg, s_q, N3, pp, act);
     __syncthreads();
 
     float F[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float s = 0.0f;
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        s += s_D[q * NG + i] * s_q[(c * 3 + 0) * N3 + q + NG * (j + NG * k)];
-        s += s_D[q * NG + j] * s_q[(c * 3 + 1) * N3 + i + NG * (q + NG * k)];
-        s += s_D[q * NG + k] * s_q[(c * 3 + 2) * N3 + i + NG * (j + NG * q)];
-      }
-      F[c] = -s;
-    }
+    ref_div<NG>(s_q, s_D, i, j, k, F);
     if (act) {
       float* fg = f + 3 * (size_t)cur.g;
       if constexpr (ATOMIC) {

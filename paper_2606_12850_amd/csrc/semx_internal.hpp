@@ -122,6 +122,11 @@ struct semx_ctx {
   semx::SourceSet src;
   semx::ReceiverSet rec;
 
+  // forward checkpoints for the adjoint: state (u, v, a) at it = k * ckpt_every
+  int64_t ckpt_every = 0;
+  int64_t ckpt_count = 0;
+  std::vector<semx::DevBuf> ckpts;  // one buffer of 3 * state_len floats per checkpoint
+
   // optional event timing of force launches
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // 2 per recorded launch, reused
@@ -168,5 +173,14 @@ struct ForceArgs {
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);
+
+// ---- host helpers shared between translation units (api.hip) ----------------
+int step_once(semx_ctx* c, bool record);
+int apply_force_accumulate(semx_ctx* c, const float* u, float* f);
+int fill_zero(semx_ctx* c, float* p, int64_t n);
+int complete_step(semx_ctx* c);
+unsigned grid_1d(int64_t n, int cap = 1 << 16);
+// adjoint.hip
+int save_checkpoint(semx_ctx* c);
 
 }  // namespace semx
