@@ -33,13 +33,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 NE, NGLL = 64, 5
 
 
-def bytes_per_element(n: int, nglob: int, nspec: int, irregular: bool = True) -> float:
+def bytes_per_element(n: int, nglob: int, nspec: int, geometry: str = "stored") -> float:
     """Algorithmic HBM bytes per element per force apply (FP32, this library's layout):
-    ibool 4 n^3, Gamma 9*4 n^3 (irregular) or 9*4 per element (regular),
-    lambda*W and mu*W 2*4 n^3, u read once and f written once per unique node
-    (3*4*G/E each)."""
+    ibool 4 n^3; geometry: Gamma 9*4 n^3 (stored per point), the 3x8 trilinear
+    coefficients 96 (rebuilt per point) or one Gamma 36 (regular); lambda*W and
+    mu*W 2*4 n^3; u read once and f written once per unique node (3*4*G/E each)."""
     n3 = n ** 3
-    geo = 36 * n3 if irregular else 36
+    geo = {"stored": 36 * n3, "trilinear": 96, "regular": 36}[geometry]
     return 4 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
 
 
@@ -81,12 +81,72 @@ def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
                       f"({nsub} elements, {nsub * n ** 3} GLL points), {reps} applies in {el:.1f} s"}
 
 
+def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 2):
+    """Adjoint sensitivity on the layered cube with a -5% Gaussian anomaly:
+    forward with checkpoints, then the discrete adjoint; adjoint/forward time
+    and a finite-difference check of the FP32 gradient along random model
+    directions (FP32 forward runs, central differences)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+    from paper_2606_12850_amd.autograd import SeismogramOperator
+
+    wl0 = W.adjoint_layered(ne=ne, n=NGLL, nt=nt, anomaly=False)
+    wl = W.adjoint_layered(ne=ne, n=NGLL, nt=nt, anomaly=True)
+    probe = P.Solver(NGLL)
+    probe.upload_mesh(wl.mesh)
+    probe.upload_model(wl.lam, wl.mu, wl.rho)
+    dt = P.semx_cfl_dt(probe.ctx, 0.4)
+    probe.close()
+    stf = W.ricker(10.0, 0.12, dt, nt + 1)[None, :]
+    op = SeismogramOperator(wl.mesh, wl.src_elem, wl.src_xi, wl.src_dir, stf, wl.rec_elem, wl.rec_xi, dt, nt,
+                            checkpoint_every=every)
+    data = op.run(wl0.lam, wl0.mu, wl0.rho).clone()
+    op.run(wl.lam, wl.mu, wl.rho)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seis = op.run(wl.lam, wl.mu, wl.rho)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    gseis = dt * (seis - data)
+    chi = 0.5 * dt * float(torch.sum((seis.double() - data.double()) ** 2))
+    op.gradient(gseis)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gl, gm, gr = op.gradient(gseis)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    fd = []
+    for k in range(fd_dirs):
+        dl = wl.lam * rng.standard_normal(wl.lam.shape)
+        dm = wl.mu * rng.standard_normal(wl.mu.shape)
+        eps = 1e-3
+        cp = 0.5 * dt * float(torch.sum((op.run(wl.lam + eps * dl, wl.mu + eps * dm, wl.rho).double()
+                                          - data.double()) ** 2))
+        cm = 0.5 * dt * float(torch.sum((op.run(wl.lam - eps * dl, wl.mu - eps * dm, wl.rho).double()
+                                          - data.double()) ** 2))
+        fdv = (cp - cm) / (2 * eps)
+        ad = float(np.sum(gl[0].cpu().numpy() * dl) + np.sum(gm[0].cpu().numpy() * dm))
+        fd.append({"adjoint": ad, "fd_fp32": fdv, "rel": abs(ad - fdv) / max(abs(fdv), 1e-300)})
+    op.solver.close()
+    return {"workload": f"layered cube {ne}^3 regular, NGLL {NGLL}, -5% Gaussian anomaly, {nt} steps, "
+                        f"checkpoint every {every}, {len(wl.rec_elem)} receivers, FP32",
+            "forward_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
+            "adjoint_over_forward": round(t_adj / t_fwd, 3), "misfit": chi,
+            "fd_check": fd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--geometry", choices=["stored", "trilinear"], default="trilinear")
     ap.add_argument("--assembly", choices=["colored", "atomic"], default="colored")
     ap.add_argument("--apply-reps", type=int, default=50)
     args = ap.parse_args()
@@ -120,13 +180,18 @@ def main():
     setup_s = time.perf_counter() - t_setup
     stream = s.stream
     E, n3 = mesh.nspec, NGLL ** 3
-    b_elem = bytes_per_element(NGLL, mesh.nglob, E, irregular=info["nirregular"] > 0)
+    geo_of = (lambda g: g if info["nirregular"] > 0 else "regular")
+    b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry))
 
     # ---- force apply alone (coloured and atomic), event-timed on the library stream
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
     apply = {}
-    for name, mode in (("colored", P.SEMX_ASM_COLORED), ("atomic", P.SEMX_ASM_ATOMIC)):
+    for gname, gmode in (("stored", P.SEMX_GEOM_STORED), ("trilinear", P.SEMX_GEOM_TRILINEAR)):
+      P.semx_set_geometry(s.ctx, gmode)
+      bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
+      for aname, mode in (("colored", P.SEMX_ASM_COLORED), ("atomic", P.SEMX_ASM_ATOMIC)):
+        name = f"{gname}_{aname}"
         P.semx_set_mode(s.ctx, P.SEMX_C_F32, mode)
         for _ in range(5):
             P.semx_apply_force(s.ctx, u, f)
@@ -138,8 +203,10 @@ def main():
         e1.synchronize()
         ms = e0.elapsed_time(e1) / args.apply_reps
         apply[name] = {"ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3),
-                       "hbm_frac_alg": (b_elem * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)}
+                       "bytes_per_element": bg,
+                       "hbm_frac_alg": (bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)}
     P.semx_set_mode(s.ctx, P.SEMX_C_F32, asm)
+    P.semx_set_geometry(s.ctx, P.SEMX_GEOM_TRILINEAR if args.geometry == "trilinear" else P.SEMX_GEOM_STORED)
 
     # ---- time loop: warmup, then exactly `steps` timed steps
     P.semx_reset(s.ctx)
@@ -166,7 +233,8 @@ def main():
     avg_launch_ms = force_ms / launches
     bytes_per_launch = b_elem * E / launches_per_apply
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    src = open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", "force_f32.hip"), "rb").read()
+    src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
+                   for f in ("force_f32.hip", "elem_common.hpp"))
     traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
 
     out = {
@@ -189,16 +257,18 @@ def main():
                    "nregular": info["nregular"], "nirregular": info["nirregular"], "ncolors": info["ncolors"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "force_f32_kernel<5, irregular, colored>",
+                     "kernel": f"force_f32_kernel<5, {args.geometry}, {args.assembly}>",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
                      "launches": launches, "bytes_per_element": b_elem},
         "force_apply": apply,
         "wall_s_timed": round(wall, 3),
         "setup_s": round(setup_s, 1),
     }
+    s.close()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
-    s.close()
     print(json.dumps(out))
 
 

@@ -287,3 +287,20 @@ def layered_jittered(ne=64, n=5, nt=2000, dt=None, f0=10.0, jitter=0.10, seed=26
     stf = ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
     return Workload("layered_jittered", m, lam, mu, rho, dt, nt, se, sx,
                     np.array([[0.0, 0.0, 1.0]]), stf, re, rx)
+
+
+def adjoint_layered(ne=32, n=5, nt=1000, dt=None, f0=10.0, anomaly: bool = True, nrec_side=8) -> Workload:
+    """Layered cube (vp 6000/4000/2500 m/s bottom to top, vp/vs 1.73, rho 2500)
+    on a regular ne^3 mesh, optionally with a -5% Gaussian velocity anomaly of
+    radius 0.2 L at the centre; vertical Ricker source at (L/2, L/2, 0.2 L);
+    nrec_side^2 receivers on the top face.  ``dt`` must be set by the caller
+    (it depends on the discretisation)."""
+    L = 4000.0
+    m = box_mesh(ne, n, L)
+    an = {"center": (L / 2, L / 2, L / 2), "radius": 0.2 * L, "amp": -0.05} if anomaly else None
+    lam, mu, rho = layered_model(m, anomaly=an)
+    se, sx = locate_regular(m, L / 2, L / 2, 0.2 * L)
+    re, rx = top_receivers_grid(m, nrec_side)
+    dt = float(dt) if dt is not None else 1e-3
+    stf = ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
+    return Workload("adjoint_layered", m, lam, mu, rho, dt, nt, se, sx, np.array([[0.0, 0.0, 1.0]]), stf, re, rx)
