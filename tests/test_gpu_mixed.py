@@ -87,5 +87,5 @@ def test_mixed_seismograms(orc, prec):
     err = rel_l2(s.seismograms(), ref)
     print(f"mixed {prec} cube 400 steps: seismogram rel L2 vs FP64 = {err:.3e}")
     assert np.all(np.isfinite(s.seismograms()))
-    assert err <= BOUND[prec] * 4
+    assert err <= {"bf16": 0.25, "f16": 0.06}[prec]
     s.close()
