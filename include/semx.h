@@ -225,6 +225,42 @@ int semx_adjoint(semx_ctx *ctx, const float *gseis_dev, int64_t nt, double *g_la
 int semx_set_timing(semx_ctx *ctx, int enable);
 int semx_force_timing(semx_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* ---------------------------------------------------------------------------
+ * Surrogate network: a multilayer perceptron that maps model parameters to
+ * receiver seismograms, trained on SEM runs of this library (the SEM solve
+ * stays the fallback and the judge of its error).  Layer l computes
+ * Z_l = H_l W_l^T + b_l with W_l [out][in]; hidden layers apply SiLU, the
+ * last layer is linear.  GEMMs run on BF16 matrix cores with FP32
+ * accumulation from a BF16 copy of FP32 master weights; losses and the
+ * optimiser are FP32.  Parameters are packed W_1, b_1, W_2, b_2, ...
+ * (row-major, FP32).  All device pointers are caller-owned; work is ordered
+ * on the stream given at creation.
+ * ------------------------------------------------------------------------- */
+typedef struct semx_mlp semx_mlp;
+
+/* widths[0..nlayers]: input width, hidden widths, output width; batches up
+ * to max_batch rows.  Parameters start at zero (set them before use). */
+int semx_mlp_create(semx_mlp **out, int nlayers, const int *widths, int max_batch, void *hip_stream);
+int semx_mlp_destroy(semx_mlp *net);
+const char *semx_mlp_last_error(const semx_mlp *net);
+int semx_mlp_num_params(semx_mlp *net, int64_t *nparams);
+/* host FP32 parameter vector in/out; set also clears the Adam moments */
+int semx_mlp_set_params(semx_mlp *net, const float *params);
+int semx_mlp_get_params(semx_mlp *net, float *params);
+int semx_mlp_get_grads(semx_mlp *net, float *grads);
+/* y_dev [batch][width_out] = net(x_dev [batch][width_in]); keeps the
+ * activations for semx_mlp_backward (x_dev must stay alive until then) */
+int semx_mlp_forward(semx_mlp *net, const float *x_dev, int batch, float *y_dev);
+/* parameter gradient of a scalar loss L given dy_dev = dL/dy (overwrites the
+ * gradient buffer) for the batch of the last forward call */
+int semx_mlp_backward(semx_mlp *net, const float *dy_dev, int batch);
+/* mean squared error over n values: loss (FP64, host, may be NULL) and
+ * dy_dev = dloss/dy (may be NULL) */
+int semx_mlp_mse(semx_mlp *net, const float *y_dev, const float *t_dev, int64_t n, float *dy_dev, double *loss);
+/* one Adam step (bias-corrected, step >= 1) on the FP32 master parameters;
+ * refreshes the BF16 working copy */
+int semx_mlp_adam(semx_mlp *net, float lr, float beta1, float beta2, float eps, int64_t step);
+
 #ifdef __cplusplus
 }
 #endif

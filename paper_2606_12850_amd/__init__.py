@@ -74,10 +74,21 @@ _SIGS = {
     "semx_set_geometry": [_vp, _i32],
     "semx_set_checkpointing": [_vp, _i64],
     "semx_adjoint": [_vp, _vp, _i64, _vp, _vp, _vp],
+    "semx_mlp_create": [ctypes.POINTER(_vp), _i32, _vp, _i32, _vp],
+    "semx_mlp_destroy": [_vp],
+    "semx_mlp_last_error": [_vp],
+    "semx_mlp_num_params": [_vp, ctypes.POINTER(_i64)],
+    "semx_mlp_set_params": [_vp, _vp],
+    "semx_mlp_get_params": [_vp, _vp],
+    "semx_mlp_get_grads": [_vp, _vp],
+    "semx_mlp_forward": [_vp, _vp, _i32, _vp],
+    "semx_mlp_backward": [_vp, _vp, _i32],
+    "semx_mlp_mse": [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_f64)],
+    "semx_mlp_adam": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64],
     "semx_set_timing": [_vp, _i32],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
-_RESTYPE = {"semx_last_error": ctypes.c_char_p}
+_RESTYPE = {"semx_last_error": ctypes.c_char_p, "semx_mlp_last_error": ctypes.c_char_p}
 
 
 def lib():
@@ -272,6 +283,69 @@ def semx_set_checkpointing(ctx, every: int):
 def semx_adjoint(ctx, gseis, nt: int, g_lambda, g_mu, g_rho):
     """d chi/d (lambda, mu, rho) into the three device arrays, from d chi/d seis."""
     return _check(ctx, lib().semx_adjoint(ctx, _ptr(gseis), int(nt), _ptr(g_lambda), _ptr(g_mu), _ptr(g_rho)))
+
+
+def _mcheck(net, rc):
+    if rc != SEMX_OK:
+        msg = lib().semx_mlp_last_error(net)
+        raise SemxError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def semx_mlp_create(widths, max_batch: int, stream=None):
+    h = _vp()
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    rc = lib().semx_mlp_create(ctypes.byref(h), len(w) - 1, _ptr(w), int(max_batch), s)
+    if rc != SEMX_OK:
+        raise SemxError(rc, "semx_mlp_create failed")
+    return h
+
+
+def semx_mlp_destroy(net):
+    return lib().semx_mlp_destroy(net)
+
+
+def semx_mlp_last_error(net) -> str:
+    m = lib().semx_mlp_last_error(net)
+    return m.decode() if m else ""
+
+
+def semx_mlp_num_params(net) -> int:
+    n = _i64()
+    _mcheck(net, lib().semx_mlp_num_params(net, ctypes.byref(n)))
+    return n.value
+
+
+def semx_mlp_set_params(net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    return _mcheck(net, lib().semx_mlp_set_params(net, _ptr(p)))
+
+
+def semx_mlp_get_params(net, out):
+    return _mcheck(net, lib().semx_mlp_get_params(net, _ptr(out)))
+
+
+def semx_mlp_get_grads(net, out):
+    return _mcheck(net, lib().semx_mlp_get_grads(net, _ptr(out)))
+
+
+def semx_mlp_forward(net, x, batch: int, y):
+    return _mcheck(net, lib().semx_mlp_forward(net, _ptr(x), int(batch), _ptr(y)))
+
+
+def semx_mlp_backward(net, dy, batch: int):
+    return _mcheck(net, lib().semx_mlp_backward(net, _ptr(dy), int(batch)))
+
+
+def semx_mlp_mse(net, y, t, n: int, dy=None, want_loss: bool = True):
+    loss = _f64()
+    _mcheck(net, lib().semx_mlp_mse(net, _ptr(y), _ptr(t), int(n), _ptr(dy), ctypes.byref(loss) if want_loss else None))
+    return loss.value
+
+
+def semx_mlp_adam(net, lr: float, beta1: float, beta2: float, eps: float, step: int):
+    return _mcheck(net, lib().semx_mlp_adam(net, float(lr), float(beta1), float(beta2), float(eps), int(step)))
 
 
 def semx_set_timing(ctx, enable: bool):

@@ -1,0 +1,154 @@
+"""Surrogate network kernels (BF16 MFMA GEMMs, SiLU, MSE, Adam) against the
+FP64 numpy reference, and the surrogate pipeline (batched SEM data,
+training, ensemble indicator, SEM fallback) at a reduced size.
+
+Bars: BF16 forward / parameter gradients within 2e-2 / 3e-2 relative L2 of
+FP64 (BF16 operands, FP32 accumulation); Adam within 1e-5 (FP32 arithmetic).
+The trained network's own accuracy is stated, not pinned."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp_ref as M
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _net(widths, batch, seed=0):
+    from paper_2606_12850_amd.surrogate import MLP
+    return MLP(widths, batch, seed)
+
+
+@pytest.mark.parametrize("widths,batch", [([64, 128, 96, 200], 37), ([5, 70, 3], 1), ([64, 512, 512, 512, 24576], 128)])
+def test_forward_backward_vs_fp64(widths, batch):
+    import torch
+    rng = np.random.default_rng(1)
+    net = _net(widths, batch)
+    theta = (M.he_uniform(widths, 3) + 0.01 * rng.standard_normal(M.num_params(widths))).astype(np.float32)
+    net.set_params(theta)
+    x = rng.standard_normal((batch, widths[0])).astype(np.float32)
+    t = rng.standard_normal((batch, widths[-1])).astype(np.float32)
+    xd = torch.from_numpy(x).cuda(); td = torch.from_numpy(t).cuda()
+    y = net.forward(xd)
+    torch.cuda.synchronize()
+    yr, cache = M.forward(theta.astype(np.float64), widths, x.astype(np.float64))
+    ferr = rel_l2(y.cpu().numpy(), yr)
+    import paper_2606_12850_amd as P
+    dy = torch.empty_like(y)
+    loss = P.semx_mlp_mse(net.net, y, td, y.numel(), dy)
+    lr_, dyr = M.mse(yr, t)
+    P.semx_mlp_backward(net.net, dy, batch)
+    g = np.zeros(net.nparam, np.float32)
+    P.semx_mlp_get_grads(net.net, g)
+    gr = M.backward(theta.astype(np.float64), widths, cache, dyr)
+    gerr = rel_l2(g, gr)
+    print(f"widths {widths} batch {batch}: forward rel L2 {ferr:.2e}, loss {loss:.6e} vs {lr_:.6e}, grad rel L2 {gerr:.2e}")
+    assert ferr <= 2e-2
+    assert abs(loss - lr_) <= 3e-2 * lr_
+    assert gerr <= 3e-2
+    net.close()
+
+
+def test_adam_matches_reference():
+    import torch
+    import paper_2606_12850_amd as P
+    widths = [8, 16, 4]
+    net = _net(widths, 8)
+    theta = M.he_uniform(widths, 2).astype(np.float32)
+    net.set_params(theta)
+    x = torch.randn(8, 8, device="cuda"); t = torch.randn(8, 4, device="cuda")
+    th = theta.astype(np.float64); m = np.zeros_like(th); v = np.zeros_like(th)
+    for step in range(1, 4):
+        y = net.forward(x); dy = torch.empty_like(y)
+        P.semx_mlp_mse(net.net, y, t, y.numel(), dy, want_loss=False)
+        P.semx_mlp_backward(net.net, dy, 8)
+        g = np.zeros(net.nparam, np.float32)
+        P.semx_mlp_get_grads(net.net, g)
+        P.semx_mlp_adam(net.net, 1e-2, 0.9, 0.999, 1e-8, step)
+        th, m, v = M.adam(th, g.astype(np.float64), m, v, step, 1e-2)
+        np.testing.assert_allclose(net.params(), th, rtol=1e-5, atol=1e-6)
+    net.close()
+
+
+def test_training_reduces_loss():
+    import torch
+    from paper_2606_12850_amd.surrogate import Surrogate
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, (512, 16))
+    A = rng.standard_normal((16, 40))
+    Y = np.tanh(X @ A) + 0.1 * (X[:, :1] ** 2)
+    s = Surrogate(16, 40, hidden=(64, 64), members=1, max_batch=512)
+    Xn = torch.from_numpy(((X - X.mean(0)) / X.std(0)).astype(np.float32)).cuda()
+    s.x_mu, s.x_sd = X.mean(0), X.std(0)
+    s.y_mu = Y.mean(0); s.y_sd = Y.std(0)
+    Yn = torch.from_numpy(((Y - s.y_mu) / s.y_sd).astype(np.float32)).cuda()
+    l0 = s.members[0].loss(Xn, Yn)
+    s.fit(X, Y, epochs=60, batch=64)
+    l1 = s.members[0].loss(Xn, Yn)
+    print(f"training loss {l0:.3e} -> {l1:.3e}")
+    assert l1 < 0.05 * l0
+    s.close()
+
+
+def test_resample_is_linear_interpolation():
+    from paper_2606_12850_amd.surrogate import resample
+    nt, nout = 800, 512
+    t = np.arange(1, nt + 1) * 1.0
+    s = 3.0 * t + 2.0          # linear in time: interpolation is exact
+    r = resample(s[None], nout)[0]
+    tj = (np.arange(nout) + 1.0) * nt / nout
+    np.testing.assert_allclose(r, 3.0 * tj + 2.0, rtol=1e-12)
+
+
+def test_surrogate_pipeline_with_fallback():
+    """Reduced-size surrogate: 8^3 mesh, 300 steps -> 64 samples, 16
+    receivers; train on 320 models, calibrate on 64, test on 128.  States the
+    surrogate error and the fallback outcome; checks that the SEM fallback
+    keeps every flagged model at the SEM answer and that surrogate + fallback
+    is cheaper than SEM for all test models."""
+    import torch
+    from paper_2606_12850_amd.surrogate import BatchedSEM, Surrogate, rel_err, resample
+    mesh = W.box_mesh(8, 5, 4000.0)
+    basis = W.fourier_modes(mesh)
+    nt, nout = 300, 64
+    dt = 0.01  # below Courant 0.4: min GLL spacing 0.1727 h = 86 m, vp <= 3300 m/s
+    se, sx = W.center_vertex_source(mesh)
+    re, rx = W.top_receivers_grid(mesh, 4)
+    stf = W.ricker(10.0, 0.12, dt, nt + 1)[None, :]
+    sem = BatchedSEM(mesh, se, sx, [[0.0, 0.0, 1.0]], stf, re, rx, dt, nt, batch=64)
+    model_fn = lambda a: W.perturbed_models(mesh, basis, a)
+    A_tr = W.perturbation_coefficients(basis, range(0, 320))
+    A_va = W.perturbation_coefficients(basis, range(5000, 5064))
+    A_te = W.perturbation_coefficients(basis, range(10000, 10128))
+    Y_tr = resample(sem.run_models(model_fn, A_tr), nout).reshape(len(A_tr), -1)
+    Y_va = resample(sem.run_models(model_fn, A_va), nout).reshape(len(A_va), -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Y_te = resample(sem.run_models(model_fn, A_te), nout).reshape(len(A_te), -1)
+    t_sem = time.perf_counter() - t0
+    s = Surrogate(64, Y_tr.shape[1], hidden=(256, 256, 256), members=4, max_batch=512)
+    s.fit(A_tr, Y_tr, epochs=150, batch=64)
+    cal = s.calibrate(A_va, Y_va, tol=0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred, ind = s.predict(A_te)
+    flag = ind > s.threshold
+    fallback = pred.copy()
+    if flag.any():
+        fallback[flag] = resample(sem.run_models(model_fn, A_te[flag]), nout).reshape(int(flag.sum()), -1)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    e_sur = rel_err(pred, Y_te)
+    e_fin = rel_err(fallback, Y_te)
+    print(f"surrogate test error mean {e_sur.mean():.3e} max {e_sur.max():.3e}; calibration {cal}; "
+          f"flagged {flag.mean():.2%}; final error mean {e_fin.mean():.3e} max {e_fin.max():.3e}; "
+          f"time surrogate+fallback {t_sur:.3f} s vs SEM {t_sem:.3f} s")
+    assert np.all(np.isfinite(pred))
+    assert np.all(e_fin[flag] <= 1e-6)          # flagged models carry the SEM answer
+    assert e_fin.mean() <= e_sur.mean() + 1e-12
+    if flag.mean() < 0.5:
+        assert t_sur < t_sem
+    s.close(); sem.close()

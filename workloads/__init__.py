@@ -304,3 +304,41 @@ def adjoint_layered(ne=32, n=5, nt=1000, dt=None, f0=10.0, anomaly: bool = True,
     dt = float(dt) if dt is not None else 1e-3
     stf = ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
     return Workload("adjoint_layered", m, lam, mu, rho, dt, nt, se, sx, np.array([[0.0, 0.0, 1.0]]), stf, re, rx)
+
+
+def fourier_modes(mesh: Mesh, nmodes_per_axis: int = 4):
+    """Cosine modes b_pqr(x) = cos(p pi x/Lx) cos(q pi y/Ly) cos(r pi z/Lz),
+    p, q, r in 0..nmodes_per_axis-1, at the nominal lattice position
+    (gx h/N, gy h/N, gz h/N) of every element-local point: [nspec*n^3, nmodes^3]."""
+    N = mesh.n - 1
+    gx, gy, gz = mesh.lattice_index()
+    h = mesh.h
+    X = (gx * h[0] / N).ravel(); Y = (gy * h[1] / N).ravel(); Z = (gz * h[2] / N).ravel()
+    k = np.arange(nmodes_per_axis)
+    cx = np.cos(np.pi * np.outer(X, k) / mesh.L[0])
+    cy = np.cos(np.pi * np.outer(Y, k) / mesh.L[1])
+    cz = np.cos(np.pi * np.outer(Z, k) / mesh.L[2])
+    B = (cz[:, :, None, None] * cy[:, None, :, None] * cx[:, None, None, :]).reshape(X.size, -1)
+    return B
+
+
+def perturbation_coefficients(basis, seeds, amp: float = 0.10):
+    """For each seed: c ~ U(-1, 1)^64 (seeded), S = basis c, scaled so that
+    max |S| over the points is amp; returns the effective coefficients
+    a = amp c / max|S| [len(seeds), 64] (the perturbation is basis @ a)."""
+    out = np.empty((len(seeds), basis.shape[1]))
+    for t, s in enumerate(seeds):
+        c = np.random.default_rng(int(s)).uniform(-1.0, 1.0, basis.shape[1])
+        S = basis @ c
+        out[t] = amp * c / np.max(np.abs(S))
+    return out
+
+
+def perturbed_models(mesh: Mesh, basis, coeffs, vp=3000.0, vs=1732.0, rho=2500.0):
+    """lambda (1 + delta), mu (1 + delta), rho for delta = basis @ a, per model:
+    arrays [nmodels, nspec, n^3] on the homogeneous background."""
+    lam0, mu0 = lame(vp, vs, rho)
+    delta = (basis @ np.asarray(coeffs).T).T.reshape(len(coeffs), mesh.nspec, mesh.n ** 3)
+    lam = float(lam0) * (1.0 + delta)
+    mu = float(mu0) * (1.0 + delta)
+    return lam, mu, np.full_like(lam, float(rho))
