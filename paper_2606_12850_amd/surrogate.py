@@ -158,10 +158,19 @@ class Surrogate:
 
     def fit(self, X, Y, epochs: int = 300, batch: int = 128, lr0: float = 1e-3, lr1: float = 1e-5, seed: int = 0,
             log=None):
-        """X [S, n_in], Y [S, n_out] (host arrays)."""
+        """X [S, n_in]; Y [S, nrec, ncomp, nt] seismograms (targets normalised
+        by the training-set mean per sample and the std per (receiver,
+        component) over models and time, so quiet samples are not
+        amplified) or Y [S, n_out] (std per output)."""
         self.x_mu, self.x_sd = X.mean(0), X.std(0) + 1e-12
+        if Y.ndim == 4:
+            sd = Y.std(axis=(0, 3), keepdims=True)[0]  # [nrec, ncomp, 1]
+            sd = np.broadcast_to(sd + 1e-30 + 1e-6 * sd.max(), Y.shape[1:]).reshape(-1)
+            Y = Y.reshape(Y.shape[0], -1)
+        else:
+            sd = Y.std(0) + 1e-30
         self.y_mu = Y.mean(0)
-        self.y_sd = Y.reshape(Y.shape[0], -1).std(0) + 1e-30
+        self.y_sd = sd
         Xn = torch.from_numpy(((X - self.x_mu) / self.x_sd).astype(np.float32)).to(self.device)
         Yn = torch.from_numpy(((Y - self.y_mu) / self.y_sd).astype(np.float32)).to(self.device)
         S = X.shape[0]
