@@ -149,6 +149,10 @@ def main():
     ap.add_argument("--geometry", choices=["stored", "trilinear"], default="trilinear")
     ap.add_argument("--assembly", choices=["colored", "atomic"], default="colored")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--profile-force", action="store_true",
+                    help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
+                         "device copy (calibration for HBM traffic counters); prints one JSON line")
+    ap.add_argument("--contraction", choices=["f32", "bf16", "f16"], default="f32")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
@@ -162,6 +166,9 @@ def main():
     import paper_2606_12850_amd as P
     import workloads as W
 
+    GEOM = {"stored": P.SEMX_GEOM_STORED, "trilinear": P.SEMX_GEOM_TRILINEAR}
+    CONTRACTION = {"f32": P.SEMX_C_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}
+    ASSEMBLY = {"colored": P.SEMX_ASM_COLORED, "atomic": P.SEMX_ASM_ATOMIC}
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
     nt_total = args.warmup + args.steps
@@ -183,16 +190,19 @@ def main():
     geo_of = (lambda g: g if info["nirregular"] > 0 else "regular")
     b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry))
 
-    # ---- force apply alone (coloured and atomic), event-timed on the library stream
+    # ---- force apply alone (FP32 and mixed contractions, coloured and atomic),
+    #      event-timed on the library stream
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
+    combos = [(c, g, a) for c in ("f32", "bf16", "f16") for g in ("stored", "trilinear")
+              for a in ("colored", "atomic") if c == "f32" or a == "colored"]
+    if args.profile_force:
+        combos = [(args.contraction, args.geometry, args.assembly)]
     apply = {}
-    for gname, gmode in (("stored", P.SEMX_GEOM_STORED), ("trilinear", P.SEMX_GEOM_TRILINEAR)):
-      P.semx_set_geometry(s.ctx, gmode)
-      bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
-      for aname, mode in (("colored", P.SEMX_ASM_COLORED), ("atomic", P.SEMX_ASM_ATOMIC)):
-        name = f"{gname}_{aname}"
-        P.semx_set_mode(s.ctx, P.SEMX_C_F32, mode)
+    for cname, gname, aname in combos:
+        P.semx_set_geometry(s.ctx, GEOM[gname])
+        P.semx_set_mode(s.ctx, CONTRACTION[cname], ASSEMBLY[aname])
+        bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
         for _ in range(5):
             P.semx_apply_force(s.ctx, u, f)
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
@@ -202,11 +212,23 @@ def main():
         e1.record(stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / args.apply_reps
-        apply[name] = {"ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3),
-                       "bytes_per_element": bg,
-                       "hbm_frac_alg": (bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)}
+        apply[f"{cname}_{gname}_{aname}"] = {
+            "ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3), "bytes_per_element": bg,
+            "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
+    if args.profile_force:
+        # calibration for the traffic counters: a plain device copy of known size
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 4, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_force": apply, "elements": E, "copy_bytes_each_way": nbytes,
+                          "force_launches_per_apply": info["ncolors"] if args.assembly == "colored" else 1}))
+        s.close()
+        return
     P.semx_set_mode(s.ctx, P.SEMX_C_F32, asm)
-    P.semx_set_geometry(s.ctx, P.SEMX_GEOM_TRILINEAR if args.geometry == "trilinear" else P.SEMX_GEOM_STORED)
+    P.semx_set_geometry(s.ctx, GEOM[args.geometry])
 
     # ---- time loop: warmup, then exactly `steps` timed steps
     P.semx_reset(s.ctx)
