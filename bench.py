@@ -43,6 +43,17 @@ def bytes_per_element(n: int, nglob: int, nspec: int, geometry: str = "stored") 
     return 4 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
 
 
+def bytes_per_element_patch(n: int, nglob: int, nspec: int, geometry: str, pinfo: dict) -> float:
+    """As bytes_per_element for the patch kernel: the 4 n^3 node numbers are
+    replaced by 2 n^3 patch-local indices, one position per element, two
+    offsets per patch and one 8-byte run descriptor per run of consecutive
+    node numbers."""
+    n3 = n ** 3
+    geo = {"stored": 36 * n3, "trilinear": 96, "regular": 36}[geometry]
+    meta = 4 * nspec + 8 * pinfo["npatch"] + 8 * pinfo["nruns"]
+    return 2 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec + meta / nspec
+
+
 def traffic_from_profiles(src_hash: str):
     """HBM bytes per launch measured with rocprofv3 PMC counters, if they were
     taken on the current force kernel source."""
@@ -153,6 +164,8 @@ def main():
                     help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
                          "device copy (calibration for HBM traffic counters); prints one JSON line")
     ap.add_argument("--contraction", choices=["f32", "bf16", "f16"], default="f32")
+    ap.add_argument("--patches", type=int, default=0,
+                    help="chain length of the FP32 patch kernel (0 = per-element kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
@@ -180,6 +193,7 @@ def main():
     s.upload_model(wl.lam, wl.mu, wl.rho)
     asm = P.SEMX_ASM_COLORED if args.assembly == "colored" else P.SEMX_ASM_ATOMIC
     s.set_mode(P.SEMX_C_F32, asm)
+    P.semx_set_patches(s.ctx, args.patches)
     dt = P.semx_cfl_dt(s.ctx, 0.4)
     wl.dt = dt
     wl.stf = W.ricker(10.0, 0.12, dt, nt_total + 1)[None, :]
@@ -189,17 +203,22 @@ def main():
     E, n3 = mesh.nspec, NGLL ** 3
     geo_of = (lambda g: g if info["nirregular"] > 0 else "regular")
     b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry))
+    if args.patches:
+        P.semx_set_patches(s.ctx, args.patches)
+        b_elem = bytes_per_element_patch(NGLL, mesh.nglob, E, geo_of(args.geometry), P.semx_patch_info(s.ctx))
 
     # ---- force apply alone (FP32 and mixed contractions, coloured and atomic),
     #      event-timed on the library stream
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
-    combos = [(c, g, a) for c in ("f32", "bf16", "f16") for g in ("stored", "trilinear")
+    combos = [(c, g, a, args.patches) for c in ("f32", "bf16", "f16") for g in ("stored", "trilinear")
               for a in ("colored", "atomic") if c == "f32" or a == "colored"]
+    combos += [("f32", g, a, 8) for g in ("stored", "trilinear") for a in ("colored", "atomic")]
     if args.profile_force:
-        combos = [(args.contraction, args.geometry, args.assembly)]
+        combos = [(args.contraction, args.geometry, args.assembly, args.patches)]
     apply = {}
-    for cname, gname, aname in combos:
+    for cname, gname, aname, npt in combos:
+        P.semx_set_patches(s.ctx, npt)
         P.semx_set_geometry(s.ctx, GEOM[gname])
         P.semx_set_mode(s.ctx, CONTRACTION[cname], ASSEMBLY[aname])
         bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
@@ -212,7 +231,7 @@ def main():
         e1.record(stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / args.apply_reps
-        apply[f"{cname}_{gname}_{aname}"] = {
+        apply[f"{cname}_{gname}_{aname}" + (f"_patch{npt}" if npt else "")] = {
             "ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3), "bytes_per_element": bg,
             "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
     if args.profile_force:
@@ -227,6 +246,7 @@ def main():
                           "force_launches_per_apply": info["ncolors"] if args.assembly == "colored" else 1}))
         s.close()
         return
+    P.semx_set_patches(s.ctx, args.patches)
     P.semx_set_mode(s.ctx, P.SEMX_C_F32, asm)
     P.semx_set_geometry(s.ctx, GEOM[args.geometry])
 
@@ -279,7 +299,8 @@ def main():
                    "nregular": info["nregular"], "nirregular": info["nirregular"], "ncolors": info["ncolors"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"force_f32_kernel<5, {args.geometry}, {args.assembly}>",
+                     "kernel": (f"force_patch_kernel<5, {args.geometry}, {args.assembly}>, chains of {args.patches}"
+                                if args.patches else f"force_f32_kernel<5, {args.geometry}, {args.assembly}>"),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
                      "launches": launches, "bytes_per_element": b_elem},
         "force_apply": apply,

@@ -127,6 +127,27 @@ int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 #define SEMX_GEOM_TRILINEAR 1
 int semx_set_geometry(semx_ctx *ctx, int mode);
 
+/* Element patches of the FP32 force (assembly of Sec. IV-C, done per group
+ * of elements).  Elements are grouped, in element order, into chains of at
+ * most max_elems elements (values above 8 act as 8) that share nodes and
+ * hold at most 1024 unique nodes together; one workgroup computes a chain, sums the forces of its
+ * shared nodes on chip and writes each of its nodes once.  Chains are
+ * coloured so that chains of one colour share no node (coloured assembly:
+ * one launch per colour, the first chain to reach a node stores it, later
+ * ones add to it); with atomic assembly all chains run in one launch and
+ * nodes shared between chains take atomic adds.  max_elems = 0 selects the
+ * per-element kernels (the default).  Rebuilds the layout if a mesh is loaded
+ * (NGLL up to 9; otherwise, or when the chains would need more than 64
+ * colours, the per-element kernels are used).  The BF16/FP16 paths always
+ * run per element.  SEMX_EINVAL if max_elems < 0. */
+int semx_set_patches(semx_ctx *ctx, int max_elems);
+
+/* Patch layout in use: number of chains, colours, runs of consecutive node
+ * numbers, the summed unique-node count over chains, and the largest chain's
+ * unique-node count.  All zero when the per-element kernels are in use. */
+int semx_patch_info(semx_ctx *ctx, int64_t *npatch, int *ncolors, int64_t *nruns, int64_t *nodes_total,
+                    int *max_nodes);
+
 /* f = -K u for every model: u_dev, f_dev device FP32 [nmodels][nglob][3].
  * f_dev is overwritten (not accumulated).  u_dev and f_dev must not overlap. */
 int semx_apply_force(semx_ctx *ctx, const float *u_dev, float *f_dev);

@@ -234,10 +234,11 @@ __global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
 // Explicit Newmark (beta = 0, gamma = 1/2) update, one thread per global node
 // and model.  mode bit 1 (kCorrect): acc = M^{-1} f, v += dt/2 acc, and acc
 // is stored to a if kStoreA; without it acc is read from a.  Bit 2
-// (kPredict): u += dt v + dt^2/2 acc, v += dt/2 acc, f = 0.  A step is
-// "correct then predict" in one pass, so a never has to be written.
+// (kPredict): u += dt v + dt^2/2 acc, v += dt/2 acc, f = 0 unless kKeepF
+// (the coming force pass overwrites every node).  A step is "correct then
+// predict" in one pass, so a never has to be written.
 // ---------------------------------------------------------------------------
-constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4;
+constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8;
 
 template <int MODE>
 __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
@@ -257,7 +258,7 @@ __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const fl
     if constexpr ((MODE & kPredict) != 0) {
       u[t] = u[t] + dt * vv + hdt2 * acc;
       vv = vv + hdt * acc;
-      f[t] = 0.0f;
+      if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0f;
     }
     v[t] = vv;
   }
@@ -448,6 +449,230 @@ bool coloring_valid(int n3, int64_t nspec, int64_t nglob, const int32_t* ibool, 
   return true;
 }
 
+// Element patches for the FP32 force kernel.  Chains are grown in element
+// order: an element joins the open chain when it has the same geometry kind,
+// shares at least one node with it, the chain is shorter than patch_cmax and
+// the union of nodes stays within kPatchMaxNodes.  Chains are coloured
+// greedily (first fit, chain order; two chains conflict when they share a
+// node) and laid out by (kind, colour, chain).  Each chain's sorted unique
+// nodes are stored as runs of consecutive global indices; a run is also cut
+// where the first-touch flag (first patch to touch the node in coloured
+// execution order: colour-major, regular before irregular) or the exclusive
+// flag (node touched by this patch only) changes.  Leaves patches_ok false
+// (per-element kernels) when the order, the colour count or the LDS budget
+// rules patches out.
+int build_patches(semx_ctx* c) {
+  for (DevBuf* b : {&c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs}) dev_free(*b);
+  c->patch_colored.clear();
+  c->patch_atomic.clear();
+  c->patches_ok = false;
+  c->patch_cover = false;
+  c->npatch = c->npatch_runs = c->patch_nodes_total = 0;
+  c->patch_maxnodes = c->patch_maxruns = c->npatch_colors = 0;
+  const int n3 = c->n3;
+  const int64_t E = c->nspec, G = c->nglob;
+  if (c->patch_cmax <= 0 || n3 > kPatchMaxNodes || patch_lds_bytes(c->n, n3, 1) > (size_t)kPatchLdsLimit)
+    return SEMX_OK;
+  const int32_t* ib = c->h_ibool.data();
+
+  // 1. chains
+  std::vector<int32_t> celem;
+  celem.reserve(E);
+  std::vector<int64_t> cptr{0};
+  std::vector<int32_t> mark(G, -1), emark(G, -1);
+  int64_t cur_nodes = 0;
+  int cur_kind = -1;
+  for (int64_t e = 0; e < E; ++e) {
+    const int kind = c->h_regular[e] ? 0 : 1;
+    const int32_t cid = (int32_t)(cptr.size() - 1);
+    const int64_t len = (int64_t)celem.size() - cptr.back();
+    int shared = 0, add = 0;
+    for (int q = 0; q < n3; ++q) {
+      const int32_t g = ib[e * n3 + q];
+      if (mark[g] == cid) ++shared;
+      else if (emark[g] != (int32_t)e) { emark[g] = (int32_t)e; ++add; }
+    }
+    const bool join = len > 0 && kind == cur_kind && len < std::min(c->patch_cmax, kPatchMaxElems) && shared > 0 &&
+                      cur_nodes + add <= kPatchMaxNodes;
+    if (!join) {
+      if (len > 0) cptr.push_back((int64_t)celem.size());
+      cur_nodes = 0;
+      cur_kind = kind;
+      add = 0;
+      const int32_t nid = (int32_t)(cptr.size() - 1);
+      for (int q = 0; q < n3; ++q) {
+        const int32_t g = ib[e * n3 + q];
+        if (mark[g] != nid) { mark[g] = nid; ++add; }
+      }
+    } else {
+      for (int q = 0; q < n3; ++q) mark[ib[e * n3 + q]] = cid;
+    }
+    cur_nodes += add;
+    celem.push_back((int32_t)e);
+  }
+  cptr.push_back((int64_t)celem.size());
+  const int64_t P = (int64_t)cptr.size() - 1;
+
+  // 2. sorted unique nodes per chain
+  std::vector<int64_t> nptr(P + 1, 0);
+  std::vector<int32_t> pnodes;
+  pnodes.reserve((size_t)E * n3);
+  std::fill(mark.begin(), mark.end(), -1);
+  for (int64_t p = 0; p < P; ++p) {
+    const size_t b = pnodes.size();
+    for (int64_t t = cptr[p]; t < cptr[p + 1]; ++t)
+      for (int q = 0; q < n3; ++q) {
+        const int32_t g = ib[(int64_t)celem[t] * n3 + q];
+        if (mark[g] != (int32_t)p) { mark[g] = (int32_t)p; pnodes.push_back(g); }
+      }
+    std::sort(pnodes.begin() + b, pnodes.end());
+    nptr[p + 1] = (int64_t)pnodes.size();
+  }
+
+  // 3. greedy colouring of chains (at most 64 colours)
+  std::vector<uint64_t> cmask(G, 0);
+  std::vector<int> pcol(P);
+  int ncol = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    uint64_t forb = 0;
+    for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) forb |= cmask[pnodes[t]];
+    if (forb == ~0ull) return SEMX_OK;  // too many colours: per-element kernels
+    int col = 0;
+    while (forb & (1ull << col)) ++col;
+    pcol[p] = col;
+    ncol = std::max(ncol, col + 1);
+    for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) cmask[pnodes[t]] |= 1ull << col;
+  }
+  std::vector<uint64_t>().swap(cmask);
+
+  // 4. layout order (kind, colour, chain); launches
+  auto kind_of = [&](int64_t p) { return c->h_regular[celem[cptr[p]]] ? 0 : 1; };
+  std::vector<int64_t> porder(P);
+  for (int64_t p = 0; p < P; ++p) porder[p] = p;
+  std::stable_sort(porder.begin(), porder.end(), [&](int64_t x, int64_t y) {
+    const int kx = kind_of(x), ky = kind_of(y);
+    if (kx != ky) return kx < ky;
+    return pcol[x] < pcol[y];
+  });
+  struct Rng { int64_t beg = 0, cnt = 0; };
+  std::vector<Rng> rng(2 * (size_t)ncol);
+  for (int64_t s = 0; s < P; ++s) {
+    Rng& r = rng[(size_t)kind_of(porder[s]) * ncol + pcol[porder[s]]];
+    if (r.cnt == 0) r.beg = s;
+    ++r.cnt;
+  }
+  for (int k = 0; k < ncol; ++k)
+    for (int kind = 0; kind < 2; ++kind) {
+      const Rng& r = rng[(size_t)kind * ncol + k];
+      if (r.cnt) c->patch_colored.push_back({r.beg, r.cnt, kind == 1});
+    }
+  for (int kind = 0; kind < 2; ++kind) {
+    int64_t beg = -1, end = -1;
+    for (int k = 0; k < ncol; ++k) {
+      const Rng& r = rng[(size_t)kind * ncol + k];
+      if (!r.cnt) continue;
+      if (beg < 0) beg = r.beg;
+      end = r.beg + r.cnt;
+    }
+    if (beg >= 0) c->patch_atomic.push_back({beg, end - beg, kind == 1});
+  }
+
+  // 5. first-touch (coloured execution order) and exclusive flags per patch node
+  std::vector<uint8_t> touch(G, 0), pflag(pnodes.size(), 0);
+  for (const Launch& L : c->patch_colored)
+    for (int64_t s = L.pos0; s < L.pos0 + L.count; ++s) {
+      const int64_t p = porder[s];
+      for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) {
+        uint8_t& tc = touch[pnodes[t]];
+        if (tc == 0) pflag[t] = 1;
+        if (tc < 2) ++tc;
+      }
+    }
+  bool cover = true;
+  for (int64_t g = 0; g < G && cover; ++g) cover = touch[g] > 0;
+
+  // 6. device arrays in layout order
+  std::vector<int32_t> pos_of(E);
+  for (int64_t pos = 0; pos < E; ++pos) pos_of[c->h_order[pos]] = (int32_t)pos;
+  std::vector<int32_t> pe_pos(E), pe_off(P + 1), pr_off(P + 1), runs;
+  std::vector<uint16_t> lidx((size_t)E * n3);
+  std::vector<int32_t> loc(G, -1);
+  int64_t slot = 0;
+  int maxnodes = 0, maxruns = 0;
+  for (int64_t s = 0; s < P; ++s) {
+    const int64_t p = porder[s];
+    pe_off[s] = (int32_t)slot;
+    pr_off[s] = (int32_t)(runs.size() / 2);
+    const int64_t nb = nptr[p], nn = nptr[p + 1] - nb;
+    maxnodes = std::max(maxnodes, (int)nn);
+    for (int64_t t = 0; t < nn; ++t) loc[pnodes[nb + t]] = (int32_t)t;
+    for (int64_t t = cptr[p]; t < cptr[p + 1]; ++t, ++slot) {
+      const int64_t e = celem[t];
+      pe_pos[slot] = pos_of[e];
+      for (int q = 0; q < n3; ++q) lidx[(size_t)slot * n3 + q] = (uint16_t)loc[ib[e * n3 + q]];
+    }
+    int nr = 0;
+    int64_t t = 0;
+    while (t < nn) {
+      const int32_t g0 = pnodes[nb + t];
+      const int fl = (pflag[nb + t] ? kRunFirst : 0) | (touch[g0] == 1 ? kRunExclusive : 0);
+      int64_t l = 1;
+      while (t + l < nn && l < (1 << kRunLenBits) - 1 && pnodes[nb + t + l] == g0 + l &&
+             ((pflag[nb + t + l] ? kRunFirst : 0) | (touch[g0 + l] == 1 ? kRunExclusive : 0)) == fl)
+        ++l;
+      runs.push_back(g0);
+      runs.push_back((int32_t)l | ((int32_t)t << kRunLenBits) | fl);
+      ++nr;
+      t += l;
+    }
+    maxruns = std::max(maxruns, nr);
+  }
+  pe_off[P] = (int32_t)slot;
+  pr_off[P] = (int32_t)(runs.size() / 2);
+  // invariants the kernel's addressing relies on
+  if (slot != E) return fail(c, SEMX_EINVAL, "patch layout: element count");
+  for (int64_t s = 0; s < P; ++s) {
+    const int64_t rb = pr_off[s], re = pr_off[s + 1];
+    if (pe_off[s + 1] <= pe_off[s] || re <= rb) return fail(c, SEMX_EINVAL, "patch layout: empty patch");
+    int64_t off = 0;
+    for (int64_t r = rb; r < re; ++r) {
+      const int32_t d = runs[2 * r + 1];
+      const int64_t len = d & ((1 << kRunLenBits) - 1), o = (d >> kRunLenBits) & ((1 << kRunLenBits) - 1);
+      if (len < 1 || o != off || runs[2 * r] < 0 || runs[2 * r] + len > G)
+        return fail(c, SEMX_EINVAL, "patch layout: bad run");
+      off += len;
+    }
+    if (off > maxnodes || off > kPatchMaxNodes) return fail(c, SEMX_EINVAL, "patch layout: node count");
+    for (int64_t t = (int64_t)pe_off[s] * n3; t < (int64_t)pe_off[s + 1] * n3; ++t)
+      if (lidx[t] >= off) return fail(c, SEMX_EINVAL, "patch layout: local index");
+  }
+  if (patch_lds_bytes(c->n, maxnodes, maxruns) > (size_t)kPatchLdsLimit) {
+    c->patch_colored.clear();
+    c->patch_atomic.clear();
+    return SEMX_OK;
+  }
+  int rc = dev_alloc(c, c->d_pe_pos, sizeof(int32_t) * E);
+  if (!rc) rc = dev_alloc(c, c->d_pe_off, sizeof(int32_t) * (P + 1));
+  if (!rc) rc = dev_alloc(c, c->d_lidx, sizeof(uint16_t) * E * n3);
+  if (!rc) rc = dev_alloc(c, c->d_pr_off, sizeof(int32_t) * (P + 1));
+  if (!rc) rc = dev_alloc(c, c->d_runs, sizeof(int32_t) * runs.size());
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->d_pe_pos.p, pe_pos.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_pe_off.p, pe_off.data(), sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_lidx.p, lidx.data(), sizeof(uint16_t) * E * n3, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_pr_off.p, pr_off.data(), sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_runs.p, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice));
+  c->npatch = P;
+  c->npatch_runs = (int64_t)runs.size() / 2;
+  c->patch_nodes_total = (int64_t)pnodes.size();
+  c->patch_maxnodes = maxnodes;
+  c->patch_maxruns = maxruns;
+  c->npatch_colors = ncol;
+  c->patch_cover = cover;
+  c->patches_ok = true;
+  return SEMX_OK;
+}
+
 // Launch-ordered layout: every per-element array on the device is stored by
 // launch position, positions sorted by (geometry kind, colour, element), so
 // that each launch (one colour of one kind, or one kind for atomic assembly)
@@ -533,7 +758,7 @@ int build_layout(semx_ctx* c) {
   SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SEMX_HIP(c, hipStreamSynchronize(c->stream));
   if (hbad) return fail(c, SEMX_EGEOM, "upload_mesh: det J <= 0 at some GLL point");
-  return SEMX_OK;
+  return build_patches(c);
 }
 
 // f = -K u accumulated into f (f must already hold zeros or earlier sums).
@@ -588,6 +813,70 @@ int zero_f32(semx_ctx* c, float* p, int64_t n) {
 }
 
 int64_t state_len(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * 3; }
+
+// The FP32 force runs on element patches when they are built.
+bool use_patches(const semx_ctx* c) { return c->patches_ok && c->contraction == SEMX_C_F32; }
+
+// True when the force pass writes every node itself (coloured patches with
+// first-touch stores over a mesh whose nodes all belong to some element), so
+// f needs no clearing before it.
+bool force_overwrites(const semx_ctx* c) {
+  return use_patches(c) && c->assembly == SEMX_ASM_COLORED && c->patch_cover;
+}
+
+int force_patches(semx_ctx* c, const float* u, float* f) {
+  PatchArgs pa{};
+  ForceArgs& a = pa.fa;
+  a.gam_pt = c->d_gam_pt.as<float>();
+  a.gam_el = c->d_gam_el.as<float>();
+  a.tri = c->d_tri.as<float>();
+  a.xi = c->d_xi32.as<float>();
+  a.mat = c->d_mat.as<float>();
+  a.u = u;
+  a.f = f;
+  a.D = c->d_D.as<float>();
+  a.nspec = c->nspec;
+  a.nglob = c->nglob;
+  a.nmodels = c->nmodels;
+  pa.pe_pos = c->d_pe_pos.as<int32_t>();
+  pa.pe_off = c->d_pe_off.as<int32_t>();
+  pa.lidx = c->d_lidx.as<uint16_t>();
+  pa.pr_off = c->d_pr_off.as<int32_t>();
+  pa.runs = c->d_runs.as<int32_t>();
+  pa.maxnodes = c->patch_maxnodes;
+  pa.maxruns = c->patch_maxruns;
+  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
+  for (const auto& L : atomic ? c->patch_atomic : c->patch_colored) {
+    a.pos0 = L.pos0;
+    a.count = L.count;
+    hipEvent_t e1 = nullptr;
+    if (c->timing) {
+      while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t ev;
+        SEMX_HIP(c, hipEventCreate(&ev));
+        c->ev_pool.push_back(ev);
+      }
+      SEMX_HIP(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
+      e1 = c->ev_pool[c->ev_used + 1];
+      c->ev_used += 2;
+    }
+    const int geo = L.irregular ? c->irregular_geo : kRegular;
+    hipError_t e = launch_force_patch(c->n, geo, atomic, pa, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "patch force kernel launch");
+    if (e1) SEMX_HIP(c, hipEventRecord(e1, c->stream));
+  }
+  return SEMX_OK;
+}
+
+// f = -K u.  `f_zeroed`: f already holds zeros.
+int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
+  if (!f_zeroed && !force_overwrites(c)) {
+    int rc = zero_f32(c, f, state_len(c));
+    if (rc) return rc;
+  }
+  return use_patches(c) ? force_patches(c, u, f) : force_accumulate(c, u, f);
+}
+
 
 int inject_sources(semx_ctx* c, int64_t m, float* f) {
   if (c->src.nsrc == 0) return SEMX_OK;
@@ -657,8 +946,7 @@ int energy_model0(semx_ctx* c, double* kin, double* pot) {
   SEMX_HIP(c, hipGetLastError());
   // potential: 1/2 u^T K u = -1/2 u . f(u), f(u) computed into the work vector
   DevBuf& tmp = c->d_work;
-  rc = zero_f32(c, tmp.as<float>(), state_len(c));
-  if (!rc) rc = force_accumulate(c, c->d_u.as<float>(), tmp.as<float>());
+  rc = force_into(c, c->d_u.as<float>(), tmp.as<float>(), false);
   if (!rc) {
     dot_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(n3g, c->d_u.as<float>(), tmp.as<float>(),
                                                                scratch_d(c) + 1);
@@ -701,12 +989,17 @@ int step_once(semx_ctx* c, bool record) {
   const float dt = (float)c->dt;
   float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
   const float* minv = c->d_minv.as<float>();
-  if (c->pending_correct)
-    newmark_kernel<kCorrect | kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
-  else
-    newmark_kernel<kPredict><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+  const bool keep = force_overwrites(c);
+  const unsigned gb = grid_for(3 * nn);
+  if (c->pending_correct) {
+    if (keep) newmark_kernel<kCorrect | kPredict | kKeepF><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+    else newmark_kernel<kCorrect | kPredict><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+  } else {
+    if (keep) newmark_kernel<kPredict | kKeepF><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+    else newmark_kernel<kPredict><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+  }
   SEMX_HIP(c, hipGetLastError());
-  int rc = force_accumulate(c, u, f);
+  int rc = force_into(c, u, f, !keep);
   if (!rc) rc = inject_sources(c, c->it + 1, f);
   if (!rc && record) rc = record_receivers(c, c->it);
   if (rc) return rc;
@@ -778,7 +1071,8 @@ int semx_destroy(semx_ctx* c) {
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
-                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis})
+                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis,
+                    &c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs})
     dev_free(*b);
   delete c;
   return SEMX_OK;
@@ -1048,9 +1342,7 @@ int semx_apply_force(semx_ctx* c, const float* u_dev, float* f_dev) {
   if (!u_dev || !f_dev) return fail(c, SEMX_EINVAL, "apply_force: null pointer");
   const int64_t len = state_len(c);
   if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "apply_force: u and f overlap");
-  int rc = zero_f32(c, f_dev, len);
-  if (rc) return rc;
-  return force_accumulate(c, u_dev, f_dev);
+  return force_into(c, u_dev, f_dev, false);
 }
 
 int semx_set_dt(semx_ctx* c, double dt) {
@@ -1093,8 +1385,7 @@ int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
   if (e != hipSuccess) { dev_free(x); dev_free(y); return hip_fail(c, e, "power iteration init"); }
   double lam = 0.0;
   for (int k = 0; k < iters && !rc; ++k) {
-    rc = zero_f32(c, y.as<float>(), n3g * saved_models);
-    if (!rc) rc = force_accumulate(c, x.as<float>(), y.as<float>());  // y = -K x
+    rc = force_into(c, x.as<float>(), y.as<float>(), false);  // y = -K x
     if (rc) break;
     fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
     // Rayleigh quotient lam = (x^T K x)/(x^T M x) = -(x.y)/(x^T M x)
@@ -1307,6 +1598,26 @@ int semx_set_geometry(semx_ctx* c, int mode) {
   if (mode == SEMX_GEOM_STORED) c->irregular_geo = kStored;
   else if (mode == SEMX_GEOM_TRILINEAR) c->irregular_geo = kTrilinear;
   else return fail(c, SEMX_EINVAL, "set_geometry: unknown mode");
+  return SEMX_OK;
+}
+
+int semx_set_patches(semx_ctx* c, int max_elems) {
+  if (!c) return SEMX_EINVAL;
+  if (max_elems < 0) return fail(c, SEMX_EINVAL, "set_patches: max_elems must be >= 0");
+  c->patch_cmax = max_elems;
+  if (!c->have_mesh) return SEMX_OK;
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  return build_patches(c);
+}
+
+int semx_patch_info(semx_ctx* c, int64_t* npatch, int* ncolors, int64_t* nruns, int64_t* nodes_total,
+                    int* max_nodes) {
+  if (!c || !npatch || !ncolors || !nruns || !nodes_total || !max_nodes) return SEMX_EINVAL;
+  *npatch = c->patches_ok ? c->npatch : 0;
+  *ncolors = c->patches_ok ? c->npatch_colors : 0;
+  *nruns = c->patches_ok ? c->npatch_runs : 0;
+  *nodes_total = c->patches_ok ? c->patch_nodes_total : 0;
+  *max_nodes = c->patches_ok ? c->patch_maxnodes : 0;
   return SEMX_OK;
 }
 

@@ -60,26 +60,26 @@ __device__ __forceinline__ void ref_div(const float* s_q, const float* s_D, int 
 // transposed cofactor matrix of J (kTrilinear, J^{-1} = C^T / det J); the
 // physical gradient is g = du Mg / det' with det' = 1 (Gamma) or det J, and
 // `scale` = 1/det'^2 restores the flux weighting on the trilinear path.
-// `det` returns det J on the trilinear path (else 0).
+// `det` returns det J on the trilinear path (else 0).  `src` holds the
+// element's Gamma (kRegular, 9 floats) or trilinear coefficients
+// (kTrilinear, 24 floats: c0..c7 of x, y, z); `G` the point's Gamma (kStored).
 template <int GEO>
-__device__ __forceinline__ void geom_map(const ForceArgs& a, int pos, const float* G, float rx, float ry,
-                                         float rz, float Mg[9], float& scale, float& det) {
+__device__ __forceinline__ void geom_map_from(const float* src, const float* G, float rx, float ry, float rz,
+                                              float Mg[9], float& scale, float& det) {
   scale = 1.0f;
   det = 0.0f;
   if constexpr (GEO == kStored) {
 #pragma unroll
     for (int d = 0; d < 9; ++d) Mg[d] = G[d];
   } else if constexpr (GEO == kRegular) {
-    const float* ge = a.gam_el + (size_t)pos * 9;
 #pragma unroll
-    for (int d = 0; d < 9; ++d) Mg[d] = ge[d];
+    for (int d = 0; d < 9; ++d) Mg[d] = src[d];
   } else {
     // x_a(r) = c0 + c1 rx + c2 ry + c3 rz + c4 rx ry + c5 rx rz + c6 ry rz + c7 rx ry rz
-    const float* cf = a.tri + (size_t)pos * 24;
     float J[3][3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const float* c = cf + 8 * ax;
+      const float* c = src + 8 * ax;
       J[ax][0] = c[1] + c[4] * ry + c[5] * rz + c[7] * (ry * rz);
       J[ax][1] = c[2] + c[4] * rx + c[6] * rz + c[7] * (rx * rz);
       J[ax][2] = c[3] + c[5] * rx + c[6] * ry + c[7] * (rx * ry);
@@ -100,6 +100,16 @@ __device__ __forceinline__ void geom_map(const ForceArgs& a, int pos, const floa
     const float id = 1.0f / det;
     scale = id * id;
   }
+}
+
+// geom_map_from with the element's data read from the per-position arrays.
+template <int GEO>
+__device__ __forceinline__ void geom_map(const ForceArgs& a, int pos, const float* G, float rx, float ry,
+                                         float rz, float Mg[9], float& scale, float& det) {
+  const float* src = nullptr;
+  if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
+  if constexpr (GEO == kTrilinear) src = a.tri + (size_t)pos * 24;
+  geom_map_from<GEO>(src, G, rx, ry, rz, Mg, scale, det);
 }
 
 // gr[c][b] = sum_d du[c][d] Mg[d][b]

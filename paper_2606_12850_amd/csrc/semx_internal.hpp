@@ -19,6 +19,17 @@ constexpr int kRegular = 0;    // affine element: one Gamma per element
 constexpr int kStored = 1;     // per-point Gamma streamed from memory
 constexpr int kTrilinear = 2;  // J rebuilt per point from the trilinear map coefficients
 
+// element patches (chains of elements assembled in LDS, one workgroup each)
+constexpr int kPatchMaxNodes = 1024;   // unique global nodes per patch
+constexpr int kPatchDefaultElems = 0;  // default: per-element kernels
+constexpr int kPatchMaxElems = 8;      // longest chain the patch kernel holds
+constexpr int kPatchLdsLimit = 64 * 1024;
+// run descriptor word: bits 0-10 run length, 11-21 first patch-local node,
+// bit 29 node touched by this patch only, bit 30 first touch in colour order
+constexpr int kRunLenBits = 11;
+constexpr int kRunExclusive = 1 << 29;
+constexpr int kRunFirst = 1 << 30;
+
 // Device buffer owned by the library.
 struct DevBuf {
   void* p = nullptr;
@@ -98,6 +109,22 @@ struct semx_ctx {
   std::vector<semx::Launch> colored_launches;  // per colour: regular then irregular
   std::vector<semx::Launch> atomic_launches;   // regular list, irregular list
 
+  // element patches for the FP32 force kernel: chains of up to patch_cmax
+  // elements, each with its sorted unique nodes stored as runs of
+  // consecutive global indices; patch-level colouring
+  int patch_cmax = semx::kPatchDefaultElems;  // 0 = per-element kernels
+  bool patches_ok = false;                    // patch layout built and usable
+  bool patch_cover = false;                   // every global node lies in some patch
+  int64_t npatch = 0, npatch_runs = 0, patch_nodes_total = 0;
+  int patch_maxnodes = 0, patch_maxruns = 0, npatch_colors = 0;
+  semx::DevBuf d_pe_pos;   // int32 [nspec] launch position of each patch slot's element
+  semx::DevBuf d_pe_off;   // int32 [npatch+1] first slot of each patch
+  semx::DevBuf d_lidx;     // uint16 [nspec][n3] patch-local node of each slot point
+  semx::DevBuf d_pr_off;   // int32 [npatch+1] first run of each patch
+  semx::DevBuf d_runs;     // int32 [nruns][2]: first global node, descriptor word
+  std::vector<semx::Launch> patch_colored;  // per colour: regular then irregular patches
+  std::vector<semx::Launch> patch_atomic;   // regular patches, irregular patches
+
   // model
   bool have_model = false;
   int nmodels = 0;
@@ -171,6 +198,19 @@ struct ForceArgs {
   int nmodels;
 };
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+
+// Patch launch: ForceArgs.pos0/count name a range of patches; ibool is unused.
+struct PatchArgs {
+  ForceArgs fa;
+  const int32_t* pe_pos;
+  const int32_t* pe_off;
+  const uint16_t* lidx;
+  const int32_t* pr_off;
+  const int32_t* runs;
+  int maxnodes, maxruns;
+};
+hipError_t launch_force_patch(int n, int geo, bool atomic, const PatchArgs& a, hipStream_t s);
+size_t patch_lds_bytes(int n, int maxnodes, int maxruns);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);
 

@@ -1,0 +1,137 @@
+"""Element patches of the FP32 force (chains of elements summed on chip,
+coloured or atomic at chain level) against the FP64 oracle.
+
+Bar: relative L2 <= 1e-5 over all degrees of freedom (the FP32 force
+tolerance) for every chain length, including the per-element kernels
+(length 0), both assemblies and both geometry paths; the force output is
+overwritten whatever it held; a time loop on patches agrees with the
+per-element time loop to FP32 rounding."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import gpu_force, make_solver, oracle_geometry, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+def _setup(orc, ne, n, jitter=0.1, seed=5):
+    mesh = W.box_mesh(ne, n, 4000.0, jitter=jitter, seed=seed)
+    lam, mu, rho = W.layered_model(mesh, grf_amp=0.05, grf_seed=seed, grf_corr_elems=1.5)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    s = make_solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    return mesh, lam, mu, rho, gam, jac, s
+
+
+@pytest.mark.parametrize("assembly", ["colored", "atomic"])
+@pytest.mark.parametrize("cmax", [0, 1, 2, 3, 8, 16])
+def test_chain_lengths_match_oracle(orc, cmax, assembly):
+    import paper_2606_12850_amd as P
+    ne = (11, 4, 3)  # rows of 11 elements: chains end at row ends and at the node limit
+    mesh, lam, mu, rho, gam, jac, s = _setup(orc, ne, 5)
+    assert P.semx_patch_info(s.ctx)["npatch"] == 0  # per-element kernels by default
+    P.semx_set_patches(s.ctx, cmax)
+    info = P.semx_patch_info(s.ctx)
+    print(f"cmax={cmax} {assembly}: {info}")
+    if cmax == 0:
+        assert info["npatch"] == 0
+    else:
+        eff = min(cmax, 8)  # chains hold at most 8 elements (and 1024 nodes: 9 at n = 5)
+        assert info["npatch"] == -(-11 // eff) * ne[1] * ne[2]
+        assert 2 <= info["ncolors"] <= 8
+        assert info["max_nodes"] == (4 * min(eff, 11) + 1) * 25
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED if assembly == "colored" else P.SEMX_ASM_ATOMIC)
+    u = np.random.default_rng(cmax).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+    f_ref = orc.force(5, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+    for geo in (P.SEMX_GEOM_STORED, P.SEMX_GEOM_TRILINEAR):
+        P.semx_set_geometry(s.ctx, geo)
+        err = rel_l2(gpu_force(s, u), f_ref)
+        print(f"  geometry {geo}: rel L2 = {err:.3e}")
+        assert err <= TOL_F32
+    s.close()
+
+
+@pytest.mark.parametrize("n,ne", [(3, (9, 2, 3)), (8, (3, 2, 2)), (9, (2, 2, 1))])
+def test_orders_on_patches(orc, n, ne):
+    """Orders whose chains are limited by the node budget (n = 8: two
+    elements; n = 9: one element per patch)."""
+    import paper_2606_12850_amd as P
+    mesh, lam, mu, rho, gam, jac, s = _setup(orc, ne, n)
+    P.semx_set_patches(s.ctx, 8)
+    info = P.semx_patch_info(s.ctx)
+    print(f"n={n}: {info}")
+    assert info["npatch"] > 0 and info["max_nodes"] <= 1024
+    u = np.random.default_rng(n).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+    f_ref = orc.force(n, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        s.set_mode(P.SEMX_C_F32, asm)
+        assert rel_l2(gpu_force(s, u), f_ref) <= TOL_F32
+    s.close()
+
+
+def test_apply_overwrites_output(orc):
+    """The coloured patch path writes every node without clearing f first."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh, lam, mu, rho, gam, jac, s = _setup(orc, (6, 5, 4), 5)
+    P.semx_set_patches(s.ctx, 8)
+    assert P.semx_patch_info(s.ctx)["npatch"] > 0
+    u = np.random.default_rng(1).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32)
+    f_ref = orc.force(5, mesh.ibool, gam, jac, lam, mu, u.astype(np.float64), mesh.nglob)
+    ud = torch.from_numpy(u).to(s.device)
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        s.set_mode(P.SEMX_C_F32, asm)
+        fd = torch.full_like(ud, float("nan"))
+        P.semx_apply_force(s.ctx, ud, fd)
+        torch.cuda.synchronize()
+        assert rel_l2(fd.cpu().numpy(), f_ref) <= TOL_F32
+    s.close()
+
+
+def test_timeloop_patches_match_per_element():
+    """Seismograms of a jittered layered run, patch kernels vs per-element
+    kernels (same FP32 arithmetic, different summation order)."""
+    import paper_2606_12850_amd as P
+    wl = W.layered_jittered(ne=6, n=5, nt=300, dt=2e-3, jitter=0.1, seed=4, grf_seed=7, grf_amp=0.05)
+    out = {}
+    for cmax in (0, 8):
+        s = make_solver(5)
+        s.upload_mesh(wl.mesh)
+        s.upload_model(wl.lam, wl.mu, wl.rho)
+        P.semx_set_patches(s.ctx, cmax)
+        s.setup_run(wl)
+        s.step(wl.nt)
+        out[cmax] = s.seismograms()
+        s.close()
+    err = rel_l2(out[8], out[0])
+    print(f"patches vs per-element seismograms, 300 steps: rel L2 = {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_batched_models_on_patches(orc):
+    """nmodels > 1: every model's force through the patch kernel."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((5, 3, 2), 5, 4000.0, jitter=0.1, seed=2)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    models = [W.layered_model(mesh, grf_amp=0.05, grf_seed=k, grf_corr_elems=1.5) for k in range(3)]
+    lam = np.stack([m[0] for m in models]); mu = np.stack([m[1] for m in models]); rho = np.stack([m[2] for m in models])
+    s = make_solver(5)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    P.semx_set_patches(s.ctx, 8)
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-1, 1, (3, mesh.nglob, 3)).astype(np.float32)
+    ud = torch.from_numpy(u).to(s.device)
+    fd = torch.empty_like(ud)
+    P.semx_apply_force(s.ctx, ud, fd)
+    torch.cuda.synchronize()
+    f = fd.cpu().numpy()
+    for k in range(3):
+        ref = orc.force(5, mesh.ibool, gam, jac, lam[k], mu[k], u[k].astype(np.float64), mesh.nglob)
+        assert rel_l2(f[k], ref) <= TOL_F32
+    s.close()
