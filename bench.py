@@ -150,6 +150,90 @@ def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 2
             "fd_check": fd}
 
 
+def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: int = 4096, epochs: int = 300,
+                  members: int = 4, nt: int = 800, nout: int = 512, ne: int = 16, tol: float = 0.05):
+    """Learned surrogate on the 16^3 box: batched SEM data for the 64-mode
+    lambda/mu perturbations, an ensemble of MLPs trained by the library's
+    kernels, the spread indicator calibrated on validation models, SEM
+    fallback for flagged test models, SEM as the judge of every test model."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+    from paper_2606_12850_amd.surrogate import BatchedSEM, Surrogate, rel_err, resample
+
+    log = lambda m: print(f"[surrogate] {m}", file=sys.stderr, flush=True)
+    mesh = W.box_mesh(ne, NGLL, 4000.0)
+    basis = W.fourier_modes(mesh)
+    model_fn = lambda a: W.perturbed_models(mesh, basis, a)
+    # common dt: Courant 0.4 at the fastest admissible model (delta = +10 % everywhere)
+    probe = P.Solver(NGLL)
+    probe.upload_mesh(mesh)
+    lam0, mu0, rho0 = W.homogeneous_model(mesh)
+    probe.upload_model(lam0 * 1.1, mu0 * 1.1, rho0)
+    dt = P.semx_cfl_dt(probe.ctx, 0.4)
+    probe.close()
+    se, sx = W.center_vertex_source(mesh)
+    re, rx = W.top_receivers_grid(mesh, 4)
+    stf = W.ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
+    sem = BatchedSEM(mesh, se, sx, [[0.0, 0.0, 1.0]], stf, re, rx, dt, nt, batch=64)
+
+    def run(coeffs):
+        out = []
+        for b0 in range(0, len(coeffs), 512):
+            out.append(resample(sem.run_models(model_fn, coeffs[b0:b0 + 512]), nout).astype(np.float32))
+        return np.concatenate(out, 0)
+
+    A_tr = W.perturbation_coefficients(basis, range(0, ntrain))
+    A_va = W.perturbation_coefficients(basis, range(ntrain, ntrain + nval))
+    A_te = W.perturbation_coefficients(basis, range(10000, 10000 + ntest))
+    t0 = time.perf_counter()
+    Y_tr = run(A_tr)
+    t_data = time.perf_counter() - t0
+    log(f"training data {Y_tr.shape} in {t_data:.1f} s")
+    Y_va = run(A_va)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Y_te = run(A_te)
+    torch.cuda.synchronize()
+    t_sem = time.perf_counter() - t0
+    log(f"test data (SEM for all {ntest} models) in {t_sem:.1f} s")
+    n_out = Y_tr[0].size
+    sur = Surrogate(64, n_out, hidden=(512, 512, 512), members=members, max_batch=4096)
+    t_train = sur.fit(A_tr, Y_tr, epochs=epochs, batch=128, log=log)
+    cal = sur.calibrate(A_va, Y_va.reshape(len(A_va), -1), tol=tol)
+    log(f"trained in {t_train:.1f} s; calibration {cal}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred, ind = sur.predict(A_te)
+    flag = ind > sur.threshold
+    final = pred.copy()
+    if flag.any():
+        final[flag] = run(A_te[flag]).reshape(int(flag.sum()), -1)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    Yt = Y_te.reshape(ntest, -1)
+    e_sur, e_fin = rel_err(pred, Yt), rel_err(final, Yt)
+    e_mean = rel_err(np.broadcast_to(Y_tr.reshape(ntrain, -1).mean(0), Yt.shape), Yt)
+    bad = e_sur > tol
+    recall = float((flag & bad).sum() / max(bad.sum(), 1))
+    precision = float((flag & bad).sum() / max(flag.sum(), 1))
+    sur.close(); sem.close()
+    return {"workload": f"box {ne}^3 regular, NGLL {NGLL}, 64 cosine modes (lambda, mu x (1 +- 10 %)), Ricker {f0:g} Hz, "
+                        f"{nt} steps -> {nout} samples, 16 receivers; MLP 64-512-512-512-{n_out} x {members}, "
+                        f"{epochs} epochs batch 128; train {ntrain} / val {nval} / test {ntest}",
+            "dt": dt, "sem_data_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "surrogate_err_mean": float(e_sur.mean()), "surrogate_err_median": float(np.median(e_sur)),
+            "surrogate_err_max": float(e_sur.max()), "mean_seismogram_err_mean": float(e_mean.mean()),
+            "frac_true_err_above_tol": float(bad.mean()), "flagged_frac": float(flag.mean()),
+            "flag_recall": recall, "flag_precision": precision,
+            "final_err_mean": float(e_fin.mean()), "final_err_max": float(e_fin.max()),
+            "final_frac_above_tol": float((e_fin > tol).mean()),
+            "time_surrogate_plus_fallback_s": round(t_sur, 3), "time_sem_all_s": round(t_sem, 3),
+            "gain": round(t_sem / t_sur, 3), "calibration": cal}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +248,11 @@ def main():
                     help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
                          "device copy (calibration for HBM traffic counters); prints one JSON line")
     ap.add_argument("--contraction", choices=["f32", "bf16", "f16"], default="f32")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also run the learned-surrogate leg (16^3 box, several minutes)")
+    ap.add_argument("--surrogate-f0", type=float, default=10.0)
+    ap.add_argument("--surrogate-scale", type=float, default=1.0,
+                    help="fraction of the surrogate leg's model counts and epochs (quick checks)")
     ap.add_argument("--patches", type=int, default=0,
                     help="chain length of the FP32 patch kernel (0 = per-element kernels)")
     args = ap.parse_args()
@@ -310,6 +399,10 @@ def main():
     s.close()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
+    if args.surrogate:
+        k = args.surrogate_scale
+        out["surrogate"] = surrogate_leg(f0=args.surrogate_f0, ntrain=max(64, int(4500 * k)), nval=max(64, int(500 * k)),
+                                         ntest=max(64, int(4096 * k)), epochs=max(5, int(300 * k)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
     print(json.dumps(out))
