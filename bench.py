@@ -234,6 +234,74 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
             "gain": round(t_sem / t_sur, 3), "calibration": cal}
 
 
+ORDER_SWEEP = [(4, 90), (5, 68), (6, 54), (7, 45), (8, 39), (9, 34)]  # (NGLL, elements per side): ~2e7 points
+
+
+def order_sweep_leg(reps: int = 20):
+    """Force apply at about 2e7 unique points for NGLL 4..9 (element size
+    h = N * 69.3 / 5 m, about five GLL points per minimum wavelength of a
+    25 Hz wave at vs = 1732 m/s), homogeneous medium times a +-5 % random
+    field, regular hexahedra, coloured assembly: FP32, and BF16 / FP16 matrix
+    core contractions where supported, with the relative force difference of
+    the mixed paths against FP32 on a smooth field."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+
+    log = lambda m: print(f"[order-sweep] {m}", file=sys.stderr, flush=True)
+    rows = []
+    for n, ne in ORDER_SWEEP:
+        N = n - 1
+        h = N * 69.3 / 5
+        mesh = W.box_mesh(ne, n, ne * h)
+        lam, mu, rho = W.layered_model(mesh, vp_layers=(3000.0,), vpvs=3000.0 / 1732.0, grf_amp=0.05,
+                                       grf_seed=12850, grf_corr_elems=4.0)
+        s = P.Solver(n)
+        s.upload_mesh(mesh)
+        s.upload_model(lam, mu, rho)
+        del lam, mu, rho
+        G = mesh.nglob
+        Gx = ne * N + 1
+        g = np.arange(G)
+        xs = (g % Gx, (g // Gx) % Gx, g // (Gx * Gx))
+        k = 2.0 * np.pi / (Gx - 1)
+        u_np = np.stack([np.sin(k * xs[0] + 0.3) * np.cos(k * xs[1]), np.cos(k * xs[1] + 0.7) * np.sin(k * xs[2]),
+                         np.sin(k * xs[2] + 1.1) * np.cos(k * xs[0])], axis=1).astype(np.float32)
+        u = torch.from_numpy(u_np).to("cuda")
+        del u_np, xs, g
+        f = torch.empty_like(u)
+        row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2)}
+        b_elem = bytes_per_element(n, G, mesh.nspec, "regular")
+        ref = None
+        for cname, cmode in (("f32", P.SEMX_C_F32), ("bf16", P.SEMX_C_BF16), ("f16", P.SEMX_C_F16)):
+            if cname != "f32" and not (4 <= n <= 8):
+                continue
+            P.semx_set_mode(s.ctx, cmode, P.SEMX_ASM_COLORED)
+            for _ in range(3):
+                P.semx_apply_force(s.ctx, u, f)
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            for _ in range(reps):
+                P.semx_apply_force(s.ctx, u, f)
+            e1.record(s.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[f"{cname}_ms"] = round(ms, 4)
+            row[f"{cname}_gll_pts_per_s"] = mesh.nspec * n ** 3 / (ms * 1e-3)
+            row[f"{cname}_hbm_frac_alg"] = round(b_elem * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            if ref is None:
+                ref = f.clone()
+            else:
+                row[f"{cname}_rel_diff_vs_f32"] = (torch.linalg.norm(f - ref) / torch.linalg.norm(ref)).item()
+        log(json.dumps(row))
+        rows.append(row)
+        del u, f, ref
+        s.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +321,8 @@ def main():
     ap.add_argument("--surrogate-f0", type=float, default=10.0)
     ap.add_argument("--surrogate-scale", type=float, default=1.0,
                     help="fraction of the surrogate leg's model counts and epochs (quick checks)")
+    ap.add_argument("--order-sweep", action="store_true",
+                    help="also time the force apply for NGLL 4..9 at ~2e7 points (FP32 and mixed)")
     ap.add_argument("--patches", type=int, default=0,
                     help="chain length of the FP32 patch kernel (0 = per-element kernels)")
     args = ap.parse_args()
@@ -399,6 +469,8 @@ def main():
     s.close()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
+    if args.order_sweep:
+        out["order_sweep"] = order_sweep_leg()
     if args.surrogate:
         k = args.surrogate_scale
         out["surrogate"] = surrogate_leg(f0=args.surrogate_f0, ntrain=max(64, int(4500 * k)), nval=max(64, int(500 * k)),

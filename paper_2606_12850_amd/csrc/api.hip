@@ -215,7 +215,7 @@ __global__ void mass_serial_kernel(int n3, int64_t nspec, int64_t nglob, int nmo
 __global__ void minv_kernel(int64_t n, const double* __restrict__ mass, float* __restrict__ minv) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
-    minv[t] = (float)(1.0 / mass[t]);
+    minv[t] = mass[t] > 0.0 ? (float)(1.0 / mass[t]) : 0.0f;  // a node no element reaches stays at rest
 }
 
 __global__ void fill_f32(float* __restrict__ p, int64_t n, float v) {
@@ -736,7 +736,30 @@ int build_layout(semx_ctx* c) {
     for (int a = 0; a < 3; ++a)
       for (int m = 0; m < 8; ++m) tri[pos * 24 + 8 * a + m] = (float)cm[a][m];
   }
+  // first touch in coloured launch order (colour-major, regular then irregular)
+  const int fw = (n3 + 31) / 32;
+  std::vector<uint32_t> first;
+  c->elem_cover = false;
+  c->first_words = 0;
+  if (c->ncolors > 0) {
+    first.assign((size_t)nspec * fw, 0u);
+    std::vector<uint8_t> touched(c->nglob, 0);
+    for (const auto& L : c->colored_launches)
+      for (int64_t pos = L.pos0; pos < L.pos0 + L.count; ++pos)
+        for (int q = 0; q < n3; ++q) {
+          const int32_t g = ib[pos * n3 + q];
+          if (!touched[g]) {
+            touched[g] = 1;
+            first[pos * fw + q / 32] |= 1u << (q % 32);
+          }
+        }
+    c->elem_cover = true;
+    for (int64_t g = 0; g < c->nglob && c->elem_cover; ++g) c->elem_cover = touched[g] != 0;
+    c->first_words = fw;
+  }
   int rc = dev_alloc(c, c->d_order, sizeof(int32_t) * nspec);
+  if (!rc && !first.empty()) rc = dev_alloc(c, c->d_first, sizeof(uint32_t) * first.size());
+  if (!rc && first.empty()) dev_free(c->d_first);
   if (!rc) rc = dev_alloc(c, c->d_ibool, sizeof(int32_t) * nspec * n3);
   if (!rc) rc = dev_alloc(c, c->d_gam_el, sizeof(float) * 9 * nspec);
   if (!rc) rc = dev_alloc(c, c->d_tri, sizeof(float) * 24 * nspec);
@@ -746,6 +769,8 @@ int build_layout(semx_ctx* c) {
   if (rc) return rc;
   SEMX_HIP(c, hipMemcpy(c->d_order.p, order.data(), sizeof(int32_t) * nspec, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_ibool.p, ib.data(), sizeof(int32_t) * nspec * n3, hipMemcpyHostToDevice));
+  if (!first.empty())
+    SEMX_HIP(c, hipMemcpy(c->d_first.p, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gel.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_tri.p, tri.data(), sizeof(float) * 24 * nspec, hipMemcpyHostToDevice));
   int* bad = scratch_i(c);
@@ -762,7 +787,9 @@ int build_layout(semx_ctx* c) {
 }
 
 // f = -K u accumulated into f (f must already hold zeros or earlier sums).
-int force_accumulate(semx_ctx* c, const float* u, float* f) {
+// With `first_touch` (FP32 coloured per-element path) the first point to
+// reach each node stores instead of adding, so f's prior content is ignored.
+int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false) {
   ForceArgs a{};
   a.ibool = c->d_ibool.as<int32_t>();
   a.gam_pt = c->d_gam_pt.as<float>();
@@ -778,6 +805,10 @@ int force_accumulate(semx_ctx* c, const float* u, float* f) {
   a.nglob = c->nglob;
   a.nmodels = c->nmodels;
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
+  if (first_touch && !atomic && c->contraction == SEMX_C_F32 && c->d_first.p) {
+    a.first = c->d_first.as<uint32_t>();
+    a.first_words = c->first_words;
+  }
   const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
   for (const auto& L : launches) {
     a.pos0 = L.pos0;
@@ -821,7 +852,8 @@ bool use_patches(const semx_ctx* c) { return c->patches_ok && c->contraction == 
 // first-touch stores over a mesh whose nodes all belong to some element), so
 // f needs no clearing before it.
 bool force_overwrites(const semx_ctx* c) {
-  return use_patches(c) && c->assembly == SEMX_ASM_COLORED && c->patch_cover;
+  if (c->assembly != SEMX_ASM_COLORED || c->contraction != SEMX_C_F32) return false;
+  return use_patches(c) ? c->patch_cover : (c->elem_cover && c->d_first.p != nullptr);
 }
 
 int force_patches(semx_ctx* c, const float* u, float* f) {
@@ -874,7 +906,7 @@ int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
     int rc = zero_f32(c, f, state_len(c));
     if (rc) return rc;
   }
-  return use_patches(c) ? force_patches(c, u, f) : force_accumulate(c, u, f);
+  return use_patches(c) ? force_patches(c, u, f) : force_accumulate(c, u, f, force_overwrites(c));
 }
 
 
@@ -1072,7 +1104,7 @@ int semx_destroy(semx_ctx* c) {
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
                     &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis,
-                    &c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs})
+                    &c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs, &c->d_first})
     dev_free(*b);
   delete c;
   return SEMX_OK;

@@ -9,6 +9,9 @@
 //   inverse-Jacobian map, isotropic stress, weighted fluxes in registers,
 //   fluxes -> LDS, three transpose contractions with D^T (Sec. II-B, weak form),
 //   scatter-add to f (plain read-modify-write inside a colour, or atomics).
+// Coloured assembly may come with first-touch flags: the point that reaches
+// its node first in launch order stores its force without reading f, so the
+// force vector needs no clearing before the pass.
 //
 // Geometry paths (the paper's Sec. IV-D regular/irregular specialisation,
 // chosen per launch, never per point):
@@ -31,6 +34,7 @@ namespace {
 // Per-lane inputs of one element.
 struct PointIn {
   int g;
+  bool first;  // the lane's point is the first to reach its node (store, no read)
   float G[9];  // Gamma (kStored); unused otherwise
   float lw, mw;
   float u[3];
@@ -53,10 +57,15 @@ __device__ __forceinline__ void load_point(const ForceArgs& a, const float* __re
   P.u[0] = u[3 * (size_t)g + 0];
   P.u[1] = u[3 * (size_t)g + 1];
   P.u[2] = u[3 * (size_t)g + 2];
+  P.first = false;
   if constexpr (!ATOMIC) {
-    P.f[0] = f[3 * (size_t)g + 0];
-    P.f[1] = f[3 * (size_t)g + 1];
-    P.f[2] = f[3 * (size_t)g + 2];
+    if (a.first) P.first = (a.first[(size_t)pos * a.first_words + (pp >> 5)] >> (pp & 31)) & 1u;
+    P.f[0] = P.f[1] = P.f[2] = 0.0f;
+    if (!P.first) {
+      P.f[0] = f[3 * (size_t)g + 0];
+      P.f[1] = f[3 * (size_t)g + 1];
+      P.f[2] = f[3 * (size_t)g + 2];
+    }
   }
 }
 

@@ -103,6 +103,13 @@ struct semx_ctx {
   int64_t nregular = 0, nirregular = 0;
   double hmin = 0.0;               // min distance between adjacent GLL points
 
+  // first touch of each node in coloured launch order, per launch position:
+  // bit q of d_first[pos * first_words + q / 32] set when local point q is the
+  // first to reach its node; elem_cover = every node is reached by an element
+  semx::DevBuf d_first;
+  int first_words = 0;
+  bool elem_cover = false;
+
   // colouring
   int ncolors = 0;
   std::vector<int32_t> color_ptr, elem_order;
@@ -192,6 +199,9 @@ struct ForceArgs {
   float* f;              // [nmodels][nglob][3]
   const float* D;        // [n][n] FP32
   const void* Dh;        // packed low-precision D tables (MFMA paths)
+  const uint32_t* first; // FP32 coloured path: per-position bitmask of the points that
+                         // reach their node first in launch order (store, no read), or null
+  int first_words;       // 32-bit words per position in `first`
   int64_t pos0;          // first launch position of this launch
   int64_t count;
   int64_t nspec, nglob;

@@ -73,13 +73,15 @@ def test_orders_on_patches(orc, n, ne):
     s.close()
 
 
-def test_apply_overwrites_output(orc):
-    """The coloured patch path writes every node without clearing f first."""
+@pytest.mark.parametrize("cmax", [0, 8])
+def test_apply_overwrites_output(orc, cmax):
+    """The coloured paths (per element with first-touch stores, or patches)
+    write every node without clearing f first."""
     import torch
     import paper_2606_12850_amd as P
     mesh, lam, mu, rho, gam, jac, s = _setup(orc, (6, 5, 4), 5)
-    P.semx_set_patches(s.ctx, 8)
-    assert P.semx_patch_info(s.ctx)["npatch"] > 0
+    P.semx_set_patches(s.ctx, cmax)
+    assert (P.semx_patch_info(s.ctx)["npatch"] > 0) == (cmax > 0)
     u = np.random.default_rng(1).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32)
     f_ref = orc.force(5, mesh.ibool, gam, jac, lam, mu, u.astype(np.float64), mesh.nglob)
     ud = torch.from_numpy(u).to(s.device)
@@ -134,4 +136,32 @@ def test_batched_models_on_patches(orc):
     for k in range(3):
         ref = orc.force(5, mesh.ibool, gam, jac, lam[k], mu[k], u[k].astype(np.float64), mesh.nglob)
         assert rel_l2(f[k], ref) <= TOL_F32
+    s.close()
+
+
+@pytest.mark.parametrize("cmax", [0, 8])
+def test_unreferenced_node_gets_zero_force(orc, cmax):
+    """A node no element references (nglob one larger than the mesh needs):
+    the coloured paths cannot cover it by first touch, so f is cleared and the
+    extra node's force is exactly zero."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((4, 3, 2), 5, 4000.0, jitter=0.1, seed=6)
+    lam, mu, rho = W.layered_model(mesh, grf_amp=0.05, grf_seed=6, grf_corr_elems=1.5)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    G = mesh.nglob + 1
+    s = make_solver(5)
+    P.semx_upload_mesh(s.ctx, mesh.ibool, mesh.vert, mesh.elem_vert, G)
+    s.nglob = G
+    s.upload_model(lam, mu, rho)
+    P.semx_set_patches(s.ctx, cmax)
+    u = np.random.default_rng(2).uniform(-1, 1, (G, 3)).astype(np.float32)
+    f_ref = orc.force(5, mesh.ibool, gam, jac, lam, mu, u[:-1].astype(np.float64), mesh.nglob)
+    ud = torch.from_numpy(u).to(s.device)
+    fd = torch.full_like(ud, float("nan"))
+    P.semx_apply_force(s.ctx, ud, fd)
+    torch.cuda.synchronize()
+    f = fd.cpu().numpy()
+    assert np.all(f[-1] == 0.0)
+    assert rel_l2(f[:-1], f_ref) <= TOL_F32
     s.close()
