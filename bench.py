@@ -133,14 +133,14 @@ def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 1
     # runs, (-chi(2e) + 8 chi(e) - 8 chi(-e) + chi(-2e)) / (12 e), relative
     # directions lambda xi, mu xi', rho xi'' with xi ~ N(0, 1) per point
     rng = np.random.default_rng(0)
-    chi = lambda lam, mu, rho: 0.5 * dt * float(torch.sum((op.run(lam, mu, rho).double() - data.double()) ** 2))
+    misfit_of = lambda lam, mu, rho: 0.5 * dt * float(torch.sum((op.run(lam, mu, rho).double() - data.double()) ** 2))
     fd = []
     eps = 1e-2
     for k in range(fd_dirs):
         dl = wl.lam * rng.standard_normal(wl.lam.shape)
         dm = wl.mu * rng.standard_normal(wl.mu.shape)
         dr = wl.rho * rng.standard_normal(wl.rho.shape)
-        c = {h: chi(wl.lam + h * eps * dl, wl.mu + h * eps * dm, wl.rho + h * eps * dr) for h in (-2, -1, 1, 2)}
+        c = {h: misfit_of(wl.lam + h * eps * dl, wl.mu + h * eps * dm, wl.rho + h * eps * dr) for h in (-2, -1, 1, 2)}
         fdv = (-c[2] + 8 * c[1] - 8 * c[-1] + c[-2]) / (12 * eps)
         ad = float(np.sum(gl[0].cpu().numpy() * dl) + np.sum(gm[0].cpu().numpy() * dm) + np.sum(gr[0].cpu().numpy() * dr))
         fd.append({"adjoint": ad, "fd_fp32": fdv, "rel": abs(ad - fdv) / max(abs(fdv), 1e-300)})
