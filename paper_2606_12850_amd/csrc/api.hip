@@ -787,7 +787,7 @@ int build_layout(semx_ctx* c) {
 }
 
 // f = -K u accumulated into f (f must already hold zeros or earlier sums).
-// With `first_touch` (FP32 coloured per-element path) the first point to
+// With `first_touch` (coloured per-element paths) the first point to
 // reach each node stores instead of adding, so f's prior content is ignored.
 int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false) {
   ForceArgs a{};
@@ -805,7 +805,7 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
   a.nglob = c->nglob;
   a.nmodels = c->nmodels;
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
-  if (first_touch && !atomic && c->contraction == SEMX_C_F32 && c->d_first.p) {
+  if (first_touch && !atomic && c->d_first.p) {
     a.first = c->d_first.as<uint32_t>();
     a.first_words = c->first_words;
   }
@@ -852,7 +852,7 @@ bool use_patches(const semx_ctx* c) { return c->patches_ok && c->contraction == 
 // first-touch stores over a mesh whose nodes all belong to some element), so
 // f needs no clearing before it.
 bool force_overwrites(const semx_ctx* c) {
-  if (c->assembly != SEMX_ASM_COLORED || c->contraction != SEMX_C_F32) return false;
+  if (c->assembly != SEMX_ASM_COLORED) return false;
   return use_patches(c) ? c->patch_cover : (c->elem_cover && c->d_first.p != nullptr);
 }
 

@@ -199,7 +199,7 @@ struct ForceArgs {
   float* f;              // [nmodels][nglob][3]
   const float* D;        // [n][n] FP32
   const void* Dh;        // packed low-precision D tables (MFMA paths)
-  const uint32_t* first; // FP32 coloured path: per-position bitmask of the points that
+  const uint32_t* first; // coloured per-element paths: per-position bitmask of the points that
                          // reach their node first in launch order (store, no read), or null
   int first_words;       // 32-bit words per position in `first`
   int64_t pos0;          // first launch position of this launch
