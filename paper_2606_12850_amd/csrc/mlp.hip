@@ -9,7 +9,9 @@
 //   dL/dZ_{l-1} = dH_l * SiLU'(Z_{l-1}).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -27,6 +29,7 @@ struct semx_mlp {
   std::vector<semx::DevBuf> Z, H;  // Z[l] [B][w[l+1]], H[l] (l >= 1) [B][w[l]]
   semx::DevBuf g0, g1;             // backward work [B][max width]
   semx::DevBuf scratch;
+  semx::DevBuf splitk;             // split-K partial sums
   const float* x_saved = nullptr;
   int batch_saved = 0;
 };
@@ -38,43 +41,89 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32, PADK = 8;
+constexpr int64_t kSplitWs = 2 << 20;  // floats of split-K partial sums per network (8 MB)
 
 __device__ __forceinline__ float to_f(float x) { return x; }
 __device__ __forceinline__ float to_f(__bf16 x) { return (float)x; }
 
+// Eight consecutive elements starting at p (16-byte aligned when `vec`).
+template <class T>
+__device__ __forceinline__ void load8(const T* p, float v[8]);
+template <>
+__device__ __forceinline__ void load8<float>(const float* p, float v[8]) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+template <>
+__device__ __forceinline__ void load8<__bf16>(const __bf16* p, float v[8]) {
+  const bf16x8 a = *reinterpret_cast<const bf16x8*>(p);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (float)a[e];
+}
+
+// One operand tile T[r][k] (64 rows x BK) of X(r, k) = X[r * sr + k * sk],
+// rows r0 .. r0+63, k in [k0, kend).  KC: X is contiguous along k (sk = 1),
+// a thread loads 8 consecutive k of one row; otherwise it is contiguous
+// along r (sr = 1) and a thread loads 8 consecutive rows of one k.  `vec`
+// allows 16-byte vector loads (checked alignment); ragged edges use scalar
+// loads with bounds.
+template <class T, bool KC>
+__device__ __forceinline__ void load_tile(__bf16 (*Ts)[BK + PADK], const T* __restrict__ X, int64_t sr, int64_t sk,
+                                          int R, int r0, int k0, int kend, bool vec, int t) {
+  float v[8];
+  if constexpr (KC) {
+    const int rr = t >> 2, kk = (t & 3) * 8;
+    const int r = r0 + rr, k = k0 + kk;
+    if (vec && r < R && k + 8 <= kend) {
+      load8<T>(X + (int64_t)r * sr + k, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (r < R && k + e < kend) ? to_f(X[(int64_t)r * sr + (int64_t)(k + e) * sk]) : 0.0f;
+    }
+    bf16x8 w;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = (__bf16)v[e];
+    *reinterpret_cast<bf16x8*>(&Ts[rr][kk]) = w;
+  } else {
+    const int kk = t >> 3, rr = (t & 7) * 8;
+    const int r = r0 + rr, k = k0 + kk;
+    if (vec && k < kend && r + 8 <= R) {
+      load8<T>(X + r + (int64_t)k * sk, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (r + e < R && k < kend) ? to_f(X[(int64_t)(r + e) * sr + (int64_t)k * sk]) : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Ts[rr + e][kk] = (__bf16)v[e];
+  }
+}
+
 // C[m][n] (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
 // EPI 1: + bias[n]; EPI 2: + bias[n] and H[m][n] = SiLU(C[m][n]).
-template <class TA, class TB, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const TA* __restrict__ A, int64_t sam,
-                                                   int64_t sak, const TB* __restrict__ B, int64_t sbk, int64_t sbn,
-                                                   float* __restrict__ C, int64_t ldc, const float* __restrict__ bias,
-                                                   float* __restrict__ H, int accumulate) {
+// Split-K (gridDim.z > 1, EPI 0 only): slice z covers k in [z kchunk,
+// (z+1) kchunk) and stores its partial sums to C + z M N (row stride N).
+template <class TA, class TB, int EPI, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, int kchunk, const TA* __restrict__ A,
+                                                   int64_t sam, int64_t sak, int veca, const TB* __restrict__ B,
+                                                   int64_t sbk, int64_t sbn, int vecb, float* __restrict__ C,
+                                                   int64_t ldc, const float* __restrict__ bias, float* __restrict__ H,
+                                                   int accumulate) {
   __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PADK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PADK];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
   const int wm = wv >> 1, wn = wv & 1;
+  const bool split = gridDim.z > 1;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
   f32x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const int lr = t >> 2, lk = (t & 3) * 8;  // tile loader: row/col t/4, 8 consecutive k
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    {
-      const int m = bm + lr;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int kk = k0 + lk + e;
-        As[lr][lk + e] = (__bf16)((m < M && kk < K) ? to_f(A[(int64_t)m * sam + (int64_t)kk * sak]) : 0.0f);
-      }
-      const int n = bn + lr;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int kk = k0 + lk + e;
-        Bs[lr][lk + e] = (__bf16)((n < N && kk < K) ? to_f(B[(int64_t)kk * sbk + (int64_t)n * sbn]) : 0.0f);
-      }
-    }
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    load_tile<TA, AKC>(As, A, sam, sak, M, bm, k0, kend, veca != 0, t);
+    load_tile<TB, BKC>(Bs, B, sbn, sbk, N, bn, k0, kend, vecb != 0, t);
     __syncthreads();
     bf16x8 av[2], bv[2];
 #pragma unroll
@@ -87,6 +136,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const TA
       for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
+  float* Cz = split ? C + (int64_t)blockIdx.z * M * N : C;
+  const int64_t ldz = split ? N : ldc;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -97,21 +148,75 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const TA
         const int n = bn + wn * 32 + b * 16 + (lane & 15);
         if (m < M && n < N) {
           float v = acc[a][b][r];
-          const int64_t o = (int64_t)m * ldc + n;
-          if (accumulate) v += C[o];
-          if (EPI >= 1) v += bias[n];
-          C[o] = v;
+          const int64_t o = (int64_t)m * ldz + n;
+          if (!split) {
+            if (accumulate) v += Cz[o];
+            if (EPI >= 1) v += bias[n];
+          }
+          Cz[o] = v;
           if (EPI == 2) H[o] = v / (1.0f + expf(-v));
         }
       }
 }
 
+// C[m][n] = sum over the nz slices of P (fixed order: deterministic).
+__global__ void splitk_reduce_kernel(int M, int N, int nz, const float* __restrict__ P, float* __restrict__ C,
+                                     int64_t ldc) {
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < MN; t += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int z = 0; z < nz; ++z) s += P[z * MN + t];
+    C[(t / N) * ldc + t % N] = s;
+  }
+}
+
+template <class T>
+bool aligned16(const T* p, int64_t stride) {
+  return (reinterpret_cast<uintptr_t>(p) % 16 == 0) && ((stride * (int64_t)sizeof(T)) % 16 == 0);
+}
+
+template <class TA, class TB, int EPI, bool AKC, bool BKC>
+hipError_t gemm_launch(hipStream_t s, int M, int N, int K, const TA* A, int64_t sam, int64_t sak, const TB* B,
+                       int64_t sbk, int64_t sbn, float* C, int64_t ldc, const float* bias, float* H, int accumulate,
+                       float* ws) {
+  // vector loads need unit stride along the loaded direction and 16-byte alignment
+  const int veca = (AKC ? sak == 1 : sam == 1) && aligned16(A, AKC ? sam : sak);
+  const int vecb = (BKC ? sbk == 1 : sbn == 1) && aligned16(B, BKC ? sbn : sbk);
+  const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+  int nz = 1, kchunk = K;
+  if (EPI == 0 && !accumulate && ws && tiles < 128 && K >= 1024) {
+    nz = std::min<int>(32, (512 + tiles - 1) / tiles);
+    kchunk = (((K + nz - 1) / nz + BK - 1) / BK) * BK;
+    nz = (K + kchunk - 1) / kchunk;
+    while (nz > 1 && (int64_t)nz * M * N > kSplitWs) {
+      kchunk *= 2;
+      nz = (K + kchunk - 1) / kchunk;
+    }
+  }
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz), block(256);
+  gemm_kernel<TA, TB, EPI, AKC, BKC><<<grid, block, 0, s>>>(M, N, K, kchunk, A, sam, sak, veca, B, sbk, sbn, vecb,
+                                                            nz > 1 ? ws : C, ldc, bias, H, accumulate);
+  if (nz > 1) {
+    const int64_t MN = (int64_t)M * N;
+    const unsigned nb = (unsigned)std::min<int64_t>((MN + 255) / 256, 4096);
+    splitk_reduce_kernel<<<nb, 256, 0, s>>>(M, N, nz, ws, C, ldc);
+  }
+  return hipGetLastError();
+}
+
+// Dispatch on operand layout: contiguous along k (stride 1) or along m / n.
 template <class TA, class TB, int EPI>
 hipError_t gemm(hipStream_t s, int M, int N, int K, const TA* A, int64_t sam, int64_t sak, const TB* B, int64_t sbk,
-                int64_t sbn, float* C, int64_t ldc, const float* bias, float* H, int accumulate) {
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(256);
-  gemm_kernel<TA, TB, EPI><<<grid, block, 0, s>>>(M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, accumulate);
-  return hipGetLastError();
+                int64_t sbn, float* C, int64_t ldc, const float* bias, float* H, int accumulate, float* ws = nullptr) {
+  const bool akc = sak == 1 || sam != 1;
+  const bool bkc = sbk == 1 || sbn != 1;
+  if (akc && bkc)
+    return gemm_launch<TA, TB, EPI, true, true>(s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, accumulate, ws);
+  if (akc)
+    return gemm_launch<TA, TB, EPI, true, false>(s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, accumulate, ws);
+  if (bkc)
+    return gemm_launch<TA, TB, EPI, false, true>(s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, accumulate, ws);
+  return gemm_launch<TA, TB, EPI, false, false>(s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, H, accumulate, ws);
 }
 
 // g *= SiLU'(z)
@@ -240,6 +345,7 @@ int semx_mlp_create(semx_mlp** out, int nlayers, const int* widths, int max_batc
   if (!rc) rc = malloc_buf(p, p->g0, sizeof(float) * max_batch * maxw);
   if (!rc) rc = malloc_buf(p, p->g1, sizeof(float) * max_batch * maxw);
   if (!rc) rc = malloc_buf(p, p->scratch, 64);
+  if (!rc) rc = malloc_buf(p, p->splitk, sizeof(float) * semx::kSplitWs);
   p->Z.resize(nlayers);
   p->H.resize(nlayers + 1);
   for (int l = 0; l < nlayers && !rc; ++l) {
@@ -257,7 +363,8 @@ int semx_mlp_create(semx_mlp** out, int nlayers, const int* widths, int max_batc
 int semx_mlp_destroy(semx_mlp* p) {
   if (!p) return SEMX_OK;
   (void)hipStreamSynchronize(p->stream);
-  for (DevBuf* b : {&p->theta, &p->theta_bf, &p->grad, &p->m, &p->v, &p->g0, &p->g1, &p->scratch}) dev_free(*b);
+  for (DevBuf* b : {&p->theta, &p->theta_bf, &p->grad, &p->m, &p->v, &p->g0, &p->g1, &p->scratch, &p->splitk})
+    dev_free(*b);
   for (auto& b : p->Z) dev_free(b);
   for (auto& b : p->H) dev_free(b);
   delete p;
@@ -337,13 +444,14 @@ int semx_mlp_backward(semx_mlp* p, const float* dy_dev, int batch) {
     const float* h = (l == 0) ? p->x_saved : p->H[l].as<float>();
     // dW = G^T H : C[n_out][k_in] = sum_b G[b][n_out] H[b][k_in]
     hipError_t e = gemm<float, float, 0>(p->stream, out, in, batch, g, 1, out, h, in, 1, gr + p->woff[l], in, nullptr,
-                                          nullptr, 0);
+                                          nullptr, 0, p->splitk.as<float>());
     if (e != hipSuccess) return mhip(p, e, "mlp wgrad gemm");
     colsum_kernel<<<g1(out), 256, 0, p->stream>>>(batch, out, g, gr + p->boff[l]);
     if (l == 0) break;
     // dH = G W : C[b][k_in] = sum_o G[b][o] W[o][k_in]
     float* dh = bufs[cur];
-    e = gemm<float, __bf16, 0>(p->stream, batch, in, out, g, out, 1, W + p->woff[l], in, 1, dh, in, nullptr, nullptr, 0);
+    e = gemm<float, __bf16, 0>(p->stream, batch, in, out, g, out, 1, W + p->woff[l], in, 1, dh, in, nullptr, nullptr, 0,
+                               p->splitk.as<float>());
     if (e != hipSuccess) return mhip(p, e, "mlp dgrad gemm");
     silu_bwd_kernel<<<g1((int64_t)batch * in), 256, 0, p->stream>>>((int64_t)batch * in, p->Z[l - 1].as<float>(), dh);
     g = dh;
