@@ -241,67 +241,26 @@ __global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
 constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8;
 
 template <int MODE>
-__device__ __forceinline__ void newmark_point(float dt, float mi, float& u, float& v, float& a, float& f) {
-  const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
-  float acc, vv = v;
-  if constexpr ((MODE & kCorrect) != 0) {
-    acc = mi * f;
-    vv = vv + hdt * acc;
-    if constexpr ((MODE & kStoreA) != 0) a = acc;
-  } else {
-    acc = a;
-  }
-  if constexpr ((MODE & kPredict) != 0) {
-    u = u + dt * vv + hdt2 * acc;
-    vv = vv + hdt * acc;
-    if constexpr ((MODE & kKeepF) == 0) f = 0.0f;
-  }
-  v = vv;
-}
-
-// Four nodes (12 values, three 16-byte words per array) per thread; the
-// nnodes % 4 tail nodes one per thread after them.
-template <int MODE>
 __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
                                float* __restrict__ u, float* __restrict__ v, float* __restrict__ a,
                                float* __restrict__ f) {
-  const int64_t n4 = nnodes / 4;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n4; q += stride) {
-    const float4 mi = reinterpret_cast<const float4*>(minv)[q];
-    const float mv[4] = {mi.x, mi.y, mi.z, mi.w};
-    float4 U[3], V[3], A[3], F[3];
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      V[w] = reinterpret_cast<const float4*>(v)[3 * q + w];
-      if constexpr ((MODE & kPredict) != 0) U[w] = reinterpret_cast<const float4*>(u)[3 * q + w];
-      if constexpr ((MODE & kCorrect) != 0) F[w] = reinterpret_cast<const float4*>(f)[3 * q + w];
-      else A[w] = reinterpret_cast<const float4*>(a)[3 * q + w];
+  const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    float acc, vv = v[t];
+    if constexpr ((MODE & kCorrect) != 0) {
+      acc = minv[t / 3] * f[t];
+      vv = vv + hdt * acc;
+      if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+    } else {
+      acc = a[t];
     }
-    float* uf = reinterpret_cast<float*>(U);
-    float* vf = reinterpret_cast<float*>(V);
-    float* af = reinterpret_cast<float*>(A);
-    float* ff = reinterpret_cast<float*>(F);
-#pragma unroll
-    for (int e = 0; e < 12; ++e) newmark_point<MODE>(dt, mv[e / 3], uf[e], vf[e], af[e], ff[e]);
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      reinterpret_cast<float4*>(v)[3 * q + w] = V[w];
-      if constexpr ((MODE & kPredict) != 0) reinterpret_cast<float4*>(u)[3 * q + w] = U[w];
-      if constexpr ((MODE & kCorrect) != 0 && (MODE & kStoreA) != 0) reinterpret_cast<float4*>(a)[3 * q + w] = A[w];
-      if constexpr ((MODE & kPredict) != 0 && (MODE & kKeepF) == 0) reinterpret_cast<float4*>(f)[3 * q + w] = F[w];
+    if constexpr ((MODE & kPredict) != 0) {
+      u[t] = u[t] + dt * vv + hdt2 * acc;
+      vv = vv + hdt * acc;
+      if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0f;
     }
-  }
-  for (int64_t t = 12 * n4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes; t += stride) {
-    float uu = 0.0f, vv = v[t], aa = 0.0f, ff = 0.0f;
-    if constexpr ((MODE & kPredict) != 0) uu = u[t];
-    if constexpr ((MODE & kCorrect) != 0) ff = f[t];
-    else aa = a[t];
-    newmark_point<MODE>(dt, minv[t / 3], uu, vv, aa, ff);
     v[t] = vv;
-    if constexpr ((MODE & kPredict) != 0) u[t] = uu;
-    if constexpr ((MODE & kCorrect) != 0 && (MODE & kStoreA) != 0) a[t] = aa;
-    if constexpr ((MODE & kPredict) != 0 && (MODE & kKeepF) == 0) f[t] = ff;
   }
 }
 
