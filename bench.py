@@ -282,7 +282,8 @@ def order_sweep_leg(reps: int = 20):
         row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2)}
         b_elem = bytes_per_element(n, G, mesh.nspec, "regular")
         ref = None
-        for cname, cmode in (("f32", P.SEMX_C_F32), ("bf16", P.SEMX_C_BF16), ("f16", P.SEMX_C_F16)):
+        for cname, cmode in (("f32", P.SEMX_C_F32), ("mf32", P.SEMX_C_MFMA_F32), ("bf16", P.SEMX_C_BF16),
+                             ("f16", P.SEMX_C_F16)):
             if cname != "f32" and not (4 <= n <= 8):
                 continue
             P.semx_set_mode(s.ctx, cmode, P.SEMX_ASM_COLORED)
@@ -322,7 +323,7 @@ def main():
     ap.add_argument("--profile-force", action="store_true",
                     help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
                          "device copy (calibration for HBM traffic counters); prints one JSON line")
-    ap.add_argument("--contraction", choices=["f32", "bf16", "f16"], default="f32")
+    ap.add_argument("--contraction", choices=["f32", "mf32", "bf16", "f16"], default="f32")
     ap.add_argument("--surrogate", action="store_true",
                     help="also run the learned-surrogate leg (16^3 box, several minutes)")
     ap.add_argument("--surrogate-f0", type=float, default=10.0)
@@ -346,7 +347,7 @@ def main():
     import workloads as W
 
     GEOM = {"stored": P.SEMX_GEOM_STORED, "trilinear": P.SEMX_GEOM_TRILINEAR}
-    CONTRACTION = {"f32": P.SEMX_C_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}
+    CONTRACTION = {"f32": P.SEMX_C_F32, "mf32": P.SEMX_C_MFMA_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}
     ASSEMBLY = {"colored": P.SEMX_ASM_COLORED, "atomic": P.SEMX_ASM_ATOMIC}
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
@@ -377,7 +378,7 @@ def main():
     #      event-timed on the library stream
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
-    combos = [(c, g, a, args.patches) for c in ("f32", "bf16", "f16") for g in ("stored", "trilinear")
+    combos = [(c, g, a, args.patches) for c in ("f32", "mf32", "bf16", "f16") for g in ("stored", "trilinear")
               for a in ("colored", "atomic") if c == "f32" or a == "colored"]
     combos += [("f32", g, a, 8) for g in ("stored", "trilinear") for a in ("colored", "atomic")]
     if args.profile_force:

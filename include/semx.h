@@ -59,6 +59,7 @@ typedef struct semx_ctx semx_ctx;
 #define SEMX_C_F32 0       /* FP32 VALU contractions through LDS */
 #define SEMX_C_BF16 1      /* BF16-operand MFMA contractions, FP32 accumulation */
 #define SEMX_C_F16 2       /* FP16-operand MFMA contractions, FP32 accumulation */
+#define SEMX_C_MFMA_F32 3  /* FP32-operand MFMA contractions (v_mfma_f32_16x16x4f32) */
 
 /* assembly of element forces into the global vector (Sec. IV-C) */
 #define SEMX_ASM_COLORED 0 /* colour by colour, plain read-modify-write, deterministic */
@@ -111,7 +112,10 @@ int semx_mesh_info(semx_ctx *ctx, int64_t *nregular, int64_t *nirregular, int *n
 int semx_upload_model(semx_ctx *ctx, int nmodels, const double *lambda, const double *mu,
                       const double *rho);
 
-/* Select the contraction arithmetic and the assembly (constants above). */
+/* Select the contraction arithmetic and the assembly (constants above).
+ * The matrix-core contractions (SEMX_C_BF16, SEMX_C_F16, SEMX_C_MFMA_F32)
+ * need 4 <= NGLL <= 8; SEMX_EINVAL otherwise, or for an unknown value, or
+ * for coloured assembly on a mesh whose elements repeat a node. */
 int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 
 /* Geometry path of irregular (non-affine) elements (Sec. IV-D keeps the

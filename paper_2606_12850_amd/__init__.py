@@ -31,6 +31,7 @@ SEMX_ENUMERIC = -7
 SEMX_C_F32 = 0
 SEMX_C_BF16 = 1
 SEMX_C_F16 = 2
+SEMX_C_MFMA_F32 = 3
 SEMX_ASM_COLORED = 0
 SEMX_ASM_ATOMIC = 1
 SEMX_GEOM_STORED = 0

@@ -1355,7 +1355,8 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
 
 int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
   if (!c) return SEMX_EINVAL;
-  if (contraction != SEMX_C_F32 && contraction != SEMX_C_BF16 && contraction != SEMX_C_F16)
+  if (contraction != SEMX_C_F32 && contraction != SEMX_C_BF16 && contraction != SEMX_C_F16 &&
+      contraction != SEMX_C_MFMA_F32)
     return fail(c, SEMX_EINVAL, "set_mode: unknown contraction");
   if (assembly != SEMX_ASM_COLORED && assembly != SEMX_ASM_ATOMIC)
     return fail(c, SEMX_EINVAL, "set_mode: unknown assembly");

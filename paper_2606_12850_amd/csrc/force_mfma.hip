@@ -1,7 +1,8 @@
-// Mixed-precision force kernel: the six small contractions of the operator
+// Matrix-core force kernel: the six small contractions of the operator
 // (three forward, three transpose; Sec. II-B) run on gfx950 matrix cores as
-// v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation; the geometry map,
-// stress and assembly stay FP32.
+// v_mfma_f32_16x16x32_{bf16,f16} (mixed precision) or v_mfma_f32_16x16x4f32
+// (FP32 operands, n instructions of K = 4 per tile) with FP32 accumulation;
+// the geometry map, stress and assembly stay FP32.
 //
 // MFMA mapping.  For direction d the contraction of component c along the
 // element's "lines" (the n^2 index pairs orthogonal to d) is
@@ -43,6 +44,12 @@ struct Op<SEMX_C_BF16> {
   using vec = bf16x8;
   using elt = __bf16;
   __device__ static f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Op<SEMX_C_MFMA_F32> {  // FP32 operands: K = 4 per instruction, one value per lane
+  using vec = float __attribute__((ext_vector_type(8)));
+  using elt = float;
+  __device__ static f32x4 mma1(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 template <>
 struct Op<SEMX_C_F16> {
@@ -87,10 +94,11 @@ __device__ __forceinline__ float pow2_scale(float x) {
 // block-diagonal matrix of the pass; C[line][c NG + i] lands at point i of
 // the line in dst[(c, dir)].  `dst_cd` selects the index of the
 // (component, direction) slice: (c * 3 + dir) forward, (dir * 3 + c) transpose.
-template <int NG, class O, bool TRANSPOSE>
+template <int NG, int PREC, bool TRANSPOSE>
 __device__ __forceinline__ void contract_pass(const float* src, int src_stride_c, int src_stride_d, float* dst,
-                                              typename O::vec B, const float* ub, float sc, float isc, int wave,
-                                              int lane) {
+                                              typename Op<PREC>::vec B, const float* ub, float sc, float isc,
+                                              int wave, int lane) {
+  using O = Op<PREC>;
   using vec = typename O::vec;
   using elt = typename O::elt;
   constexpr int N3 = NG * NG * NG;
@@ -115,15 +123,22 @@ __device__ __forceinline__ void contract_pass(const float* src, int src_stride_c
     const bool va = kg < G && ca < 3 && line < NL;
     const float* sp = src + (va ? ca * src_stride_c + dir * src_stride_d + line_base<NG>(dir, line) : 0);
     const float off = !va ? 0.0f : (ca == 0 ? ub[0] : (ca == 1 ? ub[1] : ub[2]));
-    vec A;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      float v = 0.0f;
-      if (t < NG && va) v = (sp[t * stride] - off) * sc;
-      A[t] = (elt)v;
-    }
     f32x4 C = {0.f, 0.f, 0.f, 0.f};
-    C = O::mma(A, B, C);
+    if constexpr (PREC == SEMX_C_MFMA_F32) {
+      // one K = 4 step per point a of the line: lane group kg supplies its
+      // component's value at point a and the matching row of the block of D
+#pragma unroll
+      for (int t = 0; t < NG; ++t) C = O::mma1(va ? sp[t * stride] : 0.0f, B[t], C);
+    } else {
+      vec A;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        float v = 0.0f;
+        if (t < NG && va) v = (sp[t * stride] - off) * sc;
+        A[t] = (elt)v;
+      }
+      C = O::mma(A, B, C);
+    }
     // C rows 4 kg + r of the tile, column col = c_local * NG + i
     const int cc = cg * G + col / NG, i = col % NG;
     if (col < G * NG && cc < 3) {
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_mfma_kernel(ForceArgs a)
   // FP16 also scales it per element by a power of two
   float ub[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) ub[c] = s_u[c * N3];
+  for (int c = 0; c < 3; ++c) ub[c] = PREC == SEMX_C_MFMA_F32 ? 0.0f : s_u[c * N3];
   float su = 1.0f, isu = 1.0f;
   if constexpr (SCALE) {
     float um = 0.0f;
@@ -229,7 +244,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_mfma_kernel(ForceArgs a)
     su = pow2_scale(m);
     isu = 1.0f / su;
   }
-  contract_pass<NG, O, false>(s_u, N3, 0, s_d, Bf, ub, su, isu, wave, lane);
+  contract_pass<NG, PREC, false>(s_u, N3, 0, s_d, Bf, ub, su, isu, wave, lane);
   __syncthreads();
 
   // pointwise: geometry map, stress, fluxes (FP32)
@@ -261,7 +276,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_mfma_kernel(ForceArgs a)
   }
   const float zero3[3] = {0.f, 0.f, 0.f};
   // flux slice (c, d) sits at s_q[(c * 3 + d) * N3]: component stride 3 N3, direction stride N3
-  contract_pass<NG, O, true>(s_q, 3 * N3, N3, s_d, Bt, zero3, sq, isq, wave, lane);
+  contract_pass<NG, PREC, true>(s_q, 3 * N3, N3, s_d, Bt, zero3, sq, isq, wave, lane);
   __syncthreads();
 
   if (act) {
@@ -318,6 +333,7 @@ bool mfma_supported(int n) { return n >= 4 && n <= 8; }
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (prec == SEMX_C_BF16) return launch_mfma_p<SEMX_C_BF16>(n, geo, atomic, a, s);
   if (prec == SEMX_C_F16) return launch_mfma_p<SEMX_C_F16>(n, geo, atomic, a, s);
+  if (prec == SEMX_C_MFMA_F32) return launch_mfma_p<SEMX_C_MFMA_F32>(n, geo, atomic, a, s);
   return hipErrorInvalidValue;
 }
 
