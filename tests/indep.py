@@ -110,3 +110,26 @@ def mass_numpy(n, ibool, elem_vert, vert, rho, nglob):
     M = np.zeros(nglob)
     np.add.at(M, ibool.ravel(), (rho * det * w3[None, :]).ravel())
     return M
+
+
+def sem1d_bloch_omega(n, h, c, k):
+    """Frequency of the plane-wave branch exp(i k x) of the 1-D GLL spectral
+    element discretisation of u'' = c^2 u'' on a uniform lattice of side h
+    (lumped GLL mass, exact GLL stiffness), from the N x N Bloch system."""
+    N = n - 1
+    xi, w = gll_numpy(n)
+    D = dmatrix_barycentric(xi)
+    Ke = (2.0 / h) * c * c * (D.T * w) @ D
+    me = 0.5 * h * w
+    r = np.arange(n) % N
+    ph = np.exp(1j * k * h * (np.arange(n) // N))
+    P = np.zeros((n, N), dtype=np.complex128)
+    P[np.arange(n), r] = ph
+    Kr = P.conj().T @ Ke @ P
+    mr = np.zeros(N)
+    np.add.at(mr, r, me)
+    ev, V = np.linalg.eigh(Kr / np.sqrt(np.outer(mr, mr)))
+    x = 0.5 * (xi[:N] + 1.0) * h
+    pw = np.sqrt(mr) * np.exp(1j * k * x)
+    j = int(np.argmax(np.abs(V.conj().T @ pw)))
+    return float(np.sqrt(max(ev[j], 0.0)))

@@ -1,0 +1,124 @@
+"""Plane-wave dispersion of the library's time loop against the oracle's
+Bloch analysis (GPU).
+
+A periodic box of 5^3 cubic elements (wrap-around numbering, no special
+API) starts at rest from a P or S plane wave at about 5 GLL points per
+wavelength along [100] and [111], and is stepped by the library's explicit
+Newmark loop without sources.  Each step's displacement is projected,
+M-weighted, on the real Bloch mode that carries the wave; every other
+discrete mode is M-orthogonal to it, so the series has a single frequency
+and the fit of s_{n+1} + s_{n-1} = 2 C s_n returns the frequency omega_h of
+the library's space operator (the time step's own error is separated
+exactly, since the scheme is the central difference on each mode).
+
+The frequency is a Rayleigh quotient of the operator, so a relative operator
+error e moves it by at most about e / 2: FP32 operands (VALU and matrix-core
+paths) are held to 1e-5 relative, the FP32 force bar; BF16 and FP16 operands
+to half of their force bounds.  The measured dispersion errors
+omega / (c k) - 1 are printed next to the oracle's.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dispersion as Dp
+from tests.gpu_common import make_solver
+
+pytestmark = pytest.mark.gpu
+
+VP, VS, RHO = 3000.0, 1732.0, 2500.0
+MU = RHO * VS * VS
+LAM = RHO * VP * VP - 2.0 * MU
+NE = 5
+H = 100.0
+NSTEPS = 300
+COURANT = 0.4
+FREQ_BOUND = {"f32": 1e-5, "mf32": 1e-5, "f16": 2.5e-3, "bf16": 2.5e-2}
+
+
+def wave_numbers(n):
+    """Integer wave numbers m (k = 2 pi m / L) giving about 5 points per
+    wavelength, off the Brillouin-zone boundaries (m a multiple of NE)."""
+    N = n - 1
+    mx = N if N % NE else N - 1
+    q = max(1, int(round(N / np.sqrt(3.0))))
+    if q % NE == 0:
+        q -= 1
+    return {"[100]": (mx, 0, 0), "[111]": (q, q, q)}
+
+
+def cprec(P, prec):
+    return {"f32": P.SEMX_C_F32, "mf32": P.SEMX_C_MFMA_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}[prec]
+
+
+def projected_series(P, s, u0, w, nsteps):
+    import torch
+    u = torch.from_numpy(np.ascontiguousarray(u0, dtype=np.float32)).to(s.device)
+    z = torch.zeros_like(u)
+    wt = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to(s.device)
+    P.semx_set_state(s.ctx, u, z, z, 0)
+    buf = torch.empty_like(u)
+    out = [(u.double() * wt).sum()]
+    for _ in range(nsteps):
+        P.semx_step(s.ctx, 1)
+        P.semx_get_state(s.ctx, buf)
+        out.append((buf.double() * wt).sum())
+    return torch.stack(out).cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 9])
+def test_plane_wave_frequency_matches_bloch(n):
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh(NE, n, NE * H, periodic=True)
+    lam, mu, rho = W.homogeneous_model(mesh, VP, VS, RHO)
+    elem = Dp.element_matrices(n, H, LAM, MU, RHO)
+    s = make_solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    precs = ["f32", "mf32", "bf16", "f16"] if n <= 8 else ["f32"]
+    fails = []
+    for dname, m in wave_numbers(n).items():
+        for wave in "PS":
+            pw = Dp.periodic_plane_wave(mesh, LAM, MU, RHO, m, wave, elem)
+            ck = pw["c"] * pw["k"]
+            for prec in precs:
+                s.set_mode(cprec(P, prec), P.SEMX_ASM_COLORED)
+                dt = P.semx_cfl_dt(s.ctx, COURANT)
+                P.semx_set_dt(s.ctx, dt)
+                ser = projected_series(P, s, pw["u0"], pw["w"], NSTEPS)
+                omega_h, omega_run = Dp.fit_frequency(ser, dt)
+                C = 1.0 - 0.5 * (omega_h * dt) ** 2
+                resid = np.linalg.norm(ser[2:] + ser[:-2] - 2 * C * ser[1:-1]) / np.linalg.norm(ser)
+                dev = omega_h / pw["omega_h"] - 1.0
+                print(f"dispersion n={n} {dname} {wave} ppw={pw['ppw']:.2f} {prec}: "
+                      f"omega_h/(ck)-1 library {omega_h / ck - 1:+.4e} oracle {pw['omega_h'] / ck - 1:+.4e} "
+                      f"(rel diff {dev:+.2e}); with dt {omega_run / ck - 1:+.4e}; fit residual {resid:.1e}")
+                if not abs(dev) <= FREQ_BOUND[prec]:
+                    fails.append((dname, wave, prec, dev))
+    s.close()
+    assert not fails, fails
+
+
+def test_plane_wave_atomic_assembly_and_reset():
+    """The atomic assembly path gives the same frequency, and a second run
+    from the same state reproduces the first series (state fully reset)."""
+    import paper_2606_12850_amd as P
+    n = 5
+    mesh = W.box_mesh(NE, n, NE * H, periodic=True)
+    lam, mu, rho = W.homogeneous_model(mesh, VP, VS, RHO)
+    pw = Dp.periodic_plane_wave(mesh, LAM, MU, RHO, (2, 1, 0), "S")
+    s = make_solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    dt = P.semx_cfl_dt(s.ctx, COURANT)
+    P.semx_set_dt(s.ctx, dt)
+    res = {}
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        s.set_mode(P.SEMX_C_F32, asm)
+        a = projected_series(P, s, pw["u0"], pw["w"], 120)
+        b = projected_series(P, s, pw["u0"], pw["w"], 120)
+        if asm == P.SEMX_ASM_COLORED:
+            assert np.array_equal(a, b)
+        res[asm] = Dp.fit_frequency(a, dt)[0]
+        assert abs(res[asm] / pw["omega_h"] - 1.0) <= 1e-5
+    s.close()

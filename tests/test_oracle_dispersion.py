@@ -1,0 +1,190 @@
+"""Pins of the oracle's Bloch dispersion analysis (no GPU).
+
+The Bloch eigenproblem is assembled from the oracle's own element force, so
+these tests pin that operator through its plane-wave spectrum:
+  * linear elements (N = 1) with lumped mass reduce, for waves along a
+    lattice axis, to the 1-D lattice omega = (2 c / h) sin(k h / 2);
+  * for every order, a P or S wave along a lattice axis reduces exactly to the
+    1-D GLL spectral element problem (the cross-axis terms telescope to zero
+    across periodic neighbours), re-derived independently in tests/indep.py;
+  * the relative error decays like (k h)^{2N} (spectral accuracy of GLL
+    elements with lumped mass, Sec. II-B; the paper's dispersion study relies
+    on it), and at long wavelength every direction propagates at the
+    continuum P and S speeds of isotropic Hooke's law;
+  * k = 0 leaves exactly the three rigid translations at zero frequency.
+"""
+import numpy as np
+import pytest
+
+from oracle import dispersion as Dp
+from tests import indep
+
+H = 100.0
+# vp/vs = 2.5, so lambda != mu: a swapped pair of Lame moduli changes both speeds
+RHO = 2200.0
+VP, VS = 4000.0, 1600.0
+MU = RHO * VS * VS
+LAM = RHO * VP * VP - 2.0 * MU
+
+
+def main_branch(branches):
+    return max(branches, key=lambda b: b[2])[0]
+
+
+@pytest.fixture(scope="module")
+def elem():
+    cache = {}
+
+    def get(n):
+        if n not in cache:
+            cache[n] = Dp.element_matrices(n, H, LAM, MU, RHO)
+        return cache[n]
+    return get
+
+
+def test_element_stiffness_symmetric_psd(elem):
+    for n in (2, 4):
+        K, m = elem(n)
+        assert np.max(np.abs(K - K.T)) <= 1e-12 * np.max(np.abs(K))
+        ev = np.linalg.eigvalsh(0.5 * (K + K.T))
+        assert ev[0] >= -1e-10 * ev[-1]
+        assert np.all(m > 0) and abs(m.sum() - RHO * H ** 3) <= 1e-9 * RHO * H ** 3
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_linear_element_closed_form(elem, axis):
+    K, m = elem(2)
+    cp, cs = VP, VS
+    for kh in (0.3, 1.0, 2.5):
+        kvec = np.zeros(3); kvec[axis] = kh / H
+        pol_s = np.zeros(3); pol_s[(axis + 1) % 3] = 1.0
+        pol_p = np.zeros(3); pol_p[axis] = 1.0
+        wp = main_branch(Dp.plane_wave_branches(2, H, K, m, kvec, [pol_p])[0])
+        ws = main_branch(Dp.plane_wave_branches(2, H, K, m, kvec, [pol_s])[0])
+        np.testing.assert_allclose(wp, 2 * cp / H * np.sin(kh / 2), rtol=1e-12)
+        np.testing.assert_allclose(ws, 2 * cs / H * np.sin(kh / 2), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 8])
+def test_axis_waves_equal_1d_sem(elem, n):
+    K, m = elem(n)
+    for kh in (0.7, 1.9, 2.6, 4.0):
+        k = kh / H
+        for axis, pol, c in ((0, [1, 0, 0], VP), (0, [0, 1, 0], VS), (2, [1, 0, 0], VS), (1, [0, 1, 0], VP)):
+            kvec = np.zeros(3); kvec[axis] = k
+            w = main_branch(Dp.plane_wave_branches(n, H, K, m, kvec, [pol])[0])
+            np.testing.assert_allclose(w, indep.sem1d_bloch_omega(n, H, c, k), rtol=1e-11)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6])
+def test_spectral_convergence_axis(elem, n):
+    """Error ratio between 9 and 18 points per wavelength: 2^{2N}."""
+    K, m = elem(n)
+    N = n - 1
+    for wave in "PS":
+        e9 = Dp.dispersion_error(n, H, LAM, MU, RHO, [1, 0, 0], 9.0, wave, K, m)["error"]
+        e18 = Dp.dispersion_error(n, H, LAM, MU, RHO, [1, 0, 0], 18.0, wave, K, m)["error"]
+        assert e9 < 0 and e18 < 0  # lumped GLL mass: axis waves are slow
+        assert abs(np.log2(e9 / e18) - 2 * N) <= 0.25
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_spectral_convergence_oblique(elem, n):
+    """Off-axis the P and S error terms mix before the asymptotic range, so
+    the ratio is taken between 18 and 36 points per wavelength (at higher
+    orders the error there is at the eigen-solver's rounding level)."""
+    K, m = elem(n)
+    N = n - 1
+    for d in ([1, 2, 0], [1, 1, 1], [1, 2, 3]):
+        for wave in "PS":
+            e18 = Dp.dispersion_error(n, H, LAM, MU, RHO, d, 18.0, wave, K, m)["error"]
+            e36 = Dp.dispersion_error(n, H, LAM, MU, RHO, d, 36.0, wave, K, m)["error"]
+            assert abs(np.log2(abs(e18 / e36)) - 2 * N) <= 0.25
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_long_wave_isotropic_speeds(elem, n):
+    K, m = elem(n)
+    for d in ([1, 0, 0], [0, 1, 1], [1, 1, 1], [1, 2, 3], [-3, 1, 2]):
+        for wave in "PS":
+            r = Dp.dispersion_error(n, H, LAM, MU, RHO, d, 60.0, wave, K, m)
+            assert not r["boundary"] and r["captured"] > 0.9999
+            assert max(abs(e) for e in r["branches"]) <= 1e-5
+
+
+def test_cubic_symmetry(elem):
+    K, m = elem(4)
+    for wave in "PS":
+        ref = Dp.dispersion_error(4, H, LAM, MU, RHO, [1, 0, 0], 5.0, wave, K, m)["error"]
+        for d in ([0, 1, 0], [0, 0, 1], [-1, 0, 0]):
+            e = Dp.dispersion_error(4, H, LAM, MU, RHO, d, 5.0, wave, K, m)["error"]
+            assert abs(e - ref) <= 1e-12
+        ref = Dp.dispersion_error(4, H, LAM, MU, RHO, [1, 1, 1], 5.0, wave, K, m)["error"]
+        for d in ([-1, 1, 1], [1, -1, 1], [1, 1, -1]):
+            e = Dp.dispersion_error(4, H, LAM, MU, RHO, d, 5.0, wave, K, m)["error"]
+            assert abs(e - ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_rigid_translations(elem, n):
+    K, m = elem(n)
+    w, V, Mr = Dp.bloch_modes(n, H, K, m, [0.0, 0.0, 0.0])
+    assert np.all(w[:3] <= 1e-6 * w[-1])
+    assert w[3] >= 1e-2 * w[-1]
+
+
+def test_zone_boundary_split(elem):
+    """At k h = 2 pi (N = 5, 5 points per wavelength) k and -k coincide as
+    Bloch vectors: the wave is carried by two standing modes, both close to
+    c k; at 5.5 points per wavelength by one travelling mode."""
+    K, m = elem(6)
+    r = Dp.dispersion_error(6, H, LAM, MU, RHO, [1, 0, 0], 5.0, "P", K, m)
+    assert r["boundary"] and len(r["branches"]) == 2 and r["captured"] > 0.999
+    e0, e1 = r["branches"]
+    assert e0 < e1 and abs(e0) < 0.02 and abs(e1) < 0.02
+    r = Dp.dispersion_error(6, H, LAM, MU, RHO, [1, 0, 0], 5.5, "P", K, m)
+    assert not r["boundary"] and len(r["branches"]) == 1 and r["captured"] > 0.999
+
+
+def test_shear_branches(elem):
+    """Along [100] and [111] the two S polarisations are degenerate by
+    symmetry (one eigenspace); along [1,2,3] the discrete lattice splits
+    them into two quasi-S branches."""
+    K, m = elem(4)
+    for d in ([1, 0, 0], [1, 1, 1]):
+        r = Dp.dispersion_error(4, H, LAM, MU, RHO, d, 5.0, "S", K, m)
+        assert len(r["branches"]) == 1 and r["captured"] > 0.99
+    r = Dp.dispersion_error(4, H, LAM, MU, RHO, [1, 2, 3], 5.0, "S", K, m)
+    assert len(r["branches"]) == 2 and r["captured"] > 0.98
+    assert abs(r["branches"][0] - r["branches"][1]) > 1e-6
+
+
+def test_mode_on_lattice_is_bloch_periodic():
+    n, N = 4, 3
+    k = np.array([2 * np.pi / (5 * H), 0.0, 4 * np.pi / (5 * H)])
+    v = np.arange(3 * N ** 3) + 1j
+    g = np.arange(5 * N)
+    phi = Dp.mode_on_lattice(n, H, v, k, g, np.zeros_like(g), np.zeros_like(g))
+    # one element to the right multiplies by exp(i k_x h)
+    np.testing.assert_allclose(phi[N:], phi[:-N] * np.exp(1j * k[0] * H), rtol=1e-13)
+    x = Dp.lattice_coordinates(n, H, g, g, g)
+    assert np.all(np.diff(x[:, 0]) > 0) and abs(x[N, 0] - H) < 1e-12
+
+
+@pytest.mark.parametrize("n,m,wave", [(4, (3, 0, 0), "P"), (4, (2, 2, 2), "S"), (5, (1, 2, 0), "S")])
+def test_periodic_mesh_time_loop_recovers_bloch_frequency(n, m, wave):
+    """The assembled operator of a periodic 5^3-element box (wrap-around
+    numbering), stepped in FP64 from a sampled plane wave, projected on the
+    Bloch mode and fitted, gives the one-element Bloch frequency: pins the
+    Bloch reduction against the assembled operator, and the projection and
+    fit that the GPU dispersion test uses."""
+    import workloads as W
+    mesh = W.box_mesh(5, n, 5 * H, periodic=True)
+    pw = Dp.periodic_plane_wave(mesh, LAM, MU, RHO, m, wave)
+    assert pw["captured"] > 0.99
+    dt = 0.3 * 0.17 * H / VP
+    s = Dp.newmark_free(mesh, LAM, MU, RHO, pw["u0"], dt, 60, pw["w"])
+    omega_h, omega_run = Dp.fit_frequency(s, dt)
+    assert abs(omega_h / pw["omega_h"] - 1.0) <= 1e-10
+    # the run's frequency is the central-difference image of omega_h
+    assert abs(omega_run - 2.0 / dt * np.arcsin(pw["omega_h"] * dt / 2.0)) <= 1e-9 * omega_run
