@@ -30,8 +30,9 @@
  *     coordinates (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the geometry is the
  *     trilinear map of the 8 corners.
  *   - Vectors over global nodes are FP32 [nmodels][nglob][3], component
- *     fastest.  f = -K u is the internal force (the negative stiffness
- *     action), the right-hand-side term of the weak form.
+ *     fastest (FP64 with SEMX_F64 storage, see semx_set_storage()).
+ *     f = -K u is the internal force (the negative stiffness action), the
+ *     right-hand-side term of the weak form.
  */
 #ifndef SEMX_H
 #define SEMX_H
@@ -64,6 +65,10 @@ typedef struct semx_ctx semx_ctx;
 /* assembly of element forces into the global vector (Sec. IV-C) */
 #define SEMX_ASM_COLORED 0 /* colour by colour, plain read-modify-write, deterministic */
 #define SEMX_ASM_ATOMIC 1  /* one launch, FP32 global atomic adds */
+
+/* storage and arithmetic of the state vectors and the time loop */
+#define SEMX_F32 0         /* FP32 fields, force and Newmark update (default) */
+#define SEMX_F64 1         /* FP64 fields, FP64 force, Newmark, sources and receivers */
 
 /* Create a context for n = ngll GLL points per direction whose GPU work runs
  * on hip_stream (a hipStream_t; NULL = the default stream) of the current
@@ -241,6 +246,46 @@ int semx_set_checkpointing(semx_ctx *ctx, int64_t every);
  * semx_reset() that started the forward run. */
 int semx_adjoint(semx_ctx *ctx, const float *gseis_dev, int64_t nt, double *g_lambda_dev,
                  double *g_mu_dev, double *g_rho_dev);
+
+/* ---------------------------------------------------------------------------
+ * FP64 storage.  The same operator (Sec. II-B) and time loop (Sec. V-C) with
+ * state vectors, geometry map Gamma, lambda W, mu W, M^{-1}, the force and
+ * all sums in FP64, for runs that must agree with an FP64 reference to FP64
+ * rounding and for finite-difference checks.  Contractions run on the
+ * vector units (SEMX_C_F32 is the only valid contraction setting; other
+ * settings give SEMX_EINVAL); coloured and atomic assembly both work, the
+ * atomic one with FP64 atomic adds.  In this mode the FP32 entry points that
+ * move state vectors or seismograms (semx_apply_force, semx_get_state,
+ * semx_set_state, semx_read_seismograms) and the adjoint
+ * (semx_set_checkpointing, semx_adjoint) return SEMX_ESTATE; the _f64
+ * variants below take their place.  Everything else (mesh, model, dt,
+ * receivers, reset, step, energy, watchdog) works unchanged.
+ * ------------------------------------------------------------------------- */
+
+/* Select SEMX_F32 or SEMX_F64 (default SEMX_F32).  Allowed before
+ * semx_upload_model() only (SEMX_ESTATE after it, and while checkpointing is
+ * on); SEMX_EINVAL for an unknown value or, for SEMX_F64, while a
+ * matrix-core contraction is selected. */
+int semx_set_storage(semx_ctx *ctx, int storage);
+
+/* f = -K u in FP64: u_dev, f_dev device FP64 [nmodels][nglob][3], f
+ * overwritten, no overlap.  Needs SEMX_F64 storage. */
+int semx_apply_force_f64(semx_ctx *ctx, const double *u_dev, double *f_dev);
+
+/* semx_set_sources() with an FP64 time function stf [nsrc][nstf] (used
+ * exactly by SEMX_F64 storage, rounded to FP32 for SEMX_F32). */
+int semx_set_sources_f64(semx_ctx *ctx, int nsrc, const int32_t *elem, const double *xi,
+                         const double *dir, int64_t nstf, const double *stf);
+
+/* FP64 seismograms [nmodels][nrec][3][nt_max] to device (out_on_device != 0)
+ * or host memory.  Needs SEMX_F64 storage. */
+int semx_read_seismograms_f64(semx_ctx *ctx, double *out, int out_on_device);
+
+/* FP64 checkpoint copies of u, v, a (device [nmodels][nglob][3]; NULL skips
+ * one in get_state).  Needs SEMX_F64 storage. */
+int semx_get_state_f64(semx_ctx *ctx, double *u_dev, double *v_dev, double *a_dev, int64_t *it);
+int semx_set_state_f64(semx_ctx *ctx, const double *u_dev, const double *v_dev, const double *a_dev,
+                       int64_t it);
 
 /* Kernel timing.  While enabled, every force-kernel launch is bracketed by a
  * pair of HIP events recorded on the context stream.  semx_force_timing()

@@ -36,6 +36,8 @@ SEMX_ASM_COLORED = 0
 SEMX_ASM_ATOMIC = 1
 SEMX_GEOM_STORED = 0
 SEMX_GEOM_TRILINEAR = 1
+SEMX_F32 = 0
+SEMX_F64 = 1
 
 _ERRNAMES = {-1: "EINVAL", -2: "ESTATE", -3: "EGEOM", -4: "EUNSTABLE", -5: "EHIP", -6: "ENOMEM",
              -7: "ENUMERIC"}
@@ -89,6 +91,12 @@ _SIGS = {
     "semx_mlp_backward": [_vp, _vp, _i32],
     "semx_mlp_mse": [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_f64)],
     "semx_mlp_adam": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64],
+    "semx_set_storage": [_vp, _i32],
+    "semx_apply_force_f64": [_vp, _vp, _vp],
+    "semx_set_sources_f64": [_vp, _i32, _vp, _vp, _vp, _i64, _vp],
+    "semx_read_seismograms_f64": [_vp, _vp, _i32],
+    "semx_get_state_f64": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i64)],
+    "semx_set_state_f64": [_vp, _vp, _vp, _vp, _i64],
     "semx_set_timing": [_vp, _i32],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
@@ -232,6 +240,16 @@ def semx_set_sources(ctx, elem, xi, direction, stf):
     return _check(ctx, lib().semx_set_sources(ctx, nsrc, _ptr(el), _ptr(x), _ptr(d), nstf, _ptr(s)))
 
 
+def semx_set_sources_f64(ctx, elem, xi, direction, stf):
+    el = np.ascontiguousarray(elem, dtype=np.int32)
+    x = np.ascontiguousarray(xi, dtype=np.float64)
+    d = np.ascontiguousarray(direction, dtype=np.float64)
+    s = np.ascontiguousarray(stf, dtype=np.float64)
+    nsrc = len(el)
+    nstf = s.shape[-1] if nsrc else 0
+    return _check(ctx, lib().semx_set_sources_f64(ctx, nsrc, _ptr(el), _ptr(x), _ptr(d), nstf, _ptr(s)))
+
+
 def semx_set_receivers(ctx, elem, xi, nt_max: int):
     el = np.ascontiguousarray(elem, dtype=np.int32)
     x = np.ascontiguousarray(xi, dtype=np.float64)
@@ -264,6 +282,28 @@ def semx_get_state(ctx, u=None, v=None, a=None) -> int:
 
 def semx_set_state(ctx, u, v, a, it: int):
     return _check(ctx, lib().semx_set_state(ctx, _ptr(u), _ptr(v), _ptr(a), int(it)))
+
+
+def semx_set_storage(ctx, storage: int):
+    return _check(ctx, lib().semx_set_storage(ctx, int(storage)))
+
+
+def semx_apply_force_f64(ctx, u, f):
+    return _check(ctx, lib().semx_apply_force_f64(ctx, _ptr(u), _ptr(f)))
+
+
+def semx_read_seismograms_f64(ctx, out, on_device: bool):
+    return _check(ctx, lib().semx_read_seismograms_f64(ctx, _ptr(out), 1 if on_device else 0))
+
+
+def semx_get_state_f64(ctx, u=None, v=None, a=None) -> int:
+    it = _i64()
+    _check(ctx, lib().semx_get_state_f64(ctx, _ptr(u), _ptr(v), _ptr(a), ctypes.byref(it)))
+    return it.value
+
+
+def semx_set_state_f64(ctx, u, v, a, it: int):
+    return _check(ctx, lib().semx_set_state_f64(ctx, _ptr(u), _ptr(v), _ptr(a), int(it)))
 
 
 def semx_energy(ctx):
@@ -378,15 +418,19 @@ def semx_force_timing(ctx):
 # ---- convenience wrapper -------------------------------------------------------
 
 class Solver:
-    """One library context bound to torch's current HIP stream on ``device``."""
+    """One library context bound to torch's current HIP stream on ``device``;
+    ``storage`` SEMX_F32 (default) or SEMX_F64 (fields and time loop in FP64)."""
 
-    def __init__(self, ngll: int, device: str = "cuda:0"):
+    def __init__(self, ngll: int, device: str = "cuda:0", storage: int = SEMX_F32):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             self.ctx = semx_create(ngll, self.stream)
+        self.storage = storage
+        if storage != SEMX_F32:
+            semx_set_storage(self.ctx, storage)
         self.n = ngll
         self.nspec = self.nglob = self.nmodels = 0
         self.nrec = 0
@@ -418,16 +462,23 @@ class Solver:
 
     def empty_field(self):
         shape = (self.nmodels, self.nglob, 3) if self.nmodels > 1 else (self.nglob, 3)
-        return self.torch.zeros(shape, dtype=self.torch.float32, device=self.device)
+        dt = self.torch.float64 if self.storage == SEMX_F64 else self.torch.float32
+        return self.torch.zeros(shape, dtype=dt, device=self.device)
 
     def apply_force(self, u, out=None):
         f = self.empty_field() if out is None else out
-        semx_apply_force(self.ctx, u, f)
+        if self.storage == SEMX_F64:
+            semx_apply_force_f64(self.ctx, u, f)
+        else:
+            semx_apply_force(self.ctx, u, f)
         return f
 
     def setup_run(self, wl, dt=None):
         """Sources, receivers and dt from a workloads.Workload."""
-        semx_set_sources(self.ctx, wl.src_elem, wl.src_xi, wl.src_dir, wl.stf.astype(np.float32))
+        if self.storage == SEMX_F64:
+            semx_set_sources_f64(self.ctx, wl.src_elem, wl.src_xi, wl.src_dir, wl.stf)
+        else:
+            semx_set_sources(self.ctx, wl.src_elem, wl.src_xi, wl.src_dir, wl.stf.astype(np.float32))
         semx_set_receivers(self.ctx, wl.rec_elem, wl.rec_xi, wl.nt)
         self.nrec, self.nt_max = len(wl.rec_elem), wl.nt
         semx_set_dt(self.ctx, wl.dt if dt is None else dt)
@@ -437,6 +488,10 @@ class Solver:
         semx_step(self.ctx, nsteps)
 
     def seismograms(self):
-        out = np.zeros((max(self.nmodels, 1), self.nrec, 3, self.nt_max), np.float32)
-        semx_read_seismograms(self.ctx, out, False)
+        if self.storage == SEMX_F64:
+            out = np.zeros((max(self.nmodels, 1), self.nrec, 3, self.nt_max), np.float64)
+            semx_read_seismograms_f64(self.ctx, out, False)
+        else:
+            out = np.zeros((max(self.nmodels, 1), self.nrec, 3, self.nt_max), np.float32)
+            semx_read_seismograms(self.ctx, out, False)
         return out if self.nmodels > 1 else out[0]

@@ -60,13 +60,14 @@ inline unsigned grid_for(int64_t n, int cap = 1 << 16) {
 // ---------------------------------------------------------------------------
 // Geometry (FP64): J = dx/dxi of the trilinear map at every GLL point,
 // det J, Gamma = J^{-1} (rows: gradients of the reference coordinates), and
-// W = w_i w_j w_k det J.  Gamma goes out in FP32 when requested.  Outputs
-// are stored at the element's launch position (order[pos] = element).
+// W = w_i w_j w_k det J.  Gamma goes out in FP32 and/or FP64 when requested.
+// Outputs are stored at the element's launch position (order[pos] = element).
 // ---------------------------------------------------------------------------
 __global__ void geom_kernel(int n, int64_t nspec, const double* __restrict__ vert,
                             const int32_t* __restrict__ ev, const int32_t* __restrict__ order,
                             const double* __restrict__ xi, const double* __restrict__ w,
-                            float* __restrict__ gam_pt, double* __restrict__ wdet, int* __restrict__ bad) {
+                            float* __restrict__ gam_pt, double* __restrict__ wdet, int* __restrict__ bad,
+                            double* __restrict__ gam64) {
   const int n3 = n * n * n;
   const int64_t total = nspec * n3;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -111,6 +112,13 @@ __global__ void geom_kernel(int n, int64_t nspec, const double* __restrict__ ver
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int b = 0; b < 3; ++b) gp[(d * 3 + b) * n3] = (float)(C[b][d] * inv);
+    }
+    if (gam64) {
+      double* gp = gam64 + pos * 9 * n3 + q;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gp[(d * 3 + b) * n3] = C[b][d] * inv;
     }
   }
 }
@@ -777,7 +785,8 @@ int build_layout(semx_ctx* c) {
   SEMX_HIP(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
   geom_kernel<<<grid_for(nspec * n3, 8192), kThreads, 0, c->stream>>>(
       c->n, nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_order.as<int32_t>(),
-      c->d_xi64.as<double>(), c->d_w64.as<double>(), c->d_gam_pt.as<float>(), c->d_wdet.as<double>(), bad);
+      c->d_xi64.as<double>(), c->d_w64.as<double>(), c->d_gam_pt.as<float>(), c->d_wdet.as<double>(), bad,
+      nullptr);
   SEMX_HIP(c, hipGetLastError());
   int hbad = 0;
   SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -844,6 +853,24 @@ int zero_f32(semx_ctx* c, float* p, int64_t n) {
 }
 
 int64_t state_len(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * 3; }
+
+// Seismogram buffer [nmodels][nrec][3][nt_max] in the storage precision, zeroed.
+int alloc_seismograms(semx_ctx* c) {
+  const int nm = c->nmodels > 0 ? c->nmodels : 1;
+  const int64_t cnt = (int64_t)nm * c->rec.nrec * 3 * c->rec.nt_max;
+  if (c->storage == SEMX_F64) {
+    dev_free(c->rec.seis);
+    int rc = dev_alloc(c, c->rec.seis64, sizeof(double) * cnt);
+    if (rc) return rc;
+    fill_f64<<<grid_for(cnt), kThreads, 0, c->stream>>>(c->rec.seis64.as<double>(), cnt, 0.0);
+    SEMX_HIP(c, hipGetLastError());
+    return SEMX_OK;
+  }
+  dev_free(c->rec.seis64);
+  int rc = dev_alloc(c, c->rec.seis, sizeof(float) * cnt);
+  if (rc) return rc;
+  return zero_f32(c, c->rec.seis.as<float>(), cnt);
+}
 
 // The FP32 force runs on element patches when they are built.
 bool use_patches(const semx_ctx* c) { return c->patches_ok && c->contraction == SEMX_C_F32; }
@@ -921,6 +948,7 @@ int inject_sources(semx_ctx* c, int64_t m, float* f) {
 }
 
 int finalize_state(semx_ctx* c) {
+  if (c->storage == SEMX_F64) return f64_finalize(c);
   if (!c->pending_correct) return SEMX_OK;
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
   newmark_kernel<kCorrect | kStoreA><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(
@@ -932,6 +960,7 @@ int finalize_state(semx_ctx* c) {
 }
 
 int do_reset(semx_ctx* c) {
+  if (c->storage == SEMX_F64) return f64_reset(c);
   const int64_t len = state_len(c);
   for (auto* b : {&c->d_u, &c->d_v, &c->d_a, &c->d_f}) {
     int rc = zero_f32(c, b->as<float>(), len);
@@ -968,6 +997,7 @@ int record_receivers(semx_ctx* c, int64_t idx) {
 
 
 int energy_model0(semx_ctx* c, double* kin, double* pot) {
+  if (c->storage == SEMX_F64) return f64_energy(c, kin, pot);
   int rc = finalize_state(c);
   if (rc) return rc;
   const int64_t n3g = 3 * c->nglob;
@@ -998,6 +1028,7 @@ int energy_model0(semx_ctx* c, double* kin, double* pot) {
 }
 
 int check_finite(semx_ctx* c, bool* ok) {
+  if (c->storage == SEMX_F64) return f64_check_finite(c, ok);
   int* flag = scratch_i(c);
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync flag");
@@ -1017,6 +1048,7 @@ int check_finite(semx_ctx* c, bool* ok) {
 // One explicit Newmark step (correct the pending step, predict, force,
 // sources; optionally record receivers).  Leaves f = -K u + f_src pending.
 int step_once(semx_ctx* c, bool record) {
+  if (c->storage == SEMX_F64) return f64_step_once(c, record);
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
   const float dt = (float)c->dt;
   float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
@@ -1043,6 +1075,67 @@ int step_once(semx_ctx* c, bool record) {
 int apply_force_accumulate(semx_ctx* c, const float* u, float* f) { return force_accumulate(c, u, f); }
 int fill_zero(semx_ctx* c, float* p, int64_t n) { return zero_f32(c, p, n); }
 int complete_step(semx_ctx* c) { return finalize_state(c); }
+// Point sources with the time function given in FP32 (stf32) or FP64
+// (stf64); both precisions are kept on the device for the two storage modes.
+int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* xi, const double* dir,
+                     int64_t nstf, const float* stf32, const double* stf64) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "set_sources: no mesh");
+  if (nsrc < 0) return fail(c, SEMX_EINVAL, "set_sources: nsrc < 0");
+  if (nsrc == 0) {
+    c->src.nsrc = 0;
+    return SEMX_OK;
+  }
+  if (!elem || !xi || !dir || (!stf32 && !stf64) || nstf <= 0)
+    return fail(c, SEMX_EINVAL, "set_sources: bad arguments");
+  const int n = c->n, n3 = c->n3;
+  std::vector<int32_t> nodes((size_t)nsrc * n3);
+  std::vector<float> wdir((size_t)nsrc * n3 * 3);
+  std::vector<double> wdir64((size_t)nsrc * n3 * 3);
+  for (int s = 0; s < nsrc; ++s) {
+    if (elem[s] < 0 || elem[s] >= c->nspec) return fail(c, SEMX_EINVAL, "set_sources: element out of range");
+    for (int d = 0; d < 3; ++d)
+      if (!(xi[3 * s + d] >= -1.0 && xi[3 * s + d] <= 1.0))
+        return fail(c, SEMX_EINVAL, "set_sources: reference coordinate outside [-1, 1]");
+    double lx[kMaxN], ly[kMaxN], lz[kMaxN];
+    lagrange_at(n, c->xi, xi[3 * s + 0], lx);
+    lagrange_at(n, c->xi, xi[3 * s + 1], ly);
+    lagrange_at(n, c->xi, xi[3 * s + 2], lz);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const int q = i + n * (j + n * k);
+          nodes[(size_t)s * n3 + q] = c->h_ibool[(size_t)elem[s] * n3 + q];
+          const double wq = lx[i] * ly[j] * lz[k];
+          for (int d = 0; d < 3; ++d) {
+            wdir64[((size_t)s * n3 + q) * 3 + d] = wq * dir[3 * s + d];
+            wdir[((size_t)s * n3 + q) * 3 + d] = (float)(wq * dir[3 * s + d]);
+          }
+        }
+  }
+  const size_t ns = (size_t)nsrc * nstf;
+  std::vector<float> s32(ns);
+  std::vector<double> s64(ns);
+  for (size_t t = 0; t < ns; ++t) {
+    s64[t] = stf64 ? stf64[t] : (double)stf32[t];
+    s32[t] = stf32 ? stf32[t] : (float)stf64[t];
+  }
+  int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
+  if (!rc) rc = dev_alloc(c, c->src.wdir, wdir.size() * sizeof(float));
+  if (!rc) rc = dev_alloc(c, c->src.stf, sizeof(float) * ns);
+  if (!rc) rc = dev_alloc(c, c->src.wdir64, wdir64.size() * sizeof(double));
+  if (!rc) rc = dev_alloc(c, c->src.stf64, sizeof(double) * ns);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpy(c->src.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.wdir.p, wdir.data(), wdir.size() * sizeof(float), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.stf.p, s32.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.wdir64.p, wdir64.data(), wdir64.size() * sizeof(double), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.stf64.p, s64.data(), sizeof(double) * ns, hipMemcpyHostToDevice));
+  c->src.nsrc = nsrc;
+  c->src.nstf = nstf;
+  return SEMX_OK;
+}
+
 unsigned grid_1d(int64_t n, int cap) { return grid_for(n, cap); }
 
 }  // namespace semx
@@ -1104,6 +1197,8 @@ int semx_destroy(semx_ctx* c) {
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
                     &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis,
+                    &c->src.wdir64, &c->src.stf64, &c->rec.wts64, &c->rec.seis64, &c->d_gam64, &c->d_mat64,
+                    &c->d_minv64, &c->d_D64,
                     &c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs, &c->d_first})
     dev_free(*b);
   delete c;
@@ -1307,11 +1402,15 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
   if (!rc) rc = dev_alloc(c, c->d_mass64, sizeof(double) * nmodels * c->nglob);
   if (!rc) rc = dev_alloc(c, c->d_minv, sizeof(float) * nmodels * c->nglob);
   const int64_t len = 3 * (int64_t)nmodels * c->nglob;
-  if (!rc) rc = dev_alloc(c, c->d_u, sizeof(float) * len);
-  if (!rc) rc = dev_alloc(c, c->d_v, sizeof(float) * len);
-  if (!rc) rc = dev_alloc(c, c->d_a, sizeof(float) * len);
-  if (!rc) rc = dev_alloc(c, c->d_f, sizeof(float) * len);
-  if (!rc) rc = dev_alloc(c, c->d_work, sizeof(float) * len);
+  const size_t es = c->storage == SEMX_F64 ? sizeof(double) : sizeof(float);
+  if (!rc) rc = dev_alloc(c, c->d_u, es * len);
+  if (!rc) rc = dev_alloc(c, c->d_v, es * len);
+  if (!rc) rc = dev_alloc(c, c->d_a, es * len);
+  if (!rc) rc = dev_alloc(c, c->d_f, es * len);
+  if (!rc) rc = dev_alloc(c, c->d_work, es * len);
+  if (!rc && c->storage == SEMX_F64) rc = dev_alloc(c, c->d_gam64, sizeof(double) * 9 * c->nspec * c->n3);
+  if (!rc && c->storage != SEMX_F64)
+    for (DevBuf* b : {&c->d_gam64, &c->d_mat64, &c->d_minv64}) dev_free(*b);
   auto cleanup = [&]() { dev_free(dl); dev_free(dm); dev_free(dr); };
   if (rc) { cleanup(); return rc; }
   hipError_t e = hipMemcpy(dl.p, lambda, sizeof(double) * npt, hipMemcpyHostToDevice);
@@ -1340,14 +1439,24 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
                                                                         c->d_mass64.as<double>(),
                                                                         c->d_minv.as<float>());
   e = hipGetLastError();
+  if (e == hipSuccess && c->storage == SEMX_F64) {
+    // FP64 Gamma by launch position (the same map; W is recomputed bitwise equal)
+    geom_kernel<<<grid_for(c->nspec * c->n3, 8192), kThreads, 0, c->stream>>>(
+        c->n, c->nspec, c->d_vert.as<double>(), c->d_elem_vert.as<int32_t>(), c->d_order.as<int32_t>(),
+        c->d_xi64.as<double>(), c->d_w64.as<double>(), nullptr, c->d_wdet.as<double>(), scratch_i(c),
+        c->d_gam64.as<double>());
+    e = hipGetLastError();
+    if (e == hipSuccess) rc = f64_model_setup(c, dl.as<double>(), dm.as<double>());
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) return hip_fail(c, e, "upload_model kernels");
+  if (rc) return rc;
   c->have_model = true;
   c->lambda_max = 0.0;
   // receivers depend on nmodels
   if (c->rec.nrec > 0) {
-    rc = dev_alloc(c, c->rec.seis, sizeof(float) * nmodels * c->rec.nrec * 3 * c->rec.nt_max);
+    rc = alloc_seismograms(c);
     if (rc) return rc;
   }
   return do_reset(c);
@@ -1362,6 +1471,8 @@ int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
     return fail(c, SEMX_EINVAL, "set_mode: unknown assembly");
   if (contraction != SEMX_C_F32 && !mfma_supported(c->n))
     return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8");
+  if (contraction != SEMX_C_F32 && c->storage == SEMX_F64)
+    return fail(c, SEMX_EINVAL, "set_mode: FP64 storage contracts on the vector units (SEMX_C_F32 only)");
   if (assembly == SEMX_ASM_COLORED && c->have_mesh && c->ncolors == 0)
     return fail(c, SEMX_EINVAL, "set_mode: mesh has elements with repeated nodes; only atomic assembly is exact");
   c->contraction = contraction;
@@ -1372,6 +1483,7 @@ int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
 int semx_apply_force(semx_ctx* c, const float* u_dev, float* f_dev) {
   if (!c) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "apply_force: mesh and model required");
+  if (c->storage == SEMX_F64) return fail(c, SEMX_ESTATE, "apply_force: FP64 storage; use semx_apply_force_f64");
   if (!u_dev || !f_dev) return fail(c, SEMX_EINVAL, "apply_force: null pointer");
   const int64_t len = state_len(c);
   if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "apply_force: u and f overlap");
@@ -1447,45 +1559,12 @@ int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
 
 int semx_set_sources(semx_ctx* c, int nsrc, const int32_t* elem, const double* xi, const double* dir,
                      int64_t nstf, const float* stf) {
-  if (!c) return SEMX_EINVAL;
-  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "set_sources: no mesh");
-  if (nsrc < 0) return fail(c, SEMX_EINVAL, "set_sources: nsrc < 0");
-  if (nsrc == 0) {
-    c->src.nsrc = 0;
-    return SEMX_OK;
-  }
-  if (!elem || !xi || !dir || !stf || nstf <= 0) return fail(c, SEMX_EINVAL, "set_sources: bad arguments");
-  const int n = c->n, n3 = c->n3;
-  std::vector<int32_t> nodes((size_t)nsrc * n3);
-  std::vector<float> wdir((size_t)nsrc * n3 * 3);
-  for (int s = 0; s < nsrc; ++s) {
-    if (elem[s] < 0 || elem[s] >= c->nspec) return fail(c, SEMX_EINVAL, "set_sources: element out of range");
-    for (int d = 0; d < 3; ++d)
-      if (!(xi[3 * s + d] >= -1.0 && xi[3 * s + d] <= 1.0))
-        return fail(c, SEMX_EINVAL, "set_sources: reference coordinate outside [-1, 1]");
-    double lx[kMaxN], ly[kMaxN], lz[kMaxN];
-    lagrange_at(n, c->xi, xi[3 * s + 0], lx);
-    lagrange_at(n, c->xi, xi[3 * s + 1], ly);
-    lagrange_at(n, c->xi, xi[3 * s + 2], lz);
-    for (int k = 0; k < n; ++k)
-      for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
-          const int q = i + n * (j + n * k);
-          nodes[(size_t)s * n3 + q] = c->h_ibool[(size_t)elem[s] * n3 + q];
-          const double wq = lx[i] * ly[j] * lz[k];
-          for (int d = 0; d < 3; ++d) wdir[((size_t)s * n3 + q) * 3 + d] = (float)(wq * dir[3 * s + d]);
-        }
-  }
-  int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
-  if (!rc) rc = dev_alloc(c, c->src.wdir, wdir.size() * sizeof(float));
-  if (!rc) rc = dev_alloc(c, c->src.stf, sizeof(float) * nsrc * nstf);
-  if (rc) return rc;
-  SEMX_HIP(c, hipMemcpy(c->src.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->src.wdir.p, wdir.data(), wdir.size() * sizeof(float), hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->src.stf.p, stf, sizeof(float) * nsrc * nstf, hipMemcpyHostToDevice));
-  c->src.nsrc = nsrc;
-  c->src.nstf = nstf;
-  return SEMX_OK;
+  return set_sources_impl(c, nsrc, elem, xi, dir, nstf, stf, nullptr);
+}
+
+int semx_set_sources_f64(semx_ctx* c, int nsrc, const int32_t* elem, const double* xi, const double* dir,
+                         int64_t nstf, const double* stf) {
+  return set_sources_impl(c, nsrc, elem, xi, dir, nstf, nullptr, stf);
 }
 
 int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double* xi, int64_t nt_max) {
@@ -1500,6 +1579,7 @@ int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double*
   const int n = c->n, n3 = c->n3;
   std::vector<int32_t> nodes((size_t)nrec * n3);
   std::vector<float> wts((size_t)nrec * n3);
+  std::vector<double> wts64((size_t)nrec * n3);
   for (int r = 0; r < nrec; ++r) {
     if (elem[r] < 0 || elem[r] >= c->nspec) return fail(c, SEMX_EINVAL, "set_receivers: element out of range");
     for (int d = 0; d < 3; ++d)
@@ -1514,19 +1594,20 @@ int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double*
         for (int i = 0; i < n; ++i) {
           const int q = i + n * (j + n * k);
           nodes[(size_t)r * n3 + q] = c->h_ibool[(size_t)elem[r] * n3 + q];
-          wts[(size_t)r * n3 + q] = (float)(lx[i] * ly[j] * lz[k]);
+          wts64[(size_t)r * n3 + q] = lx[i] * ly[j] * lz[k];
+          wts[(size_t)r * n3 + q] = (float)wts64[(size_t)r * n3 + q];
         }
   }
-  const int nm = c->nmodels > 0 ? c->nmodels : 1;
   int rc = dev_alloc(c, c->rec.nodes, nodes.size() * sizeof(int32_t));
   if (!rc) rc = dev_alloc(c, c->rec.wts, wts.size() * sizeof(float));
-  if (!rc) rc = dev_alloc(c, c->rec.seis, sizeof(float) * nm * nrec * 3 * nt_max);
+  if (!rc) rc = dev_alloc(c, c->rec.wts64, wts64.size() * sizeof(double));
   if (rc) return rc;
   SEMX_HIP(c, hipMemcpy(c->rec.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->rec.wts.p, wts.data(), wts.size() * sizeof(float), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->rec.wts64.p, wts64.data(), wts64.size() * sizeof(double), hipMemcpyHostToDevice));
   c->rec.nrec = nrec;
   c->rec.nt_max = nt_max;
-  return zero_f32(c, c->rec.seis.as<float>(), (int64_t)nm * nrec * 3 * nt_max);
+  return alloc_seismograms(c);
 }
 
 int semx_reset(semx_ctx* c) {
@@ -1577,6 +1658,7 @@ int semx_time_index(semx_ctx* c, int64_t* it) {
 
 int semx_read_seismograms(semx_ctx* c, float* out, int out_on_device) {
   if (!c || !out) return SEMX_EINVAL;
+  if (c->storage == SEMX_F64) return fail(c, SEMX_ESTATE, "read_seismograms: FP64 storage; use semx_read_seismograms_f64");
   if (c->rec.nrec == 0 || !c->rec.seis.p) return fail(c, SEMX_ESTATE, "read_seismograms: no receivers");
   SEMX_HIP(c, hipMemcpyAsync(out, c->rec.seis.p, c->rec.seis.bytes,
                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
@@ -1587,6 +1669,7 @@ int semx_read_seismograms(semx_ctx* c, float* out, int out_on_device) {
 int semx_get_state(semx_ctx* c, float* u_dev, float* v_dev, float* a_dev, int64_t* it) {
   if (!c) return SEMX_EINVAL;
   if (!c->have_model) return fail(c, SEMX_ESTATE, "get_state: no model");
+  if (c->storage == SEMX_F64) return fail(c, SEMX_ESTATE, "get_state: FP64 storage; use semx_get_state_f64");
   int rc = finalize_state(c);
   if (rc) return rc;
   const size_t bytes = sizeof(float) * state_len(c);
@@ -1600,6 +1683,7 @@ int semx_get_state(semx_ctx* c, float* u_dev, float* v_dev, float* a_dev, int64_
 int semx_set_state(semx_ctx* c, const float* u_dev, const float* v_dev, const float* a_dev, int64_t it) {
   if (!c) return SEMX_EINVAL;
   if (!c->have_model) return fail(c, SEMX_ESTATE, "set_state: no model");
+  if (c->storage == SEMX_F64) return fail(c, SEMX_ESTATE, "set_state: FP64 storage; use semx_set_state_f64");
   if (!u_dev || !v_dev || !a_dev || it < 0) return fail(c, SEMX_EINVAL, "set_state: null pointer or negative index");
   const size_t bytes = sizeof(float) * state_len(c);
   SEMX_HIP(c, hipMemcpyAsync(c->d_u.p, u_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1673,6 +1757,68 @@ int semx_force_timing(semx_ctx* c, int64_t* launches, double* total_ms) {
   *launches = (int64_t)(c->ev_used / 2);
   *total_ms = tot;
   c->ev_used = 0;
+  return SEMX_OK;
+}
+
+int semx_set_storage(semx_ctx* c, int storage) {
+  if (!c) return SEMX_EINVAL;
+  if (storage != SEMX_F32 && storage != SEMX_F64) return fail(c, SEMX_EINVAL, "set_storage: unknown storage");
+  if (c->have_model) return fail(c, SEMX_ESTATE, "set_storage: call before semx_upload_model");
+  if (c->ckpt_every > 0) return fail(c, SEMX_ESTATE, "set_storage: turn checkpointing off first");
+  if (storage == SEMX_F64 && c->contraction != SEMX_C_F32)
+    return fail(c, SEMX_EINVAL, "set_storage: FP64 storage needs the SEMX_C_F32 contraction setting");
+  c->storage = storage;
+  if (c->rec.nrec > 0) return alloc_seismograms(c);
+  return SEMX_OK;
+}
+
+int semx_apply_force_f64(semx_ctx* c, const double* u_dev, double* f_dev) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "apply_force_f64: mesh and model required");
+  if (c->storage != SEMX_F64) return fail(c, SEMX_ESTATE, "apply_force_f64: needs SEMX_F64 storage");
+  if (!u_dev || !f_dev) return fail(c, SEMX_EINVAL, "apply_force_f64: null pointer");
+  const int64_t len = state_len(c);
+  if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "apply_force_f64: u and f overlap");
+  return f64_force_into(c, u_dev, f_dev, false);
+}
+
+int semx_read_seismograms_f64(semx_ctx* c, double* out, int out_on_device) {
+  if (!c || !out) return SEMX_EINVAL;
+  if (c->storage != SEMX_F64) return fail(c, SEMX_ESTATE, "read_seismograms_f64: needs SEMX_F64 storage");
+  if (c->rec.nrec == 0 || !c->rec.seis64.p) return fail(c, SEMX_ESTATE, "read_seismograms_f64: no receivers");
+  SEMX_HIP(c, hipMemcpyAsync(out, c->rec.seis64.p, c->rec.seis64.bytes,
+                             out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  if (!out_on_device) SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  return SEMX_OK;
+}
+
+int semx_get_state_f64(semx_ctx* c, double* u_dev, double* v_dev, double* a_dev, int64_t* it) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_model) return fail(c, SEMX_ESTATE, "get_state_f64: no model");
+  if (c->storage != SEMX_F64) return fail(c, SEMX_ESTATE, "get_state_f64: needs SEMX_F64 storage");
+  int rc = f64_finalize(c);
+  if (rc) return rc;
+  const size_t bytes = sizeof(double) * state_len(c);
+  if (u_dev) SEMX_HIP(c, hipMemcpyAsync(u_dev, c->d_u.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (v_dev) SEMX_HIP(c, hipMemcpyAsync(v_dev, c->d_v.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (a_dev) SEMX_HIP(c, hipMemcpyAsync(a_dev, c->d_a.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (it) *it = c->it;
+  return SEMX_OK;
+}
+
+int semx_set_state_f64(semx_ctx* c, const double* u_dev, const double* v_dev, const double* a_dev, int64_t it) {
+  if (!c) return SEMX_EINVAL;
+  if (!c->have_model) return fail(c, SEMX_ESTATE, "set_state_f64: no model");
+  if (c->storage != SEMX_F64) return fail(c, SEMX_ESTATE, "set_state_f64: needs SEMX_F64 storage");
+  if (!u_dev || !v_dev || !a_dev || it < 0) return fail(c, SEMX_EINVAL, "set_state_f64: null pointer or negative index");
+  const size_t bytes = sizeof(double) * state_len(c);
+  SEMX_HIP(c, hipMemcpyAsync(c->d_u.p, u_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  SEMX_HIP(c, hipMemcpyAsync(c->d_v.p, v_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  SEMX_HIP(c, hipMemcpyAsync(c->d_a.p, a_dev, bytes, hipMemcpyDeviceToDevice, c->stream));
+  fill_f64<<<grid_for(state_len(c)), kThreads, 0, c->stream>>>(c->d_f.as<double>(), state_len(c), 0.0);
+  SEMX_HIP(c, hipGetLastError());
+  c->it = it;
+  c->pending_correct = false;
   return SEMX_OK;
 }
 

@@ -1,0 +1,437 @@
+// FP64 storage path: the same discrete operator and time loop as the FP32
+// path, with every field, coefficient and sum in double.
+//
+//   f = -K u   (Sec. II-B weak form, GLL quadrature, lumped mass):
+//     du_c/dxi_d at every GLL point by the 1-D derivative matrix,
+//     grad u = du/dxi Gamma, sigma = lambda tr(grad u) I + mu (grad u + grad u^T),
+//     Phi_cd = W sum_b sigma_cb Gamma_db, F_c = -sum_d D^T_d Phi_cd, scatter-add;
+//   explicit Newmark, beta = 0, gamma = 1/2 (Sec. V-C), point sources, receivers.
+//
+// It serves runs that must agree with an FP64 reference to FP64 rounding and
+// finite-difference checks that need FP64 forward solves.  The kernels are
+// plain: one workgroup per element and model, one GLL point per lane, LDS
+// holding one component's three cubes at a time (3 n^3 doubles, 24 KB at
+// NGLL 10).  Assembly is coloured (plain read-modify-write: no two elements
+// of a colour share a node, so it is deterministic) or atomic (hardware FP64
+// atomic adds).
+#include <hip/hip_runtime.h>
+
+#include "semx_internal.hpp"
+
+namespace semx {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4;
+
+template <int NG>
+__global__ void force64_kernel(int64_t pos0, int64_t nspec, int64_t nglob, int atomic,
+                               const int32_t* __restrict__ ibool, const double* __restrict__ gam,
+                               const double* __restrict__ mat, const double* __restrict__ Dg,
+                               const double* __restrict__ u, double* __restrict__ f) {
+  constexpr int n3 = NG * NG * NG;
+  __shared__ double D[NG * NG];  // D[a * NG + b] = l'_b(xi_a)
+  __shared__ double s[3][n3];
+  const int64_t pos = pos0 + blockIdx.x;
+  const int64_t model = blockIdx.y;
+  const int q = threadIdx.x;
+  for (int t = q; t < NG * NG; t += blockDim.x) D[t] = Dg[t];
+  const bool live = q < n3;
+  const int i = q % NG, j = (q / NG) % NG, k = q / (NG * NG);
+  int64_t g = 0;
+  if (live) {
+    g = ibool[pos * n3 + q];
+    const double* um = u + (model * nglob + g) * 3;
+    s[0][q] = um[0];
+    s[1][q] = um[1];
+    s[2][q] = um[2];
+  }
+  __syncthreads();
+  double phi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (live) {
+    double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // du[c][d] = d u_c / d xi_d
+#pragma unroll
+    for (int a = 0; a < NG; ++a) {
+      const double d0 = D[i * NG + a], d1 = D[j * NG + a], d2 = D[k * NG + a];
+      const int q0 = a + NG * (j + NG * k), q1 = i + NG * (a + NG * k), q2 = i + NG * (j + NG * a);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        du[c][0] += d0 * s[c][q0];
+        du[c][1] += d1 * s[c][q1];
+        du[c][2] += d2 * s[c][q2];
+      }
+    }
+    const double* G = gam + pos * 9 * n3 + q;  // Gamma_db = d xi_d / d x_b at [(3 d + b) n3]
+    double Gm[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Gm[d][b] = G[(3 * d + b) * n3];
+    double gr[3][3];  // gr[c][b] = d u_c / d x_b
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gr[c][b] = du[c][0] * Gm[0][b] + du[c][1] * Gm[1][b] + du[c][2] * Gm[2][b];
+    const double* mp = mat + (model * nspec + pos) * 2 * n3;
+    const double lw = mp[q], mw = mp[n3 + q];  // lambda W, mu W
+    const double ltr = lw * (gr[0][0] + gr[1][1] + gr[2][2]);
+    double sig[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) sig[c][b] = mw * (gr[c][b] + gr[b][c]) + (c == b ? ltr : 0.0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) phi[c][d] = sig[c][0] * Gm[d][0] + sig[c][1] * Gm[d][1] + sig[c][2] * Gm[d][2];
+  }
+  double F[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();
+    if (live) {
+      s[0][q] = phi[c][0];
+      s[1][q] = phi[c][1];
+      s[2][q] = phi[c][2];
+    }
+    __syncthreads();
+    if (live) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NG; ++a)
+        acc += D[a * NG + i] * s[0][a + NG * (j + NG * k)] + D[a * NG + j] * s[1][i + NG * (a + NG * k)] +
+               D[a * NG + k] * s[2][i + NG * (j + NG * a)];
+      F[c] = -acc;
+    }
+  }
+  if (live) {
+    double* fm = f + (model * nglob + g) * 3;
+    if (atomic) {
+      atomicAdd(fm + 0, F[0]);
+      atomicAdd(fm + 1, F[1]);
+      atomicAdd(fm + 2, F[2]);
+    } else {
+      fm[0] += F[0];
+      fm[1] += F[1];
+      fm[2] += F[2];
+    }
+  }
+}
+
+__global__ void fill64_kernel(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+// lambda W and mu W in FP64 at launch position pos (user element order[pos]).
+__global__ void material64_kernel(int n3, int64_t nspec, int nmodels, const int32_t* __restrict__ order,
+                                  const double* __restrict__ lam, const double* __restrict__ mu,
+                                  const double* __restrict__ wdet, double* __restrict__ mat) {
+  const int64_t total = (int64_t)nmodels * nspec * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t mp = t / n3;
+    const int q = (int)(t - mp * n3);
+    const int64_t model = mp / nspec, pos = mp - model * nspec;
+    const int64_t src = (model * nspec + order[pos]) * n3 + q;
+    const double W = wdet[pos * n3 + q];
+    mat[mp * 2 * n3 + q] = lam[src] * W;
+    mat[mp * 2 * n3 + n3 + q] = mu[src] * W;
+  }
+}
+
+__global__ void minv64_kernel(int64_t n, const double* __restrict__ mass, double* __restrict__ minv) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    minv[t] = mass[t] > 0.0 ? 1.0 / mass[t] : 0.0;  // a node no element reaches stays at rest
+}
+
+// Newmark update, one lane per degree of freedom; kCorrect: acc = M^{-1} f,
+// v += dt/2 acc (acc stored to a with kStoreA); kPredict: u += dt v + dt^2/2
+// acc, v += dt/2 acc, f = 0 for the coming force pass.
+template <int MODE>
+__global__ void newmark64_kernel(int64_t nnodes, double dt, const double* __restrict__ minv, double* __restrict__ u,
+                                 double* __restrict__ v, double* __restrict__ a, double* __restrict__ f) {
+  const double hdt = 0.5 * dt, hdt2 = 0.5 * dt * dt;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double acc, vv = v[t];
+    if constexpr ((MODE & kCorrect) != 0) {
+      acc = minv[t / 3] * f[t];
+      vv += hdt * acc;
+      if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+    } else {
+      acc = a[t];
+    }
+    if constexpr ((MODE & kPredict) != 0) {
+      u[t] += dt * vv + hdt2 * acc;
+      vv += hdt * acc;
+      f[t] = 0.0;
+    }
+    v[t] = vv;
+  }
+}
+
+__global__ void accel64_kernel(int64_t nnodes, const double* __restrict__ minv, const double* __restrict__ f,
+                               double* __restrict__ a) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+       t += (int64_t)gridDim.x * blockDim.x)
+    a[t] = minv[t / 3] * f[t];
+}
+
+__global__ void source64_kernel(int nsrc, int n3, int64_t nstf, int64_t m, int nmodels, int64_t nglob,
+                                const int32_t* __restrict__ nodes, const double* __restrict__ wdir,
+                                const double* __restrict__ stf, double* __restrict__ f) {
+  const int64_t total = (int64_t)nmodels * nsrc * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sq = t % ((int64_t)nsrc * n3);
+    const int64_t model = t / ((int64_t)nsrc * n3);
+    const int s = (int)(sq / n3);
+    const double amp = (m >= 0 && m < nstf) ? stf[(int64_t)s * nstf + m] : 0.0;
+    if (amp == 0.0) continue;
+    double* fg = f + (model * nglob + nodes[sq]) * 3;
+    atomicAdd(fg + 0, amp * wdir[3 * sq + 0]);
+    atomicAdd(fg + 1, amp * wdir[3 * sq + 1]);
+    atomicAdd(fg + 2, amp * wdir[3 * sq + 2]);
+  }
+}
+
+// one block of kT lanes per (receiver, model)
+__global__ void receiver64_kernel(int nrec, int n3, int64_t nglob, int64_t nt_max, int64_t it,
+                                  const int32_t* __restrict__ nodes, const double* __restrict__ wts,
+                                  const double* __restrict__ u, double* __restrict__ seis) {
+  __shared__ double red[3][kT];
+  const int r = blockIdx.x;
+  const int64_t model = blockIdx.y;
+  const double* um = u + model * nglob * 3;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    const double wq = wts[(int64_t)r * n3 + q];
+    const int64_t g = nodes[(int64_t)r * n3 + q];
+    s0 += wq * um[3 * g + 0];
+    s1 += wq * um[3 * g + 1];
+    s2 += wq * um[3 * g + 2];
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) seis[((model * nrec + r) * 3 + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
+}
+
+__device__ inline void block_sum64(double v, double* out) {
+  __shared__ double red[kT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// out += sum_g mass_g |x_g|^2 over one model
+__global__ void mnorm64_kernel(int64_t nglob, const double* __restrict__ mass, const double* __restrict__ x,
+                               double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nglob; t += (int64_t)gridDim.x * blockDim.x)
+    s += mass[t / 3] * x[t] * x[t];
+  block_sum64(s, out);
+}
+
+__global__ void dot64_kernel(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                             double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    s += x[t] * y[t];
+  block_sum64(s, out);
+}
+
+__global__ void finite64_kernel(int64_t n, const double* __restrict__ x, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[t]);
+  if (bad) atomicOr(flag, 1);
+}
+
+template <int NG>
+hipError_t launch_force64_n(const semx_ctx* c, const double* u, double* f) {
+  constexpr int n3 = NG * NG * NG;
+  const unsigned threads = (unsigned)((n3 + 63) / 64 * 64);
+  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
+  for (const auto& L : atomic ? c->atomic_launches : c->colored_launches) {
+    if (L.count <= 0) continue;
+    dim3 grid((unsigned)L.count, (unsigned)c->nmodels);
+    force64_kernel<NG><<<grid, threads, 0, c->stream>>>(L.pos0, c->nspec, c->nglob, atomic ? 1 : 0,
+                                                        c->d_ibool.as<int32_t>(), c->d_gam64.as<double>(),
+                                                        c->d_mat64.as<double>(), c->d_D64.as<double>(), u, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_force64(const semx_ctx* c, const double* u, double* f) {
+  switch (c->n) {
+    case 2: return launch_force64_n<2>(c, u, f);
+    case 3: return launch_force64_n<3>(c, u, f);
+    case 4: return launch_force64_n<4>(c, u, f);
+    case 5: return launch_force64_n<5>(c, u, f);
+    case 6: return launch_force64_n<6>(c, u, f);
+    case 7: return launch_force64_n<7>(c, u, f);
+    case 8: return launch_force64_n<8>(c, u, f);
+    case 9: return launch_force64_n<9>(c, u, f);
+    case 10: return launch_force64_n<10>(c, u, f);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int zero64(semx_ctx* c, double* p, int64_t n) {
+  fill64_kernel<<<grid_1d(n), kT, 0, c->stream>>>(p, n, 0.0);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int64_t len64(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * 3; }
+
+int inject64(semx_ctx* c, int64_t m, double* f) {
+  if (c->src.nsrc == 0) return SEMX_OK;
+  const int64_t total = (int64_t)c->nmodels * c->src.nsrc * c->n3;
+  source64_kernel<<<grid_1d(total), kT, 0, c->stream>>>(c->src.nsrc, c->n3, c->src.nstf, m, c->nmodels, c->nglob,
+                                                         c->src.nodes.as<int32_t>(), c->src.wdir64.as<double>(),
+                                                         c->src.stf64.as<double>(), f);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int record64(semx_ctx* c, int64_t idx) {
+  if (c->rec.nrec == 0 || idx < 0 || idx >= c->rec.nt_max) return SEMX_OK;
+  dim3 grid(c->rec.nrec, c->nmodels);
+  receiver64_kernel<<<grid, kT, 0, c->stream>>>(c->rec.nrec, c->n3, c->nglob, c->rec.nt_max, idx,
+                                                c->rec.nodes.as<int32_t>(), c->rec.wts64.as<double>(),
+                                                c->d_u.as<double>(), c->rec.seis64.as<double>());
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+}  // namespace
+
+int f64_model_setup(semx_ctx* c, const double* lam_dev, const double* mu_dev) {
+  const int64_t npt = (int64_t)c->nmodels * c->nspec * c->n3;
+  int rc = dev_alloc(c, c->d_mat64, sizeof(double) * 2 * npt);
+  if (!rc) rc = dev_alloc(c, c->d_minv64, sizeof(double) * c->nmodels * c->nglob);
+  if (!rc && c->d_D64.bytes != sizeof(double) * c->n * c->n) rc = dev_alloc(c, c->d_D64, sizeof(double) * c->n * c->n);
+  if (rc) return rc;
+  SEMX_HIP(c, hipMemcpyAsync(c->d_D64.p, c->D.data(), sizeof(double) * c->n * c->n, hipMemcpyHostToDevice, c->stream));
+  material64_kernel<<<grid_1d(npt, 8192), kT, 0, c->stream>>>(c->n3, c->nspec, c->nmodels, c->d_order.as<int32_t>(),
+                                                               lam_dev, mu_dev, c->d_wdet.as<double>(),
+                                                               c->d_mat64.as<double>());
+  minv64_kernel<<<grid_1d((int64_t)c->nmodels * c->nglob), kT, 0, c->stream>>>(
+      (int64_t)c->nmodels * c->nglob, c->d_mass64.as<double>(), c->d_minv64.as<double>());
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int f64_force_into(semx_ctx* c, const double* u, double* f, bool f_zeroed) {
+  if (!f_zeroed) {
+    int rc = zero64(c, f, len64(c));
+    if (rc) return rc;
+  }
+  hipError_t e = launch_force64(c, u, f);
+  if (e != hipSuccess) return hip_fail(c, e, "FP64 force kernel launch");
+  return SEMX_OK;
+}
+
+int f64_finalize(semx_ctx* c) {
+  if (!c->pending_correct) return SEMX_OK;
+  const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  newmark64_kernel<kCorrect | kStoreA><<<grid_1d(3 * nn), kT, 0, c->stream>>>(
+      nn, c->dt, c->d_minv64.as<double>(), c->d_u.as<double>(), c->d_v.as<double>(), c->d_a.as<double>(),
+      c->d_f.as<double>());
+  SEMX_HIP(c, hipGetLastError());
+  c->pending_correct = false;
+  return SEMX_OK;
+}
+
+int f64_reset(semx_ctx* c) {
+  const int64_t len = len64(c);
+  for (auto* b : {&c->d_u, &c->d_v, &c->d_a, &c->d_f}) {
+    int rc = zero64(c, b->as<double>(), len);
+    if (rc) return rc;
+  }
+  c->it = 0;
+  c->pending_correct = false;
+  if (c->rec.nrec > 0 && c->rec.seis64.p) {
+    int rc = zero64(c, c->rec.seis64.as<double>(), c->rec.seis64.bytes / sizeof(double));
+    if (rc) return rc;
+  }
+  if (c->src.nsrc > 0) {
+    int rc = inject64(c, 0, c->d_f.as<double>());
+    if (rc) return rc;
+    const int64_t nn = (int64_t)c->nmodels * c->nglob;
+    accel64_kernel<<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->d_minv64.as<double>(), c->d_f.as<double>(),
+                                                           c->d_a.as<double>());
+    SEMX_HIP(c, hipGetLastError());
+    rc = zero64(c, c->d_f.as<double>(), len);
+    if (rc) return rc;
+  }
+  return SEMX_OK;
+}
+
+int f64_step_once(semx_ctx* c, bool record) {
+  const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  double *u = c->d_u.as<double>(), *v = c->d_v.as<double>(), *a = c->d_a.as<double>(), *f = c->d_f.as<double>();
+  const double* minv = c->d_minv64.as<double>();
+  if (c->pending_correct)
+    newmark64_kernel<kCorrect | kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+  else
+    newmark64_kernel<kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+  SEMX_HIP(c, hipGetLastError());
+  int rc = f64_force_into(c, u, f, true);
+  if (!rc) rc = inject64(c, c->it + 1, f);
+  if (!rc && record) rc = record64(c, c->it);
+  if (rc) return rc;
+  c->it++;
+  c->pending_correct = true;
+  return SEMX_OK;
+}
+
+int f64_energy(semx_ctx* c, double* kin, double* pot) {
+  int rc = f64_finalize(c);
+  if (rc) return rc;
+  const int64_t n3g = 3 * c->nglob;
+  double* acc = scratch_doubles(c);
+  fill64_kernel<<<1, 64, 0, c->stream>>>(acc, 8, 0.0);
+  mnorm64_kernel<<<grid_1d(n3g, 2048), kT, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(), c->d_v.as<double>(), acc);
+  SEMX_HIP(c, hipGetLastError());
+  // potential 1/2 u^T K u = -1/2 u . f(u) for model 0, f(u) in the work vector
+  rc = f64_force_into(c, c->d_u.as<double>(), c->d_work.as<double>(), false);
+  if (rc) return rc;
+  dot64_kernel<<<grid_1d(n3g, 2048), kT, 0, c->stream>>>(n3g, c->d_u.as<double>(), c->d_work.as<double>(), acc + 1);
+  SEMX_HIP(c, hipGetLastError());
+  double h[2] = {0, 0};
+  SEMX_HIP(c, hipMemcpyAsync(h, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  *kin = 0.5 * h[0];
+  *pot = -0.5 * h[1];
+  return SEMX_OK;
+}
+
+int f64_check_finite(semx_ctx* c, bool* ok) {
+  int* flag = scratch_flags(c);
+  SEMX_HIP(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  const int64_t len = len64(c);
+  finite64_kernel<<<grid_1d(len, 4096), kT, 0, c->stream>>>(len, c->d_u.as<double>(), flag);
+  finite64_kernel<<<grid_1d(len, 4096), kT, 0, c->stream>>>(len, c->d_v.as<double>(), flag);
+  SEMX_HIP(c, hipGetLastError());
+  int h = 0;
+  SEMX_HIP(c, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  *ok = (h == 0);
+  return SEMX_OK;
+}
+
+}  // namespace semx

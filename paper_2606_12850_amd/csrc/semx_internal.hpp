@@ -51,6 +51,8 @@ struct SourceSet {
   DevBuf nodes;   // int32 [nsrc][n3]
   DevBuf wdir;    // float [nsrc][n3][3]: l_q(x_s) * dir_c
   DevBuf stf;     // float [nsrc][nstf]
+  DevBuf wdir64;  // double copies of wdir and stf (FP64 storage)
+  DevBuf stf64;
 };
 
 struct ReceiverSet {
@@ -58,7 +60,9 @@ struct ReceiverSet {
   int64_t nt_max = 0;
   DevBuf nodes;   // int32 [nrec][n3]
   DevBuf wts;     // float [nrec][n3]
-  DevBuf seis;    // float [nmodels][nrec][3][nt_max]
+  DevBuf seis;    // float [nmodels][nrec][3][nt_max] (FP32 storage)
+  DevBuf wts64;   // double [nrec][n3]
+  DevBuf seis64;  // double [nmodels][nrec][3][nt_max] (FP64 storage)
 };
 
 }  // namespace semx
@@ -72,6 +76,7 @@ struct semx_ctx {
 
   int contraction = SEMX_C_F32;
   int assembly = SEMX_ASM_COLORED;
+  int storage = SEMX_F32;  // SEMX_F64: state, force and time loop in double (fp64.hip)
 
   // GLL data (library's own, FP64 on host)
   std::vector<double> xi, w, D;  // D[a*n+b] = l'_b(xi_a)
@@ -141,7 +146,11 @@ struct semx_ctx {
   semx::DevBuf d_wrho;     // float [nmodels][nspec][n3] rho * W (adjoint density kernel)
   double vp_max = 0.0;
 
-  // time loop state, [nmodels][nglob][3]
+  // FP64 storage: Gamma [nspec][9][n3], lambda W / mu W [nmodels][nspec][2][n3]
+  // by launch position, M^{-1} [nmodels][nglob], D [n][n]
+  semx::DevBuf d_gam64, d_mat64, d_minv64, d_D64;
+
+  // time loop state, [nmodels][nglob][3], float or double by `storage`
   semx::DevBuf d_u, d_v, d_a, d_f;
   semx::DevBuf d_work;     // scratch vector of the same shape (energy, power iteration)
   semx::DevBuf d_scratch;  // double reduction scratch + flags
@@ -232,5 +241,18 @@ int complete_step(semx_ctx* c);
 unsigned grid_1d(int64_t n, int cap = 1 << 16);
 // adjoint.hip
 int save_checkpoint(semx_ctx* c);
+
+// scratch layout: [0..7] doubles for reductions, then int flags
+inline double* scratch_doubles(semx_ctx* c) { return c->d_scratch.as<double>(); }
+inline int* scratch_flags(semx_ctx* c) { return reinterpret_cast<int*>(c->d_scratch.as<double>() + 8); }
+
+// fp64.hip: the FP64 storage path (state buffers hold doubles)
+int f64_model_setup(semx_ctx* c, const double* lam_dev, const double* mu_dev);
+int f64_force_into(semx_ctx* c, const double* u, double* f, bool f_zeroed);
+int f64_finalize(semx_ctx* c);
+int f64_reset(semx_ctx* c);
+int f64_step_once(semx_ctx* c, bool record);
+int f64_energy(semx_ctx* c, double* kin, double* pot);
+int f64_check_finite(semx_ctx* c, bool* ok);
 
 }  // namespace semx
