@@ -459,6 +459,9 @@ def main():
     seis = s.seismograms()
     assert np.all(np.isfinite(seis)), "non-finite seismograms"
 
+    # ---- streaming reference: the library's own 1 GiB copy kernel (read + write)
+    bw_copy = P.semx_stream_bandwidth(s.ctx, 1 << 30, 20)
+
     # ---- roofline of the force kernel (per launch)
     launches_per_apply = launches / args.steps
     avg_launch_ms = force_ms / launches
@@ -491,7 +494,9 @@ def main():
                      "kernel": (f"force_patch_kernel<5, {args.geometry}, {args.assembly}>, chains of {args.patches}"
                                 if args.patches else f"force_f32_kernel<5, {args.geometry}, {args.assembly}>"),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
-                     "launches": launches, "bytes_per_element": b_elem},
+                     "launches": launches, "bytes_per_element": b_elem,
+                     "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4)},
+        "unique_nodes_per_s": mesh.nglob / (step_ms * 1e-3),
         "force_apply": apply,
         "wall_s_timed": round(wall, 3),
         "setup_s": round(setup_s, 1),

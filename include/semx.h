@@ -295,6 +295,14 @@ int semx_set_state_f64(semx_ctx *ctx, const double *u_dev, const double *v_dev, 
 int semx_set_timing(semx_ctx *ctx, int enable);
 int semx_force_timing(semx_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* Streaming reference: copy nbytes (a positive multiple of 16) between two
+ * device buffers the library allocates and frees, reps times, with its own
+ * 16-byte, non-temporal, grid-stride copy kernel on the context stream;
+ * returns the read+write bandwidth 2 nbytes reps / time in GB/s (HIP
+ * events).  A measured ceiling for HBM-bound kernels beside the published
+ * peak.  SEMX_ENOMEM if the two buffers do not fit. */
+int semx_stream_bandwidth(semx_ctx *ctx, int64_t nbytes, int reps, double *gbps);
+
 /* ---------------------------------------------------------------------------
  * Surrogate network: a multilayer perceptron that maps model parameters to
  * receiver seismograms, trained on SEM runs of this library (the SEM solve

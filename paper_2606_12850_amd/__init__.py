@@ -97,6 +97,7 @@ _SIGS = {
     "semx_read_seismograms_f64": [_vp, _vp, _i32],
     "semx_get_state_f64": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i64)],
     "semx_set_state_f64": [_vp, _vp, _vp, _vp, _i64],
+    "semx_stream_bandwidth": [_vp, _i64, _i32, ctypes.POINTER(_f64)],
     "semx_set_timing": [_vp, _i32],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
@@ -304,6 +305,12 @@ def semx_get_state_f64(ctx, u=None, v=None, a=None) -> int:
 
 def semx_set_state_f64(ctx, u, v, a, it: int):
     return _check(ctx, lib().semx_set_state_f64(ctx, _ptr(u), _ptr(v), _ptr(a), int(it)))
+
+
+def semx_stream_bandwidth(ctx, nbytes: int, reps: int) -> float:
+    out = _f64()
+    _check(ctx, lib().semx_stream_bandwidth(ctx, int(nbytes), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def semx_energy(ctx):

@@ -176,3 +176,18 @@ def test_periodic_atomic_matches_oracle(orc):
     f_ref = orc.force(4, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
     assert rel_l2(gpu_force(s, u), f_ref) <= TOL_F32
     s.close()
+
+
+def test_stream_bandwidth_reference():
+    """The library's streaming copy gives a bandwidth between a plausible
+    floor and the published 8 TB/s peak, and rejects bad sizes."""
+    import paper_2606_12850_amd as P
+    s = make_solver(4)
+    bw = P.semx_stream_bandwidth(s.ctx, 256 << 20, 5)
+    print(f"stream copy: {bw:.0f} GB/s")
+    assert 500.0 < bw < 8000.0 * 1.05
+    for nbytes, reps in ((0, 1), (100, 1), (1 << 20, 0)):
+        with pytest.raises(P.SemxError) as ei:
+            P.semx_stream_bandwidth(s.ctx, nbytes, reps)
+        assert ei.value.code == P.SEMX_EINVAL
+    s.close()
