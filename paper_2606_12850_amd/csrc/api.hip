@@ -837,7 +837,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     }
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->contraction == SEMX_C_F32)
-      e = launch_force_f32(c->n, geo, atomic, a, c->stream);
+      e = c->n > kMaxNLow ? launch_force_high(c->n, geo, atomic, a, c->stream)
+                          : launch_force_f32(c->n, geo, atomic, a, c->stream);
     else
       e = launch_force_mfma(c->n, c->contraction, geo, atomic, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
@@ -1054,7 +1055,7 @@ int step_once(semx_ctx* c, bool record) {
   float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
   const float* minv = c->d_minv.as<float>();
   const bool keep = force_overwrites(c);
-  const unsigned gb = grid_for(3 * nn);
+  const unsigned gb = grid_for(3 * nn, 1 << 30);  // one pass per lane (streams faster than grid-stride)
   if (c->pending_correct) {
     if (keep) newmark_kernel<kCorrect | kPredict | kKeepF><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
     else newmark_kernel<kCorrect | kPredict><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
@@ -1767,6 +1768,8 @@ int semx_set_storage(semx_ctx* c, int storage) {
   if (c->ckpt_every > 0) return fail(c, SEMX_ESTATE, "set_storage: turn checkpointing off first");
   if (storage == SEMX_F64 && c->contraction != SEMX_C_F32)
     return fail(c, SEMX_EINVAL, "set_storage: FP64 storage needs the SEMX_C_F32 contraction setting");
+  if (storage == SEMX_F64 && c->n > kMaxNLow)
+    return fail(c, SEMX_EINVAL, "set_storage: FP64 storage supports NGLL <= 10");
   c->storage = storage;
   if (c->rec.nrec > 0) return alloc_seismograms(c);
   return SEMX_OK;

@@ -1,0 +1,243 @@
+// FP32 element internal-force kernel for high orders (NGLL 11..16).
+//
+// Same operator as force_f32.hip (Sec. II-B weak form: three forward and
+// three transpose sum-factorised contractions around the pointwise
+// Gamma map, isotropic stress and weighted flux; Sec. IV-D fused traversal
+// and regular/irregular geometry paths), laid out for elements whose n^3
+// points (up to 4096) do not fit one lane each:
+//   one workgroup per element, one lane per (i, j) column (n^2 lanes, at most
+//   256), the lane keeping u and the force accumulators of its n points
+//   along zeta in registers;
+//   the element is walked slice by slice in k: the xi and eta derivatives
+//   read the slice of u from LDS, the zeta derivative the lane's own column;
+//   the zeta part of the transpose contraction goes straight into the
+//   column accumulators (point k feeds every k' with D[k][k']), the xi and
+//   eta parts through one LDS slice of fluxes.
+// LDS holds the element's node numbers, one slice of u (3 n^2), one slice of
+// fluxes (6 n^2) and D: 26 KB at NGLL 16, instead of the 12 n^3 floats
+// (192 KB) a point-per-lane layout would need.
+// Assembly: plain read-modify-write inside a colour (with first-touch stores)
+// or FP32 atomics, as in the lower-order kernel.
+#include "elem_common.hpp"
+
+namespace semx {
+namespace {
+
+template <int NG>
+struct ColShape {
+  static constexpr int N2 = NG * NG;
+  static constexpr int N3 = NG * NG * NG;
+  static constexpr int BLK = ((N2 + 63) / 64) * 64;
+};
+
+template <int NG, int GEO, bool ATOMIC>
+__global__ __launch_bounds__(ColShape<NG>::BLK) void force_col_kernel(ForceArgs a) {
+  constexpr int N2 = ColShape<NG>::N2;
+  constexpr int N3 = ColShape<NG>::N3;
+  __shared__ int s_g[N3];
+  __shared__ float s_u[3 * N2];
+  __shared__ float s_q[6 * N2];
+  __shared__ float s_D[N2];
+
+  const int ngrp = (int)a.count;
+  const int grp = xcd_group(ngrp);
+  if (grp >= ngrp) return;  // uniform over the block
+  const int pos = (int)a.pos0 + grp;
+
+  const int l = threadIdx.x;
+  const bool act = l < N2;
+  const int ll = act ? l : 0;
+  const int i = ll % NG, j = ll / NG;
+
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
+  float* f = a.f + (size_t)model * a.nglob * 3;
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3 + (size_t)pos * 2 * N3;
+
+  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
+  __syncthreads();
+
+  // the lane's column of u
+  float uc[3][NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int g = s_g[ll + N2 * k];
+    uc[0][k] = u[3 * (size_t)g + 0];
+    uc[1][k] = u[3 * (size_t)g + 1];
+    uc[2][k] = u[3 * (size_t)g + 2];
+  }
+  float acc[3][NG];  // sum_d sum_a D_{a, l_d} Phi_cd(...) at the column's points
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < NG; ++k) acc[c][k] = 0.0f;
+
+  float rx = 0.f, ry = 0.f;
+  const float* src = nullptr;
+  if constexpr (GEO == kTrilinear) {
+    rx = a.xi[i];
+    ry = a.xi[j];
+    src = a.tri + (size_t)pos * 24;
+  }
+  if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
+
+  // The slice loop stays rolled (unrolled, the compiler hoists work across
+  // slices and spills); the column arrays are indexed by the slice through
+  // selects over the static column index, so they stay in registers.
+#pragma unroll 1
+  for (int k = 0; k < NG; ++k) {
+    const int q = ll + N2 * k;
+    if (k > 0) __syncthreads();  // the previous slice's readers are done
+    float uk[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) {
+        uk[0] = uc[0][b];
+        uk[1] = uc[1][b];
+        uk[2] = uc[2][b];
+      }
+    if (act) {
+      s_u[ll] = uk[0];
+      s_u[N2 + ll] = uk[1];
+      s_u[2 * N2 + ll] = uk[2];
+    }
+    __syncthreads();
+    // reference derivatives du[c][d] at (i, j, k)
+    float du[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c][0] = du[c][1] = du[c][2] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const float di = s_D[i * NG + b], dj = s_D[j * NG + b], dk = s_D[k * NG + b];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        du[c][0] += di * s_u[c * N2 + b + NG * j];
+        du[c][1] += dj * s_u[c * N2 + i + NG * b];
+        du[c][2] += dk * uc[c][b];
+      }
+    }
+    float G[9];
+    if constexpr (GEO == kStored) {
+      const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + q;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) G[d] = ldnt(gp + d * N3);
+    }
+    float Mg[9], scale, det;
+    geom_map_from<GEO>(src, G, rx, ry, (GEO == kTrilinear) ? a.xi[k] : 0.f, Mg, scale, det);
+    float gr[3][3];
+    apply_map(du, Mg, gr);
+    const float lw = ldnt(mat + q), mw = ldnt(mat + N3 + q);
+    const float ltr = lw * (gr[0][0] + gr[1][1] + gr[2][2]);
+    float sg[3][3];
+    sg[0][0] = ltr + 2.0f * mw * gr[0][0];
+    sg[1][1] = ltr + 2.0f * mw * gr[1][1];
+    sg[2][2] = ltr + 2.0f * mw * gr[2][2];
+    sg[0][1] = sg[1][0] = mw * (gr[0][1] + gr[1][0]);
+    sg[0][2] = sg[2][0] = mw * (gr[0][2] + gr[2][0]);
+    sg[1][2] = sg[2][1] = mw * (gr[1][2] + gr[2][1]);
+    float phi[3][3];  // phi[c][d] = scale sum_b sg[c][b] Mg[d][b]
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        phi[c][d] = scale * (sg[c][0] * Mg[d * 3 + 0] + sg[c][1] * Mg[d * 3 + 1] + sg[c][2] * Mg[d * 3 + 2]);
+    // zeta part: point k feeds every point k' of the column with D[k][k']
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const float dkb = s_D[k * NG + b];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c][b] += dkb * phi[c][2];
+    }
+    // xi and eta parts through the slice of fluxes
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_q[(2 * c + 0) * N2 + ll] = phi[c][0];
+        s_q[(2 * c + 1) * N2 + ll] = phi[c][1];
+      }
+    }
+    __syncthreads();
+    float sxy[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float s = 0.0f;
+#pragma unroll
+      for (int b = 0; b < NG; ++b) {
+        s += s_D[b * NG + i] * s_q[(2 * c + 0) * N2 + b + NG * j];
+        s += s_D[b * NG + j] * s_q[(2 * c + 1) * N2 + i + NG * b];
+      }
+      sxy[c] = s;
+    }
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) {
+        acc[0][b] += sxy[0];
+        acc[1][b] += sxy[1];
+        acc[2][b] += sxy[2];
+      }
+  }
+
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int q = ll + N2 * k;
+      float* fg = f + 3 * (size_t)s_g[q];
+      if constexpr (ATOMIC) {
+        unsafeAtomicAdd(fg + 0, -acc[0][k]);
+        unsafeAtomicAdd(fg + 1, -acc[1][k]);
+        unsafeAtomicAdd(fg + 2, -acc[2][k]);
+      } else {
+        const bool first = a.first && ((a.first[(size_t)pos * a.first_words + (q >> 5)] >> (q & 31)) & 1u);
+        if (first) {
+          fg[0] = -acc[0][k];
+          fg[1] = -acc[1][k];
+          fg[2] = -acc[2][k];
+        } else {
+          fg[0] = fg[0] - acc[0][k];
+          fg[1] = fg[1] - acc[1][k];
+          fg[2] = fg[2] - acc[2][k];
+        }
+      }
+    }
+  }
+}
+
+template <int NG, int GEO, bool ATOMIC>
+hipError_t launch_col(const ForceArgs& a, hipStream_t s) {
+  const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(ColShape<NG>::BLK);
+  force_col_kernel<NG, GEO, ATOMIC><<<grid, block, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int NG>
+hipError_t launch_col_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  switch (geo) {
+    case kRegular:
+      return atomic ? launch_col<NG, kRegular, true>(a, s) : launch_col<NG, kRegular, false>(a, s);
+    case kStored:
+      return atomic ? launch_col<NG, kStored, true>(a, s) : launch_col<NG, kStored, false>(a, s);
+    case kTrilinear:
+      return atomic ? launch_col<NG, kTrilinear, true>(a, s) : launch_col<NG, kTrilinear, false>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  switch (n) {
+    case 11: return launch_col_n<11>(geo, atomic, a, s);
+    case 12: return launch_col_n<12>(geo, atomic, a, s);
+    case 13: return launch_col_n<13>(geo, atomic, a, s);
+    case 14: return launch_col_n<14>(geo, atomic, a, s);
+    case 15: return launch_col_n<15>(geo, atomic, a, s);
+    case 16: return launch_col_n<16>(geo, atomic, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace semx

@@ -11,7 +11,8 @@
 
 namespace semx {
 
-constexpr int kMaxN = 10;   // largest supported NGLL
+constexpr int kMaxN = 16;     // largest supported NGLL
+constexpr int kMaxNLow = 10;  // largest NGLL of the one-point-per-lane kernels (FP64 storage, adjoint, patches)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin block dispatch
 
 // geometry path of a force launch
@@ -231,6 +232,8 @@ struct PatchArgs {
 hipError_t launch_force_patch(int n, int geo, bool atomic, const PatchArgs& a, hipStream_t s);
 size_t patch_lds_bytes(int n, int maxnodes, int maxruns);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+// force_high.hip: NGLL 11..16 (one lane per (i, j) column)
+hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);
 
 // ---- host helpers shared between translation units (api.hip) ----------------
