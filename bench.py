@@ -263,11 +263,12 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
             "gain": round(t_sem / t_sur, 3), "calibration": cal}
 
 
-ORDER_SWEEP = [(4, 90), (5, 68), (6, 54), (7, 45), (8, 39), (9, 34)]  # (NGLL, elements per side): ~2e7 points
+ORDER_SWEEP = [(4, 90), (5, 68), (6, 54), (7, 45), (8, 39), (9, 34), (10, 30), (11, 27), (12, 25), (13, 23),
+               (14, 21), (15, 19), (16, 18)]  # (NGLL, elements per side): ~2e7 points
 
 
 def order_sweep_leg(reps: int = 20):
-    """Force apply at about 2e7 unique points for NGLL 4..9 (element size
+    """Force apply at about 2e7 unique points for NGLL 4..16 (element size
     h = N * 69.3 / 5 m, about five GLL points per minimum wavelength of a
     25 Hz wave at vs = 1732 m/s), homogeneous medium times a +-5 % random
     field, regular hexahedra, coloured assembly: FP32, and BF16 / FP16 matrix
@@ -287,9 +288,14 @@ def order_sweep_leg(reps: int = 20):
         mesh = W.box_mesh(ne, n, ne * h)
         lam, mu, rho = W.layered_model(mesh, vp_layers=(3000.0,), vpvs=3000.0 / 1732.0, grf_amp=0.05,
                                        grf_seed=12850, grf_corr_elems=4.0)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
         s = P.Solver(n)
         s.upload_mesh(mesh)
         s.upload_model(lam, mu, rho)
+        torch.cuda.synchronize()
+        device_bytes = free0 - torch.cuda.mem_get_info()[0]  # the library's own allocations
+        vp_max = float(np.sqrt((lam + 2.0 * mu) / rho).max())
         del lam, mu, rho
         G = mesh.nglob
         Gx = ne * N + 1
@@ -301,8 +307,21 @@ def order_sweep_leg(reps: int = 20):
         u = torch.from_numpy(u_np).to("cuda")
         del u_np, xs, g
         f = torch.empty_like(u)
-        row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2)}
+        row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2), "device_bytes": device_bytes}
         b_elem = bytes_per_element(n, G, mesh.nspec, "regular")
+        # full explicit step (FP32, coloured) from a nonzero state, CFL time step
+        dt = P.semx_cfl_dt(s.ctx, 0.4)
+        P.semx_set_dt(s.ctx, dt)
+        P.semx_set_state(s.ctx, u, torch.zeros_like(u), torch.zeros_like(u), 0)
+        s.step(3)
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(reps)
+        e1.record(s.stream)
+        e1.synchronize()
+        row["step_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+        row["dt_cfl"] = dt
+        row["hmin_over_h"] = dt * vp_max / 0.4 / h  # smallest GLL spacing over the element size
         ref = None
         for cname, cmode in (("f32", P.SEMX_C_F32), ("mf32", P.SEMX_C_MFMA_F32), ("bf16", P.SEMX_C_BF16),
                              ("f16", P.SEMX_C_F16)):
@@ -330,6 +349,44 @@ def order_sweep_leg(reps: int = 20):
         del u, f, ref
         s.close()
     return rows
+
+
+def iso_accuracy_summary(rows, eps: float = 1e-5):
+    """Equal-accuracy comparison across orders (the paper's dispersion-based
+    (h, p) frontier, Sec. IV-B and V-C): with ppw_p the GLL points per
+    wavelength at which an axis plane wave has relative phase-velocity error
+    eps (tests/golden/iso_accuracy.json, from the oracle's Bloch analysis),
+    a volume of one minimum wavelength cubed holds ppw_p^3 unique nodes.
+    The per-node costs come from the order sweep (about 2e7 nodes per order,
+    where every order fills the GPU): FP32 step time and device bytes per
+    node, and the CFL time step through the smallest GLL spacing.  Reported
+    per lambda^3 and relative to NGLL 5 (p = 4)."""
+    with open(os.path.join(ROOT, "tests", "golden", "iso_accuracy.json")) as fh:
+        tab = json.load(fh)
+    ppw_of = dict(zip(tab["ngll"], tab["ppw"][tab["eps"].index(eps)]))
+    out = []
+    for r in rows:
+        n = r["ngll"]
+        if n not in ppw_of or "step_ms" not in r:
+            continue
+        ppw = ppw_of[n]
+        nodes = ppw ** 3
+        step_ns = r["step_ms"] * 1e6 / r["nglob"] * nodes      # ns per step per lambda^3
+        apply_ns = r["f32_ms"] * 1e6 / r["nglob"] * nodes
+        mem = r["device_bytes"] / r["nglob"] * nodes
+        dt_rel = r["hmin_over_h"] * (n - 1) / ppw              # CFL dt in units of lambda / vp
+        out.append({"ngll": n, "p": n - 1, "ppw": ppw, "h_over_lambda": round((n - 1) / ppw, 4),
+                    "nodes_per_lambda3": round(nodes, 1), "step_ns_per_lambda3": round(step_ns, 3),
+                    "apply_ns_per_lambda3": round(apply_ns, 3), "device_bytes_per_lambda3": round(mem, 1),
+                    "cfl_dt_lambda_over_vp": round(dt_rel, 5),
+                    "time_to_solution_cfl": step_ns / dt_rel})
+    base = next((o for o in out if o["ngll"] == 5), None)
+    if base:
+        for o in out:
+            o["rel_step_cost_fixed_dt"] = round(o["step_ns_per_lambda3"] / base["step_ns_per_lambda3"], 4)
+            o["rel_time_cfl_dt"] = round(o["time_to_solution_cfl"] / base["time_to_solution_cfl"], 4)
+            o["rel_memory"] = round(o["device_bytes_per_lambda3"] / base["device_bytes_per_lambda3"], 4)
+    return {"eps": eps, "rows": out}
 
 
 def main():
@@ -506,6 +563,7 @@ def main():
         out["adjoint"] = adjoint_leg()
     if args.order_sweep:
         out["order_sweep"] = order_sweep_leg()
+        out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]
     if args.surrogate:
         k = args.surrogate_scale
         out["surrogate"] = surrogate_leg(f0=args.surrogate_f0, ntrain=max(64, int(4500 * k)), nval=max(64, int(500 * k)),

@@ -11,6 +11,8 @@ the discrete operator the oracle implements.  Only tests use this module.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.linalg
 
@@ -301,3 +303,72 @@ if __name__ == "__main__":
     for n, d, wt, e, br, bd in table():
         extra = "  standing modes " + ", ".join(f"{b:+.3e}" for b in br) if bd else ""
         print(f"n={n} {d} {wt}: {e:+.3e}{extra}")
+
+
+@functools.lru_cache(maxsize=None)
+def _axis_element(n: int):
+    """GLL nodes, weights and the 1-D element stiffness (h = c = 1)."""
+    xi, w = O.gll(n)
+    D = O.dmatrix(n)  # D[a, b] = l'_b(xi_a)
+    return xi, w, 2.0 * (D.T * w) @ D
+
+
+def axis_omega(n: int, kh: float) -> float:
+    """omega h / c of the plane wave exp(i k x) along a lattice axis, for
+    the 1-D GLL spectral element lattice (element size h, lumped GLL mass,
+    weak-form stiffness): the N x N Bloch problem.  A P or S wave along an
+    axis of the 3-D operator reduces exactly to it (cross-axis terms cancel
+    between periodic neighbours), for every wave speed c."""
+    N = n - 1
+    xi, w, Ke = _axis_element(n)
+    me = 0.5 * w
+    r = np.arange(n) % N
+    ph = np.exp(1j * kh * (np.arange(n) // N))
+    P = np.zeros((n, N), dtype=np.complex128)
+    P[np.arange(n), r] = ph
+    Kr = P.conj().T @ Ke @ P
+    mr = np.bincount(r, weights=me, minlength=N)
+    s = 1.0 / np.sqrt(mr)
+    A = s[:, None] * Kr * s[None, :]
+    ev, V = np.linalg.eigh(0.5 * (A + A.conj().T))
+    x = 0.5 * (xi[:N] + 1.0)
+    pw = np.sqrt(mr) * np.exp(1j * kh * x)
+    j = int(np.argmax(np.abs(V.conj().T @ pw)))
+    return float(np.sqrt(max(ev[j], 0.0)))
+
+
+def axis_error(n: int, ppw: float) -> float:
+    """Relative phase-velocity error omega_h / (c k) - 1 along a lattice axis
+    at ppw GLL points per wavelength (average spacing h / N)."""
+    kh = 2.0 * np.pi * (n - 1) / ppw
+    return axis_omega(n, kh) / kh - 1.0
+
+
+def iso_accuracy_ppw(n: int, eps: float, lo: float = 2.0, hi: float = 2000.0) -> float:
+    """Fewest points per wavelength at which |axis_error| stays <= eps for
+    every finer resolution.  The error is smooth except next to the
+    Brillouin-zone boundaries k h = m pi (ppw = 2N/m), where the travelling
+    branch bends towards a small band gap; candidates are a geometric grid
+    plus points packed log-densely on both sides of every boundary, and the
+    last candidate above eps is refined by bisection towards the next one."""
+    N = n - 1
+    cand = list(np.geomspace(lo, hi, 4000))
+    for m in range(1, N):
+        pb = 2.0 * N / m
+        for d in np.geomspace(1e-7, 3e-2, 40):
+            cand += [pb * (1.0 - d), pb * (1.0 + d)]
+    cand = np.array(sorted(p for p in cand if lo <= p <= hi))
+    bad = np.array([abs(axis_error(n, p)) > eps for p in cand])
+    if bad[-1]:
+        raise ValueError(f"iso_accuracy_ppw: error above {eps} at {hi} ppw")
+    if not bad.any():
+        return float(lo)
+    last = int(np.nonzero(bad)[0][-1])
+    a, b = cand[last], cand[last + 1]  # error > eps at a, <= eps at b
+    for _ in range(60):
+        mid = 0.5 * (a + b)
+        if abs(axis_error(n, mid)) > eps:
+            a = mid
+        else:
+            b = mid
+    return float(b)

@@ -188,3 +188,63 @@ def test_periodic_mesh_time_loop_recovers_bloch_frequency(n, m, wave):
     assert abs(omega_h / pw["omega_h"] - 1.0) <= 1e-10
     # the run's frequency is the central-difference image of omega_h
     assert abs(omega_run - 2.0 / dt * np.arcsin(pw["omega_h"] * dt / 2.0)) <= 1e-9 * omega_run
+
+
+# --- axis (1-D) Bloch analysis and the equal-accuracy table --------------------
+
+@pytest.mark.parametrize("n", [3, 5, 8, 12, 16])
+def test_axis_omega_equals_independent_1d(n):
+    for kh in (0.7, 1.9, 4.0, 9.0):
+        if kh > 0.9 * np.pi * (n - 1):
+            continue
+        assert abs(Dp.axis_omega(n, kh) / indep.sem1d_bloch_omega(n, 1.0, 1.0, kh) - 1.0) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+def test_axis_omega_equals_3d_operator(elem, n):
+    """The cheap 1-D routine is the 3-D operator's frequency along an axis
+    (assembled from the oracle force), for both wave speeds."""
+    K, m = elem(n)
+    for kh in (0.9, 2.3):
+        for pol, c in (([1, 0, 0], VP), ([0, 0, 1], VS)):
+            w3 = main_branch(Dp.plane_wave_branches(n, H, K, m, [kh / H, 0, 0], [pol])[0])
+            assert abs(w3 * H / c / Dp.axis_omega(n, kh) - 1.0) <= 1e-11
+
+
+def test_axis_linear_closed_form_and_crossing():
+    for kh in (0.2, 1.0, 2.5):
+        assert abs(Dp.axis_omega(2, kh) - 2.0 * np.sin(kh / 2.0)) <= 1e-13
+    # linear elements: error(ppw) = sin(pi/ppw) ppw/pi - 1; its eps-crossing by a root finder
+    from scipy.optimize import brentq
+    for eps in (1e-3, 1e-4):
+        ref = brentq(lambda p: 1.0 - np.sin(np.pi / p) * p / np.pi - eps, 3.0, 3000.0, xtol=1e-12)
+        assert abs(Dp.iso_accuracy_ppw(2, eps) / ref - 1.0) <= 1e-8
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_iso_accuracy_ppw_is_the_last_crossing(n):
+    for eps in (1e-3, 1e-5):
+        p = Dp.iso_accuracy_ppw(n, eps)
+        assert abs(abs(Dp.axis_error(n, p)) / eps - 1.0) <= 1e-3
+        for q in np.geomspace(p * 1.001, 3 * p, 25):
+            assert abs(Dp.axis_error(n, q)) <= eps
+
+
+def test_iso_accuracy_table_reproducible():
+    """tests/golden/iso_accuracy.json is what its generator writes from the
+    oracle (values rounded to 6 decimals)."""
+    import json
+    import os
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_iso_accuracy", os.path.join(here, "make_iso_accuracy.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(here, "iso_accuracy.json")) as fh:
+        stored = json.load(fh)
+    fresh = mod.table()
+    assert stored["eps"] == fresh["eps"] and stored["ngll"] == fresh["ngll"]
+    np.testing.assert_allclose(stored["ppw"], fresh["ppw"], rtol=0, atol=2e-6)
+    # fewer points per wavelength are needed as the order grows (asymptotic range)
+    for row in stored["ppw"]:
+        assert row[0] > row[3] > row[6] > row[14]
