@@ -48,6 +48,6 @@ def test_create_rejects_bad_ngll_without_gpu():
     import paper_2606_12850_amd as P
     h = ctypes.c_void_p()
     assert P.lib().semx_create(ctypes.byref(h), 1, None) == P.SEMX_EINVAL
-    assert P.lib().semx_create(ctypes.byref(h), 11, None) == P.SEMX_EINVAL
+    assert P.lib().semx_create(ctypes.byref(h), 17, None) == P.SEMX_EINVAL
     assert P.lib().semx_create(None, 5, None) == P.SEMX_EINVAL
     assert P.lib().semx_destroy(None) == P.SEMX_OK
