@@ -31,8 +31,8 @@ def _sampled_reference(orc, wl, u, sample):
     m = wl.mesh
     nodes = np.unique(m.ibool[sample])
     touch = np.nonzero(np.isin(m.ibool, nodes).any(axis=1))[0]
-    gam, jac, _ = orc.geometry(5, m.elem_vert[touch], m.vert)
-    f = orc.force(5, m.ibool[touch], gam, jac, wl.lam[touch], wl.mu[touch], u, m.nglob)
+    gam, jac, _ = orc.geometry(m.n, m.elem_vert[touch], m.vert)
+    f = orc.force(m.n, m.ibool[touch], gam, jac, wl.lam[touch], wl.mu[touch], u, m.nglob)
     return nodes, f[nodes]
 
 
@@ -76,3 +76,37 @@ def test_fullsize_timeloop_properties(big):
     P.semx_reset(s.ctx)
     s.step(wl.nt)
     np.testing.assert_array_equal(s.seismograms(), a)
+
+
+@pytest.mark.parametrize("n,ne,jitter", [(12, 25, 0.0), (16, 18, 0.0), (16, 18, 0.1)])
+def test_fullsize_high_order_force_sampled(orc, n, ne, jitter):
+    """High orders at the order-sweep sizes (about 2e7 nodes, h = N 69.3/5 m),
+    in the sweep's launch configuration (coloured; regular geometry, or both
+    irregular paths on the jittered mesh), sampled against the oracle."""
+    import torch
+    from types import SimpleNamespace
+    import paper_2606_12850_amd as P
+    N = n - 1
+    mesh = W.box_mesh(ne, n, ne * N * 69.3 / 5, jitter=jitter, seed=7)
+    lam, mu, rho = W.layered_model(mesh, vp_layers=(3000.0,), vpvs=3000.0 / 1732.0, grf_amp=0.05,
+                                   grf_seed=12850, grf_corr_elems=4.0)
+    wl = SimpleNamespace(mesh=mesh, lam=lam, mu=mu)
+    s = P.Solver(n)
+    info = s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    rng = np.random.default_rng(n)
+    u = rng.uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32)
+    E = mesh.nspec
+    sample = np.unique(np.concatenate([rng.choice(E, 8, replace=False), [0, E - 1, E // 2]]))
+    nodes, ref = _sampled_reference(orc, wl, u.astype(np.float64), sample)
+    geos = ["regular"] if jitter == 0.0 else ["stored", "trilinear"]
+    assert (info["nirregular"] == 0) == (jitter == 0.0)
+    for geo in geos:
+        if geo != "regular":
+            P.semx_set_geometry(s.ctx, P.SEMX_GEOM_STORED if geo == "stored" else P.SEMX_GEOM_TRILINEAR)
+        f = s.apply_force(torch.from_numpy(u).cuda())
+        torch.cuda.synchronize()
+        err = rel_l2(f.cpu().numpy().astype(np.float64)[nodes], ref)
+        print(f"full-size NGLL {n} {geo}: {mesh.nglob} nodes, sampled rel L2 = {err:.3e} over {len(nodes)} nodes")
+        assert err <= 1e-5
+    s.close()
