@@ -24,10 +24,10 @@
  *     call that returns data to host memory synchronises that stream.
  *     A context is not thread-safe; use one context per host thread.
  *   - ngll = n = N+1 GLL points per direction, 2 <= n <= 16 (N = polynomial
- *     degree up to 15).  NGLL 11..16 run the FP32 operator and time loop on
- *     a column-per-lane kernel; FP64 storage, the adjoint and element patches
- *     support n <= 10 (SEMX_EINVAL above), the matrix-core contractions
- *     4 <= n <= 8.  Element-local point q = i + n*(j + n*k), i fastest (i
+ *     degree up to 15).  NGLL 11..16 run the FP32 operator, the time loop
+ *     and the adjoint on column-per-lane kernels; FP64 storage and element
+ *     patches support n <= 10 (SEMX_EINVAL above, patches are simply not
+ *     built), the matrix-core contractions 4 <= n <= 8.  Element-local point q = i + n*(j + n*k), i fastest (i
  *     along xi, j along eta, k along zeta).
  *   - Corner v = a + 2b + 4c of an 8-node hexahedron sits at reference
  *     coordinates (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the geometry is the

@@ -153,6 +153,216 @@ hipError_t launch_adj_n(int geo, bool atomic, const AdjArgs& A, hipStream_t s) {
   return hipGetLastError();
 }
 
+// NGLL 11..16: the same fused adjoint force and sensitivity accumulation
+// on the column layout of the high-order force kernel (one lane per (i, j)
+// column, psi and u^m of the column in registers, slices of both and of
+// the fluxes through LDS; the zeta part of the transpose contraction goes
+// into the column accumulators).
+template <int NG>
+struct AdjCol {
+  static constexpr int N2 = NG * NG;
+  static constexpr int N3 = NG * NG * NG;
+  static constexpr int BLK = ((N2 + 63) / 64) * 64;
+};
+
+template <int NG, int GEO, bool ATOMIC>
+__global__ __launch_bounds__(AdjCol<NG>::BLK) void adjoint_col_kernel(AdjArgs A) {
+  constexpr int N2 = AdjCol<NG>::N2;
+  constexpr int N3 = AdjCol<NG>::N3;
+  __shared__ int s_g[N3];
+  __shared__ float s_w[6 * N2];  // slice of psi (components 0..2) and u^m (3..5)
+  __shared__ float s_q[6 * N2];  // slice of xi and eta fluxes
+  __shared__ float s_D[N2];
+  const ForceArgs& a = A.fa;
+  const int grp = xcd_group((int)a.count);
+  if (grp >= a.count) return;
+  const int pos = (int)a.pos0 + grp;
+  const int l = threadIdx.x;
+  const bool act = l < N2;
+  const int ll = act ? l : 0;
+  const int i = ll % NG, j = ll / NG;
+  const int model = blockIdx.y;
+  const size_t vofs = (size_t)model * a.nglob * 3;
+  const float* psi = a.u + vofs;
+  float* f = a.f + vofs;
+  const float* mat = a.mat + (size_t)model * a.nspec * 2 * N3 + (size_t)pos * 2 * N3;
+
+  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N3; t += blockDim.x) s_g[t] = a.ibool[(size_t)pos * N3 + t];
+  __syncthreads();
+
+  float pc[3][NG], uc[3][NG], acc[3][NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const size_t g3 = 3 * (size_t)s_g[ll + N2 * k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pc[c][k] = psi[g3 + c];
+      uc[c][k] = A.uscale * A.um[vofs + g3 + c];
+      acc[c][k] = 0.0f;
+    }
+  }
+  float rx = 0.f, ry = 0.f;
+  const float* src = nullptr;
+  if constexpr (GEO == kTrilinear) {
+    rx = a.xi[i];
+    ry = a.xi[j];
+    src = a.tri + (size_t)pos * 24;
+  }
+  if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
+
+#pragma unroll 1
+  for (int k = 0; k < NG; ++k) {
+    const int q = ll + N2 * k;
+    if (k > 0) __syncthreads();  // the previous slice's readers are done
+    float pk[3] = {0.f, 0.f, 0.f}, uk[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pk[c] = pc[c][b];
+          uk[c] = uc[c][b];
+        }
+      }
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_w[c * N2 + ll] = pk[c];
+        s_w[(3 + c) * N2 + ll] = uk[c];
+      }
+    }
+    __syncthreads();
+    float dp[3][3], du[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dp[c][d] = du[c][d] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const float di = s_D[i * NG + b], dj = s_D[j * NG + b], dk = s_D[k * NG + b];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dp[c][0] += di * s_w[c * N2 + b + NG * j];
+        dp[c][1] += dj * s_w[c * N2 + i + NG * b];
+        dp[c][2] += dk * pc[c][b];
+        du[c][0] += di * s_w[(3 + c) * N2 + b + NG * j];
+        du[c][1] += dj * s_w[(3 + c) * N2 + i + NG * b];
+        du[c][2] += dk * uc[c][b];
+      }
+    }
+    float G[9];
+    if constexpr (GEO == kStored) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d) G[d] = a.gam_pt[((size_t)pos * 9 + d) * N3 + q];
+    }
+    float Mg[9], scale, det;
+    geom_map_from<GEO>(src, G, rx, ry, (GEO == kTrilinear) ? a.xi[k] : 0.f, Mg, scale, det);
+    float gp[3][3], gu[3][3];
+    apply_map(dp, Mg, gp);
+    apply_map(du, Mg, gu);
+    if (act) {
+      const float W = (float)A.wdet[(size_t)pos * N3 + q];
+      const size_t g3 = 3 * (size_t)s_g[q];
+      float aa[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) aa[c] = A.uscale * A.am[vofs + g3 + c];
+      const float divp = gp[0][0] + gp[1][1] + gp[2][2];
+      const float divu = gu[0][0] + gu[1][1] + gu[2][2];
+      float ee = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ee += 0.25f * (gp[c][b] + gp[b][c]) * (gu[c][b] + gu[b][c]);
+      const size_t kq = ((size_t)model * a.nspec + pos) * N3 + q;
+      const float ws = A.coef * W * scale;
+      A.kl[kq] += (double)(ws * divp * divu) * A.inv_uscale;
+      A.km[kq] += (double)(2.0f * ws * ee) * A.inv_uscale;
+      A.kr[kq] += (double)(A.coef * W * (pk[0] * aa[0] + pk[1] * aa[1] + pk[2] * aa[2])) * A.inv_uscale;
+    }
+    const float lw = mat[q], mw = mat[N3 + q];
+    const float ltr = lw * (gp[0][0] + gp[1][1] + gp[2][2]);
+    float sg[3][3];
+    sg[0][0] = ltr + 2.0f * mw * gp[0][0];
+    sg[1][1] = ltr + 2.0f * mw * gp[1][1];
+    sg[2][2] = ltr + 2.0f * mw * gp[2][2];
+    sg[0][1] = sg[1][0] = mw * (gp[0][1] + gp[1][0]);
+    sg[0][2] = sg[2][0] = mw * (gp[0][2] + gp[2][0]);
+    sg[1][2] = sg[2][1] = mw * (gp[1][2] + gp[2][1]);
+    float phi[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        phi[c][d] = scale * (sg[c][0] * Mg[d * 3 + 0] + sg[c][1] * Mg[d * 3 + 1] + sg[c][2] * Mg[d * 3 + 2]);
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const float dkb = s_D[k * NG + b];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c][b] += dkb * phi[c][2];
+    }
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_q[(2 * c + 0) * N2 + ll] = phi[c][0];
+        s_q[(2 * c + 1) * N2 + ll] = phi[c][1];
+      }
+    }
+    __syncthreads();
+    float sxy[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float sacc = 0.0f;
+#pragma unroll
+      for (int b = 0; b < NG; ++b) {
+        sacc += s_D[b * NG + i] * s_q[(2 * c + 0) * N2 + b + NG * j];
+        sacc += s_D[b * NG + j] * s_q[(2 * c + 1) * N2 + i + NG * b];
+      }
+      sxy[c] = sacc;
+    }
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) {
+        acc[0][b] += sxy[0];
+        acc[1][b] += sxy[1];
+        acc[2][b] += sxy[2];
+      }
+  }
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      float* fg = f + 3 * (size_t)s_g[ll + N2 * k];
+      if constexpr (ATOMIC) {
+        unsafeAtomicAdd(fg + 0, -acc[0][k]);
+        unsafeAtomicAdd(fg + 1, -acc[1][k]);
+        unsafeAtomicAdd(fg + 2, -acc[2][k]);
+      } else {
+        fg[0] = fg[0] - acc[0][k];
+        fg[1] = fg[1] - acc[1][k];
+        fg[2] = fg[2] - acc[2][k];
+      }
+    }
+  }
+}
+
+template <int NG>
+hipError_t launch_adj_col(int geo, bool atomic, const AdjArgs& A, hipStream_t s) {
+  if (A.fa.count <= 0) return hipSuccess;
+  const int64_t nb = ((A.fa.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  dim3 grid((unsigned)nb, (unsigned)A.fa.nmodels), block(AdjCol<NG>::BLK);
+#define SEMX_ADJC_LAUNCH(GEO)                                                   \
+  if (atomic) adjoint_col_kernel<NG, GEO, true><<<grid, block, 0, s>>>(A);     \
+  else adjoint_col_kernel<NG, GEO, false><<<grid, block, 0, s>>>(A);
+  switch (geo) {
+    case kRegular: SEMX_ADJC_LAUNCH(kRegular) break;
+    case kStored: SEMX_ADJC_LAUNCH(kStored) break;
+    case kTrilinear: SEMX_ADJC_LAUNCH(kTrilinear) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SEMX_ADJC_LAUNCH
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_force(int n, int geo, bool atomic, const AdjArgs& A, hipStream_t s) {
   switch (n) {
     case 2: return launch_adj_n<2>(geo, atomic, A, s);
@@ -164,6 +374,12 @@ hipError_t launch_adjoint_force(int n, int geo, bool atomic, const AdjArgs& A, h
     case 8: return launch_adj_n<8>(geo, atomic, A, s);
     case 9: return launch_adj_n<9>(geo, atomic, A, s);
     case 10: return launch_adj_n<10>(geo, atomic, A, s);
+    case 11: return launch_adj_col<11>(geo, atomic, A, s);
+    case 12: return launch_adj_col<12>(geo, atomic, A, s);
+    case 13: return launch_adj_col<13>(geo, atomic, A, s);
+    case 14: return launch_adj_col<14>(geo, atomic, A, s);
+    case 15: return launch_adj_col<15>(geo, atomic, A, s);
+    case 16: return launch_adj_col<16>(geo, atomic, A, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -296,7 +512,6 @@ int semx_set_checkpointing(semx_ctx* c, int64_t every) {
   if (!c) return SEMX_EINVAL;
   if (every < 0) return fail(c, SEMX_EINVAL, "set_checkpointing: negative interval");
   if (every > 0 && c->storage != SEMX_F32) return fail(c, SEMX_ESTATE, "set_checkpointing: the adjoint needs FP32 storage");
-  if (every > 0 && c->n > kMaxNLow) return fail(c, SEMX_EINVAL, "set_checkpointing: the adjoint supports NGLL <= 10");
   c->ckpt_every = every;
   c->ckpt_count = 0;
   if (every == 0) {
@@ -312,7 +527,6 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
   c->err.clear();
   if (!c->have_mesh || !c->have_model || !c->have_dt) return fail(c, SEMX_ESTATE, "adjoint: mesh, model and dt required");
   if (c->storage != SEMX_F32) return fail(c, SEMX_ESTATE, "adjoint: needs FP32 storage");
-  if (c->n > kMaxNLow) return fail(c, SEMX_EINVAL, "adjoint: supports NGLL <= 10");
   if (!gseis_dev || !g_lambda_dev || !g_mu_dev || !g_rho_dev) return fail(c, SEMX_EINVAL, "adjoint: null pointer");
   if (c->rec.nrec == 0) return fail(c, SEMX_ESTATE, "adjoint: no receivers");
   if (c->ckpt_every <= 0 || c->ckpt_count == 0)

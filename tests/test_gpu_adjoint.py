@@ -118,3 +118,42 @@ def test_adjoint_requires_checkpoints():
         op.gradient(torch.zeros((1, 4, 3, Pb["nt"])))
     assert ei.value.code == P.SEMX_ESTATE
     op.solver.close()
+
+
+@pytest.mark.parametrize("n,geometry", [(12, "stored"), (16, "trilinear")])
+def test_adjoint_high_order(orc, n, geometry):
+    """NGLL 12 and 16 (the column kernels): sensitivity kernels against the
+    oracle adjoint and one FP64 central-difference direction."""
+    import torch
+    import paper_2606_12850_amd as P
+    Pb = _problem(n=n, ne=(2, 2, 1), nt=60, seed=3)
+    Pb["dt"] = 1e-3
+    Pb["stf"] = W.ricker(25.0, 0.04, Pb["dt"], Pb["nt"] + 1)[None, :]
+    m = Pb["m"]
+    _, data = _oracle_chi(orc, Pb, Pb["lam"] * 1.03, Pb["mu"] * 0.97, Pb["rho"], np.zeros((4, 3, Pb["nt"])))
+    chi0, s0 = _oracle_chi(orc, Pb, Pb["lam"], Pb["mu"], Pb["rho"], data)
+    gseis = Pb["dt"] * (s0 - data)
+    gam, jac, _ = orc.geometry(m.n, m.elem_vert, m.vert)
+    rl, rm, rr = orc.adjoint(m.n, m.ibool, gam, jac, Pb["lam"], Pb["mu"], Pb["rho"], m.nglob, Pb["dt"], Pb["nt"],
+                             Pb["se"], Pb["sx"], Pb["sd"], Pb["stf"], Pb["re"], Pb["rx"], gseis)
+    op = _gpu_op(Pb, every=20, geometry=P.SEMX_GEOM_STORED if geometry == "stored" else P.SEMX_GEOM_TRILINEAR)
+    seis = op.run(Pb["lam"], Pb["mu"], Pb["rho"])
+    torch.cuda.synchronize()
+    assert rel_l2(seis[0].cpu().numpy(), s0) < 1e-4
+    gl, gm, gr = (t[0].cpu().numpy().astype(np.float64) for t in op.gradient(torch.from_numpy(gseis[None])))
+    for name, a, b in (("lambda", gl, rl), ("mu", gm, rm), ("rho", gr, rr)):
+        err = rel_l2(a, b)
+        print(f"NGLL {n} {geometry} K_{name}: rel L2 vs oracle adjoint {err:.2e}")
+        assert err <= 1e-3, (name, err)
+    rng = np.random.default_rng(9)
+    dl = Pb["lam"] * rng.standard_normal(Pb["lam"].shape)
+    dm = Pb["mu"] * rng.standard_normal(Pb["mu"].shape)
+    dr = Pb["rho"] * rng.standard_normal(Pb["rho"].shape)
+    eps = 1e-6
+    cp, _ = _oracle_chi(orc, Pb, Pb["lam"] + eps * dl, Pb["mu"] + eps * dm, Pb["rho"] + eps * dr, data)
+    cm, _ = _oracle_chi(orc, Pb, Pb["lam"] - eps * dl, Pb["mu"] - eps * dm, Pb["rho"] - eps * dr, data)
+    fd = (cp - cm) / (2 * eps)
+    ad = np.sum(gl * dl) + np.sum(gm * dm) + np.sum(gr * dr)
+    print(f"NGLL {n} direction: adjoint {ad:.6e} FD {fd:.6e} rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-3 * abs(fd)
+    op.solver.close()

@@ -96,8 +96,8 @@ def test_high_order_seismograms(orc, n):
 
 
 def test_high_order_limits():
-    """FP64 storage, the adjoint and the matrix-core paths stop at lower
-    orders and say so."""
+    """FP64 storage and the matrix-core paths stop at lower orders and say
+    so; checkpointing for the adjoint is accepted at every order."""
     import paper_2606_12850_amd as P
     mesh = W.box_mesh((1, 1, 1), 12, 1000.0)
     lam, mu, rho = W.homogeneous_model(mesh)
@@ -107,9 +107,8 @@ def test_high_order_limits():
     assert ei.value.code == P.SEMX_EINVAL
     s.upload_mesh(mesh)
     s.upload_model(lam, mu, rho)
-    with pytest.raises(P.SemxError) as ei:
-        P.semx_set_checkpointing(s.ctx, 10)
-    assert ei.value.code == P.SEMX_EINVAL
+    P.semx_set_checkpointing(s.ctx, 10)
+    P.semx_set_checkpointing(s.ctx, 0)
     with pytest.raises(P.SemxError) as ei:
         P.semx_set_mode(s.ctx, P.SEMX_C_BF16, P.SEMX_ASM_COLORED)
     assert ei.value.code == P.SEMX_EINVAL
