@@ -30,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def progress(msg: str):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 NE, NGLL = 64, 5
 
 
@@ -131,6 +136,7 @@ def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 1
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     op.solver.close()
+    progress(f"adjoint: forward {t_fwd:.3f} s, adjoint {t_adj:.3f} s")
     # FP64 forward runs of the same discrete problem (FP64 storage)
     s64 = P.Solver(NGLL, storage=P.SEMX_F64)
     s64.upload_mesh(wl.mesh)
@@ -164,6 +170,7 @@ def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 1
         fdv = (cp - cm) / (2 * fd_eps)
         ad = float(np.sum(gl[0].cpu().numpy() * dl) + np.sum(gm[0].cpu().numpy() * dm) + np.sum(gr[0].cpu().numpy() * dr))
         fd.append({"adjoint": ad, "fd_fp64": fdv, "rel": abs(ad - fdv) / max(abs(fdv), 1e-300)})
+        progress(f"adjoint: FD direction {k + 1}/{fd_dirs}, rel {fd[-1]['rel']:.2e}")
     s64.close()
     scale = max(abs(d["fd_fp64"]) for d in fd)
     for d in fd:
@@ -480,6 +487,7 @@ def main():
         apply[f"{cname}_{gname}_{aname}" + (f"_patch{npt}" if npt else "")] = {
             "ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3), "bytes_per_element": bg,
             "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
+    progress(f"force-apply matrix done ({len(apply)} variants)")
     if args.profile_force:
         # calibration for the traffic counters: a plain device copy of known size
         nbytes = 1 << 30
@@ -513,6 +521,7 @@ def main():
     launches, force_ms = P.semx_force_timing(s.ctx)
     P.semx_set_timing(s.ctx, False)
     step_ms = e0.elapsed_time(e1) / args.steps
+    progress(f"time loop: {args.steps} steps, {step_ms:.4f} ms per step")
     seis = s.seismograms()
     assert np.all(np.isfinite(seis)), "non-finite seismograms"
 
