@@ -615,12 +615,13 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
     c->pending_correct = false;
     if (!rc) rc = d2d(c, segu.as<char>(), c->d_u.p, vb);
     if (!rc) rc = d2d(c, sega.as<char>(), c->d_a.p, vb);
-    for (int64_t s = 1; s <= n1 - n0 && !rc; ++s) {
-      rc = step_once(c, false);
-      if (!rc) rc = complete_step(c);
-      if (!rc) rc = d2d(c, segu.as<char>() + s * vb, c->d_u.p, vb);
-      if (!rc) rc = d2d(c, sega.as<char>() + s * vb, c->d_a.p, vb);
-    }
+    // the forward run's own fused Newmark pass stores u^s and a^{s-1} into the
+    // segment buffers (bitwise the forward states); the last a after the loop
+    float* su0 = segu.as<float>();
+    float* sa0 = sega.as<float>();
+    for (int64_t s = 1; s <= n1 - n0 && !rc; ++s)
+      rc = step_once(c, false, su0 + s * len, s >= 2 ? sa0 + (s - 1) * len : nullptr);
+    if (!rc) rc = complete_step(c, sa0 + (n1 - n0) * len);
     // normaliser of this segment's forward field
     if (!rc) {
       float umax = 0.0f;

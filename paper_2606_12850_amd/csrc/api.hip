@@ -246,12 +246,14 @@ __global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
 // (the coming force pass overwrites every node).  A step is "correct then
 // predict" in one pass, so a never has to be written.
 // ---------------------------------------------------------------------------
-constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8;
+// kSeg (the adjoint's forward recomputation): also store acc to seg_a and the
+// predicted u to seg_u, the segment buffers, in the same pass.
+constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8, kSeg = 16;
 
 template <int MODE>
 __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
                                float* __restrict__ u, float* __restrict__ v, float* __restrict__ a,
-                               float* __restrict__ f) {
+                               float* __restrict__ f, float* __restrict__ seg_u, float* __restrict__ seg_a) {
   const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -260,16 +262,29 @@ __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const fl
       acc = minv[t / 3] * f[t];
       vv = vv + hdt * acc;
       if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+      if constexpr ((MODE & kSeg) != 0) seg_a[t] = acc;
     } else {
       acc = a[t];
     }
     if constexpr ((MODE & kPredict) != 0) {
-      u[t] = u[t] + dt * vv + hdt2 * acc;
+      const float un = u[t] + dt * vv + hdt2 * acc;
+      u[t] = un;
+      if constexpr ((MODE & kSeg) != 0) seg_u[t] = un;
       vv = vv + hdt * acc;
       if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0f;
     }
     v[t] = vv;
   }
+}
+
+// Launch one Newmark variant, with the segment stores when seg_u or seg_a is given.
+template <int MODE>
+void launch_newmark(semx_ctx* c, int64_t nn, unsigned gb, float dt, const float* minv, float* u, float* v, float* a,
+                    float* f, float* seg_u, float* seg_a) {
+  if (seg_u || seg_a)
+    newmark_kernel<MODE | kSeg><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, seg_u, seg_a);
+  else
+    newmark_kernel<MODE><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
 }
 
 // a = M^{-1} f without touching v (initial acceleration).
@@ -948,13 +963,13 @@ int inject_sources(semx_ctx* c, int64_t m, float* f) {
   return SEMX_OK;
 }
 
-int finalize_state(semx_ctx* c) {
+int finalize_state(semx_ctx* c, float* seg_a = nullptr) {
   if (c->storage == SEMX_F64) return f64_finalize(c);
   if (!c->pending_correct) return SEMX_OK;
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
-  newmark_kernel<kCorrect | kStoreA><<<grid_for(3 * nn), kThreads, 0, c->stream>>>(
-      nn, c->nglob, (float)c->dt, c->d_minv.as<float>(), c->d_u.as<float>(), c->d_v.as<float>(),
-      c->d_a.as<float>(), c->d_f.as<float>());
+  launch_newmark<kCorrect | kStoreA>(c, nn, grid_for(3 * nn), (float)c->dt, c->d_minv.as<float>(),
+                                     c->d_u.as<float>(), c->d_v.as<float>(), c->d_a.as<float>(),
+                                     c->d_f.as<float>(), nullptr, seg_a);
   SEMX_HIP(c, hipGetLastError());
   c->pending_correct = false;
   return SEMX_OK;
@@ -1048,7 +1063,7 @@ int check_finite(semx_ctx* c, bool* ok) {
 
 // One explicit Newmark step (correct the pending step, predict, force,
 // sources; optionally record receivers).  Leaves f = -K u + f_src pending.
-int step_once(semx_ctx* c, bool record) {
+int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
   if (c->storage == SEMX_F64) return f64_step_once(c, record);
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
   const float dt = (float)c->dt;
@@ -1057,11 +1072,11 @@ int step_once(semx_ctx* c, bool record) {
   const bool keep = force_overwrites(c);
   const unsigned gb = grid_for(3 * nn, 1 << 30);  // one pass per lane (streams faster than grid-stride)
   if (c->pending_correct) {
-    if (keep) newmark_kernel<kCorrect | kPredict | kKeepF><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
-    else newmark_kernel<kCorrect | kPredict><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+    if (keep) launch_newmark<kCorrect | kPredict | kKeepF>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
+    else launch_newmark<kCorrect | kPredict>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
   } else {
-    if (keep) newmark_kernel<kPredict | kKeepF><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
-    else newmark_kernel<kPredict><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f);
+    if (keep) launch_newmark<kPredict | kKeepF>(c, nn, gb, dt, minv, u, v, a, f, seg_u, nullptr);
+    else launch_newmark<kPredict>(c, nn, gb, dt, minv, u, v, a, f, seg_u, nullptr);
   }
   SEMX_HIP(c, hipGetLastError());
   int rc = force_into(c, u, f, !keep);
@@ -1075,7 +1090,7 @@ int step_once(semx_ctx* c, bool record) {
 
 int apply_force_accumulate(semx_ctx* c, const float* u, float* f) { return force_accumulate(c, u, f); }
 int fill_zero(semx_ctx* c, float* p, int64_t n) { return zero_f32(c, p, n); }
-int complete_step(semx_ctx* c) { return finalize_state(c); }
+int complete_step(semx_ctx* c, float* seg_a) { return finalize_state(c, seg_a); }
 // Point sources with the time function given in FP32 (stf32) or FP64
 // (stf64); both precisions are kept on the device for the two storage modes.
 int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* xi, const double* dir,

@@ -237,10 +237,15 @@ hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hi
 bool mfma_supported(int n);
 
 // ---- host helpers shared between translation units (api.hip) ----------------
-int step_once(semx_ctx* c, bool record);
+// One explicit step.  seg_u / seg_a (the adjoint's forward recomputation,
+// may be null): the Newmark pass also stores the predicted u and, when it
+// corrects the previous step, that step's acceleration, into them.
+int step_once(semx_ctx* c, bool record, float* seg_u = nullptr, float* seg_a = nullptr);
 int apply_force_accumulate(semx_ctx* c, const float* u, float* f);
 int fill_zero(semx_ctx* c, float* p, int64_t n);
-int complete_step(semx_ctx* c);
+// Apply the pending correction (a = M^{-1} f, v += dt/2 a); seg_a, if given,
+// receives a as well.
+int complete_step(semx_ctx* c, float* seg_a = nullptr);
 unsigned grid_1d(int64_t n, int cap = 1 << 16);
 // adjoint.hip
 int save_checkpoint(semx_ctx* c);
