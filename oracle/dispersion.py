@@ -372,3 +372,56 @@ def iso_accuracy_ppw(n: int, eps: float, lo: float = 2.0, hi: float = 2000.0) ->
         else:
             b = mid
     return float(b)
+
+
+def axis_mode(n: int, kh: float):
+    """axis_omega with its mode: (omega h / c, v, mr), v the M-normalised
+    Bloch eigenvector over the N cell nodes of the 1-D lattice (h = c = 1)
+    and mr the lumped cell mass."""
+    N = n - 1
+    xi, w, Ke = _axis_element(n)
+    r = np.arange(n) % N
+    ph = np.exp(1j * kh * (np.arange(n) // N))
+    P = np.zeros((n, N), dtype=np.complex128)
+    P[np.arange(n), r] = ph
+    Kr = P.conj().T @ Ke @ P
+    mr = np.bincount(r, weights=0.5 * w, minlength=N)
+    s = 1.0 / np.sqrt(mr)
+    A = s[:, None] * Kr * s[None, :]
+    ev, V = np.linalg.eigh(0.5 * (A + A.conj().T))
+    x = 0.5 * (xi[:N] + 1.0)
+    pw = np.sqrt(mr) * np.exp(1j * kh * x)
+    j = int(np.argmax(np.abs(V.conj().T @ pw)))
+    return float(np.sqrt(max(ev[j], 0.0))), s * V[:, j], mr
+
+
+def periodic_axis_wave(mesh, lam: float, mu: float, rho: float, m: int, wave_type: str):
+    """periodic_plane_wave for a wave along x (k = 2 pi m / L_x) from the 1-D
+    Bloch analysis, for any order: the 3-D mode of an axis wave is the 1-D
+    mode, uniform across the axis, times the polarisation (x for P, y for
+    S).  Returns the same dict as periodic_plane_wave."""
+    n = mesh.n
+    N = n - 1
+    h = mesh.h[0]
+    if not (mesh.periodic and np.allclose(mesh.h, h) and mesh.jitter == 0.0):
+        raise ValueError("periodic_axis_wave: needs a periodic box of undistorted cubic elements")
+    k = 2.0 * np.pi * m / mesh.L[0]
+    kh = k * h
+    t = kh / np.pi
+    if abs(t - round(t)) < 1e-9:
+        raise ValueError("periodic_axis_wave: k on a Brillouin-zone boundary")
+    pol = np.array([1.0, 0.0, 0.0]) if wave_type == "P" else np.array([0.0, 1.0, 0.0])
+    c = float(np.sqrt((lam + 2.0 * mu) / rho)) if wave_type == "P" else float(np.sqrt(mu / rho))
+    w1, v, _ = axis_mode(n, kh)
+    G = np.zeros(mesh.nglob, dtype=np.int64)
+    gx, _, _ = mesh.lattice_index()
+    G[mesh.ibool.ravel()] = gx.ravel() % (mesh.nex * N)
+    phi = v[G % N] * np.exp(1j * kh * (G // N))
+    xi, _ = O.gll(n)
+    X = (G // N) * h + 0.5 * (xi[:N][G % N] + 1.0) * h
+    u0 = np.cos(k * X)[:, None] * pol[None, :]
+    _, jac, _ = O.geometry(n, mesh.elem_vert, mesh.vert)
+    mass = O.mass(n, mesh.ibool, jac, np.full(mesh.ibool.shape, float(rho)), mesh.nglob)
+    wts = (mass * np.real(phi))[:, None] * pol[None, :]
+    return {"u0": u0, "w": wts, "omega_h": w1 * c / h, "c": c, "k": k, "ppw": 2.0 * np.pi / k / (h / N),
+            "captured": None}

@@ -122,3 +122,28 @@ def test_plane_wave_atomic_assembly_and_reset():
         res[asm] = Dp.fit_frequency(a, dt)[0]
         assert abs(res[asm] / pw["omega_h"] - 1.0) <= 1e-5
     s.close()
+
+
+@pytest.mark.parametrize("n,m", [(9, 8), (12, 11), (16, 14)])
+def test_axis_wave_high_order(n, m):
+    """Axis P and S waves at about 5 points per wavelength on the high-order
+    kernels (NGLL 12, 16; NGLL 9 cross-checks the lower-order kernel), the
+    expected frequency from the 1-D Bloch analysis (exact for axis waves)."""
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh(NE, n, NE * H, periodic=True)
+    lam, mu, rho = W.homogeneous_model(mesh, VP, VS, RHO)
+    s = make_solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    dt = P.semx_cfl_dt(s.ctx, COURANT)
+    P.semx_set_dt(s.ctx, dt)
+    for wave in "PS":
+        pw = Dp.periodic_axis_wave(mesh, LAM, MU, RHO, m, wave)
+        ser = projected_series(P, s, pw["u0"], pw["w"], NSTEPS)
+        omega_h, omega_run = Dp.fit_frequency(ser, dt)
+        ck = pw["c"] * pw["k"]
+        dev = omega_h / pw["omega_h"] - 1.0
+        print(f"axis dispersion NGLL {n} {wave} ppw={pw['ppw']:.2f}: omega_h/(ck)-1 library {omega_h / ck - 1:+.4e} "
+              f"oracle {pw['omega_h'] / ck - 1:+.4e} (rel diff {dev:+.2e}); with dt {omega_run / ck - 1:+.4e}")
+        assert abs(dev) <= FREQ_BOUND["f32"]
+    s.close()

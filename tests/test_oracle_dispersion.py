@@ -248,3 +248,19 @@ def test_iso_accuracy_table_reproducible():
     # fewer points per wavelength are needed as the order grows (asymptotic range)
     for row in stored["ppw"]:
         assert row[0] > row[3] > row[6] > row[14]
+
+
+@pytest.mark.parametrize("n,m,wave", [(4, 4, "P"), (6, 3, "S")])
+def test_periodic_axis_wave_from_1d_mode(n, m, wave):
+    """The 1-D Bloch mode, extended uniformly across the axis, is an exact
+    mode of the assembled periodic 3-D operator: the FP64 time loop projected
+    on it recovers the 1-D frequency, which is also the 3-D Bloch one."""
+    import workloads as W
+    mesh = W.box_mesh(5, n, 5 * H, periodic=True)
+    pw = Dp.periodic_axis_wave(mesh, LAM, MU, RHO, m, wave)
+    dt = 0.03 * H / VP
+    s = Dp.newmark_free(mesh, LAM, MU, RHO, pw["u0"], dt, 60, pw["w"])
+    omega_h, _ = Dp.fit_frequency(s, dt)
+    assert abs(omega_h / pw["omega_h"] - 1.0) <= 1e-10
+    pw3 = Dp.periodic_plane_wave(mesh, LAM, MU, RHO, (m, 0, 0), wave)
+    assert abs(pw3["omega_h"] / pw["omega_h"] - 1.0) <= 1e-11
