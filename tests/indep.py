@@ -133,3 +133,17 @@ def sem1d_bloch_omega(n, h, c, k):
     pw = np.sqrt(mr) * np.exp(1j * k * x)
     j = int(np.argmax(np.abs(V.conj().T @ pw)))
     return float(np.sqrt(max(ev[j], 0.0)))
+
+
+def dense_stiffness_acoustic(n, ibool, elem_vert, vert, rho, nglob):
+    """Scalar stiffness K_ab = sum_{e,q} w_q detJ_q / rho_q grad phi_a . grad phi_b
+    (nglob x nglob), from the bilinear form, column by column (tiny meshes only)."""
+    _, det, gam, _ = geometry_numpy(n, elem_vert, vert)
+    _, w = gll_numpy(n)
+    w3 = np.einsum("k,j,i->kji", w, w, w).ravel()
+    grads = []
+    for col in range(nglob):
+        u = np.zeros((nglob, 3)); u[col, 0] = 1.0
+        grads.append(grad_at_points(n, ibool, u, gam)[:, :, 0, :])  # [e, q, b]
+    G = np.stack(grads)
+    return np.einsum("aeqb,ceqb,eq->ac", G, G, w3[None, :] * det / rho)
