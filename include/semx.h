@@ -290,6 +290,48 @@ int semx_get_state_f64(semx_ctx *ctx, double *u_dev, double *v_dev, double *a_de
 int semx_set_state_f64(semx_ctx *ctx, const double *u_dev, const double *v_dev, const double *a_dev,
                        int64_t it);
 
+/* -------------------------------------------------------------------------
+ * Acoustic physics.  The paper selects its equal-accuracy (h, p) pairs with
+ * an acoustic solver in a homogeneous medium (Sec. V-C).  With
+ * SEMX_ACOUSTIC the context solves for a scalar field p,
+ *     (1/kappa) p_tt = div(rho^-1 grad p) + sources,
+ * discretised as the elastic operator is (Sec. II-B GLL weak form): lumped
+ * mass M_g = sum w_i w_j w_k det J / kappa, force f = -K p with
+ * K_gh = sum w_i w_j w_k det J rho^-1 grad phi_g . grad phi_h, the same
+ * explicit Newmark loop.  Every state vector, force vector and seismogram
+ * then has ONE component per node: u, v, a, f are [nmodels][nglob] and
+ * seismograms [nmodels][nrec][1][nt_max] in the entry points above
+ * (semx_apply_force, semx_get_state, semx_set_state, semx_read_seismograms,
+ * semx_max_eigenvalue, semx_energy, semx_step, semx_cfl_dt with
+ * c = sqrt(kappa/rho)).  semx_set_sources() ignores dir (it may be NULL):
+ * a source adds stf[s][m] l_q(x_s) to the nodes of its element.  Both
+ * assemblies, both geometry paths and NGLL 2..16 are supported; the
+ * matrix-core contractions, FP64 storage, element patches and the adjoint
+ * are elastic only (SEMX_EINVAL).
+ * ------------------------------------------------------------------------- */
+#define SEMX_ELASTIC 0   /* vector displacement, isotropic elasticity (default) */
+#define SEMX_ACOUSTIC 1  /* scalar field, acoustic wave equation */
+
+/* Select the physics.  Allowed before a model is uploaded (SEMX_ESTATE
+ * after it, or while checkpointing is on); SEMX_EINVAL for an unknown value
+ * or, for SEMX_ACOUSTIC, with FP64 storage or a matrix-core contraction. */
+int semx_set_physics(semx_ctx *ctx, int physics);
+
+/* Acoustic model per element-local point, FP64 host arrays
+ * [nmodels][nspec][n^3]: bulk modulus kappa = rho c^2 and density rho, both
+ * > 0 (SEMX_EINVAL otherwise).  The library forms w_i w_j w_k det J / rho
+ * (FP32) and M_g = sum w_i w_j w_k det J / kappa (FP64 accumulate, FP32
+ * M^{-1}).  SEMX_ESTATE unless the physics is SEMX_ACOUSTIC (and
+ * semx_upload_model returns SEMX_ESTATE while it is).  Resets the time loop. */
+int semx_upload_model_acoustic(semx_ctx *ctx, int nmodels, const double *kappa, const double *rho);
+
+/* The library's GLL nodes (ascending) and weights for ngll points
+ * (Sec. II-B), FP64, into host arrays of ngll entries; no context, no GPU
+ * work.  For callers that place sources or receivers at nodes or weight them
+ * by quadrature (e.g. a plane source on an element face).  SEMX_EINVAL
+ * unless 2 <= ngll <= 16 and both pointers are non-NULL. */
+int semx_gll(int ngll, double *xi, double *w);
+
 /* Kernel timing.  While enabled, every force-kernel launch is bracketed by a
  * pair of HIP events recorded on the context stream.  semx_force_timing()
  * synchronises the stream, returns the number of force launches and their

@@ -38,6 +38,8 @@ SEMX_GEOM_STORED = 0
 SEMX_GEOM_TRILINEAR = 1
 SEMX_F32 = 0
 SEMX_F64 = 1
+SEMX_ELASTIC = 0
+SEMX_ACOUSTIC = 1
 
 _ERRNAMES = {-1: "EINVAL", -2: "ESTATE", -3: "EGEOM", -4: "EUNSTABLE", -5: "EHIP", -6: "ENOMEM",
              -7: "ENUMERIC"}
@@ -99,6 +101,9 @@ _SIGS = {
     "semx_set_state_f64": [_vp, _vp, _vp, _vp, _i64],
     "semx_stream_bandwidth": [_vp, _i64, _i32, ctypes.POINTER(_f64)],
     "semx_set_timing": [_vp, _i32],
+    "semx_set_physics": [_vp, _i32],
+    "semx_upload_model_acoustic": [_vp, _i32, _vp, _vp],
+    "semx_gll": [_i32, _vp, _vp],
     "semx_force_timing": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
 }
 _RESTYPE = {"semx_last_error": ctypes.c_char_p, "semx_mlp_last_error": ctypes.c_char_p}
@@ -207,6 +212,26 @@ def semx_upload_model(ctx, lam, mu, rho):
     return _check(ctx, lib().semx_upload_model(ctx, nm, _ptr(lam), _ptr(mu), _ptr(rho)))
 
 
+def semx_set_physics(ctx, physics: int):
+    return _check(ctx, lib().semx_set_physics(ctx, int(physics)))
+
+
+def semx_upload_model_acoustic(ctx, kappa, rho):
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    nm = kappa.shape[0] if kappa.ndim == 3 else 1
+    return _check(ctx, lib().semx_upload_model_acoustic(ctx, nm, _ptr(kappa), _ptr(rho)))
+
+
+def semx_gll(ngll: int):
+    """The library's GLL nodes and weights (FP64 numpy arrays)."""
+    xi = np.zeros(int(ngll)); w = np.zeros(int(ngll))
+    rc = lib().semx_gll(int(ngll), _ptr(xi), _ptr(w))
+    if rc != SEMX_OK:
+        raise SemxError(rc, f"semx_gll: ngll={ngll} outside [2, 16]")
+    return xi, w
+
+
 def semx_set_mode(ctx, contraction: int, assembly: int):
     return _check(ctx, lib().semx_set_mode(ctx, int(contraction), int(assembly)))
 
@@ -232,13 +257,15 @@ def semx_max_eigenvalue(ctx, iters: int) -> float:
 
 
 def semx_set_sources(ctx, elem, xi, direction, stf):
+    """``direction`` may be None for the acoustic physics."""
     el = np.ascontiguousarray(elem, dtype=np.int32)
     x = np.ascontiguousarray(xi, dtype=np.float64)
-    d = np.ascontiguousarray(direction, dtype=np.float64)
+    d = None if direction is None else np.ascontiguousarray(direction, dtype=np.float64)
     s = np.ascontiguousarray(stf, dtype=np.float32)
     nsrc = len(el)
     nstf = s.shape[-1] if nsrc else 0
-    return _check(ctx, lib().semx_set_sources(ctx, nsrc, _ptr(el), _ptr(x), _ptr(d), nstf, _ptr(s)))
+    return _check(ctx, lib().semx_set_sources(ctx, nsrc, _ptr(el), _ptr(x), None if d is None else _ptr(d),
+                                              nstf, _ptr(s)))
 
 
 def semx_set_sources_f64(ctx, elem, xi, direction, stf):
@@ -428,7 +455,7 @@ class Solver:
     """One library context bound to torch's current HIP stream on ``device``;
     ``storage`` SEMX_F32 (default) or SEMX_F64 (fields and time loop in FP64)."""
 
-    def __init__(self, ngll: int, device: str = "cuda:0", storage: int = SEMX_F32):
+    def __init__(self, ngll: int, device: str = "cuda:0", storage: int = SEMX_F32, physics: int = SEMX_ELASTIC):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -438,6 +465,10 @@ class Solver:
         self.storage = storage
         if storage != SEMX_F32:
             semx_set_storage(self.ctx, storage)
+        self.physics = physics
+        self.ncomp = 1 if physics == SEMX_ACOUSTIC else 3
+        if physics != SEMX_ELASTIC:
+            semx_set_physics(self.ctx, physics)
         self.n = ngll
         self.nspec = self.nglob = self.nmodels = 0
         self.nrec = 0
@@ -464,11 +495,17 @@ class Solver:
         self.nmodels = lam.shape[0] if lam.ndim == 3 else 1
         semx_upload_model(self.ctx, lam, mu, rho)
 
+    def upload_model_acoustic(self, kappa, rho):
+        kappa = np.asarray(kappa)
+        self.nmodels = kappa.shape[0] if kappa.ndim == 3 else 1
+        semx_upload_model_acoustic(self.ctx, kappa, rho)
+
     def set_mode(self, contraction=SEMX_C_F32, assembly=SEMX_ASM_COLORED):
         semx_set_mode(self.ctx, contraction, assembly)
 
     def empty_field(self):
-        shape = (self.nmodels, self.nglob, 3) if self.nmodels > 1 else (self.nglob, 3)
+        per = (self.nglob, 3) if self.ncomp == 3 else (self.nglob,)
+        shape = (self.nmodels,) + per if self.nmodels > 1 else per
         dt = self.torch.float64 if self.storage == SEMX_F64 else self.torch.float32
         return self.torch.zeros(shape, dtype=dt, device=self.device)
 
@@ -496,9 +533,9 @@ class Solver:
 
     def seismograms(self):
         if self.storage == SEMX_F64:
-            out = np.zeros((max(self.nmodels, 1), self.nrec, 3, self.nt_max), np.float64)
+            out = np.zeros((max(self.nmodels, 1), self.nrec, self.ncomp, self.nt_max), np.float64)
             semx_read_seismograms_f64(self.ctx, out, False)
         else:
-            out = np.zeros((max(self.nmodels, 1), self.nrec, 3, self.nt_max), np.float32)
+            out = np.zeros((max(self.nmodels, 1), self.nrec, self.ncomp, self.nt_max), np.float32)
             semx_read_seismograms(self.ctx, out, False)
         return out if self.nmodels > 1 else out[0]

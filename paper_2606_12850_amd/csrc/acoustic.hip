@@ -1,0 +1,283 @@
+// FP32 element force kernels of the scalar (acoustic) operator f = -K p.
+//
+// The acoustic weak form (the paper's equal-accuracy experiment runs an
+// acoustic solver, Sec. V-C) with GLL quadrature (Sec. II-B) has the
+// elastic operator's structure with one field component: three forward
+// contractions with D give the reference gradient of p, the geometry map
+// gives the physical gradient, the flux is Phi_d = (W / rho) sum_b g_b
+// Gamma_db, and three transpose contractions with D^T give the force.  The
+// per-point weight W / rho (W = w_i w_j w_k det J) sits in the first half of
+// the material table; the mass carries W / kappa.
+//
+// Two layouts, as for the elastic operator:
+//   force_ac_kernel      NGLL <= 10: one workgroup per element, one lane per
+//                        point, p and the three flux cubes in LDS;
+//   force_ac_col_kernel  NGLL 11..16: one lane per (i, j) column, the
+//                        column of p and its force accumulators in registers,
+//                        the element walked slice by slice in k.
+// Geometry paths, first-touch coloured stores and atomic assembly follow
+// the elastic kernels.
+#include "elem_common.hpp"
+
+namespace semx {
+namespace {
+
+// physical gradient times det' (geometry map Mg), then the weighted flux
+// phi_d = scale * r * sum_b g_b Mg[d][b]
+__device__ __forceinline__ void scalar_flux(const float d[3], const float Mg[9], float r, float scale,
+                                            float phi[3]) {
+  float g[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) g[b] = d[0] * Mg[0 * 3 + b] + d[1] * Mg[1 * 3 + b] + d[2] * Mg[2 * 3 + b];
+  const float s = r * scale;
+#pragma unroll
+  for (int dd = 0; dd < 3; ++dd) phi[dd] = s * (g[0] * Mg[dd * 3 + 0] + g[1] * Mg[dd * 3 + 1] + g[2] * Mg[dd * 3 + 2]);
+}
+
+__device__ __forceinline__ bool first_bit(const ForceArgs& a, int pos, int q) {
+  return a.first && ((a.first[(size_t)pos * a.first_words + (q >> 5)] >> (q & 31)) & 1u);
+}
+
+template <int NG, int GEO, bool ATOMIC>
+__global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
+  constexpr int N3 = Shape<NG>::N3;
+  __shared__ float s_p[N3];
+  __shared__ float s_q[3 * N3];
+  __shared__ float s_D[NG * NG];
+
+  const int ngrp = (int)a.count;
+  const int grp = xcd_group(ngrp);
+  if (grp >= ngrp) return;  // uniform over the block
+  const int pos = (int)a.pos0 + grp;
+
+  const int p = threadIdx.x;
+  const bool act = p < N3;
+  const int pp = act ? p : 0;
+  const int i = pp % NG, j = (pp / NG) % NG, k = pp / (NG * NG);
+
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob;
+  float* f = a.f + (size_t)model * a.nglob;
+  const float* __restrict__ mat = a.mat + ((size_t)model * a.nspec + pos) * 2 * N3;
+
+  const int g = ldnt(a.ibool + (size_t)pos * N3 + pp);
+  float G[9];
+  if constexpr (GEO == kStored) {
+    const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) G[d] = ldnt(gp + d * N3);
+  }
+  const float r = ldnt(mat + pp);
+  const float pv = u[g];
+  bool first = false;
+  float fo = 0.0f;
+  if constexpr (!ATOMIC) {
+    first = first_bit(a, pos, pp);
+    if (!first) fo = f[g];
+  }
+  if (p < NG * NG) s_D[p] = a.D[p];
+  if (act) s_p[pp] = pv;
+  float rx = 0.f, ry = 0.f, rz = 0.f;
+  if constexpr (GEO == kTrilinear) {
+    rx = a.xi[i];
+    ry = a.xi[j];
+    rz = a.xi[k];
+  }
+  __syncthreads();
+
+  float d[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    d[0] += s_D[i * NG + q] * s_p[q + NG * (j + NG * k)];
+    d[1] += s_D[j * NG + q] * s_p[i + NG * (q + NG * k)];
+    d[2] += s_D[k * NG + q] * s_p[i + NG * (j + NG * q)];
+  }
+  float Mg[9], scale, det;
+  geom_map<GEO>(a, pos, G, rx, ry, rz, Mg, scale, det);
+  float phi[3];
+  scalar_flux(d, Mg, r, scale, phi);
+  if (act) {
+    s_q[pp] = phi[0];
+    s_q[N3 + pp] = phi[1];
+    s_q[2 * N3 + pp] = phi[2];
+  }
+  __syncthreads();
+
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    s += s_D[q * NG + i] * s_q[q + NG * (j + NG * k)];
+    s += s_D[q * NG + j] * s_q[N3 + i + NG * (q + NG * k)];
+    s += s_D[q * NG + k] * s_q[2 * N3 + i + NG * (j + NG * q)];
+  }
+  if (act) {
+    if constexpr (ATOMIC) unsafeAtomicAdd(f + g, -s);
+    else f[g] = fo - s;
+  }
+}
+
+template <int NG>
+struct AcColShape {
+  static constexpr int N2 = NG * NG;
+  static constexpr int N3 = NG * NG * NG;
+  static constexpr int BLK = ((N2 + 63) / 64) * 64;
+};
+
+template <int NG, int GEO, bool ATOMIC>
+__global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(ForceArgs a) {
+  constexpr int N2 = AcColShape<NG>::N2;
+  constexpr int N3 = AcColShape<NG>::N3;
+  __shared__ int s_g[N3];
+  __shared__ float s_p[N2];
+  __shared__ float s_q[2 * N2];
+  __shared__ float s_D[N2];
+
+  const int ngrp = (int)a.count;
+  const int grp = xcd_group(ngrp);
+  if (grp >= ngrp) return;  // uniform over the block
+  const int pos = (int)a.pos0 + grp;
+
+  const int l = threadIdx.x;
+  const bool act = l < N2;
+  const int ll = act ? l : 0;
+  const int i = ll % NG, j = ll / NG;
+
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob;
+  float* f = a.f + (size_t)model * a.nglob;
+  const float* __restrict__ mat = a.mat + ((size_t)model * a.nspec + pos) * 2 * N3;
+
+  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
+  __syncthreads();
+
+  float pc[NG];  // the lane's column of p
+#pragma unroll
+  for (int k = 0; k < NG; ++k) pc[k] = u[s_g[ll + N2 * k]];
+  float acc[NG];  // sum_d sum_a D_{a, l_d} Phi_d(...) at the column's points
+#pragma unroll
+  for (int k = 0; k < NG; ++k) acc[k] = 0.0f;
+
+  float rx = 0.f, ry = 0.f;
+  const float* src = nullptr;
+  if constexpr (GEO == kTrilinear) {
+    rx = a.xi[i];
+    ry = a.xi[j];
+    src = a.tri + (size_t)pos * 24;
+  }
+  if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
+
+  // rolled slice loop, column entries picked by selects (stay in registers)
+#pragma unroll 1
+  for (int k = 0; k < NG; ++k) {
+    const int q = ll + N2 * k;
+    if (k > 0) __syncthreads();  // the previous slice's readers are done
+    float pk = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) pk = pc[b];
+    if (act) s_p[ll] = pk;
+    __syncthreads();
+    float d[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      d[0] += s_D[i * NG + b] * s_p[b + NG * j];
+      d[1] += s_D[j * NG + b] * s_p[i + NG * b];
+      d[2] += s_D[k * NG + b] * pc[b];
+    }
+    float G[9];
+    if constexpr (GEO == kStored) {
+      const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + q;
+#pragma unroll
+      for (int dd = 0; dd < 9; ++dd) G[dd] = ldnt(gp + dd * N3);
+    }
+    float Mg[9], scale, det;
+    geom_map_from<GEO>(src, G, rx, ry, (GEO == kTrilinear) ? a.xi[k] : 0.f, Mg, scale, det);
+    float phi[3];
+    scalar_flux(d, Mg, ldnt(mat + q), scale, phi);
+    // zeta part: point k feeds every point k' of the column with D[k][k']
+#pragma unroll
+    for (int b = 0; b < NG; ++b) acc[b] += s_D[k * NG + b] * phi[2];
+    if (act) {
+      s_q[ll] = phi[0];
+      s_q[N2 + ll] = phi[1];
+    }
+    __syncthreads();
+    float sxy = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      sxy += s_D[b * NG + i] * s_q[b + NG * j];
+      sxy += s_D[b * NG + j] * s_q[N2 + i + NG * b];
+    }
+#pragma unroll
+    for (int b = 0; b < NG; ++b)
+      if (b == k) acc[b] += sxy;
+  }
+
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int q = ll + N2 * k;
+      float* fg = f + s_g[q];
+      if constexpr (ATOMIC) {
+        unsafeAtomicAdd(fg, -acc[k]);
+      } else {
+        if (first_bit(a, pos, q)) *fg = -acc[k];
+        else *fg = *fg - acc[k];
+      }
+    }
+  }
+}
+
+template <int NG, int GEO, bool ATOMIC>
+hipError_t launch_ac(const ForceArgs& a, hipStream_t s) {
+  const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  if constexpr (NG <= kMaxNLow) {
+    dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
+    force_ac_kernel<NG, GEO, ATOMIC><<<grid, block, 0, s>>>(a);
+  } else {
+    dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(AcColShape<NG>::BLK);
+    force_ac_col_kernel<NG, GEO, ATOMIC><<<grid, block, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <int NG>
+hipError_t launch_ac_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  switch (geo) {
+    case kRegular:
+      return atomic ? launch_ac<NG, kRegular, true>(a, s) : launch_ac<NG, kRegular, false>(a, s);
+    case kStored:
+      return atomic ? launch_ac<NG, kStored, true>(a, s) : launch_ac<NG, kStored, false>(a, s);
+    case kTrilinear:
+      return atomic ? launch_ac<NG, kTrilinear, true>(a, s) : launch_ac<NG, kTrilinear, false>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  switch (n) {
+    case 2: return launch_ac_n<2>(geo, atomic, a, s);
+    case 3: return launch_ac_n<3>(geo, atomic, a, s);
+    case 4: return launch_ac_n<4>(geo, atomic, a, s);
+    case 5: return launch_ac_n<5>(geo, atomic, a, s);
+    case 6: return launch_ac_n<6>(geo, atomic, a, s);
+    case 7: return launch_ac_n<7>(geo, atomic, a, s);
+    case 8: return launch_ac_n<8>(geo, atomic, a, s);
+    case 9: return launch_ac_n<9>(geo, atomic, a, s);
+    case 10: return launch_ac_n<10>(geo, atomic, a, s);
+    case 11: return launch_ac_n<11>(geo, atomic, a, s);
+    case 12: return launch_ac_n<12>(geo, atomic, a, s);
+    case 13: return launch_ac_n<13>(geo, atomic, a, s);
+    case 14: return launch_ac_n<14>(geo, atomic, a, s);
+    case 15: return launch_ac_n<15>(geo, atomic, a, s);
+    case 16: return launch_ac_n<16>(geo, atomic, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace semx

@@ -512,6 +512,8 @@ int semx_set_checkpointing(semx_ctx* c, int64_t every) {
   if (!c) return SEMX_EINVAL;
   if (every < 0) return fail(c, SEMX_EINVAL, "set_checkpointing: negative interval");
   if (every > 0 && c->storage != SEMX_F32) return fail(c, SEMX_ESTATE, "set_checkpointing: the adjoint needs FP32 storage");
+  if (every > 0 && c->physics != SEMX_ELASTIC)
+    return fail(c, SEMX_EINVAL, "set_checkpointing: the adjoint covers the elastic operator only");
   c->ckpt_every = every;
   c->ckpt_count = 0;
   if (every == 0) {
@@ -527,6 +529,7 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
   c->err.clear();
   if (!c->have_mesh || !c->have_model || !c->have_dt) return fail(c, SEMX_ESTATE, "adjoint: mesh, model and dt required");
   if (c->storage != SEMX_F32) return fail(c, SEMX_ESTATE, "adjoint: needs FP32 storage");
+  if (c->physics != SEMX_ELASTIC) return fail(c, SEMX_EINVAL, "adjoint: the elastic operator only");
   if (!gseis_dev || !g_lambda_dev || !g_mu_dev || !g_rho_dev) return fail(c, SEMX_EINVAL, "adjoint: null pointer");
   if (c->rec.nrec == 0) return fail(c, SEMX_ESTATE, "adjoint: no receivers");
   if (c->ckpt_every <= 0 || c->ckpt_count == 0)

@@ -250,16 +250,17 @@ __global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
 // predicted u to seg_u, the segment buffers, in the same pass.
 constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8, kSeg = 16;
 
-template <int MODE>
+// NC: field components per node (3 elastic, 1 acoustic).
+template <int MODE, int NC>
 __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
                                float* __restrict__ u, float* __restrict__ v, float* __restrict__ a,
                                float* __restrict__ f, float* __restrict__ seg_u, float* __restrict__ seg_a) {
   const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NC * nnodes;
        t += (int64_t)gridDim.x * blockDim.x) {
     float acc, vv = v[t];
     if constexpr ((MODE & kCorrect) != 0) {
-      acc = minv[t / 3] * f[t];
+      acc = minv[t / NC] * f[t];
       vv = vv + hdt * acc;
       if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
       if constexpr ((MODE & kSeg) != 0) seg_a[t] = acc;
@@ -281,22 +282,25 @@ __global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const fl
 template <int MODE>
 void launch_newmark(semx_ctx* c, int64_t nn, unsigned gb, float dt, const float* minv, float* u, float* v, float* a,
                     float* f, float* seg_u, float* seg_a) {
-  if (seg_u || seg_a)
-    newmark_kernel<MODE | kSeg><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, seg_u, seg_a);
+  if (c->ncomp == 1)
+    newmark_kernel<MODE, 1><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
+  else if (seg_u || seg_a)
+    newmark_kernel<MODE | kSeg, 3><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, seg_u, seg_a);
   else
-    newmark_kernel<MODE><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
+    newmark_kernel<MODE, 3><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
 }
 
 // a = M^{-1} f without touching v (initial acceleration).
-__global__ void accel_kernel(int64_t nnodes, const float* __restrict__ minv, const float* __restrict__ f,
+__global__ void accel_kernel(int64_t nnodes, int nc, const float* __restrict__ minv, const float* __restrict__ f,
                              float* __restrict__ a) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nc * nnodes;
        t += (int64_t)gridDim.x * blockDim.x)
-    a[t] = minv[t / 3] * f[t];
+    a[t] = minv[t / nc] * f[t];
 }
 
-// Point forces at sample m: f[node] += stf[s][m] * l_q(x_s) dir_c, all models.
-__global__ void source_kernel(int nsrc, int n3, int64_t nstf, int64_t m, int nmodels, int64_t nglob,
+// Point sources at sample m: f[node][c] += stf[s][m] * l_q(x_s) dir_c (elastic,
+// nc = 3) or f[node] += stf[s][m] * l_q(x_s) (acoustic, nc = 1), all models.
+__global__ void source_kernel(int nsrc, int n3, int nc, int64_t nstf, int64_t m, int nmodels, int64_t nglob,
                               const int32_t* __restrict__ nodes, const float* __restrict__ wdir,
                               const float* __restrict__ stf, float* __restrict__ f) {
   const int64_t total = (int64_t)nmodels * nsrc * n3;
@@ -307,39 +311,36 @@ __global__ void source_kernel(int nsrc, int n3, int64_t nstf, int64_t m, int nmo
     const int s = (int)(sq / n3);
     const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)s * nstf + m] : 0.0f;
     if (amp == 0.0f) continue;
-    float* fg = f + ((int64_t)model * nglob + nodes[sq]) * 3;
-    unsafeAtomicAdd(fg + 0, amp * wdir[3 * sq + 0]);
-    unsafeAtomicAdd(fg + 1, amp * wdir[3 * sq + 1]);
-    unsafeAtomicAdd(fg + 2, amp * wdir[3 * sq + 2]);
+    float* fg = f + ((int64_t)model * nglob + nodes[sq]) * nc;
+    for (int cc = 0; cc < nc; ++cc) unsafeAtomicAdd(fg + cc, amp * wdir[nc * sq + cc]);
   }
 }
 
-// Receivers: one block per (model, receiver); sum_q l_q(x_r) u[node_q] per component.
-__global__ void receiver_kernel(int nrec, int n3, int64_t nglob, int64_t nt_max, int64_t it,
+// Receivers: one block per (model, receiver); sum_q l_q(x_r) u[node_q] per
+// component (nc = 3 elastic, 1 acoustic).
+__global__ void receiver_kernel(int nrec, int n3, int nc, int64_t nglob, int64_t nt_max, int64_t it,
                                 const int32_t* __restrict__ nodes, const float* __restrict__ wts,
                                 const float* __restrict__ u, float* __restrict__ seis) {
   __shared__ float red[3][256];
   const int r = blockIdx.x, model = blockIdx.y;
-  const float* um = u + (int64_t)model * nglob * 3;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  const float* um = u + (int64_t)model * nglob * nc;
+  float s[3] = {0.f, 0.f, 0.f};
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     const float wq = wts[(int64_t)r * n3 + q];
     const int64_t g = nodes[(int64_t)r * n3 + q];
-    s0 += wq * um[3 * g + 0];
-    s1 += wq * um[3 * g + 1];
-    s2 += wq * um[3 * g + 2];
+    for (int c = 0; c < nc; ++c) s[c] += wq * um[nc * g + c];
   }
-  red[0][threadIdx.x] = s0;
-  red[1][threadIdx.x] = s1;
-  red[2][threadIdx.x] = s2;
+  red[0][threadIdx.x] = s[0];
+  red[1][threadIdx.x] = s[1];
+  red[2][threadIdx.x] = s[2];
   __syncthreads();
   for (int st = blockDim.x / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
       for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x < 3)
-    seis[(((int64_t)model * nrec + r) * 3 + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
+  if ((int)threadIdx.x < nc)
+    seis[(((int64_t)model * nrec + r) * nc + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
 }
 
 // FP64 block reductions accumulated with a double atomic into out[slot].
@@ -354,14 +355,14 @@ __device__ inline void block_sum_to(double v, double* out) {
   if (threadIdx.x == 0) atomicAdd(out, red[0]);
 }
 
-// out[0] += sum_g mass_g |x_g|^2 (FP64), over one model's nodes.
-__global__ void mnorm_kernel(int64_t nglob, const double* __restrict__ mass, const float* __restrict__ x,
+// out[0] += sum_g mass_g |x_g|^2 (FP64), over one model's nodes (nc components each).
+__global__ void mnorm_kernel(int64_t nglob, int nc, const double* __restrict__ mass, const float* __restrict__ x,
                              double* __restrict__ out) {
   double s = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nglob;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nc * nglob;
        t += (int64_t)gridDim.x * blockDim.x) {
     const double xv = x[t];
-    s += mass[t / 3] * xv * xv;
+    s += mass[t / nc] * xv * xv;
   }
   block_sum_to(s, out);
 }
@@ -386,11 +387,11 @@ __global__ void finite_kernel(int64_t n, const float* __restrict__ x, int* __res
 }
 
 // power iteration helpers: y = -M^{-1} f (f = -K x), so y = M^{-1} K x
-__global__ void neg_minv_kernel(int64_t nglob, const float* __restrict__ minv, const float* __restrict__ f,
+__global__ void neg_minv_kernel(int64_t nglob, int nc, const float* __restrict__ minv, const float* __restrict__ f,
                                 float* __restrict__ y, float scale) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nglob;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nc * nglob;
        t += (int64_t)gridDim.x * blockDim.x)
-    y[t] = -minv[t / 3] * f[t] * scale;
+    y[t] = -minv[t / nc] * f[t] * scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -851,7 +852,9 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
       SEMX_HIP(c, hipEventRecord(e0, c->stream));
     }
     const int geo = L.irregular ? c->irregular_geo : kRegular;
-    if (c->contraction == SEMX_C_F32)
+    if (c->physics == SEMX_ACOUSTIC)
+      e = launch_force_acoustic(c->n, geo, atomic, a, c->stream);
+    else if (c->contraction == SEMX_C_F32)
       e = c->n > kMaxNLow ? launch_force_high(c->n, geo, atomic, a, c->stream)
                           : launch_force_f32(c->n, geo, atomic, a, c->stream);
     else
@@ -868,12 +871,12 @@ int zero_f32(semx_ctx* c, float* p, int64_t n) {
   return SEMX_OK;
 }
 
-int64_t state_len(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * 3; }
+int64_t state_len(const semx_ctx* c) { return (int64_t)c->nmodels * c->nglob * c->ncomp; }
 
-// Seismogram buffer [nmodels][nrec][3][nt_max] in the storage precision, zeroed.
+// Seismogram buffer [nmodels][nrec][ncomp][nt_max] in the storage precision, zeroed.
 int alloc_seismograms(semx_ctx* c) {
   const int nm = c->nmodels > 0 ? c->nmodels : 1;
-  const int64_t cnt = (int64_t)nm * c->rec.nrec * 3 * c->rec.nt_max;
+  const int64_t cnt = (int64_t)nm * c->rec.nrec * c->ncomp * c->rec.nt_max;
   if (c->storage == SEMX_F64) {
     dev_free(c->rec.seis);
     int rc = dev_alloc(c, c->rec.seis64, sizeof(double) * cnt);
@@ -889,7 +892,9 @@ int alloc_seismograms(semx_ctx* c) {
 }
 
 // The FP32 force runs on element patches when they are built.
-bool use_patches(const semx_ctx* c) { return c->patches_ok && c->contraction == SEMX_C_F32; }
+bool use_patches(const semx_ctx* c) {
+  return c->patches_ok && c->contraction == SEMX_C_F32 && c->physics == SEMX_ELASTIC;
+}
 
 // True when the force pass writes every node itself (coloured patches with
 // first-touch stores over a mesh whose nodes all belong to some element), so
@@ -957,7 +962,7 @@ int inject_sources(semx_ctx* c, int64_t m, float* f) {
   if (c->src.nsrc == 0) return SEMX_OK;
   const int64_t total = (int64_t)c->nmodels * c->src.nsrc * c->n3;
   source_kernel<<<grid_for(total), kThreads, 0, c->stream>>>(
-      c->src.nsrc, c->n3, c->src.nstf, m, c->nmodels, c->nglob, c->src.nodes.as<int32_t>(),
+      c->src.nsrc, c->n3, c->ncomp, c->src.nstf, m, c->nmodels, c->nglob, c->src.nodes.as<int32_t>(),
       c->src.wdir.as<float>(), c->src.stf.as<float>(), f);
   SEMX_HIP(c, hipGetLastError());
   return SEMX_OK;
@@ -967,7 +972,7 @@ int finalize_state(semx_ctx* c, float* seg_a = nullptr) {
   if (c->storage == SEMX_F64) return f64_finalize(c);
   if (!c->pending_correct) return SEMX_OK;
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
-  launch_newmark<kCorrect | kStoreA>(c, nn, grid_for(3 * nn), (float)c->dt, c->d_minv.as<float>(),
+  launch_newmark<kCorrect | kStoreA>(c, nn, grid_for(c->ncomp * nn), (float)c->dt, c->d_minv.as<float>(),
                                      c->d_u.as<float>(), c->d_v.as<float>(), c->d_a.as<float>(),
                                      c->d_f.as<float>(), nullptr, seg_a);
   SEMX_HIP(c, hipGetLastError());
@@ -992,8 +997,8 @@ int do_reset(semx_ctx* c) {
     int rc = inject_sources(c, 0, c->d_f.as<float>());
     if (rc) return rc;
     const int64_t nn = (int64_t)c->nmodels * c->nglob;
-    accel_kernel<<<grid_for(3 * nn), kThreads, 0, c->stream>>>(nn, c->d_minv.as<float>(),
-                                                               c->d_f.as<float>(), c->d_a.as<float>());
+    accel_kernel<<<grid_for(c->ncomp * nn), kThreads, 0, c->stream>>>(nn, c->ncomp, c->d_minv.as<float>(),
+                                                                       c->d_f.as<float>(), c->d_a.as<float>());
     SEMX_HIP(c, hipGetLastError());
     rc = zero_f32(c, c->d_f.as<float>(), len);
     if (rc) return rc;
@@ -1004,7 +1009,7 @@ int do_reset(semx_ctx* c) {
 int record_receivers(semx_ctx* c, int64_t idx) {
   if (c->rec.nrec == 0 || idx < 0 || idx >= c->rec.nt_max) return SEMX_OK;
   dim3 grid(c->rec.nrec, c->nmodels);
-  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->nglob, c->rec.nt_max, idx,
+  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, idx,
                                                c->rec.nodes.as<int32_t>(), c->rec.wts.as<float>(),
                                                c->d_u.as<float>(), c->rec.seis.as<float>());
   SEMX_HIP(c, hipGetLastError());
@@ -1016,10 +1021,10 @@ int energy_model0(semx_ctx* c, double* kin, double* pot) {
   if (c->storage == SEMX_F64) return f64_energy(c, kin, pot);
   int rc = finalize_state(c);
   if (rc) return rc;
-  const int64_t n3g = 3 * c->nglob;
+  const int64_t n3g = c->ncomp * c->nglob;
   fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
   // kinetic: 1/2 sum M v^2
-  mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(),
+  mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->ncomp, c->d_mass64.as<double>(),
                                                                 c->d_v.as<float>(), scratch_d(c));
   SEMX_HIP(c, hipGetLastError());
   // potential: 1/2 u^T K u = -1/2 u . f(u), f(u) computed into the work vector
@@ -1070,7 +1075,7 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
   float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
   const float* minv = c->d_minv.as<float>();
   const bool keep = force_overwrites(c);
-  const unsigned gb = grid_for(3 * nn, 1 << 30);  // one pass per lane (streams faster than grid-stride)
+  const unsigned gb = grid_for(c->ncomp * nn, 1 << 30);  // one pass per lane (streams faster than grid-stride)
   if (c->pending_correct) {
     if (keep) launch_newmark<kCorrect | kPredict | kKeepF>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
     else launch_newmark<kCorrect | kPredict>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
@@ -1102,12 +1107,13 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
     c->src.nsrc = 0;
     return SEMX_OK;
   }
-  if (!elem || !xi || !dir || (!stf32 && !stf64) || nstf <= 0)
+  const int nc = c->ncomp;
+  if (!elem || !xi || (nc == 3 && !dir) || (!stf32 && !stf64) || nstf <= 0)
     return fail(c, SEMX_EINVAL, "set_sources: bad arguments");
   const int n = c->n, n3 = c->n3;
   std::vector<int32_t> nodes((size_t)nsrc * n3);
-  std::vector<float> wdir((size_t)nsrc * n3 * 3);
-  std::vector<double> wdir64((size_t)nsrc * n3 * 3);
+  std::vector<float> wdir((size_t)nsrc * n3 * nc);
+  std::vector<double> wdir64((size_t)nsrc * n3 * nc);
   for (int s = 0; s < nsrc; ++s) {
     if (elem[s] < 0 || elem[s] >= c->nspec) return fail(c, SEMX_EINVAL, "set_sources: element out of range");
     for (int d = 0; d < 3; ++d)
@@ -1123,9 +1129,10 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
           const int q = i + n * (j + n * k);
           nodes[(size_t)s * n3 + q] = c->h_ibool[(size_t)elem[s] * n3 + q];
           const double wq = lx[i] * ly[j] * lz[k];
-          for (int d = 0; d < 3; ++d) {
-            wdir64[((size_t)s * n3 + q) * 3 + d] = wq * dir[3 * s + d];
-            wdir[((size_t)s * n3 + q) * 3 + d] = (float)(wq * dir[3 * s + d]);
+          for (int d = 0; d < nc; ++d) {
+            const double v = nc == 3 ? wq * dir[3 * s + d] : wq;  // acoustic: no direction
+            wdir64[((size_t)s * n3 + q) * nc + d] = v;
+            wdir[((size_t)s * n3 + q) * nc + d] = (float)v;
           }
         }
   }
@@ -1388,22 +1395,14 @@ int semx_mesh_info(semx_ctx* c, int64_t* nregular, int64_t* nirregular, int* nco
   return SEMX_OK;
 }
 
-int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const double* mu, const double* rho) {
-  if (!c) return SEMX_EINVAL;
-  c->err.clear();
-  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "upload_model: no mesh");
-  if (nmodels <= 0 || !lambda || !mu || !rho) return fail(c, SEMX_EINVAL, "upload_model: bad arguments");
+namespace {
+
+// Shared part of the model uploads: per-point force weights wl, wm (lambda,
+// mu for the elastic operator; 1/rho, 0 for the acoustic one, whose force
+// kernels read only the first), and the mass density md (rho; 1/kappa).
+int upload_model_impl(semx_ctx* c, int nmodels, const double* lambda, const double* mu, const double* rho,
+                      double vpmax) {
   const int64_t npt = (int64_t)nmodels * c->nspec * c->n3;
-  if (npt >= ((int64_t)1 << 31) || 3 * (int64_t)nmodels * c->nglob >= ((int64_t)1 << 31))
-    return fail(c, SEMX_EINVAL, "upload_model: batch too large");
-  double vpmax = 0.0;
-  for (int64_t t = 0; t < npt; ++t) {
-    const double l = lambda[t], m = mu[t], r = rho[t];
-    if (!(r > 0.0) || !(m > 0.0) || !(l + 2.0 * m / 3.0 > 0.0) || !std::isfinite(l) || !std::isfinite(m) ||
-        !std::isfinite(r))
-      return fail(c, SEMX_EINVAL, "upload_model: need rho > 0, mu > 0, lambda + 2 mu/3 > 0");
-    vpmax = std::max(vpmax, std::sqrt((l + 2.0 * m) / r));
-  }
   int rc = set_device(c);
   if (rc) return rc;
   c->have_model = false;
@@ -1417,7 +1416,7 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
   if (!rc) rc = dev_alloc(c, c->d_wrho, sizeof(float) * npt);
   if (!rc) rc = dev_alloc(c, c->d_mass64, sizeof(double) * nmodels * c->nglob);
   if (!rc) rc = dev_alloc(c, c->d_minv, sizeof(float) * nmodels * c->nglob);
-  const int64_t len = 3 * (int64_t)nmodels * c->nglob;
+  const int64_t len = c->ncomp * (int64_t)nmodels * c->nglob;
   const size_t es = c->storage == SEMX_F64 ? sizeof(double) : sizeof(float);
   if (!rc) rc = dev_alloc(c, c->d_u, es * len);
   if (!rc) rc = dev_alloc(c, c->d_v, es * len);
@@ -1478,6 +1477,79 @@ int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const doub
   return do_reset(c);
 }
 
+}  // namespace
+
+int semx_upload_model(semx_ctx* c, int nmodels, const double* lambda, const double* mu, const double* rho) {
+  if (!c) return SEMX_EINVAL;
+  c->err.clear();
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "upload_model: no mesh");
+  if (c->physics != SEMX_ELASTIC)
+    return fail(c, SEMX_ESTATE, "upload_model: acoustic physics; use semx_upload_model_acoustic");
+  if (nmodels <= 0 || !lambda || !mu || !rho) return fail(c, SEMX_EINVAL, "upload_model: bad arguments");
+  const int64_t npt = (int64_t)nmodels * c->nspec * c->n3;
+  if (npt >= ((int64_t)1 << 31) || 3 * (int64_t)nmodels * c->nglob >= ((int64_t)1 << 31))
+    return fail(c, SEMX_EINVAL, "upload_model: batch too large");
+  double vpmax = 0.0;
+  for (int64_t t = 0; t < npt; ++t) {
+    const double l = lambda[t], m = mu[t], r = rho[t];
+    if (!(r > 0.0) || !(m > 0.0) || !(l + 2.0 * m / 3.0 > 0.0) || !std::isfinite(l) || !std::isfinite(m) ||
+        !std::isfinite(r))
+      return fail(c, SEMX_EINVAL, "upload_model: need rho > 0, mu > 0, lambda + 2 mu/3 > 0");
+    vpmax = std::max(vpmax, std::sqrt((l + 2.0 * m) / r));
+  }
+  return upload_model_impl(c, nmodels, lambda, mu, rho, vpmax);
+}
+
+int semx_upload_model_acoustic(semx_ctx* c, int nmodels, const double* kappa, const double* rho) {
+  if (!c) return SEMX_EINVAL;
+  c->err.clear();
+  if (!c->have_mesh) return fail(c, SEMX_ESTATE, "upload_model_acoustic: no mesh");
+  if (c->physics != SEMX_ACOUSTIC)
+    return fail(c, SEMX_ESTATE, "upload_model_acoustic: elastic physics; call semx_set_physics first");
+  if (nmodels <= 0 || !kappa || !rho) return fail(c, SEMX_EINVAL, "upload_model_acoustic: bad arguments");
+  const int64_t npt = (int64_t)nmodels * c->nspec * c->n3;
+  if (npt >= ((int64_t)1 << 31) || (int64_t)nmodels * c->nglob >= ((int64_t)1 << 31))
+    return fail(c, SEMX_EINVAL, "upload_model_acoustic: batch too large");
+  std::vector<double> wl((size_t)npt), wm((size_t)npt, 0.0), md((size_t)npt);
+  double vpmax = 0.0;
+  for (int64_t t = 0; t < npt; ++t) {
+    const double k = kappa[t], r = rho[t];
+    if (!(r > 0.0) || !(k > 0.0) || !std::isfinite(k) || !std::isfinite(r))
+      return fail(c, SEMX_EINVAL, "upload_model_acoustic: need kappa > 0, rho > 0");
+    wl[t] = 1.0 / r;
+    md[t] = 1.0 / k;
+    vpmax = std::max(vpmax, std::sqrt(k / r));
+  }
+  return upload_model_impl(c, nmodels, wl.data(), wm.data(), md.data(), vpmax);
+}
+
+int semx_set_physics(semx_ctx* c, int physics) {
+  if (!c) return SEMX_EINVAL;
+  if (physics != SEMX_ELASTIC && physics != SEMX_ACOUSTIC) return fail(c, SEMX_EINVAL, "set_physics: unknown physics");
+  if (c->have_model) return fail(c, SEMX_ESTATE, "set_physics: call before uploading a model");
+  if (physics == SEMX_ACOUSTIC) {
+    if (c->storage != SEMX_F32) return fail(c, SEMX_EINVAL, "set_physics: acoustic physics runs in FP32 storage");
+    if (c->contraction != SEMX_C_F32)
+      return fail(c, SEMX_EINVAL, "set_physics: acoustic physics needs the SEMX_C_F32 contraction setting");
+    if (c->ckpt_every > 0) return fail(c, SEMX_ESTATE, "set_physics: turn checkpointing off first");
+  }
+  c->physics = physics;
+  c->ncomp = physics == SEMX_ACOUSTIC ? 1 : 3;
+  if (c->rec.nrec > 0) return alloc_seismograms(c);
+  return SEMX_OK;
+}
+
+int semx_gll(int ngll, double* xi, double* w) {
+  if (ngll < 2 || ngll > kMaxN || !xi || !w) return SEMX_EINVAL;
+  std::vector<double> x, ww;
+  gll_nodes_weights(ngll, x, ww);
+  for (int a = 0; a < ngll; ++a) {
+    xi[a] = x[a];
+    w[a] = ww[a];
+  }
+  return SEMX_OK;
+}
+
 int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
   if (!c) return SEMX_EINVAL;
   if (contraction != SEMX_C_F32 && contraction != SEMX_C_BF16 && contraction != SEMX_C_F16 &&
@@ -1489,6 +1561,8 @@ int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
     return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8");
   if (contraction != SEMX_C_F32 && c->storage == SEMX_F64)
     return fail(c, SEMX_EINVAL, "set_mode: FP64 storage contracts on the vector units (SEMX_C_F32 only)");
+  if (contraction != SEMX_C_F32 && c->physics == SEMX_ACOUSTIC)
+    return fail(c, SEMX_EINVAL, "set_mode: the acoustic operator contracts on the vector units (SEMX_C_F32 only)");
   if (assembly == SEMX_ASM_COLORED && c->have_mesh && c->ncolors == 0)
     return fail(c, SEMX_EINVAL, "set_mode: mesh has elements with repeated nodes; only atomic assembly is exact");
   c->contraction = contraction;
@@ -1530,7 +1604,7 @@ int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
   if (iters <= 0) return fail(c, SEMX_EINVAL, "max_eigenvalue: iters must be positive");
   // power iteration on M^{-1} K for model 0 (nmodels entries are independent)
   const int saved_models = c->nmodels;
-  const int64_t n3g = 3 * c->nglob;
+  const int64_t n3g = c->ncomp * c->nglob;
   DevBuf x, y;
   int rc = dev_alloc(c, x, sizeof(float) * n3g * saved_models);
   if (!rc) rc = dev_alloc(c, y, sizeof(float) * n3g * saved_models);
@@ -1551,8 +1625,8 @@ int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
     fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
     // Rayleigh quotient lam = (x^T K x)/(x^T M x) = -(x.y)/(x^T M x)
     dot_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(n3g, x.as<float>(), y.as<float>(), scratch_d(c));
-    mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(), x.as<float>(),
-                                                                  scratch_d(c) + 1);
+    mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->ncomp, c->d_mass64.as<double>(),
+                                                                  x.as<float>(), scratch_d(c) + 1);
     double hd[2];
     e = hipMemcpyAsync(hd, scratch_d(c), 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1560,8 +1634,9 @@ int semx_max_eigenvalue(semx_ctx* c, int iters, double* lambda_max) {
     lam = -hd[0] / hd[1];
     // x <- M^{-1} K x, normalised to unit M-norm scale
     const double nrm = std::sqrt(hd[1]);
-    neg_minv_kernel<<<grid_for(n3g), kThreads, 0, c->stream>>>(c->nglob, c->d_minv.as<float>(), y.as<float>(),
-                                                               x.as<float>(), (float)(1.0 / (lam * nrm)));
+    neg_minv_kernel<<<grid_for(n3g), kThreads, 0, c->stream>>>(c->nglob, c->ncomp, c->d_minv.as<float>(),
+                                                               y.as<float>(), x.as<float>(),
+                                                               (float)(1.0 / (lam * nrm)));
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(c, e, "power iteration update");
   }
@@ -1785,6 +1860,8 @@ int semx_set_storage(semx_ctx* c, int storage) {
     return fail(c, SEMX_EINVAL, "set_storage: FP64 storage needs the SEMX_C_F32 contraction setting");
   if (storage == SEMX_F64 && c->n > kMaxNLow)
     return fail(c, SEMX_EINVAL, "set_storage: FP64 storage supports NGLL <= 10");
+  if (storage == SEMX_F64 && c->physics == SEMX_ACOUSTIC)
+    return fail(c, SEMX_EINVAL, "set_storage: the acoustic operator runs in FP32 storage");
   c->storage = storage;
   if (c->rec.nrec > 0) return alloc_seismograms(c);
   return SEMX_OK;

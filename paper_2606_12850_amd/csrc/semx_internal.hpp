@@ -78,6 +78,8 @@ struct semx_ctx {
   int contraction = SEMX_C_F32;
   int assembly = SEMX_ASM_COLORED;
   int storage = SEMX_F32;  // SEMX_F64: state, force and time loop in double (fp64.hip)
+  int physics = SEMX_ELASTIC;  // SEMX_ACOUSTIC: scalar field (acoustic.hip)
+  int ncomp = 3;               // field components per node: 3 elastic, 1 acoustic
 
   // GLL data (library's own, FP64 on host)
   std::vector<double> xi, w, D;  // D[a*n+b] = l'_b(xi_a)
@@ -234,6 +236,8 @@ size_t patch_lds_bytes(int n, int maxnodes, int maxruns);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // force_high.hip: NGLL 11..16 (one lane per (i, j) column)
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+// acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)
+hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);
 
 // ---- host helpers shared between translation units (api.hip) ----------------

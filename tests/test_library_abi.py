@@ -51,3 +51,17 @@ def test_create_rejects_bad_ngll_without_gpu():
     assert P.lib().semx_create(ctypes.byref(h), 17, None) == P.SEMX_EINVAL
     assert P.lib().semx_create(None, 5, None) == P.SEMX_EINVAL
     assert P.lib().semx_destroy(None) == P.SEMX_OK
+
+
+def test_gll_query_without_gpu():
+    # semx_gll makes no HIP call: nodes and weights agree with the oracle's
+    import numpy as np
+    import paper_2606_12850_amd as P
+    from oracle import oracle as O
+    for n in (2, 5, 16):
+        xi, w = P.semx_gll(n)
+        xo, wo = O.gll(n)
+        np.testing.assert_allclose(xi, xo, atol=1e-15)
+        np.testing.assert_allclose(w, wo, atol=1e-15)
+    for bad in (1, 17):
+        assert P.lib().semx_gll(bad, None, None) == P.SEMX_EINVAL

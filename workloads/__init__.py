@@ -342,3 +342,47 @@ def perturbed_models(mesh: Mesh, basis, coeffs, vp=3000.0, vs=1732.0, rho=2500.0
     lam = float(lam0) * (1.0 + delta)
     mu = float(mu0) * (1.0 + delta)
     return lam, mu, np.full_like(lam, float(rho))
+
+
+@dataclass
+class Rod:
+    """The acoustic equal-accuracy workload: a rod of ``ne`` elements of size
+    h along x and one element (side ``section``) across, natural boundaries
+    everywhere; a plane source on the end face x = 0 given as one point
+    source per face node; one receiver on the axis at ``x_rec``."""
+    mesh: Mesh
+    h: float
+    section: float
+    nt: int
+    dt: float
+    src_elem: np.ndarray   # [n^2] int32 (element 0)
+    src_xi: np.ndarray     # [n^2, 3] reference coordinates (-1, xi_j, xi_k)
+    src_amp: np.ndarray    # [n^2] face quadrature weight of each face node
+    rec_elem: np.ndarray   # [1]
+    rec_xi: np.ndarray     # [1, 3]
+    stf: np.ndarray        # [n^2, nt + 1] amplitude x Ricker at t_m = m dt
+
+
+def acoustic_rod(n: int, h: float, x_rec: float, t_end: float, gll_xi, gll_w, dt: float = 1e-4,
+                 c: float = 1500.0, f0: float = 20.0, t0: float | None = None, section: float | None = None) -> Rod:
+    """Inputs of the acoustic rod run.  The rod reaches past the station far
+    enough that the echo of its far end (path 2 L - x_rec) arrives 2.4 / f0
+    after t_end; the run has ceil(t_end / dt) steps.  ``gll_xi``, ``gll_w``
+    are the caller's GLL nodes and weights for n points (the face node
+    positions and their quadrature weights (section/2)^2 w_j w_k)."""
+    t0 = 1.2 / f0 if t0 is None else t0
+    section = h if section is None else float(section)
+    length = max(0.5 * (x_rec + c * t_end) + 2.4 * c / f0, x_rec + 2.0 * h)
+    ne = int(np.ceil(length / h))
+    nt = int(np.ceil(t_end / dt - 1e-9))
+    mesh = box_mesh((ne, 1, 1), n, (ne * h, section, section))
+    xi = np.asarray(gll_xi, dtype=np.float64); w = np.asarray(gll_w, dtype=np.float64)
+    jj, kk = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    src_xi = np.stack([-np.ones(n * n), xi[jj.ravel()], xi[kk.ravel()]], axis=1)
+    amp = 0.25 * section * section * w[jj.ravel()] * w[kk.ravel()]
+    e = min(int(x_rec // h), ne - 1)
+    rec_xi = np.array([[2.0 * (x_rec - e * h) / h - 1.0, 0.0, 0.0]])
+    stf = amp[:, None] * ricker(f0, t0, dt, nt + 1)[None, :]
+    return Rod(mesh=mesh, h=float(h), section=section, nt=nt, dt=float(dt),
+               src_elem=np.zeros(n * n, dtype=np.int32), src_xi=src_xi, src_amp=amp,
+               rec_elem=np.array([e], dtype=np.int32), rec_xi=rec_xi, stf=stf)
