@@ -396,6 +396,130 @@ def iso_accuracy_summary(rows, eps: float = 1e-5):
     return {"eps": eps, "rows": out}
 
 
+def bytes_per_element_acoustic(n: int, nglob: int, nspec: int, geometry: str = "trilinear") -> float:
+    """Algorithmic HBM bytes per element per apply of the scalar (acoustic)
+    force: ibool 4 n^3, geometry as for the elastic operator, W / rho 4 n^3,
+    p read once and f written once per unique node (4 G/E each)."""
+    n3 = n ** 3
+    geo = {"stored": 36 * n3, "trilinear": 96, "regular": 36}[geometry]
+    return 4 * n3 + geo + 4 * n3 + 2 * 4.0 * nglob / nspec
+
+
+def acoustic_leg(mesh, reps: int = 50, rods: bool = True):
+    """The scalar (acoustic) operator.  (1) Force apply on the bench mesh
+    (homogeneous 1000 kg/m^3, 1500 m/s), coloured, trilinear and stored
+    geometry, event-timed on the library stream: GLL-pt/s and the fraction of
+    8 TB/s for its own byte model.  (2) The paper's equal-accuracy runs
+    (Sec. V-C): a 20 Hz Ricker plane source on the end of a rod, the trace at
+    12 km (8 s of travel), dt = 1e-4 s, at each degree's equal-accuracy
+    element size (tests/golden/acoustic_iso.json): the library's waveform
+    error against the closed form p = rho c S(t - x/c), S(tau) = (tau - t0)
+    exp(-(pi f0 (tau - t0))^2), and the run's wall time."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+
+    rho, vp, f0 = 1000.0, 1500.0, 20.0
+    out = {"force_apply": {}}
+    s = P.Solver(mesh.n, physics=P.SEMX_ACOUSTIC)
+    info = s.upload_mesh(mesh)
+    shape = (mesh.nspec, mesh.n ** 3)
+    s.upload_model_acoustic(np.full(shape, rho * vp * vp), np.full(shape, rho))
+    p = torch.rand(mesh.nglob, device="cuda", generator=torch.Generator("cuda").manual_seed(1)) - 0.5
+    f = torch.empty_like(p)
+    for gname, gmode in (("trilinear", P.SEMX_GEOM_TRILINEAR), ("stored", P.SEMX_GEOM_STORED)):
+        P.semx_set_geometry(s.ctx, gmode)
+        for _ in range(5):
+            P.semx_apply_force(s.ctx, p, f)
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        for _ in range(reps):
+            P.semx_apply_force(s.ctx, p, f)
+        e1.record(s.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        geo = gname if info["nirregular"] > 0 else "regular"
+        b = bytes_per_element_acoustic(mesh.n, mesh.nglob, mesh.nspec, geo)
+        out["force_apply"][f"acoustic_{gname}_colored"] = {
+            "ms_per_apply": round(ms, 4), "gll_pts_per_s": mesh.nspec * mesh.n ** 3 / (ms * 1e-3),
+            "bytes_per_element": b, "hbm_frac_alg": round(b * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    s.close()
+    del p, f
+    progress("acoustic force apply done")
+    if not rods:
+        return out
+
+    with open(os.path.join(ROOT, "tests", "golden", "acoustic_iso.json")) as fh:
+        tab = json.load(fh)
+    x_rec = tab["x_rec"]
+    t0 = 1.2 / f0
+    t_end = x_rec / vp + t0 + 1.2 / f0 + 1.0 / f0
+    runs = []
+    for key, o in sorted(tab["orders"].items(), key=lambda kv: int(kv[0])):
+        n, h = int(key), o["h_max"]
+        xi, w = P.semx_gll(n)
+        rod = W.acoustic_rod(n, h, x_rec, t_end, xi, w, dt=tab["dt"], c=vp, f0=f0)
+        s = P.Solver(n, physics=P.SEMX_ACOUSTIC)
+        s.upload_mesh(rod.mesh)
+        shp = (rod.mesh.nspec, n ** 3)
+        s.upload_model_acoustic(np.full(shp, rho * vp * vp), np.full(shp, rho))
+        P.semx_set_sources(s.ctx, rod.src_elem, rod.src_xi, None, rod.stf.astype(np.float32))
+        P.semx_set_receivers(s.ctx, rod.rec_elem, rod.rec_xi, rod.nt)
+        s.nrec, s.nt_max = 1, rod.nt
+        P.semx_set_dt(s.ctx, rod.dt)
+        P.semx_reset(s.ctx)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        s.step(rod.nt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        tr = s.seismograms()[0, 0].astype(np.float64)
+        s.close()
+        t = (np.arange(rod.nt) + 1) * rod.dt
+        tau = t - x_rec / vp - t0
+        ref = rho * vp * tau * np.exp(-(np.pi * f0 * tau) ** 2)
+        err = float(np.sum((tr - ref) ** 2) / np.sum(ref ** 2))
+        runs.append({"p": n - 1, "ngll": n, "h_m": round(h, 3), "steps": rod.nt, "nspec": rod.mesh.nspec,
+                     "error_ratio": err, "rel_l2_error_pct": round(100 * np.sqrt(err), 4),
+                     "oracle_rel_l2_error_pct": round(100 * np.sqrt(o["error_at_h_max"]), 4),
+                     "wall_s": round(wall, 2), "us_per_step": round(wall / rod.nt * 1e6, 2)})
+        progress(f"acoustic rod p={n - 1} h={h:.2f}: error {100 * np.sqrt(err):.4f} % in {wall:.1f} s")
+    out["equal_accuracy_rod"] = {"x_rec_m": x_rec, "dt": tab["dt"], "bound_rel_l2_pct": 1.0, "runs": runs,
+                                 "paper_h_m": {"4": 20.0, "7": 50.0, "15": 130.0}}
+    return out
+
+
+def acoustic_frontier_summary(rows):
+    """The paper's cost comparison on its equal-accuracy frontier (Sec. V-C):
+    element sizes h_p from the acoustic rod experiment
+    (tests/golden/acoustic_iso.json), elastic FP32 costs per element from the
+    order sweep (step time and device bytes at about 2e7 nodes, where each
+    order fills the GPU), a fixed domain and the same dt for every order, so
+    time to solution and memory scale as cost per element / h_p^3."""
+    with open(os.path.join(ROOT, "tests", "golden", "acoustic_iso.json")) as fh:
+        tab = json.load(fh)
+    by_n = {r["ngll"]: r for r in rows if "step_ms" in r}
+    per = {}
+    for key, o in tab["orders"].items():
+        n = int(key)
+        if n not in by_n:
+            continue
+        r = by_n[n]
+        h = o["h_max"]
+        per[n - 1] = {"h_m": round(h, 3), "step_s_per_km3": r["step_ms"] * 1e-3 / r["nspec"] * 1e9 / h ** 3,
+                      "device_bytes_per_km3": r["device_bytes"] / r["nspec"] * 1e9 / h ** 3}
+    pairs = []
+    for a, b, paper_t, paper_m in ((4, 7, 3.85, 3.18), (7, 15, 1.4, 1.8)):
+        if a in per and b in per:
+            pairs.append({"from_p": a, "to_p": b,
+                          "time_ratio": round(per[a]["step_s_per_km3"] / per[b]["step_s_per_km3"], 3),
+                          "memory_ratio": round(per[a]["device_bytes_per_km3"] / per[b]["device_bytes_per_km3"], 3),
+                          "paper_time_ratio": paper_t, "paper_memory_ratio": paper_m})
+    return {"per_order": per, "pairs": pairs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,6 +527,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-acoustic", action="store_true")
+    ap.add_argument("--acoustic-only", action="store_true",
+                    help="time only the acoustic force apply on the bench mesh (no time loop, no rod runs); "
+                         "prints one JSON line")
     ap.add_argument("--geometry", choices=["stored", "trilinear"], default="trilinear")
     ap.add_argument("--assembly", choices=["colored", "atomic"], default="colored")
     ap.add_argument("--apply-reps", type=int, default=50)
@@ -441,6 +569,9 @@ def main():
     wl = W.layered_jittered(ne=NE, n=NGLL, nt=nt_total, dt=1.0, jitter=0.10, seed=2606,
                             grf_seed=12850, grf_amp=0.05, nrec=8)
     mesh = wl.mesh
+    if args.acoustic_only:
+        print(json.dumps({"acoustic": acoustic_leg(mesh, rods=False), "nspec": mesh.nspec, "nglob": mesh.nglob}))
+        return
     s = P.Solver(NGLL)
     info = s.upload_mesh(mesh)
     s.upload_model(wl.lam, wl.mu, wl.rho)
@@ -568,11 +699,14 @@ def main():
         "setup_s": round(setup_s, 1),
     }
     s.close()
+    if not args.no_acoustic:
+        out["acoustic"] = acoustic_leg(mesh)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
     if args.order_sweep:
         out["order_sweep"] = order_sweep_leg()
         out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]
+        out["equal_accuracy_acoustic_sizes"] = acoustic_frontier_summary(out["order_sweep"])
     if args.surrogate:
         k = args.surrogate_scale
         out["surrogate"] = surrogate_leg(f0=args.surrogate_f0, ntrain=max(64, int(4500 * k)), nval=max(64, int(500 * k)),

@@ -312,7 +312,10 @@ __global__ void source_kernel(int nsrc, int n3, int nc, int64_t nstf, int64_t m,
     const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)s * nstf + m] : 0.0f;
     if (amp == 0.0f) continue;
     float* fg = f + ((int64_t)model * nglob + nodes[sq]) * nc;
-    for (int cc = 0; cc < nc; ++cc) unsafeAtomicAdd(fg + cc, amp * wdir[nc * sq + cc]);
+    for (int cc = 0; cc < nc; ++cc) {
+      const float wv = wdir[nc * sq + cc];
+      if (wv != 0.0f) unsafeAtomicAdd(fg + cc, amp * wv);  // a source on a node has one nonzero weight
+    }
   }
 }
 
