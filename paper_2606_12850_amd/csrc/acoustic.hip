@@ -131,6 +131,8 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
   __shared__ float s_p[N2];
   __shared__ float s_q[2 * N2];
   __shared__ float s_D[N2];
+  constexpr bool TD = (NG % 4) == 0;  // D transposed for row strides 12, 16 (see force_col_kernel)
+  __shared__ float s_Dt[TD ? N2 : 1];
 
   const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
@@ -147,7 +149,10 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
   float* f = a.f + (size_t)model * a.nglob;
   const float* __restrict__ mat = a.mat + ((size_t)model * a.nspec + pos) * 2 * N3;
 
-  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N2; t += blockDim.x) {
+    s_D[t] = a.D[t];
+    if constexpr (TD) s_Dt[(t % NG) * NG + t / NG] = a.D[t];
+  }
   for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
   __syncthreads();
 
@@ -181,8 +186,8 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
     float d[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      d[0] += s_D[i * NG + b] * s_p[b + NG * j];
-      d[1] += s_D[j * NG + b] * s_p[i + NG * b];
+      d[0] += (TD ? s_Dt[b * NG + i] : s_D[i * NG + b]) * s_p[b + NG * j];
+      d[1] += (TD ? s_Dt[b * NG + j] : s_D[j * NG + b]) * s_p[i + NG * b];
       d[2] += s_D[k * NG + b] * pc[b];
     }
     float G[9];

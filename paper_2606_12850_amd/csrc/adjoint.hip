@@ -173,6 +173,8 @@ __global__ __launch_bounds__(AdjCol<NG>::BLK) void adjoint_col_kernel(AdjArgs A)
   __shared__ float s_w[6 * N2];  // slice of psi (components 0..2) and u^m (3..5)
   __shared__ float s_q[6 * N2];  // slice of xi and eta fluxes
   __shared__ float s_D[N2];
+  constexpr bool TD = (NG % 4) == 0;  // D transposed for row strides 12, 16 (see force_col_kernel)
+  __shared__ float s_Dt[TD ? N2 : 1];
   const ForceArgs& a = A.fa;
   const int grp = xcd_group((int)a.count);
   if (grp >= a.count) return;
@@ -187,7 +189,10 @@ __global__ __launch_bounds__(AdjCol<NG>::BLK) void adjoint_col_kernel(AdjArgs A)
   float* f = a.f + vofs;
   const float* mat = a.mat + (size_t)model * a.nspec * 2 * N3 + (size_t)pos * 2 * N3;
 
-  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N2; t += blockDim.x) {
+    s_D[t] = a.D[t];
+    if constexpr (TD) s_Dt[(t % NG) * NG + t / NG] = a.D[t];
+  }
   for (int t = l; t < N3; t += blockDim.x) s_g[t] = a.ibool[(size_t)pos * N3 + t];
   __syncthreads();
 
@@ -240,7 +245,9 @@ __global__ __launch_bounds__(AdjCol<NG>::BLK) void adjoint_col_kernel(AdjArgs A)
       for (int d = 0; d < 3; ++d) dp[c][d] = du[c][d] = 0.0f;
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      const float di = s_D[i * NG + b], dj = s_D[j * NG + b], dk = s_D[k * NG + b];
+      const float di = TD ? s_Dt[b * NG + i] : s_D[i * NG + b];
+      const float dj = TD ? s_Dt[b * NG + j] : s_D[j * NG + b];
+      const float dk = s_D[k * NG + b];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         dp[c][0] += di * s_w[c * N2 + b + NG * j];

@@ -14,8 +14,8 @@
 //   column accumulators (point k feeds every k' with D[k][k']), the xi and
 //   eta parts through one LDS slice of fluxes.
 // LDS holds the element's node numbers, one slice of u (3 n^2), one slice of
-// fluxes (6 n^2) and D: 26 KB at NGLL 16, instead of the 12 n^3 floats
-// (192 KB) a point-per-lane layout would need.
+// fluxes (6 n^2), D and (NGLL 12, 16) its transpose: 27 KB at NGLL 16, instead of the
+// 12 n^3 floats (192 KB) a point-per-lane layout would need.
 // Assembly: plain read-modify-write inside a colour (with first-touch stores)
 // or FP32 atomics, as in the lower-order kernel.
 #include "elem_common.hpp"
@@ -42,6 +42,13 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
   __shared__ float s_u[3 * N2];
   __shared__ float s_q[6 * N2];
   __shared__ float s_D[N2];
+  // D transposed (NGLL a multiple of 4): the xi and eta derivatives read row
+  // i (j) of D, which differs per lane; at a row stride of 12 or 16 words
+  // those reads share few LDS banks, down a column of s_Dt they are
+  // consecutive across lanes.  Odd strides are conflict-free row-wise and
+  // keep the vector reads of s_D (measured: transposing them is slower).
+  constexpr bool TD = (NG % 4) == 0;
+  __shared__ float s_Dt[TD ? N2 : 1];
 
   const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
@@ -58,7 +65,10 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
   float* f = a.f + (size_t)model * a.nglob * 3;
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3 + (size_t)pos * 2 * N3;
 
-  for (int t = l; t < N2; t += blockDim.x) s_D[t] = a.D[t];
+  for (int t = l; t < N2; t += blockDim.x) {
+    s_D[t] = a.D[t];
+    if constexpr (TD) s_Dt[(t % NG) * NG + t / NG] = a.D[t];
+  }
   for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
   __syncthreads();
 
@@ -113,7 +123,9 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
     for (int c = 0; c < 3; ++c) du[c][0] = du[c][1] = du[c][2] = 0.0f;
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      const float di = s_D[i * NG + b], dj = s_D[j * NG + b], dk = s_D[k * NG + b];
+      const float di = TD ? s_Dt[b * NG + i] : s_D[i * NG + b];
+      const float dj = TD ? s_Dt[b * NG + j] : s_D[j * NG + b];
+      const float dk = s_D[k * NG + b];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         du[c][0] += di * s_u[c * N2 + b + NG * j];
