@@ -97,6 +97,30 @@ def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
                       f"({nsub} elements, {nsub * n ** 3} GLL points), {reps} applies in {el:.1f} s"}
 
 
+def cpu_baseline_acoustic(mesh, budget_s: float = 10.0):
+    """FP64 oracle acoustic force apply (numpy) on the first 2 of the 64
+    element layers of the same mesh, homogeneous 1000 kg/m^3, 1500 m/s."""
+    import numpy as np
+    from oracle import acoustic as OA
+    n = mesh.n
+    nsub = mesh.nex * mesh.ney * 2
+    ibool = mesh.ibool[:nsub]
+    gam, jac, _ = OA.O.geometry(n, mesh.elem_vert[:nsub], mesh.vert)
+    rho = np.full((nsub, n ** 3), 1000.0)
+    p = np.random.default_rng(0).uniform(-1, 1, mesh.nglob)
+    OA.force(n, ibool, gam, jac, rho, p, mesh.nglob)  # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        OA.force(n, ibool, gam, jac, rho, p, mesh.nglob)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 100:
+            break
+    return {"value": nsub * n ** 3 * reps / el, "unit": "GLL-pt force evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy acoustic oracle force apply on the first 2 of 64 element layers "
+                      f"({nsub} elements, {nsub * n ** 3} GLL points), {reps} applies in {el:.1f} s"}
+
+
 def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 16, fd_eps: float = 1e-4):
     """Adjoint sensitivity on the layered cube with a -5% Gaussian anomaly:
     forward with checkpoints, then the discrete adjoint; adjoint/forward time
@@ -405,6 +429,24 @@ def bytes_per_element_acoustic(n: int, nglob: int, nspec: int, geometry: str = "
     return 4 * n3 + geo + 4 * n3 + 2 * 4.0 * nglob / nspec
 
 
+def acoustic_traffic(geometry: str):
+    """HBM bytes per launch of the acoustic force kernel from rocprofv3 PMC
+    counters (profiles/acoustic_traffic.json), if they were taken on the
+    current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "acoustic_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
+                   for f in ("acoustic.hip", "elem_common.hpp"))
+    if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return d.get(geometry, {}).get("bytes_per_launch")
+
+
 def acoustic_leg(mesh, reps: int = 50, rods: bool = True):
     """The scalar (acoustic) operator.  (1) Force apply on the bench mesh
     (homogeneous 1000 kg/m^3, 1500 m/s), coloured, trilinear and stored
@@ -444,7 +486,8 @@ def acoustic_leg(mesh, reps: int = 50, rods: bool = True):
         b = bytes_per_element_acoustic(mesh.n, mesh.nglob, mesh.nspec, geo)
         out["force_apply"][f"acoustic_{gname}_colored"] = {
             "ms_per_apply": round(ms, 4), "gll_pts_per_s": mesh.nspec * mesh.n ** 3 / (ms * 1e-3),
-            "bytes_per_element": b, "hbm_frac_alg": round(b * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+            "bytes_per_element": b, "hbm_frac_alg": round(b * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "traffic": acoustic_traffic(gname)}
     s.close()
     del p, f
     progress("acoustic force apply done")
@@ -570,7 +613,15 @@ def main():
                             grf_seed=12850, grf_amp=0.05, nrec=8)
     mesh = wl.mesh
     if args.acoustic_only:
-        print(json.dumps({"acoustic": acoustic_leg(mesh, rods=False), "nspec": mesh.nspec, "nglob": mesh.nglob}))
+        ac = acoustic_leg(mesh, reps=args.apply_reps, rods=False)
+        # calibration for the traffic counters: a plain device copy of known size
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 4, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"acoustic": ac, "nspec": mesh.nspec, "nglob": mesh.nglob, "copy_bytes_each_way": nbytes}))
         return
     s = P.Solver(NGLL)
     info = s.upload_mesh(mesh)
@@ -713,6 +764,8 @@ def main():
                                          ntest=max(64, int(4096 * k)), epochs=max(5, int(300 * k)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
+        if "acoustic" in out:
+            out["acoustic"]["cpu_baseline"] = cpu_baseline_acoustic(mesh)
     print(json.dumps(out))
 
 
