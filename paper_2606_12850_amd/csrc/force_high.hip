@@ -16,12 +16,45 @@
 // LDS holds the element's node numbers, one slice of u (3 n^2), one slice of
 // fluxes (6 n^2), D and (NGLL 12, 16) its transpose: 27 KB at NGLL 16, instead of the
 // 12 n^3 floats (192 KB) a point-per-lane layout would need.
+// At NGLL 16 a slice row is exactly one 16-lane DPP row of a wavefront, and
+// the xi contractions (forward derivative and transpose flux) rotate the
+// row's values across lanes (row_ror) instead of reading them from LDS.
 // Assembly: plain read-modify-write inside a colour (with first-touch stores)
 // or FP32 atomics, as in the lower-order kernel.
 #include "elem_common.hpp"
 
 namespace semx {
 namespace {
+
+// Rotation of a value within each 16-lane DPP row: lane i receives the
+// value of another lane of its row (R = 0: its own).  Every lane of the row
+// must be active.
+template <int R>
+__device__ __forceinline__ float row_ror(float x) {
+  if constexpr (R == 0) return x;
+  else return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x120 + R, 0xF, 0xF, true));
+}
+
+// out[c] += sum_R w[R * 16] * row_ror<R>(x[c]), R = 0..15
+template <int R>
+__device__ __forceinline__ void row_contract3(const float* w, const float x[3], float out[3]) {
+  if constexpr (R < 16) {
+    const float wr = w[R * 16];
+    out[0] += wr * row_ror<R>(x[0]);
+    out[1] += wr * row_ror<R>(x[1]);
+    out[2] += wr * row_ror<R>(x[2]);
+    row_contract3<R + 1>(w, x, out);
+  }
+}
+
+// Source lane (within its row) of row_ror<R> for lane i, R = 0..15.
+template <int R>
+__device__ __forceinline__ void row_sources(float i, float src[16]) {
+  if constexpr (R < 16) {
+    src[R] = row_ror<R>(i);
+    row_sources<R + 1>(i, src);
+  }
+}
 
 template <int NG>
 struct ColShape {
@@ -49,6 +82,13 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
   // keep the vector reads of s_D (measured: transposing them is slower).
   constexpr bool TD = (NG % 4) == 0;
   __shared__ float s_Dt[TD ? N2 : 1];
+  // NGLL 16: a slice row is one 16-lane DPP row, so the xi contractions
+  // rotate values across the row instead of reading it from LDS; the
+  // coefficients of rotation R are s_Cf[R][i] = D[i][src] (forward) and
+  // s_Cb[R][i] = D[src][i] (transpose), src the lane it brings in.
+  constexpr bool XDPP = NG == 16;
+  __shared__ float s_Cf[XDPP ? 256 : 1];
+  __shared__ float s_Cb[XDPP ? 256 : 1];
 
   const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
@@ -68,6 +108,18 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
   for (int t = l; t < N2; t += blockDim.x) {
     s_D[t] = a.D[t];
     if constexpr (TD) s_Dt[(t % NG) * NG + t / NG] = a.D[t];
+  }
+  if constexpr (XDPP) {
+    float src[16];
+    row_sources<0>((float)(l & 15), src);  // every lane active (n^2 = 256 = block)
+    if (l < 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int sl = (int)src[r];
+        s_Cf[r * 16 + l] = a.D[l * 16 + sl];
+        s_Cb[r * 16 + l] = a.D[sl * 16 + l];
+      }
+    }
   }
   for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
   __syncthreads();
@@ -121,14 +173,23 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
     float du[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c][0] = du[c][1] = du[c][2] = 0.0f;
+    if constexpr (XDPP) {
+      float x0[3] = {0.f, 0.f, 0.f};
+      row_contract3<0>(s_Cf + i, uk, x0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) du[c][0] = x0[c];
+    }
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      const float di = TD ? s_Dt[b * NG + i] : s_D[i * NG + b];
       const float dj = TD ? s_Dt[b * NG + j] : s_D[j * NG + b];
       const float dk = s_D[k * NG + b];
+      if constexpr (!XDPP) {
+        const float di = TD ? s_Dt[b * NG + i] : s_D[i * NG + b];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) du[c][0] += di * s_u[c * N2 + b + NG * j];
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        du[c][0] += di * s_u[c * N2 + b + NG * j];
         du[c][1] += dj * s_u[c * N2 + i + NG * b];
         du[c][2] += dk * uc[c][b];
       }
@@ -169,21 +230,25 @@ __global__ __launch_bounds__(ColShape<NG>::BLK) __attribute__((amdgpu_waves_per_
     if (act) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        s_q[(2 * c + 0) * N2 + ll] = phi[c][0];
+        if constexpr (!XDPP) s_q[(2 * c + 0) * N2 + ll] = phi[c][0];
         s_q[(2 * c + 1) * N2 + ll] = phi[c][1];
       }
     }
+    float sxy[3] = {0.f, 0.f, 0.f};
+    if constexpr (XDPP) {
+      const float p0[3] = {phi[0][0], phi[1][0], phi[2][0]};
+      row_contract3<0>(s_Cb + i, p0, sxy);
+    }
     __syncthreads();
-    float sxy[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float s = 0.0f;
 #pragma unroll
       for (int b = 0; b < NG; ++b) {
-        s += s_D[b * NG + i] * s_q[(2 * c + 0) * N2 + b + NG * j];
+        if constexpr (!XDPP) s += s_D[b * NG + i] * s_q[(2 * c + 0) * N2 + b + NG * j];
         s += s_D[b * NG + j] * s_q[(2 * c + 1) * N2 + i + NG * b];
       }
-      sxy[c] = s;
+      sxy[c] += s;
     }
 #pragma unroll
     for (int b = 0; b < NG; ++b)
