@@ -300,3 +300,36 @@ def test_point_source_matches_free_space_solution():
         err = np.sqrt(A.energy_error(got[q], ref))
         print(f"point source, station {q} at r = {r[q]:.1f} m: relative L2 error {err:.2e}")
         assert err < 2e-3  # measured 2.3e-4 .. 3.1e-4
+
+
+def test_acoustic_reciprocity_gpu():
+    """p at B for a source at A equals p at A for the source at B (jittered
+    mesh, varying kappa and rho, both assemblies), to FP32 rounding."""
+    import paper_2606_12850_amd as P
+    n = 4
+    mesh = W.box_mesh((2, 2, 2), n, (300.0, 260.0, 220.0), jitter=0.12, seed=11)
+    rng = np.random.default_rng(4)
+    kappa = A.RHO * A.VP ** 2 * rng.uniform(0.8, 1.2, (mesh.nspec, n ** 3))
+    rho = A.RHO * rng.uniform(0.8, 1.2, (mesh.nspec, n ** 3))
+    ea, xa = np.array([1], np.int32), np.array([[0.31, -0.42, 0.17]])
+    eb, xb = np.array([6], np.int32), np.array([[-0.25, 0.38, -0.61]])
+    dt, nt = 2e-4, 1000
+    stf = W.ricker(30.0, 0.04, dt, nt + 1)[None, :].astype(np.float32)
+    s = _solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model_acoustic(kappa, rho)
+    for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+        s.set_mode(P.SEMX_C_F32, asm)
+        rec = []
+        for (es, xs), (er, xr) in (((ea, xa), (eb, xb)), ((eb, xb), (ea, xa))):
+            P.semx_set_sources(s.ctx, es, xs, None, stf)
+            P.semx_set_receivers(s.ctx, er, xr, nt)
+            s.nrec, s.nt_max = 1, nt
+            P.semx_set_dt(s.ctx, dt)
+            P.semx_reset(s.ctx)
+            s.step(nt)
+            rec.append(s.seismograms()[0, 0].astype(np.float64))
+        err = np.abs(rec[0] - rec[1]).max() / np.abs(rec[0]).max()
+        print(f"acoustic reciprocity asm={asm}: max difference {err:.2e} of the peak")
+        assert err <= 1e-4
+    s.close()

@@ -191,3 +191,21 @@ def test_equal_accuracy_table_reproducible():
     assert ts["0.0001"] <= g["bound_ratio"] < ts["0.0002"]
     for key in ("5", "8", "16"):
         assert g["orders"][key]["error_at_h_max"] <= g["bound_ratio"]
+
+
+def test_source_receiver_reciprocity():
+    """p recorded at B for a source at A equals p at A for the same source at
+    B (jittered mesh, varying kappa and rho), to rounding."""
+    n = 4
+    m, gam, jac, _ = _mesh((2, 2, 2), n, (300.0, 260.0, 220.0), jitter=0.12, seed=11)
+    rng = np.random.default_rng(4)
+    kappa = A.RHO * A.VP ** 2 * rng.uniform(0.8, 1.2, (m.nspec, n ** 3))
+    rho = A.RHO * rng.uniform(0.8, 1.2, (m.nspec, n ** 3))
+    ea, xa = np.array([1], np.int32), np.array([[0.31, -0.42, 0.17]])
+    eb, xb = np.array([6], np.int32), np.array([[-0.25, 0.38, -0.61]])
+    dt, nt = 2e-4, 1000  # A and B are about 207 m apart: the wave arrives after 0.14 s
+    stf = W.ricker(30.0, 0.04, dt, nt + 1)[None, :]
+    ab = A.forward(n, m.ibool, gam, jac, kappa, rho, m.nglob, dt, nt, ea, xa, stf, eb, xb)["seis"][0]
+    ba = A.forward(n, m.ibool, gam, jac, kappa, rho, m.nglob, dt, nt, eb, xb, stf, ea, xa)["seis"][0]
+    assert np.abs(ab).max() > 0
+    np.testing.assert_allclose(ab, ba, rtol=0, atol=1e-10 * np.abs(ab).max())

@@ -318,3 +318,34 @@ def test_node_receiver_reads_node(orc):
     q = 0 + 5 * (4 + 5 * 4)
     g = m.ibool[3, q]
     np.testing.assert_array_equal(out["seis"][0], out["uhist"][1:, g, :].T)
+
+
+def _reciprocity_problem(n=4):
+    m = W.box_mesh((2, 2, 2), n, (300.0, 260.0, 220.0), jitter=0.12, seed=11)
+    rng = np.random.default_rng(2)
+    shape = (m.nspec, n ** 3)
+    lam = 7.5e9 * rng.uniform(0.8, 1.2, shape)
+    mu = 7.5e9 * rng.uniform(0.8, 1.2, shape)
+    rho = 2500.0 * rng.uniform(0.8, 1.2, shape)
+    pa = (np.array([1], np.int32), np.array([[0.31, -0.42, 0.17]]))   # interior points only
+    pb = (np.array([6], np.int32), np.array([[-0.25, 0.38, -0.61]]))
+    return m, lam, mu, rho, pa, pb
+
+
+def test_source_receiver_reciprocity(orc):
+    """G_ij(B, A) = G_ji(A, B): the component i recorded at B for a force
+    along j at A equals the component j at A for a force along i at B, to
+    rounding, because K and M are symmetric and the source injects with the
+    transpose of the receiver interpolation (same Lagrange weights).  A
+    source or receiver weighted differently, or a non-symmetric operator,
+    breaks it."""
+    m, lam, mu, rho, (ea, xa), (eb, xb) = _reciprocity_problem()
+    gam, jac, _ = orc.geometry(m.n, m.elem_vert, m.vert)
+    dt, nt = 2e-4, 800  # A and B are about 207 m apart: P arrives after 0.07 s, S after 0.12 s
+    stf = W.ricker(30.0, 0.04, dt, nt + 1)[None, :]
+    for i, j in ((0, 2), (1, 1), (2, 0)):
+        dj = np.eye(3)[[j]]; di = np.eye(3)[[i]]
+        ab = orc.forward(m.n, m.ibool, gam, jac, lam, mu, rho, m.nglob, dt, nt, ea, xa, dj, stf, eb, xb)["seis"][0, i]
+        ba = orc.forward(m.n, m.ibool, gam, jac, lam, mu, rho, m.nglob, dt, nt, eb, xb, di, stf, ea, xa)["seis"][0, j]
+        assert np.abs(ab).max() > 0
+        np.testing.assert_allclose(ab, ba, rtol=0, atol=1e-10 * np.abs(ab).max())
