@@ -375,10 +375,45 @@ def order_sweep_leg(reps: int = 20):
                 ref = f.clone()
             else:
                 row[f"{cname}_rel_diff_vs_f32"] = (torch.linalg.norm(f - ref) / torch.linalg.norm(ref)).item()
-        log(json.dumps(row))
-        rows.append(row)
         del u, f, ref
         s.close()
+        if n in (5, 8, 16):  # the acoustic experiment's orders: the scalar operator on the same mesh
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            sa = P.Solver(n, physics=P.SEMX_ACOUSTIC)
+            sa.upload_mesh(mesh)
+            shp = (mesh.nspec, n ** 3)
+            sa.upload_model_acoustic(np.full(shp, 1000.0 * 1500.0 ** 2), np.full(shp, 1000.0))
+            torch.cuda.synchronize()
+            row["acoustic_device_bytes"] = free0 - torch.cuda.mem_get_info()[0]
+            pa = torch.rand(G, device="cuda") - 0.5
+            fa = torch.empty_like(pa)
+            P.semx_set_dt(sa.ctx, P.semx_cfl_dt(sa.ctx, 0.4))
+            P.semx_set_state(sa.ctx, pa, torch.zeros_like(pa), torch.zeros_like(pa), 0)
+            sa.step(3)
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(sa.stream)
+            sa.step(reps)
+            e1.record(sa.stream)
+            e1.synchronize()
+            row["acoustic_step_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+            for _ in range(3):
+                P.semx_apply_force(sa.ctx, pa, fa)
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(sa.stream)
+            for _ in range(reps):
+                P.semx_apply_force(sa.ctx, pa, fa)
+            e1.record(sa.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            ba = bytes_per_element_acoustic(n, G, mesh.nspec, "regular")
+            row["acoustic_ms"] = round(ms, 4)
+            row["acoustic_gll_pts_per_s"] = mesh.nspec * n ** 3 / (ms * 1e-3)
+            row["acoustic_hbm_frac_alg"] = round(ba * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            del pa, fa
+            sa.close()
+        log(json.dumps(row))
+        rows.append(row)
     return rows
 
 
@@ -540,7 +575,9 @@ def acoustic_frontier_summary(rows):
     (tests/golden/acoustic_iso.json), elastic FP32 costs per element from the
     order sweep (step time and device bytes at about 2e7 nodes, where each
     order fills the GPU), a fixed domain and the same dt for every order, so
-    time to solution and memory scale as cost per element / h_p^3."""
+    time to solution and memory scale as cost per element / h_p^3.  The
+    acoustic operator's own ratios (same meshes, NGLL 5, 8, 16) come with
+    them."""
     with open(os.path.join(ROOT, "tests", "golden", "acoustic_iso.json")) as fh:
         tab = json.load(fh)
     by_n = {r["ngll"]: r for r in rows if "step_ms" in r}
@@ -553,13 +590,21 @@ def acoustic_frontier_summary(rows):
         h = o["h_max"]
         per[n - 1] = {"h_m": round(h, 3), "step_s_per_km3": r["step_ms"] * 1e-3 / r["nspec"] * 1e9 / h ** 3,
                       "device_bytes_per_km3": r["device_bytes"] / r["nspec"] * 1e9 / h ** 3}
+        if "acoustic_step_ms" in r:
+            per[n - 1]["acoustic_step_s_per_km3"] = r["acoustic_step_ms"] * 1e-3 / r["nspec"] * 1e9 / h ** 3
+            per[n - 1]["acoustic_device_bytes_per_km3"] = r["acoustic_device_bytes"] / r["nspec"] * 1e9 / h ** 3
     pairs = []
     for a, b, paper_t, paper_m in ((4, 7, 3.85, 3.18), (7, 15, 1.4, 1.8)):
         if a in per and b in per:
-            pairs.append({"from_p": a, "to_p": b,
-                          "time_ratio": round(per[a]["step_s_per_km3"] / per[b]["step_s_per_km3"], 3),
-                          "memory_ratio": round(per[a]["device_bytes_per_km3"] / per[b]["device_bytes_per_km3"], 3),
-                          "paper_time_ratio": paper_t, "paper_memory_ratio": paper_m})
+            pr = {"from_p": a, "to_p": b,
+                  "time_ratio": round(per[a]["step_s_per_km3"] / per[b]["step_s_per_km3"], 3),
+                  "memory_ratio": round(per[a]["device_bytes_per_km3"] / per[b]["device_bytes_per_km3"], 3),
+                  "paper_time_ratio": paper_t, "paper_memory_ratio": paper_m}
+            if "acoustic_step_s_per_km3" in per[a] and "acoustic_step_s_per_km3" in per[b]:
+                pr["acoustic_time_ratio"] = round(per[a]["acoustic_step_s_per_km3"] / per[b]["acoustic_step_s_per_km3"], 3)
+                pr["acoustic_memory_ratio"] = round(per[a]["acoustic_device_bytes_per_km3"]
+                                                    / per[b]["acoustic_device_bytes_per_km3"], 3)
+            pairs.append(pr)
     return {"per_order": per, "pairs": pairs}
 
 

@@ -14,9 +14,11 @@
 //                        point, p and the three flux cubes in LDS;
 //   force_ac_col_kernel  NGLL 11..16: one lane per (i, j) column, the
 //                        column of p and its force accumulators in registers,
-//                        the element walked slice by slice in k.
+//                        the element walked slice by slice in k (at NGLL 16
+//                        the xi contractions on DPP row rotations).
 // Geometry paths, first-touch coloured stores and atomic assembly follow
 // the elastic kernels.
+#include "dpp_rows.hpp"
 #include "elem_common.hpp"
 
 namespace semx {
@@ -133,6 +135,11 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
   __shared__ float s_D[N2];
   constexpr bool TD = (NG % 4) == 0;  // D transposed for row strides 12, 16 (see force_col_kernel)
   __shared__ float s_Dt[TD ? N2 : 1];
+  // NGLL 16: xi contractions on DPP row rotations, coefficients of rotation
+  // R in s_Cf[R][i] = D[i][src], s_Cb[R][i] = D[src][i] (see force_col_kernel)
+  constexpr bool XDPP = NG == 16;
+  __shared__ float s_Cf[XDPP ? 256 : 1];
+  __shared__ float s_Cb[XDPP ? 256 : 1];
 
   const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
@@ -152,6 +159,18 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
   for (int t = l; t < N2; t += blockDim.x) {
     s_D[t] = a.D[t];
     if constexpr (TD) s_Dt[(t % NG) * NG + t / NG] = a.D[t];
+  }
+  if constexpr (XDPP) {
+    float src[16];
+    row_sources<0>((float)(l & 15), src);  // every lane active (n^2 = 256 = block)
+    if (l < 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int sl = (int)src[r];
+        s_Cf[r * 16 + l] = a.D[l * 16 + sl];
+        s_Cb[r * 16 + l] = a.D[sl * 16 + l];
+      }
+    }
   }
   for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
   __syncthreads();
@@ -184,9 +203,10 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
     if (act) s_p[ll] = pk;
     __syncthreads();
     float d[3] = {0.f, 0.f, 0.f};
+    if constexpr (XDPP) row_contract1<0>(s_Cf + i, pk, d[0]);
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      d[0] += (TD ? s_Dt[b * NG + i] : s_D[i * NG + b]) * s_p[b + NG * j];
+      if constexpr (!XDPP) d[0] += (TD ? s_Dt[b * NG + i] : s_D[i * NG + b]) * s_p[b + NG * j];
       d[1] += (TD ? s_Dt[b * NG + j] : s_D[j * NG + b]) * s_p[i + NG * b];
       d[2] += s_D[k * NG + b] * pc[b];
     }
@@ -204,14 +224,15 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
 #pragma unroll
     for (int b = 0; b < NG; ++b) acc[b] += s_D[k * NG + b] * phi[2];
     if (act) {
-      s_q[ll] = phi[0];
+      if constexpr (!XDPP) s_q[ll] = phi[0];
       s_q[N2 + ll] = phi[1];
     }
-    __syncthreads();
     float sxy = 0.0f;
+    if constexpr (XDPP) row_contract1<0>(s_Cb + i, phi[0], sxy);
+    __syncthreads();
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      sxy += s_D[b * NG + i] * s_q[b + NG * j];
+      if constexpr (!XDPP) sxy += s_D[b * NG + i] * s_q[b + NG * j];
       sxy += s_D[b * NG + j] * s_q[N2 + i + NG * b];
     }
 #pragma unroll
