@@ -417,6 +417,49 @@ def order_sweep_leg(reps: int = 20):
     return rows
 
 
+def single_order_apply(n: int, reps: int):
+    """FP32 coloured force applies on the order-sweep mesh of one NGLL
+    (regular hexahedra, about 2e7 unique points), event-timed, then three
+    1 GiB device copies that calibrate traffic counters; for profiling."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    import workloads as W
+    ne = dict(ORDER_SWEEP)[n]
+    h = (n - 1) * 69.3 / 5
+    mesh = W.box_mesh(ne, n, ne * h)
+    lam, mu, rho = W.homogeneous_model(mesh)
+    s = P.Solver(n)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    del lam, mu, rho
+    u = torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5
+    f = torch.empty_like(u)
+    for _ in range(3):
+        P.semx_apply_force(s.ctx, u, f)
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for _ in range(reps):
+        P.semx_apply_force(s.ctx, u, f)
+    e1.record(s.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = P.semx_mesh_info(s.ctx)
+    s.close()
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular")
+    return {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
+            "launches_per_apply": info["ncolors"], "bytes_per_element": be,
+            "hbm_frac_alg": round(be * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "copy_bytes_each_way": nbytes}
+
+
 def iso_accuracy_summary(rows, eps: float = 1e-5):
     """Equal-accuracy comparison across orders (the paper's dispersion-based
     (h, p) frontier, Sec. IV-B and V-C): with ppw_p the GLL points per
@@ -616,6 +659,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-acoustic", action="store_true")
+    ap.add_argument("--sweep-order", type=int, default=0,
+                    help="time only the FP32 force apply on the order-sweep mesh of this NGLL, then a 1 GiB "
+                         "device copy (for counter runs); prints one JSON line")
     ap.add_argument("--acoustic-only", action="store_true",
                     help="time only the acoustic force apply on the bench mesh (no time loop, no rod runs); "
                          "prints one JSON line")
@@ -652,6 +698,9 @@ def main():
     CONTRACTION = {"f32": P.SEMX_C_F32, "mf32": P.SEMX_C_MFMA_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}
     ASSEMBLY = {"colored": P.SEMX_ASM_COLORED, "atomic": P.SEMX_ASM_ATOMIC}
     torch.cuda.set_device(0)
+    if args.sweep_order:
+        print(json.dumps({"sweep_order": single_order_apply(args.sweep_order, args.apply_reps)}))
+        return
     t_setup = time.perf_counter()
     nt_total = args.warmup + args.steps
     wl = W.layered_jittered(ne=NE, n=NGLL, nt=nt_total, dt=1.0, jitter=0.10, seed=2606,
