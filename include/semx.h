@@ -312,9 +312,12 @@ int semx_set_state_f64(semx_ctx *ctx, const double *u_dev, const double *v_dev, 
 #define SEMX_ELASTIC 0   /* vector displacement, isotropic elasticity (default) */
 #define SEMX_ACOUSTIC 1  /* scalar field, acoustic wave equation */
 
-/* Select the physics.  Allowed before a model is uploaded (SEMX_ESTATE
- * after it, or while checkpointing is on); SEMX_EINVAL for an unknown value
- * or, for SEMX_ACOUSTIC, with FP64 storage or a matrix-core contraction. */
+/* Select the physics.  Allowed before a model is uploaded and before
+ * sources are set (SEMX_ESTATE otherwise, or while checkpointing is on:
+ * source weights are stored per field component); SEMX_EINVAL for an
+ * unknown value or, for SEMX_ACOUSTIC, with FP64 storage or a matrix-core
+ * contraction.  Receivers may be set before it (their seismogram buffer is
+ * re-sized). */
 int semx_set_physics(semx_ctx *ctx, int physics);
 
 /* Acoustic model per element-local point, FP64 host arrays

@@ -1530,6 +1530,9 @@ int semx_set_physics(semx_ctx* c, int physics) {
   if (!c) return SEMX_EINVAL;
   if (physics != SEMX_ELASTIC && physics != SEMX_ACOUSTIC) return fail(c, SEMX_EINVAL, "set_physics: unknown physics");
   if (c->have_model) return fail(c, SEMX_ESTATE, "set_physics: call before uploading a model");
+  // the source weights are stored per field component
+  if (c->src.nsrc > 0 && physics != c->physics)
+    return fail(c, SEMX_ESTATE, "set_physics: call before semx_set_sources");
   if (physics == SEMX_ACOUSTIC) {
     if (c->storage != SEMX_F32) return fail(c, SEMX_EINVAL, "set_physics: acoustic physics runs in FP32 storage");
     if (c->contraction != SEMX_C_F32)

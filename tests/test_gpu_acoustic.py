@@ -198,6 +198,14 @@ def test_acoustic_api_rules():
     with pytest.raises(P.SemxError) as ei:  # elastic context
         P.semx_upload_model_acoustic(s.ctx, np.ones(shape), np.ones(shape))
     assert ei.value.code == P.SEMX_ESTATE
+    # the physics cannot change under sources set for the other one
+    P.semx_set_sources(s.ctx, np.array([0], np.int32), np.array([[0.1, 0.2, 0.3]]), np.array([[0.0, 0.0, 1.0]]),
+                       np.ones((1, 4), np.float32))
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_set_physics(s.ctx, P.SEMX_ACOUSTIC)
+    assert ei.value.code == P.SEMX_ESTATE
+    P.semx_set_physics(s.ctx, P.SEMX_ELASTIC)  # no change: accepted
+    P.lib().semx_set_sources(s.ctx, 0, None, None, None, 0, None)  # clear them
     P.semx_set_physics(s.ctx, P.SEMX_ACOUSTIC)
     with pytest.raises(P.SemxError) as ei:
         P.semx_upload_model(s.ctx, np.ones(shape), np.ones(shape), np.ones(shape))
