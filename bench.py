@@ -683,7 +683,7 @@ def main():
                     help="chain length of the FP32 patch kernel (0 = per-element kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
               "multi-GPU path; the operator would shard by mesh blocks with a halo exchange.",
               file=sys.stderr)
         sys.exit(2)
