@@ -438,8 +438,9 @@ def semx_mlp_adam(net, lr: float, beta1: float, beta2: float, eps: float, step: 
     return _mcheck(net, lib().semx_mlp_adam(net, float(lr), float(beta1), float(beta2), float(eps), int(step)))
 
 
-def semx_set_timing(ctx, enable: bool):
-    return _check(ctx, lib().semx_set_timing(ctx, 1 if enable else 0))
+def semx_set_timing(ctx, stride=1):
+    """Event-time every ``stride``-th force launch (True = every launch, 0 / False = off)."""
+    return _check(ctx, lib().semx_set_timing(ctx, int(stride)))
 
 
 def semx_force_timing(ctx):

@@ -843,7 +843,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     a.count = L.count;
     hipError_t e;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    const bool timed = c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0;
+    if (timed) {
       while (c->ev_pool.size() < c->ev_used + 2) {
         hipEvent_t ev;
         SEMX_HIP(c, hipEventCreate(&ev));
@@ -863,7 +864,7 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     else
       e = launch_force_mfma(c->n, c->contraction, geo, atomic, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
-    if (c->timing) SEMX_HIP(c, hipEventRecord(e1, c->stream));
+    if (timed) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   }
   return SEMX_OK;
 }
@@ -933,7 +934,8 @@ int force_patches(semx_ctx* c, const float* u, float* f) {
     a.pos0 = L.pos0;
     a.count = L.count;
     hipEvent_t e1 = nullptr;
-    if (c->timing) {
+    const bool timed = c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0;
+    if (timed) {
       while (c->ev_pool.size() < c->ev_used + 2) {
         hipEvent_t ev;
         SEMX_HIP(c, hipEventCreate(&ev));
@@ -1835,9 +1837,11 @@ int semx_patch_info(semx_ctx* c, int64_t* npatch, int* ncolors, int64_t* nruns, 
   return SEMX_OK;
 }
 
-int semx_set_timing(semx_ctx* c, int enable) {
+int semx_set_timing(semx_ctx* c, int stride) {
   if (!c) return SEMX_EINVAL;
-  c->timing = enable != 0;
+  if (stride < 0) return fail(c, SEMX_EINVAL, "set_timing: negative stride");
+  c->timing_stride = stride;
+  c->timing_seq = 0;
   c->ev_used = 0;
   return SEMX_OK;
 }

@@ -173,8 +173,10 @@ struct semx_ctx {
   int64_t ckpt_count = 0;
   std::vector<semx::DevBuf> ckpts;  // one buffer of 3 * state_len floats per checkpoint
 
-  // optional event timing of force launches
-  bool timing = false;
+  // optional event timing of force launches: every timing_stride-th launch
+  // (0 = off) is bracketed by an event pair
+  int timing_stride = 0;
+  int64_t timing_seq = 0;
   std::vector<hipEvent_t> ev_pool;  // 2 per recorded launch, reused
   size_t ev_used = 0;
 };
