@@ -191,3 +191,29 @@ def test_stream_bandwidth_reference():
             P.semx_stream_bandwidth(s.ctx, nbytes, reps)
         assert ei.value.code == P.SEMX_EINVAL
     s.close()
+
+
+def test_force_timing_stride():
+    """semx_set_timing(k) event-times launches 0, k, 2k, ... of the force
+    kernel (k = 1: all, 0: none); the summed durations are positive."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh(4, 4, 400.0, jitter=0.1, seed=3)
+    lam, mu, rho = W.homogeneous_model(mesh)
+    s = make_solver(4)
+    info = s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    assert info["ncolors"] == 8
+    u = torch.rand((mesh.nglob, 3), device="cuda")
+    f = torch.empty_like(u)
+    for stride, expect in ((1, 40), (9, 5), (3, 14), (0, 0)):
+        P.semx_set_timing(s.ctx, stride)
+        for _ in range(5):  # 5 applies x 8 colour launches
+            P.semx_apply_force(s.ctx, u, f)
+        n, ms = P.semx_force_timing(s.ctx)
+        assert n == expect, (stride, n)
+        assert (ms > 0) == (expect > 0)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_set_timing(s.ctx, -1)
+    assert ei.value.code == P.SEMX_EINVAL
+    s.close()
