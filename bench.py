@@ -781,16 +781,12 @@ def main():
     P.semx_set_geometry(s.ctx, GEOM[args.geometry])
 
     # ---- time loop: warmup, then exactly `steps` timed steps.  The force
-    # kernel's launch duration is sampled over the same region with HIP event
-    # pairs around every (launches per apply + 1)-th launch, i.e. one launch
-    # per step cycling through the colours: an event pair around every launch
-    # slows the step itself by about 9 % (16 extra stream records per step).
-    if args.patches:
-        launches_per_apply, stride = None, 1  # patch launches per apply vary; time them all
-    else:
-        launches_per_apply = info["ncolors"] if asm == P.SEMX_ASM_COLORED else (
-            int(info["nregular"] > 0) + int(info["nirregular"] > 0))
-        stride = launches_per_apply + 1 if launches_per_apply > 1 else 1
+    # kernel's launch duration is measured over the same region: one HIP
+    # event pair around the force pass (all colour launches back to back) of
+    # every second step, divided by its launches.  An event pair around every
+    # launch would add the event-to-kernel latency to each duration and slow
+    # the step itself by about 9 %.
+    stride = 2
     P.semx_reset(s.ctx)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -815,8 +811,7 @@ def main():
     bw_copy = P.semx_stream_bandwidth(s.ctx, 1 << 30, 20)
 
     # ---- roofline of the force kernel (per launch)
-    if launches_per_apply is None:
-        launches_per_apply = launches / args.steps
+    launches_per_apply = launches / ((args.steps + stride - 1) // stride)
     avg_launch_ms = force_ms / launches
     bytes_per_launch = b_elem * E / launches_per_apply
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
@@ -847,7 +842,7 @@ def main():
                      "kernel": (f"force_patch_kernel<5, {args.geometry}, {args.assembly}>, chains of {args.patches}"
                                 if args.patches else f"force_f32_kernel<5, {args.geometry}, {args.assembly}>"),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
-                     "launches": launches, "launch_sample_stride": stride, "bytes_per_element": b_elem,
+                     "launches": launches, "timed_pass_stride": stride, "bytes_per_element": b_elem,
                      "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4)},
         "unique_nodes_per_s": mesh.nglob / (step_ms * 1e-3),
         "force_apply": apply,

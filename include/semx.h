@@ -335,14 +335,16 @@ int semx_upload_model_acoustic(semx_ctx *ctx, int nmodels, const double *kappa, 
  * unless 2 <= ngll <= 16 and both pointers are non-NULL. */
 int semx_gll(int ngll, double *xi, double *w);
 
-/* Kernel timing.  With stride k > 0, every k-th force-kernel launch (the
- * first, then k, 2k, ... counted from this call; k = 1: all of them) is
- * bracketed by a pair of HIP events recorded on the context stream; 0 turns
- * timing off, a negative stride is SEMX_EINVAL.  Each event record adds a
- * little to the stream's work, so sampling every few launches keeps a timed
- * run close to an untimed one.  semx_force_timing() synchronises the stream,
- * returns the number of timed launches and their summed event-measured
- * duration in milliseconds since the last read, and clears the record. */
+/* Kernel timing.  With stride k > 0, every k-th force pass (one
+ * semx_apply_force, or the force part of one time step: all its colour
+ * launches back to back; the first, then k, 2k, ... counted from this call)
+ * is bracketed by one pair of HIP events recorded on the context stream; 0
+ * turns timing off, a negative stride is SEMX_EINVAL.  semx_force_timing()
+ * synchronises the stream, returns the number of force-kernel launches
+ * inside the timed passes and their summed event-measured duration in
+ * milliseconds since the last read (so the average launch includes the
+ * short gaps between launches, not the latency of an event per launch), and
+ * clears the record. */
 int semx_set_timing(semx_ctx *ctx, int stride);
 int semx_force_timing(semx_ctx *ctx, int64_t *launches, double *total_ms);
 

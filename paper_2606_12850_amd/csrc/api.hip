@@ -814,6 +814,21 @@ int build_layout(semx_ctx* c) {
   return build_patches(c);
 }
 
+// Start of a timed force pass: record the opening event of a pair from the
+// pool and hand back the closing one.
+hipError_t time_pass_begin(semx_ctx* c, hipEvent_t* e1) {
+  while (c->ev_pool.size() < c->ev_used + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    c->ev_pool.push_back(ev);
+  }
+  hipError_t e = hipEventRecord(c->ev_pool[c->ev_used], c->stream);
+  *e1 = c->ev_pool[c->ev_used + 1];
+  c->ev_used += 2;
+  return e;
+}
+
 // f = -K u accumulated into f (f must already hold zeros or earlier sums).
 // With `first_touch` (coloured per-element paths) the first point to
 // reach each node stores instead of adding, so f's prior content is ignored.
@@ -838,23 +853,15 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     a.first_words = c->first_words;
   }
   const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
+  hipEvent_t e1 = nullptr;
+  if (!launches.empty() && c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0) {
+    SEMX_HIP(c, time_pass_begin(c, &e1));
+    c->timed_launches += (int64_t)launches.size();
+  }
   for (const auto& L : launches) {
     a.pos0 = L.pos0;
     a.count = L.count;
     hipError_t e;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0;
-    if (timed) {
-      while (c->ev_pool.size() < c->ev_used + 2) {
-        hipEvent_t ev;
-        SEMX_HIP(c, hipEventCreate(&ev));
-        c->ev_pool.push_back(ev);
-      }
-      e0 = c->ev_pool[c->ev_used];
-      e1 = c->ev_pool[c->ev_used + 1];
-      c->ev_used += 2;
-      SEMX_HIP(c, hipEventRecord(e0, c->stream));
-    }
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, a, c->stream);
@@ -864,8 +871,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     else
       e = launch_force_mfma(c->n, c->contraction, geo, atomic, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
-    if (timed) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   }
+  if (e1) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   return SEMX_OK;
 }
 
@@ -930,26 +937,20 @@ int force_patches(semx_ctx* c, const float* u, float* f) {
   pa.maxnodes = c->patch_maxnodes;
   pa.maxruns = c->patch_maxruns;
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
-  for (const auto& L : atomic ? c->patch_atomic : c->patch_colored) {
+  const auto& plaunches = atomic ? c->patch_atomic : c->patch_colored;
+  hipEvent_t e1 = nullptr;
+  if (!plaunches.empty() && c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0) {
+    SEMX_HIP(c, time_pass_begin(c, &e1));
+    c->timed_launches += (int64_t)plaunches.size();
+  }
+  for (const auto& L : plaunches) {
     a.pos0 = L.pos0;
     a.count = L.count;
-    hipEvent_t e1 = nullptr;
-    const bool timed = c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0;
-    if (timed) {
-      while (c->ev_pool.size() < c->ev_used + 2) {
-        hipEvent_t ev;
-        SEMX_HIP(c, hipEventCreate(&ev));
-        c->ev_pool.push_back(ev);
-      }
-      SEMX_HIP(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
-      e1 = c->ev_pool[c->ev_used + 1];
-      c->ev_used += 2;
-    }
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     hipError_t e = launch_force_patch(c->n, geo, atomic, pa, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "patch force kernel launch");
-    if (e1) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   }
+  if (e1) SEMX_HIP(c, hipEventRecord(e1, c->stream));
   return SEMX_OK;
 }
 
@@ -1842,6 +1843,7 @@ int semx_set_timing(semx_ctx* c, int stride) {
   if (stride < 0) return fail(c, SEMX_EINVAL, "set_timing: negative stride");
   c->timing_stride = stride;
   c->timing_seq = 0;
+  c->timed_launches = 0;
   c->ev_used = 0;
   return SEMX_OK;
 }
@@ -1855,9 +1857,10 @@ int semx_force_timing(semx_ctx* c, int64_t* launches, double* total_ms) {
     SEMX_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
     tot += ms;
   }
-  *launches = (int64_t)(c->ev_used / 2);
+  *launches = c->timed_launches;
   *total_ms = tot;
   c->ev_used = 0;
+  c->timed_launches = 0;
   return SEMX_OK;
 }
 

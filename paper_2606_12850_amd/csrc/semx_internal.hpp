@@ -173,10 +173,12 @@ struct semx_ctx {
   int64_t ckpt_count = 0;
   std::vector<semx::DevBuf> ckpts;  // one buffer of 3 * state_len floats per checkpoint
 
-  // optional event timing of force launches: every timing_stride-th launch
-  // (0 = off) is bracketed by an event pair
+  // optional event timing of force passes: every timing_stride-th pass
+  // (0 = off) is bracketed by one event pair; timed_launches counts the
+  // force launches inside the timed passes
   int timing_stride = 0;
   int64_t timing_seq = 0;
+  int64_t timed_launches = 0;
   std::vector<hipEvent_t> ev_pool;  // 2 per recorded launch, reused
   size_t ev_used = 0;
 };
