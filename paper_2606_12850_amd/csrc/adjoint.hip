@@ -165,8 +165,15 @@ struct AdjCol {
   static constexpr int BLK = ((N2 + 63) / 64) * 64;
 };
 
+// Two waves per SIMD: left to itself the compiler takes up to 306 VGPRs and
+// AGPRs at NGLL 14-16 (one wave per SIMD); capped at 256 it spills 8
+// registers at NGLL 16 (trilinear) and none elsewhere, and the adjoint pass
+// measured 7-26 % faster.  The DPP row contractions of force_col_kernel
+// raise the pressure here (two column fields) and measured slower, with or
+// without the cap.
 template <int NG, int GEO, bool ATOMIC>
-__global__ __launch_bounds__(AdjCol<NG>::BLK) void adjoint_col_kernel(AdjArgs A) {
+__global__ __launch_bounds__(AdjCol<NG>::BLK) __attribute__((amdgpu_waves_per_eu(2))) void adjoint_col_kernel(
+    AdjArgs A) {
   constexpr int N2 = AdjCol<NG>::N2;
   constexpr int N3 = AdjCol<NG>::N3;
   __shared__ int s_g[N3];
