@@ -377,3 +377,30 @@ def test_acoustic_batched_time_loop():
         err = rel_l2(got[k, :, 0, :], ref)
         print(f"acoustic batched model {k}: seismogram rel L2 {err:.2e}")
         assert err <= TOL_SEIS
+
+
+@pytest.mark.parametrize("n", [2, 5, 10, 11, 16])
+def test_acoustic_force_degenerate_meshes(n):
+    """Single-element and one-element-wide meshes (one lane per point up to
+    NGLL 10, the column kernel from 11, its DPP row at 16), every assembly
+    and geometry mode, against the acoustic oracle."""
+    import paper_2606_12850_amd as P
+    from tests.test_gpu_force import _degenerate_meshes
+    rng = np.random.default_rng(70 + n)
+    for ne, distort, mesh in _degenerate_meshes(n):
+        gam, jac, _ = A.O.geometry(n, mesh.elem_vert, mesh.vert)
+        kappa, rho = _model(mesh, n)
+        p = rng.uniform(-1, 1, mesh.nglob).astype(np.float32).astype(np.float64)
+        ref = A.force(n, mesh.ibool, gam, jac, rho, p, mesh.nglob)
+        s = _solver(n)
+        info = s.upload_mesh(mesh)
+        assert (info["nirregular"] > 0) == distort
+        s.upload_model_acoustic(kappa, rho)
+        for geometry in (P.SEMX_GEOM_STORED, P.SEMX_GEOM_TRILINEAR):
+            P.semx_set_geometry(s.ctx, geometry)
+            for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+                s.set_mode(P.SEMX_C_F32, asm)
+                err = rel_l2(_force(s, p), ref)
+                print(f"acoustic n={n} ne={ne} distorted={distort} geometry={geometry} asm={asm}: {err:.2e}")
+                assert err <= TOL_F32, (ne, distort, geometry, asm, err)
+        s.close()

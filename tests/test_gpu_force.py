@@ -218,3 +218,71 @@ def test_force_timing_stride():
         P.semx_set_timing(s.ctx, -1)
     assert ei.value.code == P.SEMX_EINVAL
     s.close()
+
+
+def _degenerate_meshes(n):
+    """One element (regular, then with a displaced corner) and a strip of
+    four elements one element wide (displaced corner): the smallest grids,
+    with one and two colours."""
+    import dataclasses
+    out = []
+    for ne, distort in (((1, 1, 1), False), ((1, 1, 1), True), ((1, 1, 4), True)):
+        mesh = W.box_mesh(ne, n, 1000.0)
+        if distort:
+            vert = mesh.vert.copy()
+            c = int(np.argmax(vert.sum(axis=1)))
+            vert[c] += np.array([0.07, -0.05, 0.06]) * (np.array(mesh.L) / np.array(ne))
+            mesh = dataclasses.replace(mesh, vert=vert)
+        out.append((ne, distort, mesh))
+    return out
+
+
+@pytest.mark.parametrize("n", [2, 5, 10, 11, 16])
+def test_force_degenerate_meshes(orc, n):
+    """Single-element and one-element-wide meshes at the orders where the
+    kernel changes (one lane per point up to NGLL 10, the column kernel from
+    11, its DPP rows at 16): every assembly and geometry mode against the
+    oracle."""
+    import paper_2606_12850_amd as P
+    rng = np.random.default_rng(40 + n)
+    for ne, distort, mesh in _degenerate_meshes(n):
+        lam, mu, rho = _hetero_model(mesh, 1)
+        gam, jac, _ = oracle_geometry(orc, mesh)
+        u = rng.uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+        f_ref = orc.force(n, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+        s = make_solver(n)
+        info = s.upload_mesh(mesh)
+        assert (info["nirregular"] > 0) == distort
+        s.upload_model(lam, mu, rho)
+        for geometry in (P.SEMX_GEOM_STORED, P.SEMX_GEOM_TRILINEAR):
+            P.semx_set_geometry(s.ctx, geometry)
+            for assembly in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
+                s.set_mode(P.SEMX_C_F32, assembly)
+                err = rel_l2(gpu_force(s, u), f_ref)
+                print(f"n={n} ne={ne} distorted={distort} geometry={geometry} assembly={assembly}: {err:.2e}")
+                assert err <= TOL_F32, (ne, distort, geometry, assembly, err)
+        s.close()
+
+
+def test_zero_steps_and_silent_run():
+    """semx_step(0) changes nothing; with no sources and no receivers a run
+    from rest stays exactly at rest and the time index advances."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((3, 2, 2), 5, 1000.0, jitter=0.1, seed=3)
+    lam, mu, rho = _hetero_model(mesh, 2)
+    s = make_solver(5)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    P.semx_set_dt(s.ctx, P.semx_cfl_dt(s.ctx, 0.4))
+    P.semx_reset(s.ctx)
+    P.semx_step(s.ctx, 0)
+    assert P.semx_time_index(s.ctx) == 0
+    P.semx_step(s.ctx, 25)
+    assert P.semx_time_index(s.ctx) == 25
+    u = s.empty_field(); v = s.empty_field(); a = s.empty_field()
+    assert P.semx_get_state(s.ctx, u, v, a) == 25
+    torch.cuda.synchronize()
+    for x in (u, v, a):
+        assert int(torch.count_nonzero(x)) == 0
+    s.close()
