@@ -59,9 +59,10 @@ def bytes_per_element_patch(n: int, nglob: int, nspec: int, geometry: str, pinfo
     return 2 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec + meta / nspec
 
 
-def traffic_from_profiles(src_hash: str):
-    """HBM bytes per launch measured with rocprofv3 PMC counters, if they were
-    taken on the current force kernel source."""
+def traffic_from_profiles(src_hash: str, key: str = "trilinear"):
+    """HBM bytes per launch measured with rocprofv3 PMC counters (`key`: the
+    force kernel's geometry path, or that path's skeleton with the suffix
+    `_skeleton`), if they were taken on the current force kernel source."""
     p = os.path.join(ROOT, "profiles", "force_traffic.json")
     if not os.path.exists(p):
         return None
@@ -71,7 +72,48 @@ def traffic_from_profiles(src_hash: str):
         return None
     if d.get("kernel_source_sha256") != src_hash:
         return None
-    return d.get("bytes_per_launch")
+    return d.get(key, {}).get("bytes_per_launch")
+
+
+def write_traffic(run_dir: str):
+    """profiles/force_traffic.json from the FETCH_SIZE and WRITE_SIZE runs of
+    `bench.py --profile-force` (trilinear and stored): KiB per dispatch of the
+    NGLL 5 coloured force kernel and of its memory skeleton, each scaled by
+    what the same counter reads for the 1 GiB device copy that follows them."""
+    import collections
+    import csv
+    copy_bytes = 1 << 30
+    src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
+                   for f in ("force_f32.hip", "elem_common.hpp"))
+    out = {"kernel_source_sha256": hashlib.sha256(src).hexdigest(), "unit": "bytes per launch",
+           "workload": "layered jittered cube 64^3, NGLL 5, colored (8 launches of 32768 elements)"}
+    for geo, gid in (("trilinear", 2), ("stored", 1)):
+        d = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            agg = collections.defaultdict(list)
+            path = os.path.join(run_dir, f"pmc_{geo}_{ctr}", "run_counter_collection.csv")
+            for r in csv.DictReader(open(path)):
+                if r["Counter_Name"] == ctr:
+                    agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+            cp = [v for k, vs in agg.items() if "copyBuffer" in k for v in vs][-3:]
+            scale = copy_bytes / (sum(cp) / len(cp) * 1024.0)
+            for tag, pat in (("kernel", f"force_f32_kernel<5, {gid}, false, 1>"),
+                             ("skeleton", f"force_skeleton_kernel<5, {gid}>")):
+                kv = [v for k, vs in agg.items() if pat in k for v in vs]
+                if kv:
+                    d.setdefault(tag, {})[ctr] = {
+                        "kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv),
+                        "copy_kib_per_dispatch": sum(cp) / len(cp), "scale": scale,
+                        "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * scale}
+        for tag in d:
+            d[tag]["bytes_per_launch"] = sum(d[tag][c]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE"))
+        out[geo] = d["kernel"]
+        if "skeleton" in d:
+            out[geo + "_skeleton"] = d["skeleton"]
+    out["bytes_per_launch"] = out["trilinear"]["bytes_per_launch"]
+    with open(os.path.join(ROOT, "profiles", "force_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: (v["bytes_per_launch"] if isinstance(v, dict) else v) for k, v in out.items()}))
 
 
 def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
@@ -681,7 +723,13 @@ def main():
                     help="also time the force apply for NGLL 4..9 at ~2e7 points (FP32 and mixed)")
     ap.add_argument("--patches", type=int, default=0,
                     help="chain length of the FP32 patch kernel (0 = per-element kernels)")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="no GPU: read the four rocprofv3 --pmc runs of --profile-force (DIR/pmc_<geometry>_"
+                         "<counter>/run_counter_collection.csv) and write profiles/force_traffic.json")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
               "multi-GPU path; the operator would shard by mesh blocks with a halo exchange.",
@@ -765,6 +813,10 @@ def main():
             "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
     progress(f"force-apply matrix done ({len(apply)} variants)")
     if args.profile_force:
+        sk = None
+        if args.contraction == "f32" and args.assembly == "colored" and not args.patches:
+            # the force pass's memory skeleton, for the same counters
+            sk = round(P.semx_force_skeleton(s.ctx, u, f, args.apply_reps), 4)
         # calibration for the traffic counters: a plain device copy of known size
         nbytes = 1 << 30
         a = torch.ones(nbytes // 4, device="cuda")
@@ -772,7 +824,8 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_force": apply, "elements": E, "copy_bytes_each_way": nbytes,
+        print(json.dumps({"profile_force": apply, "skeleton_ms_per_apply": sk, "elements": E,
+                          "copy_bytes_each_way": nbytes,
                           "force_launches_per_apply": info["ncolors"] if args.assembly == "colored" else 1}))
         s.close()
         return
@@ -813,11 +866,26 @@ def main():
     # ---- roofline of the force kernel (per launch)
     launches_per_apply = launches / ((args.steps + stride - 1) // stride)
     avg_launch_ms = force_ms / launches
+
+    # ---- access-pattern reference: the memory skeleton of the same force
+    # pass (same launches, grid, loads and stores, no arithmetic) on scratch
+    # fields; the kernel cannot be faster than its skeleton
+    skeleton = None
+    if not args.patches and args.assembly == "colored":
+        uu = torch.zeros((mesh.nglob, 3), device="cuda")
+        ff = torch.zeros_like(uu)
+        sk_launch_ms = P.semx_force_skeleton(s.ctx, uu, ff, 20) / launches_per_apply
+        del uu, ff
+        skeleton = {"skeleton_ms_per_launch": round(sk_launch_ms, 5),
+                    "frac_of_skeleton": round(sk_launch_ms / avg_launch_ms, 4)}
     bytes_per_launch = b_elem * E / launches_per_apply
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
                    for f in ("force_f32.hip", "elem_common.hpp"))
-    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+    src_hash = hashlib.sha256(src).hexdigest()
+    traffic = traffic_from_profiles(src_hash, args.geometry) if not args.patches else None
+    if skeleton is not None:
+        skeleton["skeleton_traffic"] = traffic_from_profiles(src_hash, args.geometry + "_skeleton")
 
     out = {
         "metric": "GLL-point force evals/s (FP32 vs mixed) + % HBM roofline; adjoint/fwd time",
@@ -843,7 +911,8 @@ def main():
                                 if args.patches else f"force_f32_kernel<5, {args.geometry}, {args.assembly}>"),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
                      "launches": launches, "timed_pass_stride": stride, "bytes_per_element": b_elem,
-                     "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4)},
+                     "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4),
+                     **(skeleton or {})},
         "unique_nodes_per_s": mesh.nglob / (step_ms * 1e-3),
         "force_apply": apply,
         "wall_s_timed": round(wall, 3),

@@ -100,6 +100,7 @@ _SIGS = {
     "semx_get_state_f64": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i64)],
     "semx_set_state_f64": [_vp, _vp, _vp, _vp, _i64],
     "semx_stream_bandwidth": [_vp, _i64, _i32, ctypes.POINTER(_f64)],
+    "semx_force_skeleton": [_vp, _vp, _vp, _i32, ctypes.POINTER(_f64)],
     "semx_set_timing": [_vp, _i32],
     "semx_set_physics": [_vp, _i32],
     "semx_upload_model_acoustic": [_vp, _i32, _vp, _vp],
@@ -337,6 +338,13 @@ def semx_set_state_f64(ctx, u, v, a, it: int):
 def semx_stream_bandwidth(ctx, nbytes: int, reps: int) -> float:
     out = _f64()
     _check(ctx, lib().semx_stream_bandwidth(ctx, int(nbytes), int(reps), ctypes.byref(out)))
+    return out.value
+
+
+def semx_force_skeleton(ctx, u, f, reps: int) -> float:
+    """Milliseconds per pass of the force pass's memory skeleton (f is overwritten)."""
+    out = _f64()
+    _check(ctx, lib().semx_force_skeleton(ctx, _ptr(u), _ptr(f), int(reps), ctypes.byref(out)))
     return out.value
 
 

@@ -832,7 +832,8 @@ hipError_t time_pass_begin(semx_ctx* c, hipEvent_t* e1) {
 // f = -K u accumulated into f (f must already hold zeros or earlier sums).
 // With `first_touch` (coloured per-element paths) the first point to
 // reach each node stores instead of adding, so f's prior content is ignored.
-int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false) {
+// Kernel arguments of a per-element force pass (launch range left empty).
+ForceArgs force_args(const semx_ctx* c, const float* u, float* f, bool first_touch) {
   ForceArgs a{};
   a.ibool = c->d_ibool.as<int32_t>();
   a.gam_pt = c->d_gam_pt.as<float>();
@@ -847,11 +848,16 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
   a.nspec = c->nspec;
   a.nglob = c->nglob;
   a.nmodels = c->nmodels;
-  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
-  if (first_touch && !atomic && c->d_first.p) {
+  if (first_touch && c->assembly != SEMX_ASM_ATOMIC && c->d_first.p) {
     a.first = c->d_first.as<uint32_t>();
     a.first_words = c->first_words;
   }
+  return a;
+}
+
+int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false) {
+  ForceArgs a = force_args(c, u, f, first_touch);
+  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
   const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
   hipEvent_t e1 = nullptr;
   if (!launches.empty() && c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0) {
@@ -1587,6 +1593,43 @@ int semx_apply_force(semx_ctx* c, const float* u_dev, float* f_dev) {
   const int64_t len = state_len(c);
   if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "apply_force: u and f overlap");
   return force_into(c, u_dev, f_dev, false);
+}
+
+int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps, double* ms_per_pass) {
+  if (!c || !ms_per_pass) return SEMX_EINVAL;
+  if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "force_skeleton: mesh and model required");
+  if (c->storage != SEMX_F32 || c->physics != SEMX_ELASTIC || c->contraction != SEMX_C_F32 ||
+      c->assembly != SEMX_ASM_COLORED || c->n > kMaxNLow || use_patches(c))
+    return fail(c, SEMX_ESTATE,
+                "force_skeleton: covers the FP32 elastic per-element kernel with coloured assembly, NGLL <= 10");
+  if (!u_dev || !f_dev || reps <= 0) return fail(c, SEMX_EINVAL, "force_skeleton: null pointer or reps <= 0");
+  const int64_t len = state_len(c);
+  if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "force_skeleton: u and f overlap");
+  ForceArgs a = force_args(c, u_dev, f_dev, force_overwrites(c));
+  auto pass = [&]() -> hipError_t {
+    for (const auto& L : c->colored_launches) {
+      a.pos0 = L.pos0;
+      a.count = L.count;
+      const hipError_t e = launch_force_skeleton(c->n, L.irregular ? c->irregular_geo : kRegular, a, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = pass();  // warm
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  for (int k = 0; k < reps && e == hipSuccess; ++k) e = pass();
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "force_skeleton");
+  *ms_per_pass = (double)ms / reps;
+  return SEMX_OK;
 }
 
 int semx_set_dt(semx_ctx* c, double dt) {

@@ -184,7 +184,74 @@ hipError_t launch_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   }
 }
 
+// Memory skeleton of force_f32_kernel (coloured assembly, one element per
+// workgroup): the same grid, block mapping and per-lane loads and stores
+// (node number, geometry, material, u, first-touch bit, f read unless first,
+// f store), without the contractions and the pointwise arithmetic.  Its
+// duration is the floor that the kernel's access pattern alone sets on the
+// memory system.  f receives meaningless values.
+template <int NG, int GEO>
+__global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArgs a) {
+  constexpr int N3 = Shape<NG>::N3;
+  const int ngrp = (int)a.count;
+  const int grp = xcd_group(ngrp);
+  if (grp >= ngrp) return;  // uniform over the block
+  const int p = threadIdx.x;
+  if (p >= N3) return;
+  const int pos = (int)a.pos0 + grp;
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
+  float* f = a.f + (size_t)model * a.nglob * 3;
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
+  PointIn P;
+  load_point<NG, GEO, false>(a, mat, u, f, pos, p, ldnt(a.ibool + (size_t)pos * N3 + p), P);
+  float s = P.lw + P.mw;
+  if constexpr (GEO == kStored) {
+#pragma unroll
+    for (int d = 0; d < 9; ++d) s += P.G[d];
+  } else {
+    constexpr int NS = GEO == kRegular ? 9 : 24;
+    const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
+#pragma unroll
+    for (int d = 0; d < NS; ++d) s += src[d];
+  }
+  float* fg = f + 3 * (size_t)P.g;
+  fg[0] = P.f[0] + s * P.u[0];
+  fg[1] = P.f[1] + s * P.u[1];
+  fg[2] = P.f[2] + s * P.u[2];
+}
+
+template <int NG>
+hipError_t launch_skeleton_n(int geo, const ForceArgs& a, hipStream_t s) {
+  static_assert(SEMX_F32_ELEMS_PER_BLOCK == 1, "the skeleton mirrors one element per workgroup");
+  if (a.count <= 0) return hipSuccess;
+  const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
+  switch (geo) {
+    case kRegular: force_skeleton_kernel<NG, kRegular><<<grid, block, 0, s>>>(a); break;
+    case kStored: force_skeleton_kernel<NG, kStored><<<grid, block, 0, s>>>(a); break;
+    case kTrilinear: force_skeleton_kernel<NG, kTrilinear><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_force_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s) {
+  switch (n) {
+    case 2: return launch_skeleton_n<2>(geo, a, s);
+    case 3: return launch_skeleton_n<3>(geo, a, s);
+    case 4: return launch_skeleton_n<4>(geo, a, s);
+    case 5: return launch_skeleton_n<5>(geo, a, s);
+    case 6: return launch_skeleton_n<6>(geo, a, s);
+    case 7: return launch_skeleton_n<7>(geo, a, s);
+    case 8: return launch_skeleton_n<8>(geo, a, s);
+    case 9: return launch_skeleton_n<9>(geo, a, s);
+    case 10: return launch_skeleton_n<10>(geo, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   switch (n) {

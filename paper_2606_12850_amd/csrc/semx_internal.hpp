@@ -224,6 +224,8 @@ struct ForceArgs {
   int nmodels;
 };
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+// Memory skeleton of the coloured launch_force_f32 (same loads and stores, no arithmetic).
+hipError_t launch_force_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
 
 // Patch launch: ForceArgs.pos0/count name a range of patches; ibool is unused.
 struct PatchArgs {

@@ -220,6 +220,57 @@ def test_force_timing_stride():
     s.close()
 
 
+def test_force_skeleton():
+    """The memory skeleton of the coloured force pass (same launches, loads
+    and stores, no arithmetic) runs on every geometry path, takes no longer
+    than the force pass itself, leaves the operator unchanged, and rejects
+    the contexts it does not cover."""
+    import torch
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh(32, 5, 4000.0, jitter=0.1, seed=3)
+    lam, mu, rho = _hetero_model(mesh, 4)
+    s = make_solver(5)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    u = torch.rand((mesh.nglob, 3), device="cuda")
+    f = torch.empty_like(u)
+    for geometry in (P.SEMX_GEOM_STORED, P.SEMX_GEOM_TRILINEAR):
+        P.semx_set_geometry(s.ctx, geometry)
+        P.semx_apply_force(s.ctx, u, f)
+        f0 = f.clone()
+        sk = P.semx_force_skeleton(s.ctx, u, f, 20)
+        P.semx_set_timing(s.ctx, 1)
+        for _ in range(20):
+            P.semx_apply_force(s.ctx, u, f)
+        _, ms = P.semx_force_timing(s.ctx)
+        P.semx_set_timing(s.ctx, 0)
+        torch.cuda.synchronize()
+        print(f"geometry {geometry}: skeleton {sk * 1e3:.1f} us, force pass {ms / 20 * 1e3:.1f} us per pass")
+        assert 0.0 < sk <= 1.1 * ms / 20
+        assert torch.equal(f, f0)
+    for bad in (0, -3):
+        with pytest.raises(P.SemxError) as ei:
+            P.semx_force_skeleton(s.ctx, u, f, bad)
+        assert ei.value.code == P.SEMX_EINVAL
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_force_skeleton(s.ctx, u, u, 1)
+    assert ei.value.code == P.SEMX_EINVAL
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_ATOMIC)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_force_skeleton(s.ctx, u, f, 1)
+    assert ei.value.code == P.SEMX_ESTATE
+    s.close()
+    m11 = W.box_mesh(2, 11, 1000.0)
+    s = make_solver(11)
+    s.upload_mesh(m11)
+    s.upload_model(*W.homogeneous_model(m11))
+    u = torch.zeros((m11.nglob, 3), device="cuda")
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_force_skeleton(s.ctx, u, torch.empty_like(u), 1)
+    assert ei.value.code == P.SEMX_ESTATE
+    s.close()
+
+
 def _degenerate_meshes(n):
     """One element (regular, then with a displaced corner) and a strip of
     four elements one element wide (displaced corner): the smallest grids,
