@@ -487,6 +487,7 @@ def single_order_apply(n: int, reps: int):
     e1.record(s.stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    sk = P.semx_force_skeleton(s.ctx, u, f, reps)  # the memory skeleton of the same pass
     info = P.semx_mesh_info(s.ctx)
     s.close()
     nbytes = 1 << 30
@@ -499,6 +500,7 @@ def single_order_apply(n: int, reps: int):
     return {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
             "launches_per_apply": info["ncolors"], "bytes_per_element": be,
             "hbm_frac_alg": round(be * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "skeleton_ms_per_apply": round(sk, 4), "frac_of_skeleton": round(sk / ms, 4),
             "copy_bytes_each_way": nbytes}
 
 

@@ -360,11 +360,12 @@ int semx_stream_bandwidth(semx_ctx *ctx, int64_t nbytes, int reps, double *gbps)
 /* Access-pattern reference for the force pass (Sec. II-B operator, Sec. IV-D
  * fused traversal): runs, reps times after one warm-up pass, the memory
  * skeleton of the FP32 per-element force pass that semx_apply_force and
- * semx_step launch with coloured assembly: the same colour launches, grid,
+ * semx_step launch with coloured assembly (one lane per point up to NGLL
+ * 10, one lane per column from 11): the same colour launches, grid,
  * block-to-element mapping and per-point loads and stores (node numbers,
  * geometry, material, the gather of u, the first-touch bits, the read of f
  * where the point is not first and the store of f) without the
- * contractions and the stress arithmetic.  The clearing of f that a pass
+ * contractions, the stress arithmetic and the slice barriers.  The clearing of f that a pass
  * without first-touch coverage needs is not included.  Returns the average
  * milliseconds per pass (HIP events on the context stream); the force pass
  * cannot take less time than its skeleton.
@@ -372,8 +373,8 @@ int semx_stream_bandwidth(semx_ctx *ctx, int64_t nbytes, int reps, double *gbps)
  *   f_dev: device [nmodels][nglob][3] FP32, overwritten with meaningless
  *          values; must not overlap u_dev.
  * Errors: SEMX_ESTATE without mesh and model, or unless the context runs the
- * FP32 elastic per-element kernel (FP32 storage and contraction, coloured
- * assembly, NGLL <= 10, patches off); SEMX_EINVAL for null pointers,
+ * FP32 elastic per-element kernels (FP32 storage and contraction, coloured
+ * assembly, patches off); SEMX_EINVAL for null pointers,
  * overlapping buffers or reps <= 0. */
 int semx_force_skeleton(semx_ctx *ctx, const float *u_dev, float *f_dev, int reps, double *ms_per_pass);
 

@@ -1599,9 +1599,8 @@ int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps,
   if (!c || !ms_per_pass) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "force_skeleton: mesh and model required");
   if (c->storage != SEMX_F32 || c->physics != SEMX_ELASTIC || c->contraction != SEMX_C_F32 ||
-      c->assembly != SEMX_ASM_COLORED || c->n > kMaxNLow || use_patches(c))
-    return fail(c, SEMX_ESTATE,
-                "force_skeleton: covers the FP32 elastic per-element kernel with coloured assembly, NGLL <= 10");
+      c->assembly != SEMX_ASM_COLORED || use_patches(c))
+    return fail(c, SEMX_ESTATE, "force_skeleton: covers the FP32 elastic per-element kernels with coloured assembly");
   if (!u_dev || !f_dev || reps <= 0) return fail(c, SEMX_EINVAL, "force_skeleton: null pointer or reps <= 0");
   const int64_t len = state_len(c);
   if (u_dev < f_dev + len && f_dev < u_dev + len) return fail(c, SEMX_EINVAL, "force_skeleton: u and f overlap");
@@ -1610,7 +1609,9 @@ int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps,
     for (const auto& L : c->colored_launches) {
       a.pos0 = L.pos0;
       a.count = L.count;
-      const hipError_t e = launch_force_skeleton(c->n, L.irregular ? c->irregular_geo : kRegular, a, c->stream);
+      const int geo = L.irregular ? c->irregular_geo : kRegular;
+      const hipError_t e = c->n > kMaxNLow ? launch_force_high_skeleton(c->n, geo, a, c->stream)
+                                           : launch_force_skeleton(c->n, geo, a, c->stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

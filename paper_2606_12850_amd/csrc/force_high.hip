@@ -278,7 +278,87 @@ hipError_t launch_col_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s)
   }
 }
 
+// Memory skeleton of force_col_kernel (coloured assembly): the same grid,
+// block mapping, node numbers staged in LDS, column gather of u, per-point
+// material and (kStored) Gamma, first-touch bits and column scatter of f,
+// without the slice contractions, the pointwise arithmetic and the slice
+// barriers.  f receives meaningless values.
+template <int NG, int GEO>
+__global__ __launch_bounds__(ColShape<NG>::BLK) void force_col_skeleton_kernel(ForceArgs a) {
+  constexpr int N2 = ColShape<NG>::N2;
+  constexpr int N3 = ColShape<NG>::N3;
+  __shared__ int s_g[N3];
+  const int ngrp = (int)a.count;
+  const int grp = xcd_group(ngrp);
+  if (grp >= ngrp) return;  // uniform over the block
+  const int pos = (int)a.pos0 + grp;
+  const int l = threadIdx.x;
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
+  float* f = a.f + (size_t)model * a.nglob * 3;
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3 + (size_t)pos * 2 * N3;
+  for (int t = l; t < N3; t += blockDim.x) s_g[t] = ldnt(a.ibool + (size_t)pos * N3 + t);
+  __syncthreads();
+  if (l >= N2) return;  // no barrier follows
+  float sg = 0.0f;
+  if constexpr (GEO != kStored) {
+    constexpr int NS = GEO == kRegular ? 9 : 24;
+    const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
+#pragma unroll
+    for (int d = 0; d < NS; ++d) sg += src[d];
+  }
+#pragma unroll 4
+  for (int k = 0; k < NG; ++k) {
+    const int q = l + N2 * k;
+    const int g = s_g[q];
+    float m = sg + ldnt(mat + q) + ldnt(mat + N3 + q);
+    if constexpr (GEO == kStored) {
+      const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + q;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) m += ldnt(gp + d * N3);
+    }
+    const float x0 = u[3 * (size_t)g + 0], x1 = u[3 * (size_t)g + 1], x2 = u[3 * (size_t)g + 2];
+    float* fg = f + 3 * (size_t)g;
+    const bool first = a.first && ((a.first[(size_t)pos * a.first_words + (q >> 5)] >> (q & 31)) & 1u);
+    if (first) {
+      fg[0] = m * x0;
+      fg[1] = m * x1;
+      fg[2] = m * x2;
+    } else {
+      fg[0] = fg[0] + m * x0;
+      fg[1] = fg[1] + m * x1;
+      fg[2] = fg[2] + m * x2;
+    }
+  }
+}
+
+template <int NG>
+hipError_t launch_col_skeleton_n(int geo, const ForceArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(ColShape<NG>::BLK);
+  switch (geo) {
+    case kRegular: force_col_skeleton_kernel<NG, kRegular><<<grid, block, 0, s>>>(a); break;
+    case kStored: force_col_skeleton_kernel<NG, kStored><<<grid, block, 0, s>>>(a); break;
+    case kTrilinear: force_col_skeleton_kernel<NG, kTrilinear><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s) {
+  switch (n) {
+    case 11: return launch_col_skeleton_n<11>(geo, a, s);
+    case 12: return launch_col_skeleton_n<12>(geo, a, s);
+    case 13: return launch_col_skeleton_n<13>(geo, a, s);
+    case 14: return launch_col_skeleton_n<14>(geo, a, s);
+    case 15: return launch_col_skeleton_n<15>(geo, a, s);
+    case 16: return launch_col_skeleton_n<16>(geo, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   switch (n) {

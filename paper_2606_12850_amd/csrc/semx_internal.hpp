@@ -242,6 +242,8 @@ size_t patch_lds_bytes(int n, int maxnodes, int maxruns);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // force_high.hip: NGLL 11..16 (one lane per (i, j) column)
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+// Memory skeleton of the coloured launch_force_high (same loads and stores, no arithmetic).
+hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)
 hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 bool mfma_supported(int n);

@@ -260,11 +260,30 @@ def test_force_skeleton():
         P.semx_force_skeleton(s.ctx, u, f, 1)
     assert ei.value.code == P.SEMX_ESTATE
     s.close()
-    m11 = W.box_mesh(2, 11, 1000.0)
-    s = make_solver(11)
-    s.upload_mesh(m11)
-    s.upload_model(*W.homogeneous_model(m11))
-    u = torch.zeros((m11.nglob, 3), device="cuda")
+    # the column kernels (NGLL 11-16): skeleton on a jittered mesh, then the
+    # operator is unchanged
+    for n in (11, 16):
+        mh = W.box_mesh((4, 4, 2), n, 1000.0, jitter=0.1, seed=5)
+        s = make_solver(n)
+        s.upload_mesh(mh)
+        s.upload_model(*_hetero_model(mh, 6))
+        u = torch.rand((mh.nglob, 3), device="cuda")
+        f = torch.empty_like(u)
+        for geometry in (P.SEMX_GEOM_STORED, P.SEMX_GEOM_TRILINEAR):
+            P.semx_set_geometry(s.ctx, geometry)
+            P.semx_apply_force(s.ctx, u, f)
+            f0 = f.clone()
+            assert P.semx_force_skeleton(s.ctx, u, f, 3) > 0.0
+            P.semx_apply_force(s.ctx, u, f)
+            torch.cuda.synchronize()
+            assert torch.equal(f, f0)
+        s.close()
+    # acoustic physics has no skeleton
+    ma = W.box_mesh(2, 5, 1000.0)
+    s = P.Solver(5, physics=P.SEMX_ACOUSTIC)
+    s.upload_mesh(ma)
+    s.upload_model_acoustic(np.full((ma.nspec, 125), 2.25e9), np.full((ma.nspec, 125), 1000.0))
+    u = torch.zeros(ma.nglob, device="cuda")
     with pytest.raises(P.SemxError) as ei:
         P.semx_force_skeleton(s.ctx, u, torch.empty_like(u), 1)
     assert ei.value.code == P.SEMX_ESTATE
