@@ -257,7 +257,7 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
     """Learned surrogate on the 16^3 box: batched SEM data for the 64-mode
     lambda/mu perturbations, an ensemble of MLPs trained by the library's
     kernels, the spread indicator calibrated on validation models, SEM
-    fallback for flagged test models, SEM as the judge of every test model."""
+    fallback for flagged test models, SEM as the reference for every test model."""
     import numpy as np
     import torch
 

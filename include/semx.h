@@ -381,7 +381,7 @@ int semx_force_skeleton(semx_ctx *ctx, const float *u_dev, float *f_dev, int rep
 /* ---------------------------------------------------------------------------
  * Surrogate network: a multilayer perceptron that maps model parameters to
  * receiver seismograms, trained on SEM runs of this library (the SEM solve
- * stays the fallback and the judge of its error).  Layer l computes
+ * stays the fallback and the reference for its error).  Layer l computes
  * Z_l = H_l W_l^T + b_l with W_l [out][in]; hidden layers apply SiLU, the
  * last layer is linear.  GEMMs run on BF16 matrix cores with FP32
  * accumulation from a BF16 copy of FP32 master weights; losses and the

@@ -1,5 +1,5 @@
 """Learned surrogate for receiver seismograms, with the SEM solve as fallback
-and judge.
+and as the reference for its error.
 
 * Training data come from batched SEM runs of the library (many models
   sharing one mesh in one context, ``nmodels`` > 1).
