@@ -260,6 +260,21 @@ def test_force_skeleton():
         P.semx_force_skeleton(s.ctx, u, f, 1)
     assert ei.value.code == P.SEMX_ESTATE
     s.close()
+    # batched models (one grid row per model)
+    m2 = W.box_mesh((6, 5, 4), 5, 1000.0, jitter=0.1, seed=8)
+    models = [_hetero_model(m2, k) for k in (1, 2)]
+    s = make_solver(5)
+    s.upload_mesh(m2)
+    s.upload_model(*(np.stack([m[i] for m in models]) for i in range(3)))
+    u = torch.rand((2, m2.nglob, 3), device="cuda")
+    f = torch.empty_like(u)
+    P.semx_apply_force(s.ctx, u, f)
+    f0 = f.clone()
+    assert P.semx_force_skeleton(s.ctx, u, f, 3) > 0.0
+    P.semx_apply_force(s.ctx, u, f)
+    torch.cuda.synchronize()
+    assert torch.equal(f, f0)
+    s.close()
     # the column kernels (NGLL 11-16): skeleton on a jittered mesh, then the
     # operator is unchanged
     for n in (11, 16):
