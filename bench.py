@@ -48,17 +48,6 @@ def bytes_per_element(n: int, nglob: int, nspec: int, geometry: str = "stored") 
     return 4 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
 
 
-def bytes_per_element_patch(n: int, nglob: int, nspec: int, geometry: str, pinfo: dict) -> float:
-    """As bytes_per_element for the patch kernel: the 4 n^3 node numbers are
-    replaced by 2 n^3 patch-local indices, one position per element, two
-    offsets per patch and one 8-byte run descriptor per run of consecutive
-    node numbers."""
-    n3 = n ** 3
-    geo = {"stored": 36 * n3, "trilinear": 96, "regular": 36}[geometry]
-    meta = 4 * nspec + 8 * pinfo["npatch"] + 8 * pinfo["nruns"]
-    return 2 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec + meta / nspec
-
-
 def traffic_from_profiles(src_hash: str, key: str = "trilinear"):
     """HBM bytes per launch measured with rocprofv3 PMC counters (`key`: the
     force kernel's geometry path, or that path's skeleton with the suffix
@@ -723,8 +712,6 @@ def main():
                     help="fraction of the surrogate leg's model counts and epochs (quick checks)")
     ap.add_argument("--order-sweep", action="store_true",
                     help="also time the force apply for NGLL 4..9 at ~2e7 points (FP32 and mixed)")
-    ap.add_argument("--patches", type=int, default=0,
-                    help="chain length of the FP32 patch kernel (0 = per-element kernels)")
     ap.add_argument("--write-traffic", metavar="DIR",
                     help="no GPU: read the four rocprofv3 --pmc runs of --profile-force (DIR/pmc_<geometry>_"
                          "<counter>/run_counter_collection.csv) and write profiles/force_traffic.json")
@@ -772,7 +759,6 @@ def main():
     s.upload_model(wl.lam, wl.mu, wl.rho)
     asm = P.SEMX_ASM_COLORED if args.assembly == "colored" else P.SEMX_ASM_ATOMIC
     s.set_mode(P.SEMX_C_F32, asm)
-    P.semx_set_patches(s.ctx, args.patches)
     dt = P.semx_cfl_dt(s.ctx, 0.4)
     wl.dt = dt
     wl.stf = W.ricker(10.0, 0.12, dt, nt_total + 1)[None, :]
@@ -782,22 +768,17 @@ def main():
     E, n3 = mesh.nspec, NGLL ** 3
     geo_of = (lambda g: g if info["nirregular"] > 0 else "regular")
     b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry))
-    if args.patches:
-        P.semx_set_patches(s.ctx, args.patches)
-        b_elem = bytes_per_element_patch(NGLL, mesh.nglob, E, geo_of(args.geometry), P.semx_patch_info(s.ctx))
 
     # ---- force apply alone (FP32 and mixed contractions, coloured and atomic),
     #      event-timed on the library stream
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
-    combos = [(c, g, a, args.patches) for c in ("f32", "mf32", "bf16", "f16") for g in ("stored", "trilinear")
+    combos = [(c, g, a) for c in ("f32", "mf32", "bf16", "f16") for g in ("stored", "trilinear")
               for a in ("colored", "atomic") if c == "f32" or a == "colored"]
-    combos += [("f32", g, a, 8) for g in ("stored", "trilinear") for a in ("colored", "atomic")]
     if args.profile_force:
-        combos = [(args.contraction, args.geometry, args.assembly, args.patches)]
+        combos = [(args.contraction, args.geometry, args.assembly)]
     apply = {}
-    for cname, gname, aname, npt in combos:
-        P.semx_set_patches(s.ctx, npt)
+    for cname, gname, aname in combos:
         P.semx_set_geometry(s.ctx, GEOM[gname])
         P.semx_set_mode(s.ctx, CONTRACTION[cname], ASSEMBLY[aname])
         bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
@@ -810,13 +791,13 @@ def main():
         e1.record(stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / args.apply_reps
-        apply[f"{cname}_{gname}_{aname}" + (f"_patch{npt}" if npt else "")] = {
+        apply[f"{cname}_{gname}_{aname}"] = {
             "ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3), "bytes_per_element": bg,
             "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
     progress(f"force-apply matrix done ({len(apply)} variants)")
     if args.profile_force:
         sk = None
-        if args.contraction == "f32" and args.assembly == "colored" and not args.patches:
+        if args.contraction == "f32" and args.assembly == "colored":
             # the force pass's memory skeleton, for the same counters
             sk = round(P.semx_force_skeleton(s.ctx, u, f, args.apply_reps), 4)
         # calibration for the traffic counters: a plain device copy of known size
@@ -831,7 +812,6 @@ def main():
                           "force_launches_per_apply": info["ncolors"] if args.assembly == "colored" else 1}))
         s.close()
         return
-    P.semx_set_patches(s.ctx, args.patches)
     P.semx_set_mode(s.ctx, P.SEMX_C_F32, asm)
     P.semx_set_geometry(s.ctx, GEOM[args.geometry])
 
@@ -873,7 +853,7 @@ def main():
     # pass (same launches, grid, loads and stores, no arithmetic) on scratch
     # fields; the kernel cannot be faster than its skeleton
     skeleton = None
-    if not args.patches and args.assembly == "colored":
+    if args.assembly == "colored":
         uu = torch.zeros((mesh.nglob, 3), device="cuda")
         ff = torch.zeros_like(uu)
         sk_launch_ms = P.semx_force_skeleton(s.ctx, uu, ff, 20) / launches_per_apply
@@ -885,7 +865,7 @@ def main():
     src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
                    for f in ("force_f32.hip", "elem_common.hpp"))
     src_hash = hashlib.sha256(src).hexdigest()
-    traffic = traffic_from_profiles(src_hash, args.geometry) if not args.patches else None
+    traffic = traffic_from_profiles(src_hash, args.geometry)
     if skeleton is not None:
         skeleton["skeleton_traffic"] = traffic_from_profiles(src_hash, args.geometry + "_skeleton")
 
@@ -909,8 +889,7 @@ def main():
                    "nregular": info["nregular"], "nirregular": info["nirregular"], "ncolors": info["ncolors"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": (f"force_patch_kernel<5, {args.geometry}, {args.assembly}>, chains of {args.patches}"
-                                if args.patches else f"force_f32_kernel<5, {args.geometry}, {args.assembly}>"),
+                     "kernel": f"force_f32_kernel<5, {args.geometry}, {args.assembly}>",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
                      "launches": launches, "timed_pass_stride": stride, "bytes_per_element": b_elem,
                      "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4),

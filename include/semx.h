@@ -25,9 +25,8 @@
  *     A context is not thread-safe; use one context per host thread.
  *   - ngll = n = N+1 GLL points per direction, 2 <= n <= 16 (N = polynomial
  *     degree up to 15).  NGLL 11..16 run the FP32 operator, the time loop
- *     and the adjoint on column-per-lane kernels; FP64 storage and element
- *     patches support n <= 10 (SEMX_EINVAL above, patches are simply not
- *     built), the matrix-core contractions 4 <= n <= 8.  Element-local point q = i + n*(j + n*k), i fastest (i
+ *     and the adjoint on column-per-lane kernels; FP64 storage supports
+ *     n <= 10 (SEMX_EINVAL above), the matrix-core contractions 4 <= n <= 8.  Element-local point q = i + n*(j + n*k), i fastest (i
  *     along xi, j along eta, k along zeta).
  *   - Corner v = a + 2b + 4c of an 8-node hexahedron sits at reference
  *     coordinates (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the geometry is the
@@ -138,27 +137,6 @@ int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 #define SEMX_GEOM_STORED 0
 #define SEMX_GEOM_TRILINEAR 1
 int semx_set_geometry(semx_ctx *ctx, int mode);
-
-/* Element patches of the FP32 force (assembly of Sec. IV-C, done per group
- * of elements).  Elements are grouped, in element order, into chains of at
- * most max_elems elements (values above 8 act as 8) that share nodes and
- * hold at most 1024 unique nodes together; one workgroup computes a chain, sums the forces of its
- * shared nodes on chip and writes each of its nodes once.  Chains are
- * coloured so that chains of one colour share no node (coloured assembly:
- * one launch per colour, the first chain to reach a node stores it, later
- * ones add to it); with atomic assembly all chains run in one launch and
- * nodes shared between chains take atomic adds.  max_elems = 0 selects the
- * per-element kernels (the default).  Rebuilds the layout if a mesh is loaded
- * (NGLL up to 9; otherwise, or when the chains would need more than 64
- * colours, the per-element kernels are used).  The BF16/FP16 paths always
- * run per element.  SEMX_EINVAL if max_elems < 0. */
-int semx_set_patches(semx_ctx *ctx, int max_elems);
-
-/* Patch layout in use: number of chains, colours, runs of consecutive node
- * numbers, the summed unique-node count over chains, and the largest chain's
- * unique-node count.  All zero when the per-element kernels are in use. */
-int semx_patch_info(semx_ctx *ctx, int64_t *npatch, int *ncolors, int64_t *nruns, int64_t *nodes_total,
-                    int *max_nodes);
 
 /* f = -K u for every model: u_dev, f_dev device FP32 [nmodels][nglob][3].
  * f_dev is overwritten (not accumulated).  u_dev and f_dev must not overlap. */
@@ -306,8 +284,8 @@ int semx_set_state_f64(semx_ctx *ctx, const double *u_dev, const double *v_dev, 
  * c = sqrt(kappa/rho)).  semx_set_sources() ignores dir (it may be NULL):
  * a source adds stf[s][m] l_q(x_s) to the nodes of its element.  Both
  * assemblies, both geometry paths and NGLL 2..16 are supported; the
- * matrix-core contractions, FP64 storage, element patches and the adjoint
- * are elastic only (SEMX_EINVAL).
+ * matrix-core contractions, FP64 storage and the adjoint are elastic only
+ * (SEMX_EINVAL).
  * ------------------------------------------------------------------------- */
 #define SEMX_ELASTIC 0   /* vector displacement, isotropic elasticity (default) */
 #define SEMX_ACOUSTIC 1  /* scalar field, acoustic wave equation */
@@ -374,7 +352,7 @@ int semx_stream_bandwidth(semx_ctx *ctx, int64_t nbytes, int reps, double *gbps)
  *          values; must not overlap u_dev.
  * Errors: SEMX_ESTATE without mesh and model, or unless the context runs the
  * FP32 elastic per-element kernels (FP32 storage and contraction, coloured
- * assembly, patches off); SEMX_EINVAL for null pointers,
+ * assembly); SEMX_EINVAL for null pointers,
  * overlapping buffers or reps <= 0. */
 int semx_force_skeleton(semx_ctx *ctx, const float *u_dev, float *f_dev, int reps, double *ms_per_pass);
 

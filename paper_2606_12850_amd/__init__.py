@@ -77,9 +77,6 @@ _SIGS = {
     "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
     "semx_set_watchdog": [_vp, _i64, _f64],
     "semx_set_geometry": [_vp, _i32],
-    "semx_set_patches": [_vp, _i32],
-    "semx_patch_info": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
-                        ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
     "semx_set_checkpointing": [_vp, _i64],
     "semx_adjoint": [_vp, _vp, _i64, _vp, _vp, _vp],
     "semx_mlp_create": [ctypes.POINTER(_vp), _i32, _vp, _i32, _vp],
@@ -360,18 +357,6 @@ def semx_set_watchdog(ctx, interval: int, max_energy: float = 0.0):
 
 def semx_set_geometry(ctx, mode: int):
     return _check(ctx, lib().semx_set_geometry(ctx, int(mode)))
-
-
-def semx_set_patches(ctx, max_elems: int):
-    return _check(ctx, lib().semx_set_patches(ctx, int(max_elems)))
-
-
-def semx_patch_info(ctx):
-    np_, nc, nr, nt, mx = _i64(), _i32(), _i64(), _i64(), _i32()
-    _check(ctx, lib().semx_patch_info(ctx, ctypes.byref(np_), ctypes.byref(nc), ctypes.byref(nr),
-                                      ctypes.byref(nt), ctypes.byref(mx)))
-    return {"npatch": np_.value, "ncolors": nc.value, "nruns": nr.value, "nodes_total": nt.value,
-            "max_nodes": mx.value}
 
 
 def semx_set_checkpointing(ctx, every: int):

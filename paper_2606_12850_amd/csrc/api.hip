@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -476,230 +477,6 @@ bool coloring_valid(int n3, int64_t nspec, int64_t nglob, const int32_t* ibool, 
   return true;
 }
 
-// Element patches for the FP32 force kernel.  Chains are grown in element
-// order: an element joins the open chain when it has the same geometry kind,
-// shares at least one node with it, the chain is shorter than patch_cmax and
-// the union of nodes stays within kPatchMaxNodes.  Chains are coloured
-// greedily (first fit, chain order; two chains conflict when they share a
-// node) and laid out by (kind, colour, chain).  Each chain's sorted unique
-// nodes are stored as runs of consecutive global indices; a run is also cut
-// where the first-touch flag (first patch to touch the node in coloured
-// execution order: colour-major, regular before irregular) or the exclusive
-// flag (node touched by this patch only) changes.  Leaves patches_ok false
-// (per-element kernels) when the order, the colour count or the LDS budget
-// rules patches out.
-int build_patches(semx_ctx* c) {
-  for (DevBuf* b : {&c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs}) dev_free(*b);
-  c->patch_colored.clear();
-  c->patch_atomic.clear();
-  c->patches_ok = false;
-  c->patch_cover = false;
-  c->npatch = c->npatch_runs = c->patch_nodes_total = 0;
-  c->patch_maxnodes = c->patch_maxruns = c->npatch_colors = 0;
-  const int n3 = c->n3;
-  const int64_t E = c->nspec, G = c->nglob;
-  if (c->patch_cmax <= 0 || n3 > kPatchMaxNodes || patch_lds_bytes(c->n, n3, 1) > (size_t)kPatchLdsLimit)
-    return SEMX_OK;
-  const int32_t* ib = c->h_ibool.data();
-
-  // 1. chains
-  std::vector<int32_t> celem;
-  celem.reserve(E);
-  std::vector<int64_t> cptr{0};
-  std::vector<int32_t> mark(G, -1), emark(G, -1);
-  int64_t cur_nodes = 0;
-  int cur_kind = -1;
-  for (int64_t e = 0; e < E; ++e) {
-    const int kind = c->h_regular[e] ? 0 : 1;
-    const int32_t cid = (int32_t)(cptr.size() - 1);
-    const int64_t len = (int64_t)celem.size() - cptr.back();
-    int shared = 0, add = 0;
-    for (int q = 0; q < n3; ++q) {
-      const int32_t g = ib[e * n3 + q];
-      if (mark[g] == cid) ++shared;
-      else if (emark[g] != (int32_t)e) { emark[g] = (int32_t)e; ++add; }
-    }
-    const bool join = len > 0 && kind == cur_kind && len < std::min(c->patch_cmax, kPatchMaxElems) && shared > 0 &&
-                      cur_nodes + add <= kPatchMaxNodes;
-    if (!join) {
-      if (len > 0) cptr.push_back((int64_t)celem.size());
-      cur_nodes = 0;
-      cur_kind = kind;
-      add = 0;
-      const int32_t nid = (int32_t)(cptr.size() - 1);
-      for (int q = 0; q < n3; ++q) {
-        const int32_t g = ib[e * n3 + q];
-        if (mark[g] != nid) { mark[g] = nid; ++add; }
-      }
-    } else {
-      for (int q = 0; q < n3; ++q) mark[ib[e * n3 + q]] = cid;
-    }
-    cur_nodes += add;
-    celem.push_back((int32_t)e);
-  }
-  cptr.push_back((int64_t)celem.size());
-  const int64_t P = (int64_t)cptr.size() - 1;
-
-  // 2. sorted unique nodes per chain
-  std::vector<int64_t> nptr(P + 1, 0);
-  std::vector<int32_t> pnodes;
-  pnodes.reserve((size_t)E * n3);
-  std::fill(mark.begin(), mark.end(), -1);
-  for (int64_t p = 0; p < P; ++p) {
-    const size_t b = pnodes.size();
-    for (int64_t t = cptr[p]; t < cptr[p + 1]; ++t)
-      for (int q = 0; q < n3; ++q) {
-        const int32_t g = ib[(int64_t)celem[t] * n3 + q];
-        if (mark[g] != (int32_t)p) { mark[g] = (int32_t)p; pnodes.push_back(g); }
-      }
-    std::sort(pnodes.begin() + b, pnodes.end());
-    nptr[p + 1] = (int64_t)pnodes.size();
-  }
-
-  // 3. greedy colouring of chains (at most 64 colours)
-  std::vector<uint64_t> cmask(G, 0);
-  std::vector<int> pcol(P);
-  int ncol = 0;
-  for (int64_t p = 0; p < P; ++p) {
-    uint64_t forb = 0;
-    for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) forb |= cmask[pnodes[t]];
-    if (forb == ~0ull) return SEMX_OK;  // too many colours: per-element kernels
-    int col = 0;
-    while (forb & (1ull << col)) ++col;
-    pcol[p] = col;
-    ncol = std::max(ncol, col + 1);
-    for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) cmask[pnodes[t]] |= 1ull << col;
-  }
-  std::vector<uint64_t>().swap(cmask);
-
-  // 4. layout order (kind, colour, chain); launches
-  auto kind_of = [&](int64_t p) { return c->h_regular[celem[cptr[p]]] ? 0 : 1; };
-  std::vector<int64_t> porder(P);
-  for (int64_t p = 0; p < P; ++p) porder[p] = p;
-  std::stable_sort(porder.begin(), porder.end(), [&](int64_t x, int64_t y) {
-    const int kx = kind_of(x), ky = kind_of(y);
-    if (kx != ky) return kx < ky;
-    return pcol[x] < pcol[y];
-  });
-  struct Rng { int64_t beg = 0, cnt = 0; };
-  std::vector<Rng> rng(2 * (size_t)ncol);
-  for (int64_t s = 0; s < P; ++s) {
-    Rng& r = rng[(size_t)kind_of(porder[s]) * ncol + pcol[porder[s]]];
-    if (r.cnt == 0) r.beg = s;
-    ++r.cnt;
-  }
-  for (int k = 0; k < ncol; ++k)
-    for (int kind = 0; kind < 2; ++kind) {
-      const Rng& r = rng[(size_t)kind * ncol + k];
-      if (r.cnt) c->patch_colored.push_back({r.beg, r.cnt, kind == 1});
-    }
-  for (int kind = 0; kind < 2; ++kind) {
-    int64_t beg = -1, end = -1;
-    for (int k = 0; k < ncol; ++k) {
-      const Rng& r = rng[(size_t)kind * ncol + k];
-      if (!r.cnt) continue;
-      if (beg < 0) beg = r.beg;
-      end = r.beg + r.cnt;
-    }
-    if (beg >= 0) c->patch_atomic.push_back({beg, end - beg, kind == 1});
-  }
-
-  // 5. first-touch (coloured execution order) and exclusive flags per patch node
-  std::vector<uint8_t> touch(G, 0), pflag(pnodes.size(), 0);
-  for (const Launch& L : c->patch_colored)
-    for (int64_t s = L.pos0; s < L.pos0 + L.count; ++s) {
-      const int64_t p = porder[s];
-      for (int64_t t = nptr[p]; t < nptr[p + 1]; ++t) {
-        uint8_t& tc = touch[pnodes[t]];
-        if (tc == 0) pflag[t] = 1;
-        if (tc < 2) ++tc;
-      }
-    }
-  bool cover = true;
-  for (int64_t g = 0; g < G && cover; ++g) cover = touch[g] > 0;
-
-  // 6. device arrays in layout order
-  std::vector<int32_t> pos_of(E);
-  for (int64_t pos = 0; pos < E; ++pos) pos_of[c->h_order[pos]] = (int32_t)pos;
-  std::vector<int32_t> pe_pos(E), pe_off(P + 1), pr_off(P + 1), runs;
-  std::vector<uint16_t> lidx((size_t)E * n3);
-  std::vector<int32_t> loc(G, -1);
-  int64_t slot = 0;
-  int maxnodes = 0, maxruns = 0;
-  for (int64_t s = 0; s < P; ++s) {
-    const int64_t p = porder[s];
-    pe_off[s] = (int32_t)slot;
-    pr_off[s] = (int32_t)(runs.size() / 2);
-    const int64_t nb = nptr[p], nn = nptr[p + 1] - nb;
-    maxnodes = std::max(maxnodes, (int)nn);
-    for (int64_t t = 0; t < nn; ++t) loc[pnodes[nb + t]] = (int32_t)t;
-    for (int64_t t = cptr[p]; t < cptr[p + 1]; ++t, ++slot) {
-      const int64_t e = celem[t];
-      pe_pos[slot] = pos_of[e];
-      for (int q = 0; q < n3; ++q) lidx[(size_t)slot * n3 + q] = (uint16_t)loc[ib[e * n3 + q]];
-    }
-    int nr = 0;
-    int64_t t = 0;
-    while (t < nn) {
-      const int32_t g0 = pnodes[nb + t];
-      const int fl = (pflag[nb + t] ? kRunFirst : 0) | (touch[g0] == 1 ? kRunExclusive : 0);
-      int64_t l = 1;
-      while (t + l < nn && l < (1 << kRunLenBits) - 1 && pnodes[nb + t + l] == g0 + l &&
-             ((pflag[nb + t + l] ? kRunFirst : 0) | (touch[g0 + l] == 1 ? kRunExclusive : 0)) == fl)
-        ++l;
-      runs.push_back(g0);
-      runs.push_back((int32_t)l | ((int32_t)t << kRunLenBits) | fl);
-      ++nr;
-      t += l;
-    }
-    maxruns = std::max(maxruns, nr);
-  }
-  pe_off[P] = (int32_t)slot;
-  pr_off[P] = (int32_t)(runs.size() / 2);
-  // invariants the kernel's addressing relies on
-  if (slot != E) return fail(c, SEMX_EINVAL, "patch layout: element count");
-  for (int64_t s = 0; s < P; ++s) {
-    const int64_t rb = pr_off[s], re = pr_off[s + 1];
-    if (pe_off[s + 1] <= pe_off[s] || re <= rb) return fail(c, SEMX_EINVAL, "patch layout: empty patch");
-    int64_t off = 0;
-    for (int64_t r = rb; r < re; ++r) {
-      const int32_t d = runs[2 * r + 1];
-      const int64_t len = d & ((1 << kRunLenBits) - 1), o = (d >> kRunLenBits) & ((1 << kRunLenBits) - 1);
-      if (len < 1 || o != off || runs[2 * r] < 0 || runs[2 * r] + len > G)
-        return fail(c, SEMX_EINVAL, "patch layout: bad run");
-      off += len;
-    }
-    if (off > maxnodes || off > kPatchMaxNodes) return fail(c, SEMX_EINVAL, "patch layout: node count");
-    for (int64_t t = (int64_t)pe_off[s] * n3; t < (int64_t)pe_off[s + 1] * n3; ++t)
-      if (lidx[t] >= off) return fail(c, SEMX_EINVAL, "patch layout: local index");
-  }
-  if (patch_lds_bytes(c->n, maxnodes, maxruns) > (size_t)kPatchLdsLimit) {
-    c->patch_colored.clear();
-    c->patch_atomic.clear();
-    return SEMX_OK;
-  }
-  int rc = dev_alloc(c, c->d_pe_pos, sizeof(int32_t) * E);
-  if (!rc) rc = dev_alloc(c, c->d_pe_off, sizeof(int32_t) * (P + 1));
-  if (!rc) rc = dev_alloc(c, c->d_lidx, sizeof(uint16_t) * E * n3);
-  if (!rc) rc = dev_alloc(c, c->d_pr_off, sizeof(int32_t) * (P + 1));
-  if (!rc) rc = dev_alloc(c, c->d_runs, sizeof(int32_t) * runs.size());
-  if (rc) return rc;
-  SEMX_HIP(c, hipMemcpy(c->d_pe_pos.p, pe_pos.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->d_pe_off.p, pe_off.data(), sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->d_lidx.p, lidx.data(), sizeof(uint16_t) * E * n3, hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->d_pr_off.p, pr_off.data(), sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice));
-  SEMX_HIP(c, hipMemcpy(c->d_runs.p, runs.data(), sizeof(int32_t) * runs.size(), hipMemcpyHostToDevice));
-  c->npatch = P;
-  c->npatch_runs = (int64_t)runs.size() / 2;
-  c->patch_nodes_total = (int64_t)pnodes.size();
-  c->patch_maxnodes = maxnodes;
-  c->patch_maxruns = maxruns;
-  c->npatch_colors = ncol;
-  c->patch_cover = cover;
-  c->patches_ok = true;
-  return SEMX_OK;
-}
-
 // Launch-ordered layout: every per-element array on the device is stored by
 // launch position, positions sorted by (geometry kind, colour, element), so
 // that each launch (one colour of one kind, or one kind for atomic assembly)
@@ -710,14 +487,33 @@ int build_layout(semx_ctx* c) {
   const int64_t nspec = c->nspec;
   std::vector<int32_t> order;
   order.reserve(nspec);
-  struct Range { int64_t beg, cnt; bool irr; int color; };
+  struct Range { int64_t beg, cnt; bool irr; int color; int64_t naff; };
+  // affine numbering: ibool(e, i, j, k) = g0 + i sx + j sy + k sz at every point
+  // (a lattice numbering); aff[e] = {g0, sx, sy, sz}, g0 = -1 if not affine
+  const int n = c->n;
+  std::vector<std::array<int32_t, 4>> aff(nspec);
+  for (int64_t e = 0; e < nspec; ++e) {
+    const int32_t* ie = &c->h_ibool[e * n3];
+    const int64_t g0 = ie[0];
+    const int64_t sx = n > 1 ? (int64_t)ie[1] - g0 : 0, sy = n > 1 ? (int64_t)ie[n] - g0 : 0,
+                  sz = n > 1 ? (int64_t)ie[n * n] - g0 : 0;
+    bool ok = true;
+    for (int k = 0; k < n && ok; ++k)
+      for (int j = 0; j < n && ok; ++j)
+        for (int i = 0; i < n && ok; ++i) ok = ie[i + n * (j + n * k)] == g0 + i * sx + j * sy + k * sz;
+#ifdef SEMX_NO_AFFINE_NUMBERING
+    ok = false;
+#endif
+    aff[e] = ok ? std::array<int32_t, 4>{(int32_t)g0, (int32_t)sx, (int32_t)sy, (int32_t)sz}
+                : std::array<int32_t, 4>{-1, 0, 0, 0};
+  }
   std::vector<Range> col;
   const int nc = c->ncolors > 0 ? c->ncolors : 1;
   std::vector<int64_t> kind_beg(3, 0);
   for (int irr = 0; irr < 2; ++irr) {
     kind_beg[irr] = (int64_t)order.size();
     for (int k = 0; k < nc; ++k) {
-      Range r{(int64_t)order.size(), 0, irr == 1, k};
+      Range r{(int64_t)order.size(), 0, irr == 1, k, 0};
       if (c->ncolors > 0) {
         for (int32_t t = c->color_ptr[k]; t < c->color_ptr[k + 1]; ++t) {
           const int32_t e = c->elem_order[t];
@@ -728,6 +524,11 @@ int build_layout(semx_ctx* c) {
           if ((c->h_regular[e] == 0) == (irr == 1)) order.push_back((int32_t)e);
       }
       r.cnt = (int64_t)order.size() - r.beg;
+      // elements with an affine numbering first (stable): the FP32 force
+      // kernel computes their node numbers instead of streaming them
+      auto mid = std::stable_partition(order.begin() + r.beg, order.end(),
+                                       [&](int32_t e) { return aff[e][0] >= 0; });
+      r.naff = mid - (order.begin() + r.beg);
       if (r.cnt) col.push_back(r);
     }
   }
@@ -738,12 +539,14 @@ int build_layout(semx_ctx* c) {
   // coloured: colour-major execution order, regular before irregular in a colour
   for (int k = 0; k < nc; ++k)
     for (const auto& r : col)
-      if (r.color == k) c->colored_launches.push_back({r.beg, r.cnt, r.irr});
+      if (r.color == k) c->colored_launches.push_back({r.beg, r.cnt, r.irr, r.naff});
+  // atomic: one launch per kind; its affine elements are not contiguous, so
+  // the whole range takes the node-number stream
   for (int irr = 0; irr < 2; ++irr)
     if (kind_beg[irr + 1] > kind_beg[irr])
-      c->atomic_launches.push_back({kind_beg[irr], kind_beg[irr + 1] - kind_beg[irr], irr == 1});
+      c->atomic_launches.push_back({kind_beg[irr], kind_beg[irr + 1] - kind_beg[irr], irr == 1, 0});
 
-  std::vector<int32_t> ib((size_t)nspec * n3);
+  std::vector<int32_t> ib((size_t)nspec * n3), affpos((size_t)nspec * 4);
   std::vector<float> gel((size_t)nspec * 9);
   // trilinear map x_a = sum_m c_m[a] b_m(r) with monomials
   // b = (1, rx, ry, rz, rx ry, rx rz, ry rz, rx ry rz); c_m[a] = 1/8 sum_v x_v[a] b_m(s_v)
@@ -751,6 +554,7 @@ int build_layout(semx_ctx* c) {
   for (int64_t pos = 0; pos < nspec; ++pos) {
     const int64_t e = order[pos];
     std::memcpy(&ib[pos * n3], &c->h_ibool[e * n3], sizeof(int32_t) * n3);
+    std::memcpy(&affpos[pos * 4], aff[e].data(), sizeof(int32_t) * 4);
     std::memcpy(&gel[pos * 9], &c->h_gam_el[e * 9], sizeof(float) * 9);
     double cm[3][8] = {{0}};
     for (int v = 0; v < 8; ++v) {
@@ -788,6 +592,7 @@ int build_layout(semx_ctx* c) {
   if (!rc && !first.empty()) rc = dev_alloc(c, c->d_first, sizeof(uint32_t) * first.size());
   if (!rc && first.empty()) dev_free(c->d_first);
   if (!rc) rc = dev_alloc(c, c->d_ibool, sizeof(int32_t) * nspec * n3);
+  if (!rc) rc = dev_alloc(c, c->d_aff, sizeof(int32_t) * 4 * nspec);
   if (!rc) rc = dev_alloc(c, c->d_gam_el, sizeof(float) * 9 * nspec);
   if (!rc) rc = dev_alloc(c, c->d_tri, sizeof(float) * 24 * nspec);
   if (!rc) rc = dev_alloc(c, c->d_wdet, sizeof(double) * nspec * n3);
@@ -796,6 +601,7 @@ int build_layout(semx_ctx* c) {
   if (rc) return rc;
   SEMX_HIP(c, hipMemcpy(c->d_order.p, order.data(), sizeof(int32_t) * nspec, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_ibool.p, ib.data(), sizeof(int32_t) * nspec * n3, hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->d_aff.p, affpos.data(), sizeof(int32_t) * 4 * nspec, hipMemcpyHostToDevice));
   if (!first.empty())
     SEMX_HIP(c, hipMemcpy(c->d_first.p, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gel.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
@@ -811,7 +617,7 @@ int build_layout(semx_ctx* c) {
   SEMX_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   SEMX_HIP(c, hipStreamSynchronize(c->stream));
   if (hbad) return fail(c, SEMX_EGEOM, "upload_mesh: det J <= 0 at some GLL point");
-  return build_patches(c);
+  return SEMX_OK;
 }
 
 // Start of a timed force pass: record the opening event of a pair from the
@@ -836,6 +642,7 @@ hipError_t time_pass_begin(semx_ctx* c, hipEvent_t* e1) {
 ForceArgs force_args(const semx_ctx* c, const float* u, float* f, bool first_touch) {
   ForceArgs a{};
   a.ibool = c->d_ibool.as<int32_t>();
+  a.aff = c->d_aff.as<int32_t>();
   a.gam_pt = c->d_gam_pt.as<float>();
   a.gam_el = c->d_gam_el.as<float>();
   a.tri = c->d_tri.as<float>();
@@ -871,9 +678,10 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, a, c->stream);
+    else if (c->contraction == SEMX_C_F32 && c->n > kMaxNLow)
+      e = launch_force_high(c->n, geo, atomic, a, c->stream);
     else if (c->contraction == SEMX_C_F32)
-      e = c->n > kMaxNLow ? launch_force_high(c->n, geo, atomic, a, c->stream)
-                          : launch_force_f32(c->n, geo, atomic, a, c->stream);
+      e = launch_force_f32_split(c->n, geo, atomic, L.naff, a, c->stream);
     else
       e = launch_force_mfma(c->n, c->contraction, geo, atomic, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
@@ -908,56 +716,11 @@ int alloc_seismograms(semx_ctx* c) {
   return zero_f32(c, c->rec.seis.as<float>(), cnt);
 }
 
-// The FP32 force runs on element patches when they are built.
-bool use_patches(const semx_ctx* c) {
-  return c->patches_ok && c->contraction == SEMX_C_F32 && c->physics == SEMX_ELASTIC;
-}
-
-// True when the force pass writes every node itself (coloured patches with
-// first-touch stores over a mesh whose nodes all belong to some element), so
-// f needs no clearing before it.
+// True when the force pass writes every node itself (coloured per-element
+// passes with first-touch stores over a mesh whose nodes all belong to some
+// element), so f needs no clearing before it.
 bool force_overwrites(const semx_ctx* c) {
-  if (c->assembly != SEMX_ASM_COLORED) return false;
-  return use_patches(c) ? c->patch_cover : (c->elem_cover && c->d_first.p != nullptr);
-}
-
-int force_patches(semx_ctx* c, const float* u, float* f) {
-  PatchArgs pa{};
-  ForceArgs& a = pa.fa;
-  a.gam_pt = c->d_gam_pt.as<float>();
-  a.gam_el = c->d_gam_el.as<float>();
-  a.tri = c->d_tri.as<float>();
-  a.xi = c->d_xi32.as<float>();
-  a.mat = c->d_mat.as<float>();
-  a.u = u;
-  a.f = f;
-  a.D = c->d_D.as<float>();
-  a.nspec = c->nspec;
-  a.nglob = c->nglob;
-  a.nmodels = c->nmodels;
-  pa.pe_pos = c->d_pe_pos.as<int32_t>();
-  pa.pe_off = c->d_pe_off.as<int32_t>();
-  pa.lidx = c->d_lidx.as<uint16_t>();
-  pa.pr_off = c->d_pr_off.as<int32_t>();
-  pa.runs = c->d_runs.as<int32_t>();
-  pa.maxnodes = c->patch_maxnodes;
-  pa.maxruns = c->patch_maxruns;
-  const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
-  const auto& plaunches = atomic ? c->patch_atomic : c->patch_colored;
-  hipEvent_t e1 = nullptr;
-  if (!plaunches.empty() && c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0) {
-    SEMX_HIP(c, time_pass_begin(c, &e1));
-    c->timed_launches += (int64_t)plaunches.size();
-  }
-  for (const auto& L : plaunches) {
-    a.pos0 = L.pos0;
-    a.count = L.count;
-    const int geo = L.irregular ? c->irregular_geo : kRegular;
-    hipError_t e = launch_force_patch(c->n, geo, atomic, pa, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "patch force kernel launch");
-  }
-  if (e1) SEMX_HIP(c, hipEventRecord(e1, c->stream));
-  return SEMX_OK;
+  return c->assembly == SEMX_ASM_COLORED && c->elem_cover && c->d_first.p != nullptr;
 }
 
 // f = -K u.  `f_zeroed`: f already holds zeros.
@@ -966,7 +729,7 @@ int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
     int rc = zero_f32(c, f, state_len(c));
     if (rc) return rc;
   }
-  return use_patches(c) ? force_patches(c, u, f) : force_accumulate(c, u, f, force_overwrites(c));
+  return force_accumulate(c, u, f, force_overwrites(c));
 }
 
 
@@ -1234,7 +997,7 @@ int semx_destroy(semx_ctx* c) {
                     &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis,
                     &c->src.wdir64, &c->src.stf64, &c->rec.wts64, &c->rec.seis64, &c->d_gam64, &c->d_mat64,
                     &c->d_minv64, &c->d_D64,
-                    &c->d_pe_pos, &c->d_pe_off, &c->d_lidx, &c->d_pr_off, &c->d_runs, &c->d_first})
+                    &c->d_first, &c->d_aff})
     dev_free(*b);
   delete c;
   return SEMX_OK;
@@ -1599,7 +1362,7 @@ int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps,
   if (!c || !ms_per_pass) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "force_skeleton: mesh and model required");
   if (c->storage != SEMX_F32 || c->physics != SEMX_ELASTIC || c->contraction != SEMX_C_F32 ||
-      c->assembly != SEMX_ASM_COLORED || use_patches(c))
+      c->assembly != SEMX_ASM_COLORED)
     return fail(c, SEMX_ESTATE, "force_skeleton: covers the FP32 elastic per-element kernels with coloured assembly");
   if (!u_dev || !f_dev || reps <= 0) return fail(c, SEMX_EINVAL, "force_skeleton: null pointer or reps <= 0");
   const int64_t len = state_len(c);
@@ -1611,7 +1374,7 @@ int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps,
       a.count = L.count;
       const int geo = L.irregular ? c->irregular_geo : kRegular;
       const hipError_t e = c->n > kMaxNLow ? launch_force_high_skeleton(c->n, geo, a, c->stream)
-                                           : launch_force_skeleton(c->n, geo, a, c->stream);
+                                           : launch_force_skeleton(c->n, geo, L.naff, a, c->stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1859,26 +1622,6 @@ int semx_set_geometry(semx_ctx* c, int mode) {
   if (mode == SEMX_GEOM_STORED) c->irregular_geo = kStored;
   else if (mode == SEMX_GEOM_TRILINEAR) c->irregular_geo = kTrilinear;
   else return fail(c, SEMX_EINVAL, "set_geometry: unknown mode");
-  return SEMX_OK;
-}
-
-int semx_set_patches(semx_ctx* c, int max_elems) {
-  if (!c) return SEMX_EINVAL;
-  if (max_elems < 0) return fail(c, SEMX_EINVAL, "set_patches: max_elems must be >= 0");
-  c->patch_cmax = max_elems;
-  if (!c->have_mesh) return SEMX_OK;
-  SEMX_HIP(c, hipStreamSynchronize(c->stream));
-  return build_patches(c);
-}
-
-int semx_patch_info(semx_ctx* c, int64_t* npatch, int* ncolors, int64_t* nruns, int64_t* nodes_total,
-                    int* max_nodes) {
-  if (!c || !npatch || !ncolors || !nruns || !nodes_total || !max_nodes) return SEMX_EINVAL;
-  *npatch = c->patches_ok ? c->npatch : 0;
-  *ncolors = c->patches_ok ? c->npatch_colors : 0;
-  *nruns = c->patches_ok ? c->npatch_runs : 0;
-  *nodes_total = c->patches_ok ? c->patch_nodes_total : 0;
-  *max_nodes = c->patches_ok ? c->patch_maxnodes : 0;
   return SEMX_OK;
 }
 

@@ -74,7 +74,21 @@ __device__ __forceinline__ void load_point(const ForceArgs& a, const float* __re
 // computes.  Straight-line code (no loop) lets the compiler count outstanding
 // memory operations exactly, so waits for prefetched data never wait for the
 // scatter stores issued after them.
-template <int NG, int GEO, bool ATOMIC, int R>
+// Node number of local point (i, j, k) of the element at launch position
+// `pos`: from the ibool stream, or (AFF) from the element's affine numbering
+// g0 + i sx + j sy + k sz (four scalar loads per element, no per-point stream
+// and no dependent round trip before the gather).
+template <int NG, bool AFF>
+__device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp, int i, int j, int k) {
+  if constexpr (AFF) {
+    const int* r = a.aff + (size_t)pos * 4;
+    return r[0] + i * r[1] + j * r[2] + k * r[3];
+  } else {
+    return ldnt(a.ibool + (size_t)pos * Shape<NG>::N3 + pp);
+  }
+}
+
+template <int NG, int GEO, bool ATOMIC, int R, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
   __shared__ float s_u[3 * N3];
@@ -99,8 +113,8 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
 
   PointIn P[2];
-  int g_next = (nr > 1) ? ldnt(a.ibool + (size_t)(P0 + 1) * N3 + pp) : 0;
-  load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0, pp, ldnt(a.ibool + (size_t)P0 * N3 + pp), P[0]);
+  int g_next = (nr > 1) ? node_of<NG, AFF>(a, P0 + 1, pp, i, j, k) : 0;
+  load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0, pp, node_of<NG, AFF>(a, P0, pp, i, j, k), P[0]);
 
   // D in LDS: the lane's rows and columns are read per contraction step,
   // which keeps the register count low enough for 8 waves per SIMD.
@@ -125,7 +139,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     }
     if (m + 1 < nr) {
       load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0 + m + 1, pp, g_next, nxt);
-      if (m + 2 < nr) g_next = ldnt(a.ibool + (size_t)(P0 + m + 2) * N3 + pp);
+      if (m + 2 < nr) g_next = node_of<NG, AFF>(a, P0 + m + 2, pp, i, j, k);
     }
     __syncthreads();
 
@@ -159,26 +173,26 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
 #define SEMX_F32_ELEMS_PER_BLOCK 1
 #endif
 
-template <int NG, int GEO, bool ATOMIC>
+template <int NG, int GEO, bool ATOMIC, bool AFF>
 hipError_t launch_one(const ForceArgs& a, hipStream_t s) {
   constexpr int R = SEMX_F32_ELEMS_PER_BLOCK;
   const int64_t ngrp = (a.count + R - 1) / R;
   const int64_t nb = ((ngrp + kNumXcd - 1) / kNumXcd) * kNumXcd;
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
-  force_f32_kernel<NG, GEO, ATOMIC, R><<<grid, block, 0, s>>>(a);
+  force_f32_kernel<NG, GEO, ATOMIC, R, AFF><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <int NG>
+template <int NG, bool AFF>
 hipError_t launch_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   switch (geo) {
     case kRegular:
-      return atomic ? launch_one<NG, kRegular, true>(a, s) : launch_one<NG, kRegular, false>(a, s);
+      return atomic ? launch_one<NG, kRegular, true, AFF>(a, s) : launch_one<NG, kRegular, false, AFF>(a, s);
     case kStored:
-      return atomic ? launch_one<NG, kStored, true>(a, s) : launch_one<NG, kStored, false>(a, s);
+      return atomic ? launch_one<NG, kStored, true, AFF>(a, s) : launch_one<NG, kStored, false, AFF>(a, s);
     case kTrilinear:
-      return atomic ? launch_one<NG, kTrilinear, true>(a, s) : launch_one<NG, kTrilinear, false>(a, s);
+      return atomic ? launch_one<NG, kTrilinear, true, AFF>(a, s) : launch_one<NG, kTrilinear, false, AFF>(a, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -190,7 +204,7 @@ hipError_t launch_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
 // f store), without the contractions and the pointwise arithmetic.  Its
 // duration is the floor that the kernel's access pattern alone sets on the
 // memory system.  f receives meaningless values.
-template <int NG, int GEO>
+template <int NG, int GEO, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
   const int ngrp = (int)a.count;
@@ -204,7 +218,8 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArg
   float* f = a.f + (size_t)model * a.nglob * 3;
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
   PointIn P;
-  load_point<NG, GEO, false>(a, mat, u, f, pos, p, ldnt(a.ibool + (size_t)pos * N3 + p), P);
+  load_point<NG, GEO, false>(a, mat, u, f, pos, p, node_of<NG, AFF>(a, pos, p, p % NG, (p / NG) % NG, p / (NG * NG)),
+                             P);
   float s = P.lw + P.mw;
   if constexpr (GEO == kStored) {
 #pragma unroll
@@ -221,51 +236,84 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArg
   fg[2] = P.f[2] + s * P.u[2];
 }
 
-template <int NG>
+template <int NG, bool AFF>
 hipError_t launch_skeleton_n(int geo, const ForceArgs& a, hipStream_t s) {
   static_assert(SEMX_F32_ELEMS_PER_BLOCK == 1, "the skeleton mirrors one element per workgroup");
   if (a.count <= 0) return hipSuccess;
   const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
   switch (geo) {
-    case kRegular: force_skeleton_kernel<NG, kRegular><<<grid, block, 0, s>>>(a); break;
-    case kStored: force_skeleton_kernel<NG, kStored><<<grid, block, 0, s>>>(a); break;
-    case kTrilinear: force_skeleton_kernel<NG, kTrilinear><<<grid, block, 0, s>>>(a); break;
+    case kRegular: force_skeleton_kernel<NG, kRegular, AFF><<<grid, block, 0, s>>>(a); break;
+    case kStored: force_skeleton_kernel<NG, kStored, AFF><<<grid, block, 0, s>>>(a); break;
+    case kTrilinear: force_skeleton_kernel<NG, kTrilinear, AFF><<<grid, block, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-}  // namespace
+// A launch range whose first `naff` elements are affine-numbered: two launches.
+template <class F>
+hipError_t split_affine(int64_t naff, const ForceArgs& a, F launch) {
+  naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
+  ForceArgs b = a;
+  b.count = naff;
+  hipError_t e = naff > 0 ? launch(b, true) : hipSuccess;
+  if (e != hipSuccess || naff == a.count) return e;
+  b.pos0 = a.pos0 + naff;
+  b.count = a.count - naff;
+  return launch(b, false);
+}
 
-hipError_t launch_force_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s) {
+template <int NG>
+hipError_t launch_f32_any(int geo, bool atomic, bool aff, const ForceArgs& a, hipStream_t s) {
+  return aff ? launch_n<NG, true>(geo, atomic, a, s) : launch_n<NG, false>(geo, atomic, a, s);
+}
+
+template <int NG>
+hipError_t launch_skeleton_any(int geo, bool aff, const ForceArgs& a, hipStream_t s) {
+  return aff ? launch_skeleton_n<NG, true>(geo, a, s) : launch_skeleton_n<NG, false>(geo, a, s);
+}
+
+hipError_t launch_f32_n(int n, int geo, bool atomic, bool aff, const ForceArgs& a, hipStream_t s) {
   switch (n) {
-    case 2: return launch_skeleton_n<2>(geo, a, s);
-    case 3: return launch_skeleton_n<3>(geo, a, s);
-    case 4: return launch_skeleton_n<4>(geo, a, s);
-    case 5: return launch_skeleton_n<5>(geo, a, s);
-    case 6: return launch_skeleton_n<6>(geo, a, s);
-    case 7: return launch_skeleton_n<7>(geo, a, s);
-    case 8: return launch_skeleton_n<8>(geo, a, s);
-    case 9: return launch_skeleton_n<9>(geo, a, s);
-    case 10: return launch_skeleton_n<10>(geo, a, s);
+    case 2: return launch_f32_any<2>(geo, atomic, aff, a, s);
+    case 3: return launch_f32_any<3>(geo, atomic, aff, a, s);
+    case 4: return launch_f32_any<4>(geo, atomic, aff, a, s);
+    case 5: return launch_f32_any<5>(geo, atomic, aff, a, s);
+    case 6: return launch_f32_any<6>(geo, atomic, aff, a, s);
+    case 7: return launch_f32_any<7>(geo, atomic, aff, a, s);
+    case 8: return launch_f32_any<8>(geo, atomic, aff, a, s);
+    case 9: return launch_f32_any<9>(geo, atomic, aff, a, s);
+    case 10: return launch_f32_any<10>(geo, atomic, aff, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+}  // namespace
+
+hipError_t launch_force_skeleton(int n, int geo, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  return split_affine(naff, a, [&](const ForceArgs& b, bool aff) -> hipError_t {
+    switch (n) {
+      case 2: return launch_skeleton_any<2>(geo, aff, b, s);
+      case 3: return launch_skeleton_any<3>(geo, aff, b, s);
+      case 4: return launch_skeleton_any<4>(geo, aff, b, s);
+      case 5: return launch_skeleton_any<5>(geo, aff, b, s);
+      case 6: return launch_skeleton_any<6>(geo, aff, b, s);
+      case 7: return launch_skeleton_any<7>(geo, aff, b, s);
+      case 8: return launch_skeleton_any<8>(geo, aff, b, s);
+      case 9: return launch_skeleton_any<9>(geo, aff, b, s);
+      case 10: return launch_skeleton_any<10>(geo, aff, b, s);
+      default: return hipErrorInvalidValue;
+    }
+  });
+}
+
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
-  switch (n) {
-    case 2: return launch_n<2>(geo, atomic, a, s);
-    case 3: return launch_n<3>(geo, atomic, a, s);
-    case 4: return launch_n<4>(geo, atomic, a, s);
-    case 5: return launch_n<5>(geo, atomic, a, s);
-    case 6: return launch_n<6>(geo, atomic, a, s);
-    case 7: return launch_n<7>(geo, atomic, a, s);
-    case 8: return launch_n<8>(geo, atomic, a, s);
-    case 9: return launch_n<9>(geo, atomic, a, s);
-    case 10: return launch_n<10>(geo, atomic, a, s);
-    default: return hipErrorInvalidValue;
-  }
+  return launch_f32_n(n, geo, atomic, false, a, s);
+}
+
+hipError_t launch_force_f32_split(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  return split_affine(naff, a, [&](const ForceArgs& b, bool aff) { return launch_f32_n(n, geo, atomic, aff, b, s); });
 }
 
 }  // namespace semx

@@ -12,24 +12,13 @@
 namespace semx {
 
 constexpr int kMaxN = 16;     // largest supported NGLL
-constexpr int kMaxNLow = 10;  // largest NGLL of the one-point-per-lane kernels (FP64 storage, adjoint, patches)
+constexpr int kMaxNLow = 10;  // largest NGLL of the one-point-per-lane kernels (FP64 storage, adjoint)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin block dispatch
 
 // geometry path of a force launch
 constexpr int kRegular = 0;    // affine element: one Gamma per element
 constexpr int kStored = 1;     // per-point Gamma streamed from memory
 constexpr int kTrilinear = 2;  // J rebuilt per point from the trilinear map coefficients
-
-// element patches (chains of elements assembled in LDS, one workgroup each)
-constexpr int kPatchMaxNodes = 1024;   // unique global nodes per patch
-constexpr int kPatchDefaultElems = 0;  // default: per-element kernels
-constexpr int kPatchMaxElems = 8;      // longest chain the patch kernel holds
-constexpr int kPatchLdsLimit = 64 * 1024;
-// run descriptor word: bits 0-10 run length, 11-21 first patch-local node,
-// bit 29 node touched by this patch only, bit 30 first touch in colour order
-constexpr int kRunLenBits = 11;
-constexpr int kRunExclusive = 1 << 29;
-constexpr int kRunFirst = 1 << 30;
 
 // Device buffer owned by the library.
 struct DevBuf {
@@ -44,6 +33,7 @@ struct Launch {
   int64_t pos0 = 0;
   int64_t count = 0;
   bool irregular = false;  // geometry path: kRegular, else the context's irregular path
+  int64_t naff = 0;        // leading elements whose node numbers are affine in (i, j, k)
 };
 
 struct SourceSet {
@@ -99,6 +89,7 @@ struct semx_ctx {
   semx::DevBuf d_order;     // int32 [nspec]
   std::vector<float> h_gam_el;  // [nspec][9] per-element Gamma of regular elements (user order)
   semx::DevBuf d_ibool;     // int32 [nspec][n3]
+  semx::DevBuf d_aff;       // int32 [nspec][4]: g0, sx, sy, sz of affine-numbered elements (g0 = -1 otherwise)
   semx::DevBuf d_vert;      // double [nvert][3]
   semx::DevBuf d_elem_vert; // int32 [nspec][8]
   semx::DevBuf d_gam_pt;    // float [nspec][9][n3] (allocated if any irregular element)
@@ -123,22 +114,6 @@ struct semx_ctx {
   std::vector<int32_t> color_ptr, elem_order;
   std::vector<semx::Launch> colored_launches;  // per colour: regular then irregular
   std::vector<semx::Launch> atomic_launches;   // regular list, irregular list
-
-  // element patches for the FP32 force kernel: chains of up to patch_cmax
-  // elements, each with its sorted unique nodes stored as runs of
-  // consecutive global indices; patch-level colouring
-  int patch_cmax = semx::kPatchDefaultElems;  // 0 = per-element kernels
-  bool patches_ok = false;                    // patch layout built and usable
-  bool patch_cover = false;                   // every global node lies in some patch
-  int64_t npatch = 0, npatch_runs = 0, patch_nodes_total = 0;
-  int patch_maxnodes = 0, patch_maxruns = 0, npatch_colors = 0;
-  semx::DevBuf d_pe_pos;   // int32 [nspec] launch position of each patch slot's element
-  semx::DevBuf d_pe_off;   // int32 [npatch+1] first slot of each patch
-  semx::DevBuf d_lidx;     // uint16 [nspec][n3] patch-local node of each slot point
-  semx::DevBuf d_pr_off;   // int32 [npatch+1] first run of each patch
-  semx::DevBuf d_runs;     // int32 [nruns][2]: first global node, descriptor word
-  std::vector<semx::Launch> patch_colored;  // per colour: regular then irregular patches
-  std::vector<semx::Launch> patch_atomic;   // regular patches, irregular patches
 
   // model
   bool have_model = false;
@@ -206,6 +181,7 @@ void lagrange_at(int n, const std::vector<double>& xi, double x, double* l);
 
 struct ForceArgs {
   const int32_t* ibool;
+  const int32_t* aff;    // [nspec][4] affine numbering g = g0 + i sx + j sy + k sz
   const float* gam_pt;   // [nspec][9][n3]   (kStored)
   const float* gam_el;   // [nspec][9]       (kRegular)
   const float* tri;      // [nspec][3][8]    (kTrilinear: c0..c7 of each coordinate)
@@ -224,21 +200,12 @@ struct ForceArgs {
   int nmodels;
 };
 hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
-// Memory skeleton of the coloured launch_force_f32 (same loads and stores, no arithmetic).
-hipError_t launch_force_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
+// The same over a launch whose first `naff` elements have an affine numbering:
+// those compute their node numbers instead of reading ibool.
+hipError_t launch_force_f32_split(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
+// Memory skeleton of the coloured launch_force_f32_split (same loads and stores, no arithmetic).
+hipError_t launch_force_skeleton(int n, int geo, int64_t naff, const ForceArgs& a, hipStream_t s);
 
-// Patch launch: ForceArgs.pos0/count name a range of patches; ibool is unused.
-struct PatchArgs {
-  ForceArgs fa;
-  const int32_t* pe_pos;
-  const int32_t* pe_off;
-  const uint16_t* lidx;
-  const int32_t* pr_off;
-  const int32_t* runs;
-  int maxnodes, maxruns;
-};
-hipError_t launch_force_patch(int n, int geo, bool atomic, const PatchArgs& a, hipStream_t s);
-size_t patch_lds_bytes(int n, int maxnodes, int maxruns);
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // force_high.hip: NGLL 11..16 (one lane per (i, j) column)
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
