@@ -382,8 +382,26 @@ int semx_mlp_get_grads(semx_mlp *net, float *grads);
 /* y_dev [batch][width_out] = net(x_dev [batch][width_in]); keeps the
  * activations for semx_mlp_backward (x_dev must stay alive until then) */
 int semx_mlp_forward(semx_mlp *net, const float *x_dev, int batch, float *y_dev);
+/* Allocation-free inference forward, for callers that cannot allocate
+ * device memory: code under HIP graph capture and tight serving loops (the
+ * surrogate's batched inference).  Same result as semx_mlp_forward (the same
+ * GEMM kernels and accumulation order), but the hidden activations live in a
+ * workspace of 16 MB that the library holds in static device memory on each
+ * GPU it runs on, not in the network's buffers, and nothing is kept for
+ * semx_mlp_backward.  The call allocates and frees nothing.
+ *   x_dev: device FP32 [batch][widths[0]], read only; y_dev: device FP32
+ *   [batch][widths[nlayers]], overwritten.  batch is not limited by
+ *   max_batch, only by the workspace: batch x (widest hidden layer) <= 2^21
+ *   floats (e.g. 4096 x 512), else SEMX_EINVAL.
+ * Every call on one GPU uses that GPU's single workspace: calls that overlap
+ * on one GPU (several streams, several networks, several host threads) race
+ * and must be serialised by the caller.  The workspace keeps the last call's
+ * activations; nothing in it needs to start at zero.  (semx_mlp_create
+ * resolves the workspace's device address and fails with SEMX_EHIP if it
+ * cannot.) */
+int semx_mlp_forward_noalloc(semx_mlp *net, const float *x_dev, int batch, float *y_dev);
 /* parameter gradient of a scalar loss L given dy_dev = dL/dy (overwrites the
- * gradient buffer) for the batch of the last forward call */
+ * gradient buffer) for the batch of the last semx_mlp_forward call */
 int semx_mlp_backward(semx_mlp *net, const float *dy_dev, int batch);
 /* mean squared error over n values: loss (FP64, host, may be NULL) and
  * dy_dev = dloss/dy (may be NULL) */

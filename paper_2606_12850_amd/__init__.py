@@ -87,6 +87,7 @@ _SIGS = {
     "semx_mlp_get_params": [_vp, _vp],
     "semx_mlp_get_grads": [_vp, _vp],
     "semx_mlp_forward": [_vp, _vp, _i32, _vp],
+    "semx_mlp_forward_noalloc": [_vp, _vp, _i32, _vp],
     "semx_mlp_backward": [_vp, _vp, _i32],
     "semx_mlp_mse": [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_f64)],
     "semx_mlp_adam": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64],
@@ -415,6 +416,10 @@ def semx_mlp_get_grads(net, out):
 
 def semx_mlp_forward(net, x, batch: int, y):
     return _mcheck(net, lib().semx_mlp_forward(net, _ptr(x), int(batch), _ptr(y)))
+
+
+def semx_mlp_forward_noalloc(net, x, batch: int, y):
+    return _mcheck(net, lib().semx_mlp_forward_noalloc(net, _ptr(x), int(batch), _ptr(y)))
 
 
 def semx_mlp_backward(net, dy, batch: int):

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,7 @@ struct semx_mlp {
   semx::DevBuf splitk;             // split-K partial sums
   const float* x_saved = nullptr;
   int batch_saved = 0;
+  int device = 0;                  // device current at creation (allocation-free forward)
 };
 
 namespace semx {
@@ -42,6 +44,30 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32, PADK = 8;
 constexpr int64_t kSplitWs = 2 << 20;  // floats of split-K partial sums per network (8 MB)
+
+// Workspace of semx_mlp_forward_noalloc: two activation buffers of
+// kNoAllocFloats / 2 floats each, in the code object's own device memory (each
+// GPU the library runs on holds one copy until the process ends).  Host code
+// never passes `scratch` itself to a kernel: its name is a host-side handle;
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoAllocFloats = 4 << 20;  // 16 MB
+__device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kMaxDevices = 64;
+float* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+hipError_t g_scratch_err[kMaxDevices] = {};
+std::once_flag g_scratch_once[kMaxDevices];
+
+// Resolve `scratch` on the current device (once per device).
+hipError_t noalloc_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = e;
+    g_scratch_dev[dev] = e == hipSuccess ? static_cast<float*>(ptr) : nullptr;
+  });
+  return g_scratch_err[dev];
+}
 
 __device__ __forceinline__ float to_f(float x) { return x; }
 __device__ __forceinline__ float to_f(__bf16 x) { return (float)x; }
@@ -99,7 +125,8 @@ __device__ __forceinline__ void load_tile(__bf16 (*Ts)[BK + PADK], const T* __re
 }
 
 // C[m][n] (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
-// EPI 1: + bias[n]; EPI 2: + bias[n] and H[m][n] = SiLU(C[m][n]).
+// EPI 1: + bias[n]; EPI 2: + bias[n] and H[m][n] = SiLU(C[m][n]); EPI 3:
+// C[m][n] = SiLU(sum + bias[n]) (inference: the pre-activation is not kept).
 // Split-K (gridDim.z > 1, EPI 0 only): slice z covers k in [z kchunk,
 // (z+1) kchunk) and stores its partial sums to C + z M N (row stride N).
 template <class TA, class TB, int EPI, bool AKC, bool BKC>
@@ -153,8 +180,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, int kchu
             if (accumulate) v += Cz[o];
             if (EPI >= 1) v += bias[n];
           }
-          Cz[o] = v;
-          if (EPI == 2) H[o] = v / (1.0f + expf(-v));
+          if (EPI == 3) {
+            Cz[o] = v / (1.0f + expf(-v));
+          } else {
+            Cz[o] = v;
+            if (EPI == 2) H[o] = v / (1.0f + expf(-v));
+          }
         }
       }
 }
@@ -324,6 +355,15 @@ int semx_mlp_create(semx_mlp** out, int nlayers, const int* widths, int max_batc
   for (int l = 0; l <= nlayers; ++l)
     if (widths[l] < 1 || widths[l] > (1 << 20)) return SEMX_EINVAL;
   semx_mlp* p = new semx_mlp();
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return SEMX_EHIP;
+  }
+  // the allocation-free forward's workspace on this device (resolved once per device)
+  if (noalloc_setup(p->device) != hipSuccess) {
+    delete p;
+    return SEMX_EHIP;
+  }
   p->nl = nlayers;
   p->w.assign(widths, widths + nlayers + 1);
   p->max_batch = max_batch;
@@ -427,6 +467,37 @@ int semx_mlp_forward(semx_mlp* p, const float* x_dev, int batch, float* y_dev) {
   // the output layer's pre-activation is y itself; keep a copy for backward bookkeeping
   p->x_saved = x_dev;
   p->batch_saved = batch;
+  return SEMX_OK;
+}
+
+int semx_mlp_forward_noalloc(semx_mlp* p, const float* x_dev, int batch, float* y_dev) {
+  if (!p || !x_dev || !y_dev) return SEMX_EINVAL;
+  if (batch < 1) return mfail(p, SEMX_EINVAL, "forward_noalloc: batch must be >= 1");
+  int hmax = 0;
+  for (int l = 1; l < p->nl; ++l) hmax = std::max(hmax, p->w[l]);
+  if ((int64_t)batch * hmax > kNoAllocFloats / 2)
+    return mfail(p, SEMX_EINVAL, "forward_noalloc: batch x widest hidden layer above " +
+                                     std::to_string(kNoAllocFloats / 2) + " floats");
+  float* ws = (p->device >= 0 && p->device < kMaxDevices) ? g_scratch_dev[p->device] : nullptr;
+  if (!ws) return mfail(p, SEMX_ESTATE, "forward_noalloc: workspace address not resolved on this device");
+  float* buf[2] = {ws, ws + kNoAllocFloats / 2};
+  const __bf16* W = p->theta_bf.as<__bf16>();
+  const float* th = p->theta.as<float>();
+  const float* h = x_dev;
+  for (int l = 0; l < p->nl; ++l) {
+    const int in = p->w[l], out = p->w[l + 1];
+    const bool last = l + 1 == p->nl;
+    float* z = last ? y_dev : buf[l & 1];
+    hipError_t e;
+    if (last)
+      e = gemm<float, __bf16, 1>(p->stream, batch, out, in, h, in, 1, W + p->woff[l], 1, in, z, out, th + p->boff[l],
+                                 nullptr, 0);
+    else
+      e = gemm<float, __bf16, 3>(p->stream, batch, out, in, h, in, 1, W + p->woff[l], 1, in, z, out, th + p->boff[l],
+                                 nullptr, 0);
+    if (e != hipSuccess) return mhip(p, e, "mlp forward_noalloc gemm");
+    h = z;
+  }
   return SEMX_OK;
 }
 
