@@ -195,13 +195,30 @@ int semx_read_seismograms(semx_ctx *ctx, float *out, int out_on_device);
 int semx_get_state(semx_ctx *ctx, float *u_dev, float *v_dev, float *a_dev, int64_t *it);
 int semx_set_state(semx_ctx *ctx, const float *u_dev, const float *v_dev, const float *a_dev, int64_t it);
 
-/* Energy of model 0 in FP64 accumulation: kinetic 1/2 v^T M v and
- * potential 1/2 u^T K u of the current state. */
-int semx_energy(semx_ctx *ctx, double *kinetic, double *potential);
+/* Discrete energy of the explicit Newmark scheme (Sec. II-B weak form with
+ * the lumped GLL mass; Sec. V-C second-order Newmark), model 0, FP64 sums.
+ * After semx_step() has brought the run to time index it = n+1:
+ *   kinetic   = 1/2 (v^{n+1/2})^T M v^{n+1/2}, v^{n+1/2} the scheme's
+ *               half-step velocity (u^{n+1} - u^n) / dt,
+ *   potential = 1/2 (u^{n+1})^T K u^n,
+ * so E^{n+1/2} = kinetic + potential, which the scheme conserves up to the
+ * work of the sources: E^{n+1/2} - E^{n-1/2} = 1/2 (u^{n+1} - u^{n-1})^T f_src^n.
+ *   source_work (may be NULL): that work summed over the steps since the
+ *               last semx_reset(), semx_set_state() or semx_set_sources(),
+ *               from the second of them on (E^{n+1/2} minus the first tracked
+ *               E equals it in exact arithmetic).
+ * The energy is evaluated on the last step of every semx_step() call (and on
+ * the watchdog's steps): one extra read pass over v, u and f; the source
+ * work is summed on every step over the source points only.
+ * Errors: SEMX_ESTATE without mesh and model, or when no step was taken
+ * since the last reset / new state (or since a call that moved the time
+ * index otherwise, e.g. the adjoint's recomputation). */
+int semx_energy(semx_ctx *ctx, double *kinetic, double *potential, double *source_work);
 
 /* Watchdog: every `interval` steps (0 = off) semx_step checks that u and v
- * are finite, and that the total energy (if max_energy > 0) stays below
- * max_energy; a violation stops stepping and returns SEMX_ENUMERIC. */
+ * are finite, and (if max_energy > 0) that the discrete energy E^{n+1/2} of
+ * semx_energy() stays below max_energy; a violation stops stepping and
+ * returns SEMX_ENUMERIC. */
 int semx_set_watchdog(semx_ctx *ctx, int64_t interval, double max_energy);
 
 /* Forward checkpoints for the adjoint: with every > 0, semx_reset() and every

@@ -74,7 +74,7 @@ _SIGS = {
     "semx_read_seismograms": [_vp, _vp, _i32],
     "semx_get_state": [_vp, _vp, _vp, _vp, ctypes.POINTER(_i64)],
     "semx_set_state": [_vp, _vp, _vp, _vp, _i64],
-    "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
+    "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
     "semx_set_watchdog": [_vp, _i64, _f64],
     "semx_set_geometry": [_vp, _i32],
     "semx_set_checkpointing": [_vp, _i64],
@@ -346,10 +346,12 @@ def semx_force_skeleton(ctx, u, f, reps: int) -> float:
     return out.value
 
 
-def semx_energy(ctx):
-    k, p = _f64(), _f64()
-    _check(ctx, lib().semx_energy(ctx, ctypes.byref(k), ctypes.byref(p)))
-    return k.value, p.value
+def semx_energy(ctx, with_work: bool = False):
+    """(kinetic, potential) of E^{n+1/2} at the current time index, plus the
+    summed source work when ``with_work``."""
+    k, p, w = _f64(), _f64(), _f64()
+    _check(ctx, lib().semx_energy(ctx, ctypes.byref(k), ctypes.byref(p), ctypes.byref(w)))
+    return (k.value, p.value, w.value) if with_work else (k.value, p.value)
 
 
 def semx_set_watchdog(ctx, interval: int, max_energy: float = 0.0):

@@ -35,6 +35,7 @@ class SeismogramOperator:
         self.nt = int(nt)
         self.every = int(checkpoint_every)
         self.nmodels = 0
+        self.runs = 0  # forward runs so far: the adjoint replays only the latest
 
     def run(self, lam, mu, rho):
         """Upload the model, run nt steps with checkpoints, return seismograms
@@ -48,6 +49,7 @@ class SeismogramOperator:
         semx_set_checkpointing(s.ctx, self.every)
         semx_reset(s.ctx)
         semx_step(s.ctx, self.nt)
+        self.runs += 1
         out = torch.empty((self.nmodels, len(self.rec[0]), 3, self.nt), dtype=torch.float32, device=s.device)
         semx_read_seismograms(s.ctx, out, True)
         return out
@@ -75,6 +77,7 @@ class SemForward(torch.autograd.Function):
         squeeze = lam.dim() == 2
         seis = op.run(lam.detach().cpu().numpy(), mu.detach().cpu().numpy(), rho.detach().cpu().numpy())
         ctx.op = op
+        ctx.run = op.runs
         ctx.squeeze = squeeze
         ctx.dev = lam.device
         return seis[0] if squeeze else seis
@@ -82,6 +85,9 @@ class SemForward(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gseis):
         op = ctx.op
+        if op.runs != ctx.run:
+            raise RuntimeError("SemForward.backward: the operator ran another forward since this graph was built; "
+                               "its checkpoints are of that run (use one operator per graph, or run backward first)")
         g = gseis.unsqueeze(0) if ctx.squeeze else gseis
         gl, gm, gr = op.gradient(g)
         outs = []

@@ -22,6 +22,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <algorithm>
+#include <string>
+
 #include "elem_common.hpp"
 
 namespace semx {
@@ -502,7 +505,10 @@ int save_checkpoint(semx_ctx* c) {
   if (rc) return rc;
   const int64_t len = state_len(c);
   const size_t vb = sizeof(float) * len;
-  if ((int64_t)c->ckpts.size() <= k) c->ckpts.resize(k + 1);
+  if ((int64_t)c->ckpts.size() <= k) {
+    c->ckpts.resize(k + 1);
+    c->ckpt_gen.resize(k + 1, -1);
+  }
   if (c->ckpts[k].bytes != 3 * vb) {
     rc = dev_alloc(c, c->ckpts[k], 3 * vb);
     if (rc) return rc;
@@ -512,6 +518,7 @@ int save_checkpoint(semx_ctx* c) {
   if (!rc) rc = d2d(c, base + vb, c->d_v.p, vb);
   if (!rc) rc = d2d(c, base + 2 * vb, c->d_a.p, vb);
   if (rc) return rc;
+  c->ckpt_gen[k] = c->run_gen;
   c->ckpt_count = k + 1;
   return SEMX_OK;
 }
@@ -530,9 +537,11 @@ int semx_set_checkpointing(semx_ctx* c, int64_t every) {
     return fail(c, SEMX_EINVAL, "set_checkpointing: the adjoint covers the elastic operator only");
   c->ckpt_every = every;
   c->ckpt_count = 0;
+  std::fill(c->ckpt_gen.begin(), c->ckpt_gen.end(), -1);
   if (every == 0) {
     for (DevBuf& b : c->ckpts) dev_free(b);
     c->ckpts.clear();
+    c->ckpt_gen.clear();
   }
   return SEMX_OK;
 }
@@ -555,6 +564,13 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
   if (c->ckpt_count < nseg) return fail(c, SEMX_ESTATE, "adjoint: missing forward checkpoints");
   const int64_t len = state_len(c);
   const size_t vb = sizeof(float) * len;
+  // every checkpoint the backward pass restores must come from this run (the
+  // same model, sources, batch size and start) and hold the current state size
+  for (int64_t seg = 0; seg < nseg; ++seg)
+    if (seg >= (int64_t)c->ckpts.size() || c->ckpts[seg].bytes != 3 * vb || c->ckpt_gen[seg] != c->run_gen)
+      return fail(c, SEMX_ESTATE, "adjoint: forward checkpoint " + std::to_string(seg) +
+                                      " is not from the current run (reset and step again after changing the "
+                                      "model, sources or state)");
   const int64_t npt = (int64_t)c->nmodels * c->nspec * c->n3;
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
 

@@ -756,6 +756,8 @@ int finalize_state(semx_ctx* c, float* seg_a = nullptr) {
 }
 
 int do_reset(semx_ctx* c) {
+  c->run_gen++;
+  c->ckpt_count = 0;
   if (c->storage == SEMX_F64) return f64_reset(c);
   const int64_t len = state_len(c);
   for (auto* b : {&c->d_u, &c->d_v, &c->d_a, &c->d_f}) {
@@ -778,7 +780,10 @@ int do_reset(semx_ctx* c) {
     rc = zero_f32(c, c->d_f.as<float>(), len);
     if (rc) return rc;
   }
-  return SEMX_OK;
+  int rc = energy_reset(c);
+  // the forward run that the adjoint replays starts here
+  if (!rc && c->ckpt_every > 0) rc = save_checkpoint(c);
+  return rc;
 }
 
 int record_receivers(semx_ctx* c, int64_t idx) {
@@ -791,37 +796,6 @@ int record_receivers(semx_ctx* c, int64_t idx) {
   return SEMX_OK;
 }
 
-
-int energy_model0(semx_ctx* c, double* kin, double* pot) {
-  if (c->storage == SEMX_F64) return f64_energy(c, kin, pot);
-  int rc = finalize_state(c);
-  if (rc) return rc;
-  const int64_t n3g = c->ncomp * c->nglob;
-  fill_f64<<<1, 64, 0, c->stream>>>(scratch_d(c), 8, 0.0);
-  // kinetic: 1/2 sum M v^2
-  mnorm_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(c->nglob, c->ncomp, c->d_mass64.as<double>(),
-                                                                c->d_v.as<float>(), scratch_d(c));
-  SEMX_HIP(c, hipGetLastError());
-  // potential: 1/2 u^T K u = -1/2 u . f(u), f(u) computed into the work vector
-  DevBuf& tmp = c->d_work;
-  rc = force_into(c, c->d_u.as<float>(), tmp.as<float>(), false);
-  if (!rc) {
-    dot_kernel<<<grid_for(n3g, 2048), kThreads, 0, c->stream>>>(n3g, c->d_u.as<float>(), tmp.as<float>(),
-                                                               scratch_d(c) + 1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) rc = hip_fail(c, e, "dot_kernel");
-  }
-  double h[2] = {0, 0};
-  if (!rc) {
-    hipError_t e = hipMemcpyAsync(h, scratch_d(c), 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) rc = hip_fail(c, e, "energy readback");
-  }
-  if (rc) return rc;
-  *kin = 0.5 * h[0];
-  *pot = -0.5 * h[1];
-  return SEMX_OK;
-}
 
 int check_finite(semx_ctx* c, bool* ok) {
   if (c->storage == SEMX_F64) return f64_check_finite(c, ok);
@@ -849,7 +823,18 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
   const float dt = (float)c->dt;
   float *u = c->d_u.as<float>(), *v = c->d_v.as<float>(), *a = c->d_a.as<float>(), *f = c->d_f.as<float>();
   const float* minv = c->d_minv.as<float>();
-  const bool keep = force_overwrites(c);
+  const bool track = c->track_energy;
+  c->track_energy = false;
+  // a tracked step keeps f^n through the Newmark pass for the potential term;
+  // without a pending force (first step after a reset or a new state) -K u^n
+  // is computed into the work vector
+  const bool keep = force_overwrites(c) || track;
+  const float* f_pe = f;
+  if (track && !c->pending_correct) {
+    int rc = force_into(c, u, c->d_work.as<float>(), false);
+    if (rc) return rc;
+    f_pe = c->d_work.as<float>();
+  }
   const unsigned gb = grid_for(c->ncomp * nn, 1 << 30);  // one pass per lane (streams faster than grid-stride)
   if (c->pending_correct) {
     if (keep) launch_newmark<kCorrect | kPredict | kKeepF>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
@@ -859,12 +844,22 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
     else launch_newmark<kPredict>(c, nn, gb, dt, minv, u, v, a, f, seg_u, nullptr);
   }
   SEMX_HIP(c, hipGetLastError());
-  int rc = force_into(c, u, f, !keep);
+  const bool src_in_f = c->pending_correct;
+  if (track) {
+    int rc = energy_track(c, f_pe, src_in_f);
+    if (rc) return rc;
+  }
+  int rc = energy_source_step(c, c->it, track && src_in_f);
+  if (rc) return rc;
+  // f is zero here only if the Newmark pass cleared it (untracked step on a
+  // mesh the force pass does not overwrite)
+  rc = force_into(c, u, f, !track && !force_overwrites(c));
   if (!rc) rc = inject_sources(c, c->it + 1, f);
   if (!rc && record) rc = record_receivers(c, c->it);
   if (rc) return rc;
   c->it++;
   c->pending_correct = true;
+  if (track) c->energy_it = c->it;
   return SEMX_OK;
 }
 
@@ -880,7 +875,9 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
   if (nsrc < 0) return fail(c, SEMX_EINVAL, "set_sources: nsrc < 0");
   if (nsrc == 0) {
     c->src.nsrc = 0;
-    return SEMX_OK;
+    c->run_gen++;
+    c->ckpt_count = 0;
+    return c->have_model && c->d_u.p ? energy_reset(c) : SEMX_OK;
   }
   const int nc = c->ncomp;
   if (!elem || !xi || (nc == 3 && !dir) || (!stf32 && !stf64) || nstf <= 0)
@@ -918,20 +915,34 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
     s64[t] = stf64 ? stf64[t] : (double)stf32[t];
     s32[t] = stf32 ? stf32[t] : (float)stf64[t];
   }
+  // points that carry a nonzero weight (a source on a node has one per element)
+  std::vector<int32_t> pts;
+  for (size_t p = 0; p < (size_t)nsrc * n3; ++p) {
+    bool nz = false;
+    for (int d = 0; d < nc; ++d) nz |= wdir64[p * nc + d] != 0.0;
+    if (nz) pts.push_back((int32_t)p);
+  }
+  if (pts.empty()) pts.push_back(0);
   int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
+  if (!rc) rc = dev_alloc(c, c->src.pts, pts.size() * sizeof(int32_t));
   if (!rc) rc = dev_alloc(c, c->src.wdir, wdir.size() * sizeof(float));
   if (!rc) rc = dev_alloc(c, c->src.stf, sizeof(float) * ns);
   if (!rc) rc = dev_alloc(c, c->src.wdir64, wdir64.size() * sizeof(double));
   if (!rc) rc = dev_alloc(c, c->src.stf64, sizeof(double) * ns);
   if (rc) return rc;
   SEMX_HIP(c, hipMemcpy(c->src.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.pts.p, pts.data(), pts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  c->src.npts = (int)pts.size();
   SEMX_HIP(c, hipMemcpy(c->src.wdir.p, wdir.data(), wdir.size() * sizeof(float), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->src.stf.p, s32.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->src.wdir64.p, wdir64.data(), wdir64.size() * sizeof(double), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->src.stf64.p, s64.data(), sizeof(double) * ns, hipMemcpyHostToDevice));
   c->src.nsrc = nsrc;
   c->src.nstf = nstf;
-  return SEMX_OK;
+  c->run_gen++;  // checkpoints of a run with other sources are not replayable
+  c->ckpt_count = 0;
+  // the source work restarts with the new source set
+  return c->have_model && c->d_u.p ? energy_reset(c) : SEMX_OK;
 }
 
 unsigned grid_1d(int64_t n, int cap) { return grid_for(n, cap); }
@@ -994,7 +1005,8 @@ int semx_destroy(semx_ctx* c) {
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
-                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->rec.nodes, &c->rec.wts, &c->rec.seis,
+                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->src.pts, &c->rec.nodes, &c->rec.wts,
+                    &c->rec.seis,
                     &c->src.wdir64, &c->src.stf64, &c->rec.wts64, &c->rec.seis64, &c->d_gam64, &c->d_mat64,
                     &c->d_minv64, &c->d_D64,
                     &c->d_first, &c->d_aff})
@@ -1520,12 +1532,7 @@ int semx_set_receivers(semx_ctx* c, int nrec, const int32_t* elem, const double*
 int semx_reset(semx_ctx* c) {
   if (!c) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "reset: mesh and model required");
-  int rc = do_reset(c);
-  if (!rc && c->ckpt_every > 0) {
-    c->ckpt_count = 0;
-    rc = save_checkpoint(c);
-  }
-  return rc;
+  return do_reset(c);
 }
 
 int semx_step(semx_ctx* c, int64_t nsteps) {
@@ -1534,23 +1541,27 @@ int semx_step(semx_ctx* c, int64_t nsteps) {
   if (!c->have_dt) return fail(c, SEMX_ESTATE, "step: dt not set");
   if (nsteps < 0) return fail(c, SEMX_EINVAL, "step: nsteps < 0");
   for (int64_t s = 0; s < nsteps; ++s) {
+    // the discrete energy is tracked on the last step of the call and on the
+    // watchdog's steps that check it
+    const bool wd_step = c->watchdog_every > 0 && (c->it + 1) % c->watchdog_every == 0;
+    c->track_energy = s + 1 == nsteps || (wd_step && c->watchdog_emax > 0.0);
     int rc = step_once(c, true);
     if (rc) return rc;
     if (c->ckpt_every > 0 && c->it % c->ckpt_every == 0) {
       rc = save_checkpoint(c);
       if (rc) return rc;
     }
-    if (c->watchdog_every > 0 && c->it % c->watchdog_every == 0) {
+    if (wd_step) {
       bool ok = true;
       rc = check_finite(c, &ok);
       if (rc) return rc;
       if (!ok) return fail(c, SEMX_ENUMERIC, "watchdog: non-finite displacement or velocity at step " + std::to_string(c->it));
       if (c->watchdog_emax > 0.0) {
         double k = 0, p = 0;
-        rc = energy_model0(c, &k, &p);
+        rc = energy_read(c, &k, &p, nullptr);
         if (rc) return rc;
         if (!(k + p <= c->watchdog_emax))
-          return fail(c, SEMX_ENUMERIC, "watchdog: energy above the limit at step " + std::to_string(c->it));
+          return fail(c, SEMX_ENUMERIC, "watchdog: discrete energy above the limit at step " + std::to_string(c->it));
       }
     }
   }
@@ -1600,13 +1611,15 @@ int semx_set_state(semx_ctx* c, const float* u_dev, const float* v_dev, const fl
   if (rc) return rc;
   c->it = it;
   c->pending_correct = false;
-  return SEMX_OK;
+  c->run_gen++;  // earlier checkpoints belong to another run
+  c->ckpt_count = 0;
+  return energy_reset(c);
 }
 
-int semx_energy(semx_ctx* c, double* kinetic, double* potential) {
+int semx_energy(semx_ctx* c, double* kinetic, double* potential, double* source_work) {
   if (!c || !kinetic || !potential) return SEMX_EINVAL;
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "energy: mesh and model required");
-  return energy_model0(c, kinetic, potential);
+  return energy_read(c, kinetic, potential, source_work);
 }
 
 int semx_set_watchdog(semx_ctx* c, int64_t interval, double max_energy) {
@@ -1714,7 +1727,7 @@ int semx_set_state_f64(semx_ctx* c, const double* u_dev, const double* v_dev, co
   SEMX_HIP(c, hipGetLastError());
   c->it = it;
   c->pending_correct = false;
-  return SEMX_OK;
+  return energy_reset(c);
 }
 
 }  // extern "C"

@@ -1,0 +1,221 @@
+// Discrete energy of the explicit Newmark scheme and the work of the point
+// sources (Sec. II-B weak form with the diagonal GLL mass; Sec. V-C
+// second-order Newmark).  With K, M symmetric, the central-difference form of
+// the scheme conserves
+//   E^{n+1/2} = 1/2 (v^{n+1/2})^T M v^{n+1/2} + 1/2 (u^{n+1})^T K u^n,
+// v^{n+1/2} = (u^{n+1} - u^n) / dt (the scheme's half-step velocity), up to the
+// work of the sources: E^{n+1/2} - E^{n-1/2} = 1/2 (u^{n+1} - u^{n-1})^T f_src^n.
+//
+// Bookkeeping on the time loop, model 0 of the batch, FP64 sums:
+//  * energy_track(): after the Newmark pass of step n (u holds u^{n+1}, v the
+//    half-step velocity, f_pe the force f^n = -K u^n + f_src^n), one pass
+//    sums v^T M v and u^{n+1} . f_pe in fixed-size blocks, reduced in a fixed
+//    order (deterministic);
+//  * energy_source_step(): every step, one workgroup over the source points
+//    adds 1/2 (u^{n+1} - u^{n-1}) . f_src^n to the running source work and,
+//    on tracked steps, sums u^{n+1} . f_src^n (the source part of f^n, which
+//    the potential term must not see); it keeps u at the source points of
+//    the last two steps.
+// acc (double[8]): 0 sum M v^2, 1 sum u . f_pe, 2 sum u . f_src, 3 running
+// source work.  The caller's state and kernels are not touched.
+#include <algorithm>
+
+#include "semx_internal.hpp"
+
+namespace semx {
+namespace {
+
+constexpr int kEnergyBlocks = 1024;
+constexpr int kT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// part[b][0] = sum M v^2, part[b][1] = sum u . f over the entries of block b
+// (grid-stride over nc * nglob entries of model 0).
+template <class T>
+__global__ __launch_bounds__(kT) void energy_pass_kernel(int64_t nglob, int nc, const double* __restrict__ mass,
+                                                         const T* __restrict__ v, const T* __restrict__ u,
+                                                         const T* __restrict__ f, double* __restrict__ part) {
+  __shared__ double red[kT];
+  double kin = 0.0, pot = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nc * nglob;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double vv = v[t];
+    kin += mass[t / nc] * vv * vv;
+    pot += (double)u[t] * (double)f[t];
+  }
+  kin = block_sum(kin, red);
+  pot = block_sum(pot, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = kin;
+    part[2 * blockIdx.x + 1] = pot;
+  }
+}
+
+// acc[0], acc[1] = sums of the block partials, in block order.
+__global__ void energy_reduce_kernel(int nblk, const double* __restrict__ part, double* __restrict__ acc) {
+  __shared__ double red[kT];
+  double kin = 0.0, pot = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    kin += part[2 * b];
+    pot += part[2 * b + 1];
+  }
+  kin = block_sum(kin, red);
+  pot = block_sum(pot, red);
+  if (threadIdx.x == 0) {
+    acc[0] = kin;
+    acc[1] = pot;
+  }
+}
+
+// One workgroup over the source points with a nonzero weight (model 0):
+// pts[k] = s n3 + q, f_src^n at that point, component c =
+// stf[s][n] * wdir[(s n3 + q) nc + c]; hist is indexed by k.
+// work: acc[3] += 1/2 sum (u^{n+1} - u^{n-1}) . f_src^n (with_work);
+// corr: acc[2] = sum u^{n+1} . f_src^n; then hist[slot_new] = u^{n+1}.
+template <class T>
+__global__ __launch_bounds__(kT) void source_energy_kernel(int npt, int n3, int nc, int64_t nstf, int64_t n,
+                                                           const int32_t* __restrict__ pts,
+                                                           const int32_t* __restrict__ nodes,
+                                                           const T* __restrict__ wdir, const T* __restrict__ stf,
+                                                           const T* __restrict__ u, const T* hist_old,
+                                                           T* hist_new, int with_work, int with_corr,
+                                                           double* __restrict__ acc) {
+  __shared__ double red[kT];
+  double work = 0.0, corr = 0.0;
+  for (int k = threadIdx.x; k < npt; k += blockDim.x) {
+    const int p = pts[k];
+    const int s = p / n3;
+    const double amp = (n >= 0 && n < nstf) ? (double)stf[(int64_t)s * nstf + n] : 0.0;
+    const int64_t g = nodes[p];
+    for (int c = 0; c < nc; ++c) {
+      const double un = u[nc * g + c];
+      const double fs = amp * (double)wdir[(int64_t)nc * p + c];
+      work += 0.5 * (un - (double)hist_old[(int64_t)nc * k + c]) * fs;
+      corr += un * fs;
+      hist_new[(int64_t)nc * k + c] = (T)un;
+    }
+  }
+  work = block_sum(work, red);
+  corr = block_sum(corr, red);
+  if (threadIdx.x == 0) {
+    if (with_work) acc[3] += work;
+    if (with_corr) acc[2] = corr;
+  }
+}
+
+// u at the source points (model 0) into hist (at a reset or a new state).
+template <class T>
+__global__ void source_gather_kernel(int npt, int nc, const int32_t* __restrict__ pts,
+                                     const int32_t* __restrict__ nodes, const T* __restrict__ u,
+                                     T* __restrict__ hist) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npt; k += gridDim.x * blockDim.x)
+    for (int c = 0; c < nc; ++c) hist[(int64_t)nc * k + c] = u[(int64_t)nc * nodes[pts[k]] + c];
+}
+
+__global__ void zero_doubles_kernel(double* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+template <class T>
+int source_step_t(semx_ctx* c, int64_t n, bool with_corr) {
+  const int npt = c->src.npts;
+  const size_t per = (size_t)npt * c->ncomp;
+  T* hist = c->d_ehist.as<T>();
+  const bool f64 = c->storage == SEMX_F64;
+  const T* wdir = f64 ? (const T*)c->src.wdir64.p : (const T*)c->src.wdir.p;
+  const T* stf = f64 ? (const T*)c->src.stf64.p : (const T*)c->src.stf.p;
+  // slot of u^{n-1} (stored two steps ago) is the slot u^{n+1} goes to
+  T* slot = hist + (size_t)((n + 1) & 1) * per;
+  const int with_work = n > c->energy_it0 ? 1 : 0;  // u^{n-1} is known from the second step on
+  source_energy_kernel<T><<<1, kT, 0, c->stream>>>(npt, c->n3, c->ncomp, c->src.nstf, n, c->src.pts.as<int32_t>(),
+                                                   c->src.nodes.as<int32_t>(),
+                                                   wdir, stf, c->d_u.as<T>(), slot, slot, with_work,
+                                                   with_corr ? 1 : 0, c->d_eacc.as<double>());
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+}  // namespace
+
+int energy_reset(semx_ctx* c) {
+  int rc = SEMX_OK;
+  if (!c->d_eacc.p) rc = dev_alloc(c, c->d_eacc, sizeof(double) * 8);
+  if (!rc && !c->d_epart.p) rc = dev_alloc(c, c->d_epart, sizeof(double) * 2 * kEnergyBlocks);
+  if (rc) return rc;
+  zero_doubles_kernel<<<1, 64, 0, c->stream>>>(c->d_eacc.as<double>(), 8);
+  SEMX_HIP(c, hipGetLastError());
+  c->energy_it = -1;
+  c->energy_it0 = c->it;
+  const int npt = c->src.nsrc > 0 ? c->src.npts : 0;
+  if (npt == 0) return SEMX_OK;
+  const size_t tsz = c->storage == SEMX_F64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = 2 * (size_t)npt * c->ncomp * tsz;
+  if (c->d_ehist.bytes != bytes) {
+    rc = dev_alloc(c, c->d_ehist, bytes);
+    if (rc) return rc;
+  }
+  SEMX_HIP(c, hipMemsetAsync(c->d_ehist.p, 0, bytes, c->stream));
+  const size_t per = (size_t)npt * c->ncomp;
+  const unsigned nb = (unsigned)std::min(1024, (npt + kT - 1) / kT);
+  const size_t slot = (size_t)(c->it & 1) * per;
+  if (c->storage == SEMX_F64)
+    source_gather_kernel<double><<<nb, kT, 0, c->stream>>>(npt, c->ncomp, c->src.pts.as<int32_t>(),
+                                                           c->src.nodes.as<int32_t>(),
+                                                           c->d_u.as<double>(), c->d_ehist.as<double>() + slot);
+  else
+    source_gather_kernel<float><<<nb, kT, 0, c->stream>>>(npt, c->ncomp, c->src.pts.as<int32_t>(),
+                                                          c->src.nodes.as<int32_t>(),
+                                                          c->d_u.as<float>(), c->d_ehist.as<float>() + slot);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int energy_source_step(semx_ctx* c, int64_t n, bool with_corr) {
+  if (c->src.nsrc == 0 || !c->d_ehist.p) return SEMX_OK;
+  return c->storage == SEMX_F64 ? source_step_t<double>(c, n, with_corr) : source_step_t<float>(c, n, with_corr);
+}
+
+int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f) {
+  if (!c->d_eacc.p) return fail(c, SEMX_ESTATE, "energy: the run was not reset");
+  double* part = c->d_epart.as<double>();
+  if (c->storage == SEMX_F64)
+    energy_pass_kernel<double><<<kEnergyBlocks, kT, 0, c->stream>>>(
+        c->nglob, c->ncomp, c->d_mass64.as<double>(), c->d_v.as<double>(), c->d_u.as<double>(),
+        static_cast<const double*>(f_pe), part);
+  else
+    energy_pass_kernel<float><<<kEnergyBlocks, kT, 0, c->stream>>>(c->nglob, c->ncomp, c->d_mass64.as<double>(),
+                                                                  c->d_v.as<float>(), c->d_u.as<float>(),
+                                                                  static_cast<const float*>(f_pe), part);
+  SEMX_HIP(c, hipGetLastError());
+  energy_reduce_kernel<<<1, kT, 0, c->stream>>>(kEnergyBlocks, part, c->d_eacc.as<double>());
+  SEMX_HIP(c, hipGetLastError());
+  if (!source_in_f) zero_doubles_kernel<<<1, 64, 0, c->stream>>>(c->d_eacc.as<double>() + 2, 1);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int energy_read(semx_ctx* c, double* kin, double* pot, double* work) {
+  if (c->energy_it != c->it || !c->d_eacc.p)
+    return fail(c, SEMX_ESTATE,
+                "energy: no half step tracked at the current time index (call semx_step after a reset or a new state)");
+  double h[4] = {0, 0, 0, 0};
+  SEMX_HIP(c, hipMemcpyAsync(h, c->d_eacc.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  SEMX_HIP(c, hipStreamSynchronize(c->stream));
+  *kin = 0.5 * h[0];
+  *pot = -0.5 * (h[1] - h[2]);
+  if (work) *work = h[3];
+  return SEMX_OK;
+}
+
+}  // namespace semx

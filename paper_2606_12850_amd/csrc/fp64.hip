@@ -22,7 +22,7 @@ namespace semx {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4;
+constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8;
 
 template <int NG>
 __global__ void force64_kernel(int64_t pos0, int64_t nspec, int64_t nglob, int atomic,
@@ -146,7 +146,7 @@ __global__ void minv64_kernel(int64_t n, const double* __restrict__ mass, double
 
 // Newmark update, one lane per degree of freedom; kCorrect: acc = M^{-1} f,
 // v += dt/2 acc (acc stored to a with kStoreA); kPredict: u += dt v + dt^2/2
-// acc, v += dt/2 acc, f = 0 for the coming force pass.
+// acc, v += dt/2 acc, f = 0 for the coming force pass unless kKeepF.
 template <int MODE>
 __global__ void newmark64_kernel(int64_t nnodes, double dt, const double* __restrict__ minv, double* __restrict__ u,
                                  double* __restrict__ v, double* __restrict__ a, double* __restrict__ f) {
@@ -164,7 +164,7 @@ __global__ void newmark64_kernel(int64_t nnodes, double dt, const double* __rest
     if constexpr ((MODE & kPredict) != 0) {
       u[t] += dt * vv + hdt2 * acc;
       vv += hdt * acc;
-      f[t] = 0.0;
+      if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0;
     }
     v[t] = vv;
   }
@@ -378,45 +378,44 @@ int f64_reset(semx_ctx* c) {
     rc = zero64(c, c->d_f.as<double>(), len);
     if (rc) return rc;
   }
-  return SEMX_OK;
+  return energy_reset(c);
 }
 
 int f64_step_once(semx_ctx* c, bool record) {
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
   double *u = c->d_u.as<double>(), *v = c->d_v.as<double>(), *a = c->d_a.as<double>(), *f = c->d_f.as<double>();
   const double* minv = c->d_minv64.as<double>();
-  if (c->pending_correct)
-    newmark64_kernel<kCorrect | kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
-  else
-    newmark64_kernel<kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+  const bool track = c->track_energy;
+  c->track_energy = false;
+  // a tracked step keeps f^n through the Newmark pass for the potential
+  // term, or computes -K u^n into the work vector when no force is pending
+  const double* f_pe = f;
+  if (track && !c->pending_correct) {
+    int rc = f64_force_into(c, u, c->d_work.as<double>(), false);
+    if (rc) return rc;
+    f_pe = c->d_work.as<double>();
+  }
+  if (c->pending_correct) {
+    if (track) newmark64_kernel<kCorrect | kPredict | kKeepF><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+    else newmark64_kernel<kCorrect | kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+  } else {
+    if (track) newmark64_kernel<kPredict | kKeepF><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+    else newmark64_kernel<kPredict><<<grid_1d(3 * nn), kT, 0, c->stream>>>(nn, c->dt, minv, u, v, a, f);
+  }
   SEMX_HIP(c, hipGetLastError());
-  int rc = f64_force_into(c, u, f, true);
+  const bool src_in_f = c->pending_correct;
+  if (track) {
+    int rc = energy_track(c, f_pe, src_in_f);
+    if (rc) return rc;
+  }
+  int rc = energy_source_step(c, c->it, track && src_in_f);
+  if (!rc) rc = f64_force_into(c, u, f, !track);
   if (!rc) rc = inject64(c, c->it + 1, f);
   if (!rc && record) rc = record64(c, c->it);
   if (rc) return rc;
   c->it++;
   c->pending_correct = true;
-  return SEMX_OK;
-}
-
-int f64_energy(semx_ctx* c, double* kin, double* pot) {
-  int rc = f64_finalize(c);
-  if (rc) return rc;
-  const int64_t n3g = 3 * c->nglob;
-  double* acc = scratch_doubles(c);
-  fill64_kernel<<<1, 64, 0, c->stream>>>(acc, 8, 0.0);
-  mnorm64_kernel<<<grid_1d(n3g, 2048), kT, 0, c->stream>>>(c->nglob, c->d_mass64.as<double>(), c->d_v.as<double>(), acc);
-  SEMX_HIP(c, hipGetLastError());
-  // potential 1/2 u^T K u = -1/2 u . f(u) for model 0, f(u) in the work vector
-  rc = f64_force_into(c, c->d_u.as<double>(), c->d_work.as<double>(), false);
-  if (rc) return rc;
-  dot64_kernel<<<grid_1d(n3g, 2048), kT, 0, c->stream>>>(n3g, c->d_u.as<double>(), c->d_work.as<double>(), acc + 1);
-  SEMX_HIP(c, hipGetLastError());
-  double h[2] = {0, 0};
-  SEMX_HIP(c, hipMemcpyAsync(h, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SEMX_HIP(c, hipStreamSynchronize(c->stream));
-  *kin = 0.5 * h[0];
-  *pot = -0.5 * h[1];
+  if (track) c->energy_it = c->it;
   return SEMX_OK;
 }
 

@@ -44,6 +44,8 @@ struct SourceSet {
   DevBuf stf;     // float [nsrc][nstf]
   DevBuf wdir64;  // double copies of wdir and stf (FP64 storage)
   DevBuf stf64;
+  DevBuf pts;     // int32 [npts]: the points (s n3 + q) with a nonzero weight (energy bookkeeping)
+  int npts = 0;
 };
 
 struct ReceiverSet {
@@ -140,6 +142,15 @@ struct semx_ctx {
   int64_t watchdog_every = 0;
   double watchdog_emax = 0.0;
 
+  // discrete energy E^{n+1/2} and source work (energy.hip): tracked on the
+  // last step of each semx_step call and on watchdog steps
+  semx::DevBuf d_eacc;    // double [8] sums (see energy.hip)
+  semx::DevBuf d_epart;   // double block partials
+  semx::DevBuf d_ehist;   // u at the source points, last two steps [2][nsrc n3][ncomp]
+  int64_t energy_it = -1; // time index whose E^{it-1/2} is in d_eacc (-1: none)
+  int64_t energy_it0 = 0; // time index of the last reset / new state (the source work starts there)
+  bool track_energy = false;  // track the energy on the coming step
+
   semx::SourceSet src;
   semx::ReceiverSet rec;
 
@@ -147,6 +158,10 @@ struct semx_ctx {
   int64_t ckpt_every = 0;
   int64_t ckpt_count = 0;
   std::vector<semx::DevBuf> ckpts;  // one buffer of 3 * state_len floats per checkpoint
+  // run generation: bumped by every reset, new state, new sources or new
+  // model; a checkpoint is usable only by the run that saved it
+  int64_t run_gen = 0;
+  std::vector<int64_t> ckpt_gen;    // generation of each saved checkpoint
 
   // optional event timing of force passes: every timing_stride-th pass
   // (0 = off) is bracketed by one event pair; timed_launches counts the
@@ -233,13 +248,21 @@ int save_checkpoint(semx_ctx* c);
 inline double* scratch_doubles(semx_ctx* c) { return c->d_scratch.as<double>(); }
 inline int* scratch_flags(semx_ctx* c) { return reinterpret_cast<int*>(c->d_scratch.as<double>() + 8); }
 
+// energy.hip: discrete energy and source work bookkeeping (model 0)
+int energy_reset(semx_ctx* c);
+// after the Newmark pass of step n: f_pe holds f^n (-K u^n + f_src^n when
+// source_in_f, else -K u^n)
+int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f);
+// every step n after the Newmark pass (u holds u^{n+1})
+int energy_source_step(semx_ctx* c, int64_t n, bool with_corr);
+int energy_read(semx_ctx* c, double* kin, double* pot, double* work);
+
 // fp64.hip: the FP64 storage path (state buffers hold doubles)
 int f64_model_setup(semx_ctx* c, const double* lam_dev, const double* mu_dev);
 int f64_force_into(semx_ctx* c, const double* u, double* f, bool f_zeroed);
 int f64_finalize(semx_ctx* c);
 int f64_reset(semx_ctx* c);
 int f64_step_once(semx_ctx* c, bool record);
-int f64_energy(semx_ctx* c, double* kin, double* pot);
 int f64_check_finite(semx_ctx* c, bool* ok);
 
 }  // namespace semx

@@ -234,8 +234,8 @@ def test_acoustic_api_rules():
 
 
 def test_acoustic_energy_and_max_eigenvalue():
-    """semx_energy at a random state equals the oracle's 1/2 v^T M v and
-    1/2 p^T K p (M = sum W / kappa); semx_max_eigenvalue reaches the largest
+    """semx_energy after one step from a random state equals the oracle's
+    1/2 v^T M v and 1/2 (p^1)^T K p^0 (M = sum W / kappa); semx_max_eigenvalue reaches the largest
     eigenvalue of M^-1 K from a dense FP64 solve from below (tiny jittered
     mesh; power iteration, as for the elastic operator)."""
     import torch
@@ -252,12 +252,18 @@ def test_acoustic_energy_and_max_eigenvalue():
     p = rng.uniform(-1, 1, mesh.nglob).astype(np.float32)
     v = rng.uniform(-1, 1, mesh.nglob).astype(np.float32)
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(s.device)
+    # one step from (p0, v0, a0 = 0) without sources: v^{1/2} = v0, p^1 = p0 + dt v0,
+    # so E^{1/2} = 1/2 v0^T M v0 + 1/2 (p^1)^T K p0
+    dt = 1e-4
+    P.semx_set_dt(s.ctx, dt)
     P.semx_set_state(s.ctx, dev(p), dev(v), dev(np.zeros_like(p)), 0)
+    s.step(1)
     kin, pot = P.semx_energy(s.ctx)
     M = A.mass(n, mesh.ibool, jac, kappa, mesh.nglob)
     f = A.force(n, mesh.ibool, gam, jac, rho, p.astype(np.float64), mesh.nglob)
+    p1 = p.astype(np.float64) + dt * v.astype(np.float64)
     assert kin == pytest.approx(0.5 * np.sum(M * v.astype(np.float64) ** 2), rel=1e-5)
-    assert pot == pytest.approx(-0.5 * np.dot(p.astype(np.float64), f), rel=1e-5)
+    assert pot == pytest.approx(-0.5 * np.dot(p1, f), rel=1e-5)
     K = np.stack([-A.force(n, mesh.ibool, gam, jac, rho, e, mesh.nglob) for e in np.eye(mesh.nglob)], axis=1)
     lam_dense = np.linalg.eigvalsh(K / np.sqrt(np.outer(M, M)))[-1]
     lam = P.semx_max_eigenvalue(s.ctx, 2000)

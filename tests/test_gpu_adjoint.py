@@ -120,6 +120,65 @@ def test_adjoint_requires_checkpoints():
     op.solver.close()
 
 
+def test_adjoint_checkpoints_follow_the_run():
+    """Checkpoints belong to the run that saved them.  A new model with a
+    different batch size, uploaded on a checkpointed context, starts a new
+    run (checkpoint 0 saved at upload): its gradient equals a fresh
+    context's.  After semx_set_state or semx_set_sources the old run's
+    checkpoints are refused (SEMX_ESTATE) instead of being replayed."""
+    import torch
+    import paper_2606_12850_amd as P
+    Pb = _problem(seed=5, nt=40)
+    g1 = torch.from_numpy(np.random.default_rng(1).standard_normal((1, 4, 3, Pb["nt"])).astype(np.float32))
+    op = _gpu_op(Pb, every=10)
+    op.run(Pb["lam"], Pb["mu"], Pb["rho"])
+    op.gradient(g1)
+    s = op.solver
+    # two models sharing the mesh, uploaded on the same context, stepped without semx_reset
+    lam2 = np.stack([Pb["lam"], 1.02 * Pb["lam"]]); mu2 = np.stack([Pb["mu"], Pb["mu"]])
+    rho2 = np.stack([Pb["rho"], 0.99 * Pb["rho"]])
+    s.upload_model(lam2, mu2, rho2)
+    P.semx_step(s.ctx, Pb["nt"])
+    g2 = torch.from_numpy(np.random.default_rng(2).standard_normal((2, 4, 3, Pb["nt"])).astype(np.float32)).cuda()
+    shape = (2, Pb["m"].nspec, Pb["m"].n ** 3)
+    got = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+    P.semx_adjoint(s.ctx, g2, Pb["nt"], *got)
+    op2 = _gpu_op(Pb, every=10)
+    op2.run(lam2, mu2, rho2)
+    ref = op2.gradient(g2)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    # a new state or new sources: the saved checkpoints are not of this run
+    u = s.empty_field(); v = s.empty_field(); a = s.empty_field()
+    it = P.semx_get_state(s.ctx, u, v, a)
+    P.semx_set_state(s.ctx, u, v, a, it)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_adjoint(s.ctx, g2, Pb["nt"], *got)
+    assert ei.value.code == P.SEMX_ESTATE
+    P.semx_reset(s.ctx)
+    P.semx_step(s.ctx, Pb["nt"])
+    P.semx_set_sources(s.ctx, *op.src)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_adjoint(s.ctx, g2, Pb["nt"], *got)
+    assert ei.value.code == P.SEMX_ESTATE
+    op.solver.close(); op2.solver.close()
+
+
+def test_autograd_backward_refuses_a_later_forward():
+    """backward of a graph whose operator has since run another forward raises
+    (its checkpoints are of the later run)."""
+    import torch
+    from paper_2606_12850_amd.autograd import SemForward
+    Pb = _problem(seed=6, nt=30)
+    op = _gpu_op(Pb, every=10)
+    lam = torch.tensor(Pb["lam"], requires_grad=True)
+    seis = SemForward.apply(lam, torch.tensor(Pb["mu"]), torch.tensor(Pb["rho"]), op)
+    op.run(Pb["lam"] * 1.01, Pb["mu"], Pb["rho"])   # e.g. a finite-difference probe
+    with pytest.raises(RuntimeError, match="another forward"):
+        torch.sum(seis.double() ** 2).backward()
+    op.solver.close()
+
+
 @pytest.mark.parametrize("n,geometry", [(12, "stored"), (16, "trilinear")])
 def test_adjoint_high_order(orc, n, geometry):
     """NGLL 12 and 16 (the column kernels): sensitivity kernels against the

@@ -122,9 +122,9 @@ def test_fp64_layered_jittered_seismograms(orc):
 
 
 def test_fp64_state_roundtrip_and_energy():
-    """Checkpoint and restore reproduce the run bitwise; the energy call
-    works on FP64 state and matches for identical states (to the rounding of
-    its atomic block-sum reduction)."""
+    """Checkpoint and restore reproduce the run bitwise, and with it the
+    discrete energy tracked on the last step (deterministic FP64 sums); a
+    restored state has no tracked half step until it steps."""
     import torch
     import paper_2606_12850_amd as P
     wl = W.cube_homogeneous(ne=3, n=4, nt=60, dt=0.02)
@@ -136,14 +136,55 @@ def test_fp64_state_roundtrip_and_energy():
     shape = (wl.mesh.nglob, 3)
     u, v, a = (torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3))
     it = P.semx_get_state_f64(s.ctx, u, v, a)
-    e1 = P.semx_energy(s.ctx)
     s.step(30)
     first = s.seismograms()
+    e1 = P.semx_energy(s.ctx)
     P.semx_set_state_f64(s.ctx, u, v, a, it)
-    np.testing.assert_allclose(P.semx_energy(s.ctx), e1, rtol=1e-12)
+    with pytest.raises(P.SemxError) as ei:
+        P.semx_energy(s.ctx)
+    assert ei.value.code == P.SEMX_ESTATE
     s.step(30)
     assert np.array_equal(s.seismograms(), first)
+    assert P.semx_energy(s.ctx) == e1
     s.close()
+
+
+def test_fp64_energy_identity_per_step(orc):
+    """The discrete energy balance of the scheme, step by step in FP64 storage,
+    while the source acts: E^{n+1/2} - E^{n-1/2} = 1/2 (u^{n+1} - u^{n-1})^T f_src^n
+    to 1e-12 of E; and E^{n+1/2} and the work against the oracle's to 1e-10.
+    The same balance in FP32 storage is reported (its rounding drift)."""
+    import paper_2606_12850_amd as P
+    wl = W.layered_jittered(ne=4, n=5, nt=60, dt=1.0, jitter=0.1)
+    from tests.test_gpu_timeloop import cfl_dt
+    wl.dt = cfl_dt(orc, wl.mesh, wl.lam, wl.mu, wl.rho)
+    wl.stf = W.ricker(10.0, 0.12, wl.dt, wl.nt + 1)[None, :]
+    m = wl.mesh
+    gam, jac, _ = orc.geometry(5, m.elem_vert, m.vert)
+    ref = orc.forward(5, m.ibool, gam, jac, wl.lam, wl.mu, wl.rho, m.nglob, wl.dt, wl.nt, wl.src_elem, wl.src_xi,
+                      wl.src_dir, wl.stf, wl.rec_elem, wl.rec_xi, want_energy=True)
+    res = {}
+    for storage in ("f64", "f32"):
+        s = solver64(5) if storage == "f64" else P.Solver(5)
+        s.upload_mesh(m)
+        s.upload_model(wl.lam, wl.mu, wl.rho)
+        s.setup_run(wl)
+        E, Wk = [], []
+        for _ in range(wl.nt):
+            s.step(1)
+            k, p, w = P.semx_energy(s.ctx, with_work=True)
+            E.append(k + p); Wk.append(w)
+        s.close()
+        E, Wk = np.array(E), np.array(Wk)
+        scale = np.abs(E).max()
+        bal = np.abs(np.diff(E) - np.diff(Wk)).max() / scale
+        e_or = np.abs(E - ref["energy"]).max() / scale
+        w_or = np.abs(Wk - np.cumsum(ref["work"])).max() / scale
+        res[storage] = (bal, e_or, w_or)
+        print(f"{storage}: max |dE - dW| / max E = {bal:.2e}; vs oracle: E {e_or:.2e}, work {w_or:.2e}")
+    assert res["f64"][0] <= 1e-12
+    assert res["f64"][1] <= 1e-10 and res["f64"][2] <= 1e-10
+    assert res["f32"][1] <= 1e-4
 
 
 def test_fp64_mode_errors():
