@@ -38,14 +38,29 @@ def progress(msg: str):
 NE, NGLL = 64, 5
 
 
-def bytes_per_element(n: int, nglob: int, nspec: int, geometry: str = "stored") -> float:
-    """Algorithmic HBM bytes per element per force apply (FP32, this library's layout):
-    ibool 4 n^3; geometry: Gamma 9*4 n^3 (stored per point), the 3x8 trilinear
-    coefficients 96 (rebuilt per point) or one Gamma 36 (regular); lambda*W and
-    mu*W 2*4 n^3; u read once and f written once per unique node (3*4*G/E each)."""
+def bytes_per_element_model(n: int, nglob: int, nspec: int, geometry: str = "stored") -> float:
+    """The roofline's algorithmic HBM bytes per element per force apply, for the
+    formulation with a per-point inverse Jacobian: node numbers 4 n^3, Gamma and
+    det J 10 s n^3 (10 s per element on affine elements), lambda and mu 2 s n^3,
+    u read once and f written once per unique node 3 s G/E each (s = 4, FP32).
+    Kept for every path, including those that read less (the trilinear
+    geometry, the affine numbering), so fractions compare like for like."""
+    n3 = n ** 3
+    geo = 10 * 4 * (n3 if geometry != "regular" else 1)
+    return 4 * n3 + geo + 2 * 4 * n3 + 2 * 12.0 * nglob / nspec
+
+
+def bytes_per_element(n: int, nglob: int, nspec: int, geometry: str = "stored", affine: bool = False) -> float:
+    """The bytes this library's force pass actually needs per element (FP32,
+    its layout): node numbers 4 n^3 (16 for an affine numbering); geometry:
+    Gamma 9*4 n^3 (stored; det J is folded into the material), the 3x8
+    trilinear coefficients 96 (rebuilt per point) or one Gamma 36 (regular);
+    lambda W det J and mu W det J 2*4 n^3; u read once and f written once per
+    unique node (3*4*G/E each)."""
     n3 = n ** 3
     geo = {"stored": 36 * n3, "trilinear": 96, "regular": 36}[geometry]
-    return 4 * n3 + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
+    nodes = 16 if affine else 4 * n3
+    return nodes + geo + 8 * n3 + 2 * 12.0 * nglob / nspec
 
 
 def traffic_from_profiles(src_hash: str, key: str = "trilinear"):
@@ -75,7 +90,8 @@ def write_traffic(run_dir: str):
     src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
                    for f in ("force_f32.hip", "elem_common.hpp"))
     out = {"kernel_source_sha256": hashlib.sha256(src).hexdigest(), "unit": "bytes per launch",
-           "workload": "layered jittered cube 64^3, NGLL 5, colored (8 launches of 32768 elements)"}
+           "workload": "layered jittered cube 64^3, NGLL 5, colored (8 launches of 32768 elements), "
+                       "affine node numbering"}
     for geo, gid in (("trilinear", 2), ("stored", 1)):
         d = {}
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -86,8 +102,8 @@ def write_traffic(run_dir: str):
                     agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
             cp = [v for k, vs in agg.items() if "copyBuffer" in k for v in vs][-3:]
             scale = copy_bytes / (sum(cp) / len(cp) * 1024.0)
-            for tag, pat in (("kernel", f"force_f32_kernel<5, {gid}, false, 1>"),
-                             ("skeleton", f"force_skeleton_kernel<5, {gid}>")):
+            for tag, pat in (("kernel", f"force_f32_kernel<5, {gid}, false, 1, true>"),
+                             ("skeleton", f"force_skeleton_kernel<5, {gid}, true>")):
                 kv = [v for k, vs in agg.items() if pat in k for v in vs]
                 if kv:
                     d.setdefault(tag, {})[ctr] = {
@@ -122,8 +138,14 @@ def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 200:
             break
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": nsub * n ** 3 * reps / el, "unit": "GLL-pt force evals/s",
-            "cores": O.num_threads(), "kind": "oracle",
+            "cores": O.num_threads(), "cpu_model": cpu, "kind": "oracle",
             "sample": f"FP64 oracle force apply on the first 8 of 64 element layers "
                       f"({nsub} elements, {nsub * n ** 3} GLL points), {reps} applies in {el:.1f} s"}
 
@@ -325,11 +347,61 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
             "gain": round(t_sem / t_sur, 3), "calibration": cal}
 
 
+def mlp_profile(steps: int = 200, infer_batches: int = 4):
+    """The surrogate network's kernels alone (64 -> 512 -> 512 -> 512 -> 24,576,
+    SiLU, BF16 matrix-core GEMMs with FP32 accumulation): `steps` training
+    steps at batch 128 (forward, MSE, backward, Adam) on synthetic data, then
+    `infer_batches` inference batches of 4096.  Time per step and achieved
+    TFLOP/s on the GEMM flops (2 x multiply-adds of the three GEMMs per layer
+    in training, one in inference), against the 2.5 PFLOP/s dense BF16 peak."""
+    import numpy as np
+    import torch
+
+    import paper_2606_12850_amd as P
+    widths = [64, 512, 512, 512, 24576]
+    net = P.semx_mlp_create(widths, 4096)
+    nparam = P.semx_mlp_num_params(net)
+    rng = np.random.default_rng(0)
+    P.semx_mlp_set_params(net, (rng.standard_normal(nparam) * 0.02).astype(np.float32))
+    x = torch.randn((4096, widths[0]), device="cuda")
+    t = torch.randn((128, widths[-1]), device="cuda")
+    y = torch.empty((4096, widths[-1]), device="cuda")
+    dy = torch.empty((128, widths[-1]), device="cuda")
+    macs = sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1))
+
+    def train(k0, k):
+        for i in range(k):
+            P.semx_mlp_forward(net, x, 128, y)
+            P.semx_mlp_mse(net, y[:128], t, 128 * widths[-1], dy, want_loss=False)
+            P.semx_mlp_backward(net, dy, 128)
+            P.semx_mlp_adam(net, 1e-4, 0.9, 0.999, 1e-8, k0 + i + 1)
+    train(0, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    train(10, steps)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    # training: forward, weight gradient and input gradient (none for layer 0)
+    flops_step = 2 * 128 * (3 * macs - widths[0] * widths[1])
+    P.semx_mlp_forward(net, x, 4096, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(infer_batches):
+        P.semx_mlp_forward(net, x, 4096, y)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / infer_batches
+    P.semx_mlp_destroy(net)
+    return {"widths": widths, "train_batch": 128, "train_ms_per_step": round(t_step * 1e3, 4),
+            "train_tflops": round(flops_step / t_step / 1e12, 3),
+            "infer_batch": 4096, "infer_ms": round(t_inf * 1e3, 4),
+            "infer_tflops": round(2 * 4096 * macs / t_inf / 1e12, 3), "peak_tflops_bf16": 2500.0}
+
+
 ORDER_SWEEP = [(4, 90), (5, 68), (6, 54), (7, 45), (8, 39), (9, 34), (10, 30), (11, 27), (12, 25), (13, 23),
                (14, 21), (15, 19), (16, 18)]  # (NGLL, elements per side): ~2e7 points
 
 
-def order_sweep_leg(reps: int = 20):
+def order_sweep_leg(reps: int = 20, orders=None):
     """Force apply at about 2e7 unique points for NGLL 4..16 (element size
     h = N * 69.3 / 5 m, about five GLL points per minimum wavelength of a
     25 Hz wave at vs = 1732 m/s), homogeneous medium times a +-5 % random
@@ -345,6 +417,8 @@ def order_sweep_leg(reps: int = 20):
     log = lambda m: print(f"[order-sweep] {m}", file=sys.stderr, flush=True)
     rows = []
     for n, ne in ORDER_SWEEP:
+        if orders is not None and n not in orders:
+            continue
         N = n - 1
         h = N * 69.3 / 5
         mesh = W.box_mesh(ne, n, ne * h)
@@ -370,7 +444,8 @@ def order_sweep_leg(reps: int = 20):
         del u_np, xs, g
         f = torch.empty_like(u)
         row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2), "device_bytes": device_bytes}
-        b_elem = bytes_per_element(n, G, mesh.nspec, "regular")
+        b_model = bytes_per_element_model(n, G, mesh.nspec, "regular")
+        b_elem = bytes_per_element(n, G, mesh.nspec, "regular", affine=n <= 10)
         # full explicit step (FP32, coloured) from a nonzero state, CFL time step
         dt = P.semx_cfl_dt(s.ctx, 0.4)
         P.semx_set_dt(s.ctx, dt)
@@ -401,7 +476,10 @@ def order_sweep_leg(reps: int = 20):
             ms = e0.elapsed_time(e1) / reps
             row[f"{cname}_ms"] = round(ms, 4)
             row[f"{cname}_gll_pts_per_s"] = mesh.nspec * n ** 3 / (ms * 1e-3)
-            row[f"{cname}_hbm_frac_alg"] = round(b_elem * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            row[f"{cname}_hbm_frac"] = round(b_model * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            row[f"{cname}_hbm_frac_impl"] = round(b_elem * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            if cname != "f32" and "f32_ms" in row:
+                row[f"{cname}_speedup_vs_f32"] = round(row["f32_ms"] / ms, 3)
             if ref is None:
                 ref = f.clone()
             else:
@@ -485,10 +563,12 @@ def single_order_apply(n: int, reps: int):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular")
+    bm = bytes_per_element_model(n, mesh.nglob, mesh.nspec, "regular")
+    be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular", affine=n <= 10)
     return {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
-            "launches_per_apply": info["ncolors"], "bytes_per_element": be,
-            "hbm_frac_alg": round(be * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "launches_per_apply": info["ncolors"], "bytes_per_element": bm, "bytes_per_element_impl": be,
+            "hbm_frac": round(bm * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "hbm_frac_impl": round(be * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "skeleton_ms_per_apply": round(sk, 4), "frac_of_skeleton": round(sk / ms, 4),
             "copy_bytes_each_way": nbytes}
 
@@ -705,13 +785,19 @@ def main():
                     help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
                          "device copy (calibration for HBM traffic counters); prints one JSON line")
     ap.add_argument("--contraction", choices=["f32", "mf32", "bf16", "f16"], default="f32")
+    ap.add_argument("--profile-mlp", action="store_true",
+                    help="time only the surrogate network's training and inference kernels (for counter runs)")
     ap.add_argument("--surrogate", action="store_true",
-                    help="also run the learned-surrogate leg (16^3 box, several minutes)")
+                    help="run the learned-surrogate leg at its full model counts (several minutes)")
     ap.add_argument("--surrogate-f0", type=float, default=10.0)
     ap.add_argument("--surrogate-scale", type=float, default=1.0,
                     help="fraction of the surrogate leg's model counts and epochs (quick checks)")
-    ap.add_argument("--order-sweep", action="store_true",
-                    help="also time the force apply for NGLL 4..9 at ~2e7 points (FP32 and mixed)")
+    ap.add_argument("--no-order-sweep", action="store_true",
+                    help="skip the order sweep (NGLL 4..9 at ~2e7 points, FP32 and mixed)")
+    ap.add_argument("--order-sweep-full", action="store_true",
+                    help="extend the order sweep to NGLL 16 (the column kernels) with the equal-accuracy summaries")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the bounded surrogate leg (16^3 box at 10 Hz, reduced model counts)")
     ap.add_argument("--write-traffic", metavar="DIR",
                     help="no GPU: read the four rocprofv3 --pmc runs of --profile-force (DIR/pmc_<geometry>_"
                          "<counter>/run_counter_collection.csv) and write profiles/force_traffic.json")
@@ -735,6 +821,9 @@ def main():
     CONTRACTION = {"f32": P.SEMX_C_F32, "mf32": P.SEMX_C_MFMA_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}
     ASSEMBLY = {"colored": P.SEMX_ASM_COLORED, "atomic": P.SEMX_ASM_ATOMIC}
     torch.cuda.set_device(0)
+    if args.profile_mlp:
+        print(json.dumps({"mlp": mlp_profile()}))
+        return
     if args.sweep_order:
         print(json.dumps({"sweep_order": single_order_apply(args.sweep_order, args.apply_reps)}))
         return
@@ -767,33 +856,70 @@ def main():
     stream = s.stream
     E, n3 = mesh.nspec, NGLL ** 3
     geo_of = (lambda g: g if info["nirregular"] > 0 else "regular")
-    b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry))
+    # the roofline's byte model (per-point inverse Jacobian) and what this path reads
+    b_model = bytes_per_element_model(NGLL, mesh.nglob, E, geo_of(args.geometry))
+    b_elem = bytes_per_element(NGLL, mesh.nglob, E, geo_of(args.geometry), affine=args.assembly == "colored")
 
-    # ---- force apply alone (FP32 and mixed contractions, coloured and atomic),
-    #      event-timed on the library stream
+    # ---- force apply alone (FP32 and mixed contractions, coloured and atomic):
+    #      median over `apply_reps` applies after 10 warm-ups, each apply
+    #      bracketed by an event pair on the library stream; the mixed modes
+    #      carry their relative L2 difference from the FP32 force on a random
+    #      and on a smooth displacement
     u = (torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5)
     f = torch.empty_like(u)
+    g_idx = torch.arange(mesh.nglob, device="cuda", dtype=torch.float64)
+    Gx = mesh.nex * (NGLL - 1) + 1
+    kx = 2.0 * np.pi / (Gx - 1)
+    xs = (g_idx % Gx, (g_idx // Gx) % Gx, g_idx // (Gx * Gx))
+    u_smooth = torch.stack([torch.sin(kx * xs[0] + 0.3) * torch.cos(kx * xs[1]),
+                            torch.cos(kx * xs[1] + 0.7) * torch.sin(kx * xs[2]),
+                            torch.sin(kx * xs[2] + 1.1) * torch.cos(kx * xs[0])], dim=1).float().contiguous()
+    del g_idx, xs
     combos = [(c, g, a) for c in ("f32", "mf32", "bf16", "f16") for g in ("stored", "trilinear")
               for a in ("colored", "atomic") if c == "f32" or a == "colored"]
     if args.profile_force:
         combos = [(args.contraction, args.geometry, args.assembly)]
     apply = {}
+    ref_f32 = {}
     for cname, gname, aname in combos:
         P.semx_set_geometry(s.ctx, GEOM[gname])
         P.semx_set_mode(s.ctx, CONTRACTION[cname], ASSEMBLY[aname])
-        bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname))
-        for _ in range(5):
+        bm = bytes_per_element_model(NGLL, mesh.nglob, E, geo_of(gname))
+        bg = bytes_per_element(NGLL, mesh.nglob, E, geo_of(gname),
+                               affine=cname == "f32" and aname == "colored")
+        for _ in range(10):
             P.semx_apply_force(s.ctx, u, f)
-        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        ts = []
         for _ in range(args.apply_reps):
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             P.semx_apply_force(s.ctx, u, f)
-        e1.record(stream)
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / args.apply_reps
-        apply[f"{cname}_{gname}_{aname}"] = {
-            "ms_per_apply": round(ms, 4), "gll_pts_per_s": E * n3 / (ms * 1e-3), "bytes_per_element": bg,
-            "hbm_frac_alg": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        row = {"ms_per_apply": round(ms, 4), "ms_min": round(float(np.min(ts)), 4),
+               "gll_pts_per_s": E * n3 / (ms * 1e-3),
+               "hbm_frac": round((bm * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4),
+               "bytes_per_element_impl": bg,
+               "hbm_frac_impl": round((bg * E / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9), 4)}
+        if not args.profile_force:
+            outs = []
+            for uu in (u, u_smooth):
+                P.semx_apply_force(s.ctx, uu, f)
+                outs.append(f.clone())
+            if cname == "f32" and aname == "colored":
+                ref_f32[gname] = outs
+            elif gname in ref_f32:
+                for lab, a_, b_ in zip(("random", "smooth"), outs, ref_f32[gname]):
+                    row[f"rel_diff_vs_f32_{lab}"] = (torch.linalg.norm(a_ - b_) / torch.linalg.norm(b_)).item()
+        apply[f"{cname}_{gname}_{aname}"] = row
+    del u_smooth
+    fa = apply.get(f"f32_{args.geometry}_{args.assembly}")
+    for cname in ("bf16", "f16", "mf32"):
+        mx = apply.get(f"{cname}_{args.geometry}_colored")
+        if fa and mx:
+            mx["speedup_vs_f32"] = round(fa["ms_per_apply"] / mx["ms_per_apply"], 3)
     progress(f"force-apply matrix done ({len(apply)} variants)")
     if args.profile_force:
         sk = None
@@ -860,8 +986,9 @@ def main():
         del uu, ff
         skeleton = {"skeleton_ms_per_launch": round(sk_launch_ms, 5),
                     "frac_of_skeleton": round(sk_launch_ms / avg_launch_ms, 4)}
-    bytes_per_launch = b_elem * E / launches_per_apply
+    bytes_per_launch = b_model * E / launches_per_apply
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    achieved_impl = b_elem * E / launches_per_apply / (avg_launch_ms * 1e-3) / 1e9
     src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
                    for f in ("force_f32.hip", "elem_common.hpp"))
     src_hash = hashlib.sha256(src).hexdigest()
@@ -889,11 +1016,19 @@ def main():
                    "nregular": info["nregular"], "nirregular": info["nirregular"], "ncolors": info["ncolors"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"force_f32_kernel<5, {args.geometry}, {args.assembly}>",
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_launch_ms, 5),
-                     "launches": launches, "timed_pass_stride": stride, "bytes_per_element": b_elem,
+                     "kernel": f"force_f32_kernel<5, {args.geometry}, {args.assembly}"
+                               + (", affine numbering>" if args.assembly == "colored" else ">"),
+                     "bytes_model": "4 n^3 + 10 s n^3 + 2 s n^3 + 6 s G/E (node numbers, Gamma and det J per "
+                                    "point, lambda and mu, u read and f written once per unique node; s = 4)",
+                     "bytes_per_element": b_model, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches, "timed_pass_stride": stride,
+                     "bytes_per_element_impl": b_elem, "achieved_impl": round(achieved_impl, 1),
+                     "frac_impl": round(achieved_impl / HBM_PEAK_GBS, 4),
+                     "launch_ms_for_frac_0.6": round(bytes_per_launch / (0.6 * HBM_PEAK_GBS * 1e9) * 1e3, 5),
                      "bw_copy": round(bw_copy, 1), "frac_of_copy": round(achieved / bw_copy, 4),
                      **(skeleton or {})},
+        "force_apply_median": {"ms_per_apply": fa["ms_per_apply"], "gll_pts_per_s": fa["gll_pts_per_s"],
+                               "hbm_frac": fa["hbm_frac"], "applies": args.apply_reps, "warmup": 10} if fa else None,
         "unique_nodes_per_s": mesh.nglob / (step_ms * 1e-3),
         "force_apply": apply,
         "wall_s_timed": round(wall, 3),
@@ -904,14 +1039,20 @@ def main():
         out["acoustic"] = acoustic_leg(mesh)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
-    if args.order_sweep:
-        out["order_sweep"] = order_sweep_leg()
-        out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]
-        out["equal_accuracy_acoustic_sizes"] = acoustic_frontier_summary(out["order_sweep"])
-    if args.surrogate:
-        k = args.surrogate_scale
+    if not args.no_order_sweep:
+        full = args.order_sweep_full
+        out["order_sweep"] = order_sweep_leg(orders=None if full else (4, 5, 6, 7, 8, 9))
+        progress("order sweep done")
+        if full:
+            out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]
+            out["equal_accuracy_acoustic_sizes"] = acoustic_frontier_summary(out["order_sweep"])
+    if args.surrogate or not args.no_surrogate:
+        # bounded by default: the 10 Hz workload at reduced model counts and epochs
+        k = args.surrogate_scale if args.surrogate else 0.25
         out["surrogate"] = surrogate_leg(f0=args.surrogate_f0, ntrain=max(64, int(4500 * k)), nval=max(64, int(500 * k)),
                                          ntest=max(64, int(4096 * k)), epochs=max(5, int(300 * k)))
+        out["surrogate"]["scale"] = k
+        progress("surrogate leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
         if "acoustic" in out:
