@@ -10,7 +10,9 @@ receivers, components and samples (the stated seismogram tolerance after
   layered16  16^3 jittered layered cube, 8 receivers, 1000 steps (coloured and atomic)
   adjoint32  32^3 layered cube with the -5 % anomaly, 64 receivers, 1000 steps
   layered64  64^3 jittered layered cube, 8 receivers, 2000 steps; the error
-             over the first 100 steps is reported too
+             over the first 100 steps is reported too (those samples are
+             exactly zero on both sides: the first arrival reaches the
+             receivers later, so the 2000-step figure is the one that counts)
 """
 import os
 import sys
