@@ -1,0 +1,344 @@
+// FP32 element internal-force kernel for NGLL 16 on the matrix cores.
+//
+// The operator is that of force_f32.hip and force_high.hip (Sec. II-B weak
+// form: three forward and three transpose sum-factorised contractions with
+// the 16 x 16 derivative matrix D around the pointwise Gamma map, isotropic
+// stress and weighted flux; Sec. IV-D fused traversal).  At NGLL 16 every
+// contraction is an exact 16 x 16 x 16 matrix product, so all six run as
+// v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation, four K = 4 steps
+// per product) and the vector units keep only the pointwise work.
+//
+// Layout.  One workgroup per element, 16 waves.  The matrix-core result tile
+// gives lane l of a wave the rows 4 g + t (t = 0..3) of column c, with
+// g = l / 16, c = l % 16; the kernel uses that as its point layout:
+//   S layout (wave w = slice k):        lane holds (i = 4g+t, j = c, k = w)
+//   Z layout (wave w = plane j):        lane holds (i = c, j = w, k = 4g+t)
+// Summing the contraction index in the order b = 4 g + m (step m = 0..3,
+// lane group g) makes the B operand of step m the lane's own point t = m,
+// so the xi contractions (forward and transpose) read registers only, and
+// the D operands are eight constant registers per lane:
+//   Dr[m] = D[c][4g+m],  Dt[m] = D[4g+m][c].
+// The eta contractions take their other operand transposed from LDS and land
+// in S layout too; the zeta contractions need the contraction index k in the
+// tile, so they run in Z layout and exchange operands and results with the S
+// layout through LDS.  Per element: 36 + 36 matrix instructions per wave.
+//
+// LDS: three regions of 3 x 4096 floats (144 KB, so one workgroup per
+// compute unit): R0 = u, later the eta fluxes; R1 = zeta derivatives, later
+// the zeta transpose result; R2 = the zeta fluxes.  Four barriers per element.
+//
+// Assembly as in the other element kernels: read-modify-write inside a
+// colour (first-touch stores when the launch carries them) or FP32 atomics.
+#include <algorithm>
+
+#include "elem_common.hpp"
+
+namespace semx {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kN = 16;
+constexpr int kN3 = kN * kN * kN;
+constexpr int kWaves = 16;
+constexpr int kBlk = 64 * kWaves;
+
+// LDS word of element-local point (i, j, k) in one 4096-float field: rows of
+// 16 along i with two XOR swizzles, a bijection of the field.  The 4 low-row
+// bits of j pick one of four 16-word windows and the row's 4-word groups are
+// permuted by j, so that
+//   * the S-layout row reads and writes (16 bytes per lane: i = 4g .. 4g+3,
+//     j = c) give the 16 lanes of each group distinct 16-byte bank groups,
+//   * the transposed S reads (i = c, j = 4g+m) and the Z-layout accesses
+//     (i = c, k = 4g+m) give the 64 lanes 64 distinct banks.
+__device__ __forceinline__ int lds_at(int i, int j, int k) {
+  return (i ^ (j & 12)) + 16 * (j ^ (((j >> 2) ^ (k >> 2)) & 3)) + 256 * k;
+}
+
+__device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 ld4(const float* s) { return *reinterpret_cast<const f32x4*>(s); }
+__device__ __forceinline__ void st4(float* s, f32x4 v) { *reinterpret_cast<f32x4*>(s) = v; }
+
+// What the element loop requests ahead of an element's arithmetic: its node
+// numbers (computed on the affine path), first-touch word, u and material.
+struct Ahead {
+  int node[4];
+  uint32_t fw;
+  float uo[3][4];
+  f32x4 lam4, mu4;
+};
+
+template <bool ATOMIC, bool AFF>
+__device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __restrict__ u, int model, int pos,
+                                           int q0, int g, int c, int w, Ahead& h) {
+  if constexpr (AFF) {
+    const int32_t* r = a.aff + (size_t)pos * 4;
+    const int base = r[0] + c * r[2] + w * r[3];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h.node[t] = base + (4 * g + t) * r[1];
+  } else {
+    const int4 nd = *reinterpret_cast<const int4*>(a.ibool + (size_t)pos * kN3 + q0);
+    h.node[0] = nd.x;
+    h.node[1] = nd.y;
+    h.node[2] = nd.z;
+    h.node[3] = nd.w;
+  }
+  h.fw = 0;
+  if constexpr (!ATOMIC) {
+    if (a.first) h.fw = a.first[(size_t)pos * a.first_words + (q0 >> 5)] >> (q0 & 31);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) h.uo[e][t] = u[3 * (size_t)h.node[t] + e];
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * kN3 + (size_t)pos * 2 * kN3;
+  h.lam4 = ld4(mat + q0);
+  h.mu4 = ld4(mat + kN3 + q0);
+}
+
+// Element loop.  Regular path: the grid holds one workgroup per compute unit
+// (one fills its LDS) and each walks its share of the launch, dealt XCD by
+// XCD as in xcd_group (the workgroups on XCD x take the x-th eighth of the
+// range, in steps of the number of workgroups there); the next element's node
+// numbers, u and material are requested before the current one's last two
+// barriers, so that their latency hides behind its transpose contractions and
+// assembly.  With per-point geometry the registers are full: one element per
+// workgroup, its loads requested at its start.  Inside a colour the prior f
+// at the element's nodes is read at the start of its arithmetic (no other
+// workgroup of the launch touches those nodes).
+template <int GEO, bool ATOMIC, bool AFF>
+__global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
+  constexpr bool AHEAD = GEO == kRegular;  // persistent, next element requested ahead
+  __shared__ __attribute__((aligned(16))) float r0[3 * kN3];
+  __shared__ __attribute__((aligned(16))) float r1[3 * kN3];
+  __shared__ __attribute__((aligned(16))) float r2[3 * kN3];
+
+  const int ngrp = (int)a.count;
+  const int gpx = (ngrp + kNumXcd - 1) / kNumXcd;
+  const int per_xcd = (int)gridDim.x / kNumXcd;
+  const int xbeg = ((int)blockIdx.x % kNumXcd) * gpx;
+  const int xend = min(xbeg + gpx, ngrp);
+  int grp = xbeg + (int)blockIdx.x / kNumXcd;
+  if (grp >= xend) return;  // uniform over the block
+
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4, c = l & 15;
+  const int model = blockIdx.y;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
+  float* f = a.f + (size_t)model * a.nglob * 3;
+  const int q0 = 4 * g + kN * c + kN * kN * w;  // own points (S layout): q0 + t
+  const int sS = lds_at(4 * g, c, w);            // first of the 4 contiguous LDS words of the own points
+
+  float Dr[4], Dt[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    Dr[m] = a.D[c * kN + 4 * g + m];
+    Dt[m] = a.D[(4 * g + m) * kN + c];
+  }
+  float ry = 0.f, rz = 0.f;
+  if constexpr (GEO == kTrilinear) {
+    ry = a.xi[c];
+    rz = a.xi[w];
+  }
+
+  Ahead cur;
+  if constexpr (AHEAD) load_ahead<ATOMIC, AFF>(a, u, model, (int)a.pos0 + grp, q0, g, c, w, cur);
+  for (;;) {
+    const int pos = (int)a.pos0 + grp;
+    if constexpr (!AHEAD) load_ahead<ATOMIC, AFF>(a, u, model, pos, q0, g, c, w, cur);
+    float fo[3][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        fo[e][t] = (ATOMIC || ((cur.fw >> t) & 1u)) ? 0.0f : f[3 * (size_t)cur.node[t] + e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      st4(r0 + e * kN3 + sS, f32x4{cur.uo[e][0], cur.uo[e][1], cur.uo[e][2], cur.uo[e][3]});
+    __syncthreads();  // B1: u in R0
+
+    // ---- forward contractions ----
+    f32x4 dx[3], dy[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f}, z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x = mma(Dr[m], cur.uo[e][m], x);                               // sum_b D[i][b] u(b, j, k)
+        y = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dr[m], y);      // sum_b u(i, b, k) D[j][b]
+        z = mma(Dr[m], r0[e * kN3 + lds_at(c, w, 4 * g + m)], z);      // sum_b D[k][b] u(i, j, b)  (Z)
+      }
+      dx[e] = x;
+      dy[e] = y;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
+    }
+    __syncthreads();  // B2: zeta derivatives in R1; R0 free
+    f32x4 dz[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) dz[e] = ld4(r1 + e * kN3 + sS);
+
+    // ---- pointwise: geometry map, stress, weighted fluxes ----
+    const float* src = nullptr;
+    if constexpr (GEO == kTrilinear) src = a.tri + (size_t)pos * 24;
+    if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
+    f32x4 gam4[9];
+    if constexpr (GEO == kStored) {
+      const float* gp = a.gam_pt + (size_t)pos * 9 * kN3 + q0;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) gam4[d] = ld4(gp + d * kN3);
+    }
+    f32x4 p0[3], p1[3], p2[3];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float du[3][3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        du[e][0] = dx[e][t];
+        du[e][1] = dy[e][t];
+        du[e][2] = dz[e][t];
+      }
+      float G[9];
+      if constexpr (GEO == kStored) {
+#pragma unroll
+        for (int d = 0; d < 9; ++d) G[d] = gam4[d][t];
+      }
+      const float rx = (GEO == kTrilinear) ? a.xi[4 * g + t] : 0.f;
+      float Mg[9], scale, det;
+      geom_map_from<GEO>(src, G, rx, ry, rz, Mg, scale, det);
+      float gr[3][3];
+      apply_map(du, Mg, gr);
+      const float lw = cur.lam4[t], mw = cur.mu4[t];
+      const float ltr = lw * (gr[0][0] + gr[1][1] + gr[2][2]);
+      float sg[3][3];
+      sg[0][0] = ltr + 2.0f * mw * gr[0][0];
+      sg[1][1] = ltr + 2.0f * mw * gr[1][1];
+      sg[2][2] = ltr + 2.0f * mw * gr[2][2];
+      sg[0][1] = sg[1][0] = mw * (gr[0][1] + gr[1][0]);
+      sg[0][2] = sg[2][0] = mw * (gr[0][2] + gr[2][0]);
+      sg[1][2] = sg[2][1] = mw * (gr[1][2] + gr[2][1]);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        float ph[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          ph[d] = scale * (sg[e][0] * Mg[d * 3 + 0] + sg[e][1] * Mg[d * 3 + 1] + sg[e][2] * Mg[d * 3 + 2]);
+        p0[e][t] = ph[0];
+        p1[e][t] = ph[1];
+        p2[e][t] = ph[2];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      st4(r0 + e * kN3 + sS, p1[e]);
+      st4(r2 + e * kN3 + sS, p2[e]);
+    }
+    // ---- transpose contractions ----
+    f32x4 F[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      f32x4 x = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x = mma(Dt[m], p0[e][m], x);  // sum_a D[a][i] phi0(a, j, k)
+      F[e] = x;
+    }
+    const int nxt = grp + per_xcd;
+    const bool more = AHEAD && nxt < xend;  // uniform over the block
+    Ahead ahead;
+    if constexpr (AHEAD) {
+      if (more) load_ahead<ATOMIC, AFF>(a, u, model, (int)a.pos0 + nxt, q0, g, c, w, ahead);
+    }
+    __syncthreads();  // B3: eta fluxes in R0, zeta fluxes in R2; R1 free
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      f32x4 x = F[e], z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dt[m], x);  // sum_a phi1(i, a, k) D[a][j]
+        z = mma(Dt[m], r2[e * kN3 + lds_at(c, w, 4 * g + m)], z);  // sum_a D[a][k] phi2(i, j, a)  (Z)
+      }
+      F[e] = x;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
+    }
+    __syncthreads();  // B4: zeta transpose result in R1 (R0, R2 free for the next element)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) F[e] += ld4(r1 + e * kN3 + sS);
+
+    // ---- assembly ----
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float* fg = f + 3 * (size_t)cur.node[t];
+      if constexpr (ATOMIC) {
+        unsafeAtomicAdd(fg + 0, -F[0][t]);
+        unsafeAtomicAdd(fg + 1, -F[1][t]);
+        unsafeAtomicAdd(fg + 2, -F[2][t]);
+      } else {
+        fg[0] = fo[0][t] - F[0][t];
+        fg[1] = fo[1][t] - F[1][t];
+        fg[2] = fo[2][t] - F[2][t];
+      }
+    }
+    if (!AHEAD || !more) break;
+    grp = nxt;
+    if constexpr (AHEAD) cur = ahead;
+  }
+}
+
+// Workgroups of the persistent grid: one per compute unit of the current
+// device, rounded up to a multiple of the XCD count.
+int64_t resident_groups() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    cache[dev] = ((ncu + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  }
+  return cache[dev];
+}
+
+template <int GEO, bool ATOMIC, bool AFF>
+hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
+  int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  if (GEO == kRegular) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
+  dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
+  force_tile16_kernel<GEO, ATOMIC, AFF><<<grid, block, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <bool AFF>
+hipError_t launch_t16_geo(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  switch (geo) {
+    case kRegular:
+      return atomic ? launch_t16<kRegular, true, AFF>(a, s) : launch_t16<kRegular, false, AFF>(a, s);
+    case kStored:
+      return atomic ? launch_t16<kStored, true, AFF>(a, s) : launch_t16<kStored, false, AFF>(a, s);
+    case kTrilinear:
+      return atomic ? launch_t16<kTrilinear, true, AFF>(a, s) : launch_t16<kTrilinear, false, AFF>(a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_force_tile16(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  // the launch's first naff elements have an affine numbering
+  naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
+  ForceArgs b = a;
+  b.count = naff;
+  hipError_t e = launch_t16_geo<true>(geo, atomic, b, s);
+  if (e != hipSuccess || naff == a.count) return e;
+  b.pos0 = a.pos0 + naff;
+  b.count = a.count - naff;
+  return launch_t16_geo<false>(geo, atomic, b, s);
+}
+
+}  // namespace semx

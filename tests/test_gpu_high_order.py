@@ -1,5 +1,6 @@
-"""High orders NGLL 11..16 (polynomial degree up to 15) on the column kernel
-against the FP64 oracle (GPU).
+"""High orders NGLL 11..16 (polynomial degree up to 15) against the FP64
+oracle (GPU): the column kernel (NGLL 11..15) and the matrix-core kernel
+(NGLL 16).
 
 Bars as for the lower orders: force 1e-5 relative L2 (FP32), seismograms
 1e-4 after the run.  The meshes are small (NGLL 16 has 4096 points per
@@ -93,6 +94,28 @@ def test_high_order_seismograms(orc, n):
         s.close()
         print(f"n={n} asm={asm}: seismogram rel L2 = {err:.3e}")
         assert err <= TOL_SEIS
+
+
+def test_ngll16_matrix_core_mode_is_the_fp32_path():
+    """At NGLL 16 the FP32 path already contracts on the matrix cores with
+    FP32 operands: SEMX_C_MFMA_F32 selects the same kernel (identical bits);
+    16-bit operands are not offered there."""
+    import paper_2606_12850_amd as P
+    mesh = W.box_mesh((2, 2, 1), 16, 3000.0, jitter=0.1, seed=4)
+    lam, mu, rho = W.layered_model(mesh, grf_amp=0.05, grf_seed=2, grf_corr_elems=1.5)
+    s = make_solver(16)
+    s.upload_mesh(mesh)
+    s.upload_model(lam, mu, rho)
+    u = np.random.default_rng(8).uniform(-1, 1, (mesh.nglob, 3))
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED)
+    a = gpu_force(s, u)
+    s.set_mode(P.SEMX_C_MFMA_F32, P.SEMX_ASM_COLORED)
+    assert np.array_equal(gpu_force(s, u), a)
+    for cp in (P.SEMX_C_BF16, P.SEMX_C_F16):
+        with pytest.raises(P.SemxError) as ei:
+            P.semx_set_mode(s.ctx, cp, P.SEMX_ASM_COLORED)
+        assert ei.value.code == P.SEMX_EINVAL
+    s.close()
 
 
 def test_high_order_limits():
