@@ -152,10 +152,15 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     if constexpr (!AHEAD) load_ahead<ATOMIC, AFF>(a, u, model, pos, q0, g, c, w, cur);
     float fo[3][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int e = 0; e < 3; ++e)
-        fo[e][t] = (ATOMIC || ((cur.fw >> t) & 1u)) ? 0.0f : f[3 * (size_t)cur.node[t] + e];
+    for (int t = 0; t < 4; ++t) {
+      fo[0][t] = fo[1][t] = fo[2][t] = 0.0f;
+      if (!ATOMIC && !((cur.fw >> t) & 1u)) {  // the point's three values in one request
+        const float* fp = f + 3 * (size_t)cur.node[t];
+        fo[0][t] = fp[0];
+        fo[1][t] = fp[1];
+        fo[2][t] = fp[2];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 3; ++e)
       st4(r0 + e * kN3 + sS, f32x4{cur.uo[e][0], cur.uo[e][1], cur.uo[e][2], cur.uo[e][3]});
