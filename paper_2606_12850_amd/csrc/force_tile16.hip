@@ -59,6 +59,66 @@ __device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// 16-bit operands: one v_mfma_f32_16x16x32_{bf16,f16} per 16 x 16 x 16
+// product.  Lane group g supplies the K slots 8 g .. 8 g + 7 (A row / B
+// column l % 16); slot 8 g + t (t < 4) carries contraction index 4 g + t and
+// the upper four slots are zero, so the operands are the same values the
+// FP32 path feeds to its four K = 4 steps.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <int PREC>
+struct Low;
+template <>
+struct Low<SEMX_C_BF16> {
+  using vec = bf16x8;
+  using elt = __bf16;
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Low<SEMX_C_F16> {
+  using vec = f16x8;
+  using elt = _Float16;
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Low<SEMX_C_F32> {  // unused placeholder so that the FP32 instantiation compiles
+  using vec = f16x8;
+  using elt = _Float16;
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) { return c; }
+};
+
+// x0..x3 (times s) in the low four slots of a 16-bit operand
+template <int PREC>
+__device__ __forceinline__ typename Low<PREC>::vec pack4(float x0, float x1, float x2, float x3) {
+  using elt = typename Low<PREC>::elt;
+  typename Low<PREC>::vec v;
+  v[0] = (elt)x0;
+  v[1] = (elt)x1;
+  v[2] = (elt)x2;
+  v[3] = (elt)x3;
+  v[4] = v[5] = v[6] = v[7] = (elt)0.0f;
+  return v;
+}
+
+// power of two p with p * x in [0.5, 1) (1 for x = 0)
+__device__ __forceinline__ float pow2_scale(float x) {
+  if (!(x > 0.0f)) return 1.0f;
+  int e;
+  frexpf(x, &e);
+  return ldexpf(1.0f, -e);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// a value that is the same on every lane, moved to a scalar register
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ __forceinline__ f32x4 ld4(const float* s) { return *reinterpret_cast<const f32x4*>(s); }
 __device__ __forceinline__ void st4(float* s, f32x4 v) { *reinterpret_cast<f32x4*>(s) = v; }
 
@@ -71,7 +131,13 @@ struct Ahead {
   f32x4 lam4, mu4;
 };
 
-template <bool ATOMIC, bool AFF>
+__device__ __forceinline__ void load_mat(const ForceArgs& a, int model, int pos, int q0, Ahead& h) {
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * kN3 + (size_t)pos * 2 * kN3;
+  h.lam4 = ld4(mat + q0);
+  h.mu4 = ld4(mat + kN3 + q0);
+}
+
+template <bool ATOMIC, bool AFF, bool MAT>
 __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __restrict__ u, int model, int pos,
                                            int q0, int g, int c, int w, Ahead& h) {
   if constexpr (AFF) {
@@ -94,9 +160,7 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int e = 0; e < 3; ++e) h.uo[e][t] = u[3 * (size_t)h.node[t] + e];
-  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * kN3 + (size_t)pos * 2 * kN3;
-  h.lam4 = ld4(mat + q0);
-  h.mu4 = ld4(mat + kN3 + q0);
+  if constexpr (MAT) load_mat(a, model, pos, q0, h);
 }
 
 // Element loop.  Regular path: the grid holds one workgroup per compute unit
@@ -109,12 +173,18 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
 // workgroup, its loads requested at its start.  Inside a colour the prior f
 // at the element's nodes is read at the start of its arithmetic (no other
 // workgroup of the launch touches those nodes).
-template <int GEO, bool ATOMIC, bool AFF>
+template <int GEO, bool ATOMIC, bool AFF, int PREC>
 __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   constexpr bool AHEAD = GEO == kRegular;  // persistent, next element requested ahead
+  constexpr bool LOW = PREC == SEMX_C_BF16 || PREC == SEMX_C_F16;
+  constexpr bool MAT_AHEAD = AHEAD && !LOW;  // 16-bit operands need the registers: material at the start
+  constexpr bool SCALE = PREC == SEMX_C_F16;  // BF16 has the FP32 exponent range
+  using L = Low<PREC>;
+  using lvec = typename L::vec;
   __shared__ __attribute__((aligned(16))) float r0[3 * kN3];
   __shared__ __attribute__((aligned(16))) float r1[3 * kN3];
   __shared__ __attribute__((aligned(16))) float r2[3 * kN3];
+  __shared__ float s_red[2][kWaves];  // FP16: per-wave maxima of the operands
 
   const int ngrp = (int)a.count;
   const int gpx = (ngrp + kNumXcd - 1) / kNumXcd;
@@ -139,6 +209,11 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     Dr[m] = a.D[c * kN + 4 * g + m];
     Dt[m] = a.D[(4 * g + m) * kN + c];
   }
+  lvec Dr16{}, Dt16{};
+  if constexpr (LOW) {
+    Dr16 = pack4<PREC>(Dr[0], Dr[1], Dr[2], Dr[3]);
+    Dt16 = pack4<PREC>(Dt[0], Dt[1], Dt[2], Dt[3]);
+  }
   float ry = 0.f, rz = 0.f;
   if constexpr (GEO == kTrilinear) {
     ry = a.xi[c];
@@ -146,10 +221,11 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   }
 
   Ahead cur;
-  if constexpr (AHEAD) load_ahead<ATOMIC, AFF>(a, u, model, (int)a.pos0 + grp, q0, g, c, w, cur);
+  if constexpr (AHEAD) load_ahead<ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + grp, q0, g, c, w, cur);
   for (;;) {
     const int pos = (int)a.pos0 + grp;
-    if constexpr (!AHEAD) load_ahead<ATOMIC, AFF>(a, u, model, pos, q0, g, c, w, cur);
+    if constexpr (!AHEAD) load_ahead<ATOMIC, AFF, true>(a, u, model, pos, q0, g, c, w, cur);
+    if constexpr (AHEAD && !MAT_AHEAD) load_mat(a, model, pos, q0, cur);
     float fo[3][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -161,21 +237,62 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
         fo[2][t] = fp[2];
       }
     }
+    float u0[3] = {0.f, 0.f, 0.f};  // 16-bit operands: u at local point (0,0,0), their offset
+    if constexpr (LOW) {
+      const int n0 = AFF ? a.aff[(size_t)pos * 4] : a.ibool[(size_t)pos * kN3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) u0[e] = uniform(u[3 * (size_t)n0 + e]);
+    }
 #pragma unroll
     for (int e = 0; e < 3; ++e)
       st4(r0 + e * kN3 + sS, f32x4{cur.uo[e][0], cur.uo[e][1], cur.uo[e][2], cur.uo[e][3]});
+    if constexpr (SCALE) {  // largest |u - u0| of the element, per wave
+      float um = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) um = fmaxf(um, fabsf(cur.uo[e][t] - u0[e]));
+      um = wave_max(um);
+      if (l == 0) s_red[0][w] = um;
+    }
     __syncthreads();  // B1: u in R0
 
     // ---- forward contractions ----
     f32x4 dx[3], dy[3];
+    float su = 1.0f, isu = 1.0f;
+    if constexpr (SCALE) {
+      float m = 0.0f;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) m = fmaxf(m, s_red[0][v]);
+      su = uniform(pow2_scale(m));
+      isu = uniform(1.0f / su);
+    }
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f}, z = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (LOW) {
+        // operands (u - u0) su: a rigid translation gives exactly zero
+        const float o = u0[e];
+        float ya[4], zb[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        x = mma(Dr[m], cur.uo[e][m], x);                               // sum_b D[i][b] u(b, j, k)
-        y = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dr[m], y);      // sum_b u(i, b, k) D[j][b]
-        z = mma(Dr[m], r0[e * kN3 + lds_at(c, w, 4 * g + m)], z);      // sum_b D[k][b] u(i, j, b)  (Z)
+        for (int m = 0; m < 4; ++m) {
+          ya[m] = (r0[e * kN3 + lds_at(c, 4 * g + m, w)] - o) * su;
+          zb[m] = (r0[e * kN3 + lds_at(c, w, 4 * g + m)] - o) * su;
+        }
+        x = L::mma(Dr16, pack4<PREC>((cur.uo[e][0] - o) * su, (cur.uo[e][1] - o) * su, (cur.uo[e][2] - o) * su,
+                                     (cur.uo[e][3] - o) * su), x);
+        y = L::mma(pack4<PREC>(ya[0], ya[1], ya[2], ya[3]), Dr16, y);
+        z = L::mma(Dr16, pack4<PREC>(zb[0], zb[1], zb[2], zb[3]), z);
+        x *= isu;
+        y *= isu;
+        z *= isu;
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          x = mma(Dr[m], cur.uo[e][m], x);                               // sum_b D[i][b] u(b, j, k)
+          y = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dr[m], y);      // sum_b u(i, b, k) D[j][b]
+          z = mma(Dr[m], r0[e * kN3 + lds_at(c, w, 4 * g + m)], z);      // sum_b D[k][b] u(i, j, b)  (Z)
+        }
       }
       dx[e] = x;
       dy[e] = y;
@@ -243,32 +360,82 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       st4(r2 + e * kN3 + sS, p2[e]);
     }
     // ---- transpose contractions ----
+    // The xi and eta contractions stay inside the wave's own slice k = w
+    // (the eta operand read back from LDS was written by this wave), so
+    // 16-bit operands take a per-wave scale there; the zeta operand crosses
+    // waves and takes the element's.
     f32x4 F[3];
+    float sqw = 1.0f, isqw = 1.0f;
+    if constexpr (SCALE) {
+      float qm = 0.0f, zm = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          qm = fmaxf(qm, fmaxf(fabsf(p0[e][t]), fabsf(p1[e][t])));
+          zm = fmaxf(zm, fabsf(p2[e][t]));
+        }
+      sqw = uniform(pow2_scale(wave_max(qm)));
+      isqw = uniform(1.0f / sqw);
+      zm = wave_max(zm);
+      if (l == 0) s_red[1][w] = zm;
+    }
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (LOW) {
+        x = L::mma(Dt16, pack4<PREC>(p0[e][0] * sqw, p0[e][1] * sqw, p0[e][2] * sqw, p0[e][3] * sqw), x);
+      } else {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) x = mma(Dt[m], p0[e][m], x);  // sum_a D[a][i] phi0(a, j, k)
+        for (int m = 0; m < 4; ++m) x = mma(Dt[m], p0[e][m], x);  // sum_a D[a][i] phi0(a, j, k)
+      }
       F[e] = x;
     }
     const int nxt = grp + per_xcd;
     const bool more = AHEAD && nxt < xend;  // uniform over the block
     Ahead ahead;
     if constexpr (AHEAD) {
-      if (more) load_ahead<ATOMIC, AFF>(a, u, model, (int)a.pos0 + nxt, q0, g, c, w, ahead);
+      if (more) load_ahead<ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + nxt, q0, g, c, w, ahead);
     }
     __syncthreads();  // B3: eta fluxes in R0, zeta fluxes in R2; R1 free
+    if constexpr (LOW) {
+      float sq = 1.0f, isq = 1.0f;
+      if constexpr (SCALE) {
+        float m = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      f32x4 x = F[e], z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        x = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dt[m], x);  // sum_a phi1(i, a, k) D[a][j]
-        z = mma(Dt[m], r2[e * kN3 + lds_at(c, w, 4 * g + m)], z);  // sum_a D[a][k] phi2(i, j, a)  (Z)
+        for (int v = 0; v < kWaves; ++v) m = fmaxf(m, s_red[1][v]);
+        sq = uniform(pow2_scale(m));
+        isq = uniform(1.0f / sq);
       }
-      F[e] = x;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
+      for (int e = 0; e < 3; ++e) {
+        float xa[4], zb[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          xa[m] = r0[e * kN3 + lds_at(c, 4 * g + m, w)] * sqw;
+          zb[m] = r2[e * kN3 + lds_at(c, w, 4 * g + m)] * sq;
+        }
+        f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 x = L::mma(pack4<PREC>(xa[0], xa[1], xa[2], xa[3]), Dt16, F[e]);
+        z = L::mma(Dt16, pack4<PREC>(zb[0], zb[1], zb[2], zb[3]), z);
+        F[e] = x * isqw;
+        z *= isq;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        f32x4 x = F[e], z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          x = mma(r0[e * kN3 + lds_at(c, 4 * g + m, w)], Dt[m], x);  // sum_a phi1(i, a, k) D[a][j]
+          z = mma(Dt[m], r2[e * kN3 + lds_at(c, w, 4 * g + m)], z);  // sum_a D[a][k] phi2(i, j, a)  (Z)
+        }
+        F[e] = x;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
+      }
     }
     __syncthreads();  // B4: zeta transpose result in R1 (R0, R2 free for the next element)
 #pragma unroll
@@ -308,42 +475,53 @@ int64_t resident_groups() {
   return cache[dev];
 }
 
-template <int GEO, bool ATOMIC, bool AFF>
+template <int GEO, bool ATOMIC, bool AFF, int PREC>
 hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
   int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   if (GEO == kRegular) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
-  force_tile16_kernel<GEO, ATOMIC, AFF><<<grid, block, 0, s>>>(a);
+  force_tile16_kernel<GEO, ATOMIC, AFF, PREC><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <bool AFF>
+template <bool AFF, int PREC>
 hipError_t launch_t16_geo(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   switch (geo) {
     case kRegular:
-      return atomic ? launch_t16<kRegular, true, AFF>(a, s) : launch_t16<kRegular, false, AFF>(a, s);
+      return atomic ? launch_t16<kRegular, true, AFF, PREC>(a, s) : launch_t16<kRegular, false, AFF, PREC>(a, s);
     case kStored:
-      return atomic ? launch_t16<kStored, true, AFF>(a, s) : launch_t16<kStored, false, AFF>(a, s);
+      return atomic ? launch_t16<kStored, true, AFF, PREC>(a, s) : launch_t16<kStored, false, AFF, PREC>(a, s);
     case kTrilinear:
-      return atomic ? launch_t16<kTrilinear, true, AFF>(a, s) : launch_t16<kTrilinear, false, AFF>(a, s);
+      return atomic ? launch_t16<kTrilinear, true, AFF, PREC>(a, s) : launch_t16<kTrilinear, false, AFF, PREC>(a, s);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-}  // namespace
-
-hipError_t launch_force_tile16(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+template <int PREC>
+hipError_t launch_t16_split(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
   // the launch's first naff elements have an affine numbering
   naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
   ForceArgs b = a;
   b.count = naff;
-  hipError_t e = launch_t16_geo<true>(geo, atomic, b, s);
+  hipError_t e = launch_t16_geo<true, PREC>(geo, atomic, b, s);
   if (e != hipSuccess || naff == a.count) return e;
   b.pos0 = a.pos0 + naff;
   b.count = a.count - naff;
-  return launch_t16_geo<false>(geo, atomic, b, s);
+  return launch_t16_geo<false, PREC>(geo, atomic, b, s);
+}
+
+}  // namespace
+
+hipError_t launch_force_tile16(int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  switch (prec) {
+    case SEMX_C_F32:
+    case SEMX_C_MFMA_F32: return launch_t16_split<SEMX_C_F32>(geo, atomic, naff, a, s);
+    case SEMX_C_BF16: return launch_t16_split<SEMX_C_BF16>(geo, atomic, naff, a, s);
+    case SEMX_C_F16: return launch_t16_split<SEMX_C_F16>(geo, atomic, naff, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace semx

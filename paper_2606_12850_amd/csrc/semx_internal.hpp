@@ -226,12 +226,13 @@ hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceA
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // Memory skeleton of the coloured launch_force_high (same loads and stores, no arithmetic).
 hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
-// force_tile16.hip: NGLL 16, all six contractions on the matrix cores (FP32 operands)
-// (the launch's first naff elements have an affine numbering)
-hipError_t launch_force_tile16(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
+// force_tile16.hip: NGLL 16, all six contractions on the matrix cores; prec
+// SEMX_C_F32 / SEMX_C_MFMA_F32 (FP32 operands), SEMX_C_BF16, SEMX_C_F16 (the
+// launch's first naff elements have an affine numbering)
+hipError_t launch_force_tile16(int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)
 hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
-// MFMA contraction modes: NGLL 4..8 (all three precisions), NGLL 16 (FP32 operands).
+// MFMA contraction modes: NGLL 4..8 and 16 (all three precisions).
 bool mfma_supported(int n, int prec);
 
 // ---- host helpers shared between translation units (api.hip) ----------------

@@ -6,9 +6,13 @@ case.  The FP32-operand matrix-core path is held to the FP32 force bar
 Parity here is unpinned beyond the stated bounds: the expected relative
 error is set by the operand precision (BF16 8-bit, FP16 11-bit significand)
 times the cancellation of the operator, so the bounds below are loose
-ceilings, not tolerances of the method.  Exact properties are checked
-exactly: a rigid translation gives zero force (operand offset), and the
-result does not depend on the assembly mode beyond FP32 rounding."""
+ceilings, not tolerances of the method.  A random field has no
+cancellation: its ceiling is the same at every order.  A smooth field's
+derivatives are small against the rounding of the operands times the row
+sums of |D| (the infinity norm of D: 51 at NGLL 8, 245 at NGLL 16), so
+beyond NGLL 8 its ceiling scales with that norm.  Exact properties are
+checked exactly: a rigid translation gives zero force (operand offset), and
+the result does not depend on the assembly mode beyond FP32 rounding."""
 import numpy as np
 import pytest
 
@@ -20,16 +24,20 @@ pytestmark = pytest.mark.gpu
 BOUND = {"bf16": 5e-2, "f16": 5e-3, "mf32": 1e-5}
 
 
+def _dnorm(orc, n):
+    return float(np.abs(np.asarray(orc.dmatrix(n)).reshape(n, n)).sum(axis=1).max())
+
+
 def _cprec(P, prec):
     return {"bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16, "mf32": P.SEMX_C_MFMA_F32}[prec]
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16", "mf32"])
-@pytest.mark.parametrize("n", [4, 5, 6, 7, 8])
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 16])
 @pytest.mark.parametrize("geometry", ["stored", "trilinear"])
 def test_mixed_force_error(orc, n, prec, geometry):
     import paper_2606_12850_amd as P
-    mesh = W.box_mesh((3, 2, 3) if n <= 6 else (2, 2, 2), n, 4000.0, jitter=0.1, seed=5)
+    mesh = W.box_mesh((3, 2, 3) if n <= 6 else ((2, 2, 2) if n <= 8 else (2, 2, 1)), n, 4000.0, jitter=0.1, seed=5)
     lam, mu, rho = W.layered_model(mesh, grf_amp=0.05, grf_seed=3, grf_corr_elems=1.5)
     gam, jac, _ = oracle_geometry(orc, mesh)
     s = make_solver(n)
@@ -45,18 +53,23 @@ def test_mixed_force_error(orc, n, prec, geometry):
         for asm in (P.SEMX_ASM_COLORED, P.SEMX_ASM_ATOMIC):
             s.set_mode(cprec, asm)
             errs[asm] = rel_l2(gpu_force(s, u32), ref)
-        print(f"mixed {prec} n={n} {geometry} {label}: rel L2 vs FP64 = {errs[P.SEMX_ASM_COLORED]:.3e}")
-        assert errs[P.SEMX_ASM_COLORED] <= BOUND[prec]
+        bound = BOUND[prec]
+        if label == "smooth" and prec != "mf32":
+            bound *= max(1.0, _dnorm(orc, n) / _dnorm(orc, 8))
+        print(f"mixed {prec} n={n} {geometry} {label}: rel L2 vs FP64 = {errs[P.SEMX_ASM_COLORED]:.3e} "
+              f"(ceiling {bound:.1e})")
+        assert errs[P.SEMX_ASM_COLORED] <= bound
         assert abs(errs[P.SEMX_ASM_ATOMIC] - errs[P.SEMX_ASM_COLORED]) <= 1e-6 + 1e-3 * errs[P.SEMX_ASM_COLORED]
     s.close()
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16"])
-def test_mixed_rigid_translation_is_exactly_zero(prec):
+@pytest.mark.parametrize("n", [5, 16])
+def test_mixed_rigid_translation_is_exactly_zero(prec, n):
     import paper_2606_12850_amd as P
-    mesh = W.box_mesh((3, 3, 2), 5, 4000.0, jitter=0.1, seed=9)
+    mesh = W.box_mesh((3, 3, 2) if n == 5 else (2, 1, 2), n, 4000.0, jitter=0.1, seed=9)
     lam, mu, rho = W.homogeneous_model(mesh)
-    s = make_solver(5)
+    s = make_solver(n)
     s.upload_mesh(mesh)
     s.upload_model(lam, mu, rho)
     s.set_mode(P.SEMX_C_BF16 if prec == "bf16" else P.SEMX_C_F16, P.SEMX_ASM_COLORED)
