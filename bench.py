@@ -445,7 +445,7 @@ def order_sweep_leg(reps: int = 20, orders=None):
         f = torch.empty_like(u)
         row = {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": G, "h_m": round(h, 2), "device_bytes": device_bytes}
         b_model = bytes_per_element_model(n, G, mesh.nspec, "regular")
-        b_elem = bytes_per_element(n, G, mesh.nspec, "regular", affine=n <= 10)
+        b_elem = bytes_per_element(n, G, mesh.nspec, "regular", affine=n <= 10 or n == 16)
         # full explicit step (FP32, coloured) from a nonzero state, CFL time step
         dt = P.semx_cfl_dt(s.ctx, 0.4)
         P.semx_set_dt(s.ctx, dt)
@@ -459,31 +459,43 @@ def order_sweep_leg(reps: int = 20, orders=None):
         row["step_ms"] = round(e0.elapsed_time(e1) / reps, 4)
         row["dt_cfl"] = dt
         row["hmin_over_h"] = dt * vp_max / 0.4 / h  # smallest GLL spacing over the element size
+        # contraction modes: FP32 everywhere; the matrix-core modes where they
+        # exist (NGLL 4..8 and 16; at 16 the FP32 path is the FP32-operand
+        # matrix-core kernel itself, so mf32 is not listed again).  Timed in
+        # interleaved rounds (median), so that clock state favours no mode.
+        modes = [(c, m) for c, m in (("f32", P.SEMX_C_F32), ("mf32", P.SEMX_C_MFMA_F32), ("bf16", P.SEMX_C_BF16),
+                                     ("f16", P.SEMX_C_F16))
+                 if c == "f32" or (4 <= n <= 8) or (n == 16 and c != "mf32")]
         ref = None
-        for cname, cmode in (("f32", P.SEMX_C_F32), ("mf32", P.SEMX_C_MFMA_F32), ("bf16", P.SEMX_C_BF16),
-                             ("f16", P.SEMX_C_F16)):
-            if cname != "f32" and not (4 <= n <= 8):
-                continue
+        for cname, cmode in modes:
             P.semx_set_mode(s.ctx, cmode, P.SEMX_ASM_COLORED)
             for _ in range(3):
                 P.semx_apply_force(s.ctx, u, f)
-            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s.stream)
-            for _ in range(reps):
-                P.semx_apply_force(s.ctx, u, f)
-            e1.record(s.stream)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            row[f"{cname}_ms"] = round(ms, 4)
-            row[f"{cname}_gll_pts_per_s"] = mesh.nspec * n ** 3 / (ms * 1e-3)
-            row[f"{cname}_hbm_frac"] = round(b_model * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
-            row[f"{cname}_hbm_frac_impl"] = round(b_elem * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
-            if cname != "f32" and "f32_ms" in row:
-                row[f"{cname}_speedup_vs_f32"] = round(row["f32_ms"] / ms, 3)
             if ref is None:
                 ref = f.clone()
             else:
                 row[f"{cname}_rel_diff_vs_f32"] = (torch.linalg.norm(f - ref) / torch.linalg.norm(ref)).item()
+        times = {c: [] for c, _ in modes}
+        for _ in range(3):
+            for cname, cmode in modes:
+                P.semx_set_mode(s.ctx, cmode, P.SEMX_ASM_COLORED)
+                P.semx_apply_force(s.ctx, u, f)
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s.stream)
+                for _ in range(reps):
+                    P.semx_apply_force(s.ctx, u, f)
+                e1.record(s.stream)
+                e1.synchronize()
+                times[cname].append(e0.elapsed_time(e1) / reps)
+        for cname, _ in modes:
+            ms = float(np.median(times[cname]))
+            row[f"{cname}_ms"] = round(ms, 4)
+            row[f"{cname}_gll_pts_per_s"] = mesh.nspec * n ** 3 / (ms * 1e-3)
+            row[f"{cname}_hbm_frac"] = round(b_model * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            row[f"{cname}_hbm_frac_impl"] = round(b_elem * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+            if cname != "f32":
+                row[f"{cname}_speedup_vs_f32"] = round(row["f32_ms"] / ms, 3)
+        P.semx_set_mode(s.ctx, P.SEMX_C_F32, P.SEMX_ASM_COLORED)
         del u, f, ref
         s.close()
         if n in (5, 8, 16):  # the acoustic experiment's orders: the scalar operator on the same mesh
@@ -564,7 +576,7 @@ def single_order_apply(n: int, reps: int):
         b.copy_(a)
     torch.cuda.synchronize()
     bm = bytes_per_element_model(n, mesh.nglob, mesh.nspec, "regular")
-    be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular", affine=n <= 10)
+    be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular", affine=n <= 10 or n == 16)
     return {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
             "launches_per_apply": info["ncolors"], "bytes_per_element": bm, "bytes_per_element_impl": be,
             "hbm_frac": round(bm * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
@@ -1041,7 +1053,7 @@ def main():
         out["adjoint"] = adjoint_leg()
     if not args.no_order_sweep:
         full = args.order_sweep_full
-        out["order_sweep"] = order_sweep_leg(orders=None if full else (4, 5, 6, 7, 8, 9))
+        out["order_sweep"] = order_sweep_leg(orders=None if full else (4, 5, 6, 7, 8, 9, 16))
         progress("order sweep done")
         if full:
             out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]
