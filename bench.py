@@ -538,10 +538,11 @@ def order_sweep_leg(reps: int = 20, orders=None):
     return rows
 
 
-def single_order_apply(n: int, reps: int):
-    """FP32 coloured force applies on the order-sweep mesh of one NGLL
-    (regular hexahedra, about 2e7 unique points), event-timed, then three
-    1 GiB device copies that calibrate traffic counters; for profiling."""
+def single_order_apply(n: int, reps: int, mode: str = "f32"):
+    """Coloured force applies (contraction `mode`: f32, bf16, f16) on the
+    order-sweep mesh of one NGLL (regular hexahedra, about 2e7 unique
+    points), event-timed, then three 1 GiB device copies that calibrate
+    traffic counters; for profiling."""
     import numpy as np
     import torch
 
@@ -555,6 +556,7 @@ def single_order_apply(n: int, reps: int):
     s.upload_mesh(mesh)
     s.upload_model(lam, mu, rho)
     del lam, mu, rho
+    s.set_mode({"f32": P.SEMX_C_F32, "bf16": P.SEMX_C_BF16, "f16": P.SEMX_C_F16}[mode], P.SEMX_ASM_COLORED)
     u = torch.rand((mesh.nglob, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(0)) - 0.5
     f = torch.empty_like(u)
     for _ in range(3):
@@ -566,6 +568,7 @@ def single_order_apply(n: int, reps: int):
     e1.record(s.stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED)
     sk = P.semx_force_skeleton(s.ctx, u, f, reps)  # the memory skeleton of the same pass
     info = P.semx_mesh_info(s.ctx)
     s.close()
@@ -577,7 +580,7 @@ def single_order_apply(n: int, reps: int):
     torch.cuda.synchronize()
     bm = bytes_per_element_model(n, mesh.nglob, mesh.nspec, "regular")
     be = bytes_per_element(n, mesh.nglob, mesh.nspec, "regular", affine=n <= 10 or n == 16)
-    return {"ngll": n, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
+    return {"ngll": n, "mode": mode, "ne": ne, "nspec": mesh.nspec, "nglob": mesh.nglob, "ms_per_apply": round(ms, 4),
             "launches_per_apply": info["ncolors"], "bytes_per_element": bm, "bytes_per_element_impl": be,
             "hbm_frac": round(bm * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "hbm_frac_impl": round(be * mesh.nspec / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
@@ -785,7 +788,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-acoustic", action="store_true")
     ap.add_argument("--sweep-order", type=int, default=0,
-                    help="time only the FP32 force apply on the order-sweep mesh of this NGLL, then a 1 GiB "
+                    help="time only the force apply (--sweep-mode) on the order-sweep mesh of this NGLL, then a 1 GiB "
                          "device copy (for counter runs); prints one JSON line")
     ap.add_argument("--acoustic-only", action="store_true",
                     help="time only the acoustic force apply on the bench mesh (no time loop, no rod runs); "
@@ -793,6 +796,8 @@ def main():
     ap.add_argument("--geometry", choices=["stored", "trilinear"], default="trilinear")
     ap.add_argument("--assembly", choices=["colored", "atomic"], default="colored")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--sweep-mode", choices=("f32", "bf16", "f16"), default="f32",
+                    help="contraction mode of --sweep-order")
     ap.add_argument("--profile-force", action="store_true",
                     help="time only the force apply of --contraction/--geometry/--assembly, then a 1 GiB "
                          "device copy (calibration for HBM traffic counters); prints one JSON line")
@@ -837,7 +842,7 @@ def main():
         print(json.dumps({"mlp": mlp_profile()}))
         return
     if args.sweep_order:
-        print(json.dumps({"sweep_order": single_order_apply(args.sweep_order, args.apply_reps)}))
+        print(json.dumps({"sweep_order": single_order_apply(args.sweep_order, args.apply_reps, args.sweep_mode)}))
         return
     t_setup = time.perf_counter()
     nt_total = args.warmup + args.steps
