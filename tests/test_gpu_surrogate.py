@@ -130,11 +130,14 @@ def test_resample_is_linear_interpolation():
 
 def test_surrogate_pipeline_with_fallback():
     """Reduced-size surrogate: 8^3 mesh, 3 Hz Ricker, 200 steps -> 100
-    samples, 16 receivers; train on 1024 models, calibrate on 128, test on
+    samples, 16 receivers; train on 4096 models, calibrate on 128, test on
     256.  States the surrogate error and the fallback outcome; checks that
     the SEM fallback keeps every flagged model at the SEM answer, that the
-    trained network beats the mean seismogram, and that surrogate + fallback
-    is cheaper than SEM for all test models when most are accepted."""
+    trained network beats the mean seismogram, that most models are accepted
+    at the 5 % tolerance (measured: 1024 training models leave the mean error
+    at 6.4 % and flag 98 %; 4096 bring it to 2.4 % and flag 9 %), and that
+    surrogate + fallback is cheaper than SEM for all test models (training
+    excluded) at a final mean error within the tolerance."""
     import torch
     from paper_2606_12850_amd.surrogate import BatchedSEM, Surrogate, rel_err, resample
     mesh = W.box_mesh(8, 5, 4000.0)
@@ -146,7 +149,7 @@ def test_surrogate_pipeline_with_fallback():
     stf = W.ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
     sem = BatchedSEM(mesh, se, sx, [[0.0, 0.0, 1.0]], stf, re, rx, dt, nt, batch=64)
     model_fn = lambda a: W.perturbed_models(mesh, basis, a)
-    A_tr = W.perturbation_coefficients(basis, range(0, 1024))
+    A_tr = W.perturbation_coefficients(basis, range(0, 4096))
     A_va = W.perturbation_coefficients(basis, range(5000, 5128))
     A_te = W.perturbation_coefficients(basis, range(10000, 10256))
     Y_tr4 = resample(sem.run_models(model_fn, A_tr), nout)
@@ -157,7 +160,7 @@ def test_surrogate_pipeline_with_fallback():
     Y_te = resample(sem.run_models(model_fn, A_te), nout).reshape(len(A_te), -1)
     t_sem = time.perf_counter() - t0
     s = Surrogate(64, Y_tr.shape[1], hidden=(256, 256, 256), members=4, max_batch=512)
-    s.fit(A_tr, Y_tr4, epochs=200, batch=64)
+    s.fit(A_tr, Y_tr4, epochs=120, batch=64)
     cal = s.calibrate(A_va, Y_va, tol=0.05)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -179,6 +182,7 @@ def test_surrogate_pipeline_with_fallback():
     assert e_sur.mean() < 0.5 * e_mean.mean()
     assert np.all(e_fin[flag] <= 1e-6)          # flagged models carry the SEM answer
     assert e_fin.mean() <= e_sur.mean() + 1e-12
-    if flag.mean() < 0.5:
-        assert t_sur < t_sem
+    assert flag.mean() < 0.5                    # most models accepted
+    assert e_fin.mean() <= 0.05
+    assert t_sur < t_sem                        # the gain, unconditionally
     s.close(); sem.close()
