@@ -59,8 +59,8 @@ typedef struct semx_ctx semx_ctx;
 
 /* contraction arithmetic of the force operator (mixed precision keeps the
  * geometry map, stress and assembly in FP32) */
-#define SEMX_C_F32 0       /* FP32 contractions: vector units through LDS (NGLL 2..15),
-                              FP32-operand MFMA tiles (NGLL 16) */
+#define SEMX_C_F32 0       /* FP32 contractions: vector units through LDS (NGLL 2..12),
+                              FP32-operand MFMA tiles (NGLL 13..16) */
 #define SEMX_C_BF16 1      /* BF16-operand MFMA contractions, FP32 accumulation */
 #define SEMX_C_F16 2       /* FP16-operand MFMA contractions, FP32 accumulation */
 #define SEMX_C_MFMA_F32 3  /* FP32-operand MFMA contractions (v_mfma_f32_16x16x4f32) */
@@ -122,8 +122,8 @@ int semx_upload_model(semx_ctx *ctx, int nmodels, const double *lambda, const do
 
 /* Select the contraction arithmetic and the assembly (constants above).
  * The matrix-core contractions (SEMX_C_BF16, SEMX_C_F16, SEMX_C_MFMA_F32)
- * need 4 <= NGLL <= 8 or NGLL = 16 (where SEMX_C_MFMA_F32 is the FP32
- * path itself); SEMX_EINVAL otherwise, or for an unknown value, or for
+ * need 4 <= NGLL <= 8 or 13 <= NGLL <= 16 (where SEMX_C_MFMA_F32 is the
+ * FP32 path itself); SEMX_EINVAL otherwise, or for an unknown value, or for
  * coloured assembly on a mesh whose elements repeat a node. */
 int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 

@@ -678,8 +678,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, a, c->stream);
-    else if (c->n == 16)
-      e = launch_force_tile16(c->contraction, geo, atomic, L.naff, a, c->stream);
+    else if (c->n >= kTileMinN)
+      e = launch_force_tile16(c->n, c->contraction, geo, atomic, L.naff, a, c->stream);
     else if (c->contraction == SEMX_C_F32 && c->n > kMaxNLow)
       e = launch_force_high(c->n, geo, atomic, a, c->stream);
     else if (c->contraction == SEMX_C_F32)
@@ -1350,7 +1350,7 @@ int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
   if (assembly != SEMX_ASM_COLORED && assembly != SEMX_ASM_ATOMIC)
     return fail(c, SEMX_EINVAL, "set_mode: unknown assembly");
   if (contraction != SEMX_C_F32 && !mfma_supported(c->n, contraction))
-    return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8 or NGLL 16");
+    return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8 or 13 <= NGLL <= 16");
   if (contraction != SEMX_C_F32 && c->storage == SEMX_F64)
     return fail(c, SEMX_EINVAL, "set_mode: FP64 storage contracts on the vector units (SEMX_C_F32 only)");
   if (contraction != SEMX_C_F32 && c->physics == SEMX_ACOUSTIC)

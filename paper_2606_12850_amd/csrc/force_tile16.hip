@@ -1,4 +1,4 @@
-// FP32 element internal-force kernel for NGLL 16 on the matrix cores.
+// Element internal-force kernel for NGLL 13..16 on the matrix cores.
 //
 // The operator is that of force_f32.hip and force_high.hip (Sec. II-B weak
 // form: three forward and three transpose sum-factorised contractions with
@@ -6,7 +6,11 @@
 // stress and weighted flux; Sec. IV-D fused traversal).  At NGLL 16 every
 // contraction is an exact 16 x 16 x 16 matrix product, so all six run as
 // v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation, four K = 4 steps
-// per product) and the vector units keep only the pointwise work.
+// per product) and the vector units keep only the pointwise work.  NGLL 13
+// to 15 use the same 16-point tile with padding: D is extended by zero rows
+// and columns and u, lambda, mu are zero at the padding points, so every
+// padded product term is zero and the padding points carry zero flux; only
+// the real points are loaded and stored.
 //
 // Layout.  One workgroup per element, 16 waves.  The matrix-core result tile
 // gives lane l of a wave the rows 4 g + t (t = 0..3) of column c, with
@@ -122,62 +126,112 @@ __device__ __forceinline__ float uniform(float v) {
 __device__ __forceinline__ f32x4 ld4(const float* s) { return *reinterpret_cast<const f32x4*>(s); }
 __device__ __forceinline__ void st4(float* s, f32x4 v) { *reinterpret_cast<f32x4*>(s) = v; }
 
+// The lane's own points (S layout) in the element's arrays: element-local
+// index q[t] = i + NG j + NG^2 k of point t, and which of the four are real
+// points (i, j, k < NG; always all four at NGLL 16).
+template <int NG>
+struct OwnPts {
+  int q0;       // q of point t is q0 + t (consecutive along i)
+  uint32_t ok;  // bit t
+  __device__ OwnPts(int g, int c, int w) {
+    q0 = 4 * g + NG * c + NG * NG * w;
+    ok = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (4 * g + t < NG && c < NG && w < NG) ok |= 1u << t;
+  }
+  __device__ int q(int t) const { return q0 + t; }
+  __device__ bool real(int t) const { return (ok >> t) & 1u; }
+};
+
 // What the element loop requests ahead of an element's arithmetic: its node
-// numbers (computed on the affine path), first-touch word, u and material.
+// numbers (computed on the affine path), first-touch bits, u and material.
 struct Ahead {
   int node[4];
-  uint32_t fw;
+  uint32_t fw;  // bit t: own point t is the first to reach its node
   float uo[3][4];
   f32x4 lam4, mu4;
 };
 
-__device__ __forceinline__ void load_mat(const ForceArgs& a, int model, int pos, int q0, Ahead& h) {
-  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * kN3 + (size_t)pos * 2 * kN3;
-  h.lam4 = ld4(mat + q0);
-  h.mu4 = ld4(mat + kN3 + q0);
+// At NGLL 16 the four points are contiguous and 16-byte aligned (vector
+// loads); below it they are loaded one by one, zero at padding points.
+template <int NG>
+__device__ __forceinline__ void load_mat(const ForceArgs& a, int model, int pos, const OwnPts<NG>& P, Ahead& h) {
+  constexpr int E3 = NG * NG * NG;
+  const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * E3 + (size_t)pos * 2 * E3;
+  if constexpr (NG == kN) {
+    h.lam4 = ld4(mat + P.q0);
+    h.mu4 = ld4(mat + E3 + P.q0);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      h.lam4[t] = P.real(t) ? mat[P.q(t)] : 0.0f;
+      h.mu4[t] = P.real(t) ? mat[E3 + P.q(t)] : 0.0f;
+    }
+  }
 }
 
-template <bool ATOMIC, bool AFF, bool MAT>
+template <int NG, bool ATOMIC, bool AFF, bool MAT>
 __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __restrict__ u, int model, int pos,
-                                           int q0, int g, int c, int w, Ahead& h) {
+                                           const OwnPts<NG>& P, int g, int c, int w, Ahead& h) {
+  constexpr int E3 = NG * NG * NG;
   if constexpr (AFF) {
     const int32_t* r = a.aff + (size_t)pos * 4;
     const int base = r[0] + c * r[2] + w * r[3];
 #pragma unroll
     for (int t = 0; t < 4; ++t) h.node[t] = base + (4 * g + t) * r[1];
-  } else {
-    const int4 nd = *reinterpret_cast<const int4*>(a.ibool + (size_t)pos * kN3 + q0);
+  } else if constexpr (NG == kN) {
+    const int4 nd = *reinterpret_cast<const int4*>(a.ibool + (size_t)pos * E3 + P.q0);
     h.node[0] = nd.x;
     h.node[1] = nd.y;
     h.node[2] = nd.z;
     h.node[3] = nd.w;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h.node[t] = P.real(t) ? a.ibool[(size_t)pos * E3 + P.q(t)] : 0;
   }
   h.fw = 0;
   if constexpr (!ATOMIC) {
-    if (a.first) h.fw = a.first[(size_t)pos * a.first_words + (q0 >> 5)] >> (q0 & 31);
+    if (a.first) {
+      const uint32_t* fb = a.first + (size_t)pos * a.first_words;
+      if constexpr (NG == kN) {
+        h.fw = fb[P.q0 >> 5] >> (P.q0 & 31);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (P.real(t)) h.fw |= ((fb[P.q(t) >> 5] >> (P.q(t) & 31)) & 1u) << t;
+      }
+    }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 4; ++t) {
+    h.uo[0][t] = h.uo[1][t] = h.uo[2][t] = 0.0f;
+    if (P.real(t)) {
 #pragma unroll
-    for (int e = 0; e < 3; ++e) h.uo[e][t] = u[3 * (size_t)h.node[t] + e];
-  if constexpr (MAT) load_mat(a, model, pos, q0, h);
+      for (int e = 0; e < 3; ++e) h.uo[e][t] = u[3 * (size_t)h.node[t] + e];
+    }
+  }
+  if constexpr (MAT) load_mat<NG>(a, model, pos, P, h);
 }
 
-// Element loop.  Regular path: the grid holds one workgroup per compute unit
+// Element loop.  Regular path at NGLL 16: the grid holds one workgroup per compute unit
 // (one fills its LDS) and each walks its share of the launch, dealt XCD by
 // XCD as in xcd_group (the workgroups on XCD x take the x-th eighth of the
 // range, in steps of the number of workgroups there); the next element's node
 // numbers, u and material are requested before the current one's last two
 // barriers, so that their latency hides behind its transpose contractions and
-// assembly.  With per-point geometry the registers are full: one element per
-// workgroup, its loads requested at its start.  Inside a colour the prior f
+// assembly.  With per-point geometry or padded tiles the registers are full:
+// one element per workgroup, its loads requested at its start.  Inside a colour the prior f
 // at the element's nodes is read at the start of its arithmetic (no other
 // workgroup of the launch touches those nodes).
-template <int GEO, bool ATOMIC, bool AFF, int PREC>
+template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC>
 __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
-  constexpr bool AHEAD = GEO == kRegular;  // persistent, next element requested ahead
+  constexpr int E3 = NG * NG * NG;
+  // persistent, next element requested ahead (regular path, unpadded tiles)
+  constexpr bool AHEAD = GEO == kRegular && NG == kN;
   constexpr bool LOW = PREC == SEMX_C_BF16 || PREC == SEMX_C_F16;
-  constexpr bool MAT_AHEAD = AHEAD && !LOW;  // 16-bit operands need the registers: material at the start
+  // 16-bit operands and padded tiles need the registers: material at the start
+  constexpr bool MAT_AHEAD = AHEAD && !LOW && NG == kN;
   constexpr bool SCALE = PREC == SEMX_C_F16;  // BF16 has the FP32 exponent range
   using L = Low<PREC>;
   using lvec = typename L::vec;
@@ -200,37 +254,39 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   const int model = blockIdx.y;
   const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
   float* f = a.f + (size_t)model * a.nglob * 3;
-  const int q0 = 4 * g + kN * c + kN * kN * w;  // own points (S layout): q0 + t
-  const int sS = lds_at(4 * g, c, w);            // first of the 4 contiguous LDS words of the own points
+  const OwnPts<NG> P(g, c, w);          // own points (S layout)
+  const int sS = lds_at(4 * g, c, w);  // first of the 4 contiguous LDS words of the own points
 
+  // D (NG x NG) padded to 16 x 16 with zeros
   float Dr[4], Dt[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    Dr[m] = a.D[c * kN + 4 * g + m];
-    Dt[m] = a.D[(4 * g + m) * kN + c];
+    const bool in = c < NG && 4 * g + m < NG;
+    Dr[m] = in ? a.D[c * NG + 4 * g + m] : 0.0f;
+    Dt[m] = in ? a.D[(4 * g + m) * NG + c] : 0.0f;
   }
   lvec Dr16{}, Dt16{};
   if constexpr (LOW) {
     Dr16 = pack4<PREC>(Dr[0], Dr[1], Dr[2], Dr[3]);
     Dt16 = pack4<PREC>(Dt[0], Dt[1], Dt[2], Dt[3]);
   }
-  float ry = 0.f, rz = 0.f;
+  float ry = 0.f, rz = 0.f;  // padding points take the nearest node's coordinates (finite, zero flux)
   if constexpr (GEO == kTrilinear) {
-    ry = a.xi[c];
-    rz = a.xi[w];
+    ry = a.xi[min(c, NG - 1)];
+    rz = a.xi[min(w, NG - 1)];
   }
 
   Ahead cur;
-  if constexpr (AHEAD) load_ahead<ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + grp, q0, g, c, w, cur);
+  if constexpr (AHEAD) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + grp, P, g, c, w, cur);
   for (;;) {
     const int pos = (int)a.pos0 + grp;
-    if constexpr (!AHEAD) load_ahead<ATOMIC, AFF, true>(a, u, model, pos, q0, g, c, w, cur);
-    if constexpr (AHEAD && !MAT_AHEAD) load_mat(a, model, pos, q0, cur);
+    if constexpr (!AHEAD) load_ahead<NG, ATOMIC, AFF, true>(a, u, model, pos, P, g, c, w, cur);
+    if constexpr (AHEAD && !MAT_AHEAD) load_mat<NG>(a, model, pos, P, cur);
     float fo[3][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       fo[0][t] = fo[1][t] = fo[2][t] = 0.0f;
-      if (!ATOMIC && !((cur.fw >> t) & 1u)) {  // the point's three values in one request
+      if (!ATOMIC && P.real(t) && !((cur.fw >> t) & 1u)) {  // the point's three values in one request
         const float* fp = f + 3 * (size_t)cur.node[t];
         fo[0][t] = fp[0];
         fo[1][t] = fp[1];
@@ -239,9 +295,17 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     }
     float u0[3] = {0.f, 0.f, 0.f};  // 16-bit operands: u at local point (0,0,0), their offset
     if constexpr (LOW) {
-      const int n0 = AFF ? a.aff[(size_t)pos * 4] : a.ibool[(size_t)pos * kN3];
+      const int n0 = AFF ? a.aff[(size_t)pos * 4] : a.ibool[(size_t)pos * E3];
 #pragma unroll
       for (int e = 0; e < 3; ++e) u0[e] = uniform(u[3 * (size_t)n0 + e]);
+    }
+    // LDS holds u (FP32 operands) or u - u0 (16-bit operands), zero at
+    // padding points either way
+    if constexpr (LOW) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cur.uo[e][t] = P.real(t) ? cur.uo[e][t] - u0[e] : 0.0f;
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e)
@@ -251,7 +315,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
 #pragma unroll
       for (int e = 0; e < 3; ++e)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) um = fmaxf(um, fabsf(cur.uo[e][t] - u0[e]));
+        for (int t = 0; t < 4; ++t) um = fmaxf(um, fabsf(cur.uo[e][t]));
       um = wave_max(um);
       if (l == 0) s_red[0][w] = um;
     }
@@ -272,15 +336,13 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f}, z = {0.f, 0.f, 0.f, 0.f};
       if constexpr (LOW) {
         // operands (u - u0) su: a rigid translation gives exactly zero
-        const float o = u0[e];
         float ya[4], zb[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          ya[m] = (r0[e * kN3 + lds_at(c, 4 * g + m, w)] - o) * su;
-          zb[m] = (r0[e * kN3 + lds_at(c, w, 4 * g + m)] - o) * su;
+          ya[m] = r0[e * kN3 + lds_at(c, 4 * g + m, w)] * su;
+          zb[m] = r0[e * kN3 + lds_at(c, w, 4 * g + m)] * su;
         }
-        x = L::mma(Dr16, pack4<PREC>((cur.uo[e][0] - o) * su, (cur.uo[e][1] - o) * su, (cur.uo[e][2] - o) * su,
-                                     (cur.uo[e][3] - o) * su), x);
+        x = L::mma(Dr16, pack4<PREC>(cur.uo[e][0] * su, cur.uo[e][1] * su, cur.uo[e][2] * su, cur.uo[e][3] * su), x);
         y = L::mma(pack4<PREC>(ya[0], ya[1], ya[2], ya[3]), Dr16, y);
         z = L::mma(Dr16, pack4<PREC>(zb[0], zb[1], zb[2], zb[3]), z);
         x *= isu;
@@ -310,9 +372,16 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     if constexpr (GEO == kRegular) src = a.gam_el + (size_t)pos * 9;
     f32x4 gam4[9];
     if constexpr (GEO == kStored) {
-      const float* gp = a.gam_pt + (size_t)pos * 9 * kN3 + q0;
+      const float* gp = a.gam_pt + (size_t)pos * 9 * E3;
 #pragma unroll
-      for (int d = 0; d < 9; ++d) gam4[d] = ld4(gp + d * kN3);
+      for (int d = 0; d < 9; ++d) {
+        if constexpr (NG == kN) {
+          gam4[d] = ld4(gp + d * E3 + P.q0);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) gam4[d][t] = P.real(t) ? gp[d * E3 + P.q(t)] : 0.0f;
+        }
+      }
     }
     f32x4 p0[3], p1[3], p2[3];
 #pragma unroll
@@ -329,7 +398,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
 #pragma unroll
         for (int d = 0; d < 9; ++d) G[d] = gam4[d][t];
       }
-      const float rx = (GEO == kTrilinear) ? a.xi[4 * g + t] : 0.f;
+      const float rx = (GEO == kTrilinear) ? a.xi[min(4 * g + t, NG - 1)] : 0.f;
       float Mg[9], scale, det;
       geom_map_from<GEO>(src, G, rx, ry, rz, Mg, scale, det);
       float gr[3][3];
@@ -395,7 +464,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     const bool more = AHEAD && nxt < xend;  // uniform over the block
     Ahead ahead;
     if constexpr (AHEAD) {
-      if (more) load_ahead<ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + nxt, q0, g, c, w, ahead);
+      if (more) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + nxt, P, g, c, w, ahead);
     }
     __syncthreads();  // B3: eta fluxes in R0, zeta fluxes in R2; R1 free
     if constexpr (LOW) {
@@ -444,6 +513,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     // ---- assembly ----
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+      if (!P.real(t)) continue;
       float* fg = f + 3 * (size_t)cur.node[t];
       if constexpr (ATOMIC) {
         unsafeAtomicAdd(fg + 0, -F[0][t]);
@@ -475,51 +545,64 @@ int64_t resident_groups() {
   return cache[dev];
 }
 
-template <int GEO, bool ATOMIC, bool AFF, int PREC>
+template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC>
 hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
   int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
-  if (GEO == kRegular) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
+  if (GEO == kRegular && NG == kN) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
-  force_tile16_kernel<GEO, ATOMIC, AFF, PREC><<<grid, block, 0, s>>>(a);
+  force_tile16_kernel<NG, GEO, ATOMIC, AFF, PREC><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <bool AFF, int PREC>
+template <int NG, bool AFF, int PREC>
 hipError_t launch_t16_geo(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   switch (geo) {
     case kRegular:
-      return atomic ? launch_t16<kRegular, true, AFF, PREC>(a, s) : launch_t16<kRegular, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kRegular, true, AFF, PREC>(a, s) : launch_t16<NG, kRegular, false, AFF, PREC>(a, s);
     case kStored:
-      return atomic ? launch_t16<kStored, true, AFF, PREC>(a, s) : launch_t16<kStored, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kStored, true, AFF, PREC>(a, s) : launch_t16<NG, kStored, false, AFF, PREC>(a, s);
     case kTrilinear:
-      return atomic ? launch_t16<kTrilinear, true, AFF, PREC>(a, s) : launch_t16<kTrilinear, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kTrilinear, true, AFF, PREC>(a, s)
+                    : launch_t16<NG, kTrilinear, false, AFF, PREC>(a, s);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template <int PREC>
+template <int NG, int PREC>
 hipError_t launch_t16_split(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
   // the launch's first naff elements have an affine numbering
   naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
   ForceArgs b = a;
   b.count = naff;
-  hipError_t e = launch_t16_geo<true, PREC>(geo, atomic, b, s);
+  hipError_t e = launch_t16_geo<NG, true, PREC>(geo, atomic, b, s);
   if (e != hipSuccess || naff == a.count) return e;
   b.pos0 = a.pos0 + naff;
   b.count = a.count - naff;
-  return launch_t16_geo<false, PREC>(geo, atomic, b, s);
+  return launch_t16_geo<NG, false, PREC>(geo, atomic, b, s);
+}
+
+template <int PREC>
+hipError_t launch_t16_n(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  switch (n) {
+    case 13: return launch_t16_split<13, PREC>(geo, atomic, naff, a, s);
+    case 14: return launch_t16_split<14, PREC>(geo, atomic, naff, a, s);
+    case 15: return launch_t16_split<15, PREC>(geo, atomic, naff, a, s);
+    case 16: return launch_t16_split<16, PREC>(geo, atomic, naff, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_force_tile16(int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
+                               hipStream_t s) {
   switch (prec) {
     case SEMX_C_F32:
-    case SEMX_C_MFMA_F32: return launch_t16_split<SEMX_C_F32>(geo, atomic, naff, a, s);
-    case SEMX_C_BF16: return launch_t16_split<SEMX_C_BF16>(geo, atomic, naff, a, s);
-    case SEMX_C_F16: return launch_t16_split<SEMX_C_F16>(geo, atomic, naff, a, s);
+    case SEMX_C_MFMA_F32: return launch_t16_n<SEMX_C_F32>(n, geo, atomic, naff, a, s);
+    case SEMX_C_BF16: return launch_t16_n<SEMX_C_BF16>(n, geo, atomic, naff, a, s);
+    case SEMX_C_F16: return launch_t16_n<SEMX_C_F16>(n, geo, atomic, naff, a, s);
     default: return hipErrorInvalidValue;
   }
 }

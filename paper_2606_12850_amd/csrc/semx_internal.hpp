@@ -222,17 +222,20 @@ hipError_t launch_force_f32_split(int n, int geo, bool atomic, int64_t naff, con
 hipError_t launch_force_skeleton(int n, int geo, int64_t naff, const ForceArgs& a, hipStream_t s);
 
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
-// force_high.hip: NGLL 11..16 (one lane per (i, j) column)
+// force_high.hip: NGLL 11..16 (one lane per (i, j) column; the force pass uses it for 11..12)
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // Memory skeleton of the coloured launch_force_high (same loads and stores, no arithmetic).
 hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
-// force_tile16.hip: NGLL 16, all six contractions on the matrix cores; prec
-// SEMX_C_F32 / SEMX_C_MFMA_F32 (FP32 operands), SEMX_C_BF16, SEMX_C_F16 (the
-// launch's first naff elements have an affine numbering)
-hipError_t launch_force_tile16(int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
+// force_tile16.hip: NGLL 13..16 (16-point tiles, padded below 16), all six
+// contractions on the matrix cores; prec SEMX_C_F32 / SEMX_C_MFMA_F32 (FP32
+// operands), SEMX_C_BF16, SEMX_C_F16 (the launch's first naff elements have
+// an affine numbering)
+constexpr int kTileMinN = 13;
+hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
+                               hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)
 hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
-// MFMA contraction modes: NGLL 4..8 and 16 (all three precisions).
+// MFMA contraction modes: NGLL 4..8 and 13..16 (all three precisions).
 bool mfma_supported(int n, int prec);
 
 // ---- host helpers shared between translation units (api.hip) ----------------

@@ -1,6 +1,6 @@
 """High orders NGLL 11..16 (polynomial degree up to 15) against the FP64
-oracle (GPU): the column kernel (NGLL 11..15) and the matrix-core kernel
-(NGLL 16).
+oracle (GPU): the column kernel (NGLL 11..12) and the matrix-core kernel
+(NGLL 13..16, padded tiles below 16).
 
 Bars as for the lower orders: force 1e-5 relative L2 (FP32), seismograms
 1e-4 after the run.  The meshes are small (NGLL 16 has 4096 points per
