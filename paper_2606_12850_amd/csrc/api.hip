@@ -501,6 +501,9 @@ int build_layout(semx_ctx* c) {
     for (int k = 0; k < n && ok; ++k)
       for (int j = 0; j < n && ok; ++j)
         for (int i = 0; i < n && ok; ++i) ok = ie[i + n * (j + n * k)] == g0 + i * sx + j * sy + k * sz;
+    // the force kernels read the prior force of an affine element through a
+    // buffer over its node span, addressed with a 31-bit byte offset
+    if (ok && ((n - 1) * (std::llabs(sx) + std::llabs(sy) + std::llabs(sz)) + 1) * 12 > INT32_MAX) ok = false;
 #ifdef SEMX_NO_AFFINE_NUMBERING
     ok = false;
 #endif

@@ -31,49 +31,29 @@
 namespace semx {
 namespace {
 
-// Per-lane inputs of one element.
-struct PointIn {
-  int g;
-  bool first;  // the lane's point is the first to reach its node (store, no read)
-  float G[9];  // Gamma (kStored); unused otherwise
-  float lw, mw;
-  float u[3];
-  float f[3];
-};
-
-template <int NG, int GEO, bool ATOMIC>
-__device__ __forceinline__ void load_point(const ForceArgs& a, const float* __restrict__ mat,
-                                           const float* __restrict__ u, const float* f, int pos, int pp,
-                                           int g, PointIn& P) {
-  constexpr int N3 = Shape<NG>::N3;
-  P.g = g;
-  if constexpr (GEO == kStored) {
-    const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
+// First-touch bit of local point pp of the element at launch position pos
+// (coloured assembly): the element's NW = ceil(n^3/32) words are uniform over
+// the workgroup, so for NW <= 8 they come through the scalar cache and each
+// lane picks its word with a select chain; the f read that depends on the
+// bit then waits for a scalar load, not for a vector-memory round trip.
+template <int N3>
+__device__ __forceinline__ bool first_touch(const ForceArgs& a, int pos, int pp) {
+  constexpr int NW = (N3 + 31) / 32;
+  if (!a.first) return false;
+  const uint32_t* w = a.first + (size_t)pos * a.first_words;
+  if constexpr (NW <= 8) {
+    uint32_t word = w[0];
 #pragma unroll
-    for (int d = 0; d < 9; ++d) P.G[d] = ldnt(gp + d * N3);
-  }
-  P.lw = ldnt(mat + (size_t)pos * 2 * N3 + pp);
-  P.mw = ldnt(mat + (size_t)pos * 2 * N3 + N3 + pp);
-  P.u[0] = u[3 * (size_t)g + 0];
-  P.u[1] = u[3 * (size_t)g + 1];
-  P.u[2] = u[3 * (size_t)g + 2];
-  P.first = false;
-  if constexpr (!ATOMIC) {
-    if (a.first) P.first = (a.first[(size_t)pos * a.first_words + (pp >> 5)] >> (pp & 31)) & 1u;
-    P.f[0] = P.f[1] = P.f[2] = 0.0f;
-    if (!P.first) {
-      P.f[0] = f[3 * (size_t)g + 0];
-      P.f[1] = f[3 * (size_t)g + 1];
-      P.f[2] = f[3 * (size_t)g + 2];
+    for (int c = 1; c < NW; ++c) {
+      const uint32_t wc = w[c];
+      word = (pp >> 5) == c ? wc : word;
     }
+    return (word >> (pp & 31)) & 1u;
+  } else {
+    return (w[pp >> 5] >> (pp & 31)) & 1u;
   }
 }
 
-// One workgroup handles R consecutive launch positions (elements) in
-// straight-line code: the inputs of element m+1 are loaded while element m
-// computes.  Straight-line code (no loop) lets the compiler count outstanding
-// memory operations exactly, so waits for prefetched data never wait for the
-// scatter stores issued after them.
 // Node number of local point (i, j, k) of the element at launch position
 // `pos`: from the ibool stream, or (AFF) from the element's affine numbering
 // g0 + i sx + j sy + k sz (four scalar loads per element, no per-point stream
@@ -88,19 +68,56 @@ __device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp, int 
   }
 }
 
-template <int NG, int GEO, bool ATOMIC, int R, bool AFF>
+// Read of the prior force at node g for a coloured, affine-numbered element
+// (coloured assembly with first-touch bits): a raw buffer load over the
+// element's node span, with the offset pushed out of range at first-touch
+// points, so the hardware returns zeros there and fetches nothing, and the
+// load is a plain unconditional instruction the compiler can count exactly
+// (no branch, so later waits for u do not also wait for f).  The host
+// classifies an element as affine only when its span fits a 31-bit byte
+// offset.
+template <int NG>
+__device__ __forceinline__ void prior_force_affine(const float* f, const int* r, int g, bool first, float fo[3]) {
+  const int sx = r[1], sy = r[2], sz = r[3];
+  const int gmin = r[0] + (NG - 1) * (min(sx, 0) + min(sy, 0) + min(sz, 0));
+  const int span = (NG - 1) * (abs(sx) + abs(sy) + abs(sz)) + 1;
+  __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(f + 3 * (size_t)gmin), (short)0, span * 12, kBufferWord3);
+  typedef unsigned v3u __attribute__((ext_vector_type(3)));
+  // out of range: 2^31 lies past any num_records <= 2^31 - 1, and adding the
+  // 8 bytes of the last dword cannot wrap a 32-bit offset
+  const v3u v = __builtin_amdgcn_raw_buffer_load_b96(rs, first ? INT32_MIN : (g - gmin) * 12, 0, 0);
+  fo[0] = __uint_as_float(v.x);
+  fo[1] = __uint_as_float(v.y);
+  fo[2] = __uint_as_float(v.z);
+}
+
+// Per-element geometry that is uniform over the workgroup: Gamma (kRegular,
+// 9 floats) or the trilinear coefficients (kTrilinear, 24 floats).
+template <int GEO>
+struct ElemGeom {
+  static constexpr int NS = GEO == kRegular ? 9 : (GEO == kTrilinear ? 24 : 1);
+  float v[NS];
+};
+
+// One workgroup owns one element (one lane per GLL point).  Every load an
+// element needs is issued before its first wait: the constant tables (D and
+// the GLL nodes, L2-resident), the per-element scalars (node-numbering
+// coefficients, geometry, first-touch words), the material and the u gather.
+// The f read depends only on the first-touch bit (a scalar load) and is
+// consumed at the very end, so its latency runs under the contractions.
+template <int NG, int GEO, bool ATOMIC, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
+  constexpr int ND = NG * NG;
   __shared__ float s_u[3 * N3];
   __shared__ float s_q[9 * N3];
-  __shared__ float s_D[NG * NG];
+  __shared__ float s_D[ND + NG];  // D (row-major), then the GLL nodes
 
-  const int ngrp = (int)((a.count + R - 1) / R);
+  const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
   if (grp >= ngrp) return;  // uniform over the block
-  const int r0 = grp * R;
-  const int nr = min(R, (int)a.count - r0);
-  const int P0 = (int)a.pos0 + r0;
+  const int pos = (int)a.pos0 + grp;
 
   const int p = threadIdx.x;
   const bool act = p < N3;
@@ -112,74 +129,91 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   float* f = a.f + (size_t)model * a.nglob * 3;
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
 
-  PointIn P[2];
-  int g_next = (nr > 1) ? node_of<NG, AFF>(a, P0 + 1, pp, i, j, k) : 0;
-  load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0, pp, node_of<NG, AFF>(a, P0, pp, i, j, k), P[0]);
+  float tab = 0.0f;
+  if (p < ND) tab = a.D[p];
+  else if (GEO == kTrilinear && p < ND + NG) tab = a.xi[p - ND];
 
-  // D in LDS: the lane's rows and columns are read per contraction step,
-  // which keeps the register count low enough for 8 waves per SIMD.
-  if (p < NG * NG) s_D[p] = a.D[p];
-  float rx = 0.f, ry = 0.f, rz = 0.f;  // reference coordinates (trilinear path)
-  if constexpr (GEO == kTrilinear) {
-    rx = a.xi[i];
-    ry = a.xi[j];
-    rz = a.xi[k];
+  ElemGeom<GEO> eg;
+  if constexpr (GEO != kStored) {
+    const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
+#pragma unroll
+    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) eg.v[d] = src[d];
+  }
+  float G[9];
+  if constexpr (GEO == kStored) {
+    const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) G[d] = ldnt(gp + d * N3);
   }
 
+  const int g = node_of<NG, AFF>(a, pos, pp, i, j, k);
+  const float lw = ldnt(mat + (size_t)pos * 2 * N3 + pp);
+  const float mw = ldnt(mat + (size_t)pos * 2 * N3 + N3 + pp);
+  const float u0 = u[3 * (size_t)g + 0];
+  const float u1 = u[3 * (size_t)g + 1];
+  const float u2 = u[3 * (size_t)g + 2];
+  float fo[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (!ATOMIC && AFF) {
+    prior_force_affine<NG>(f, a.aff + (size_t)pos * 4, g, first_touch<N3>(a, pos, pp), fo);
+  } else if constexpr (!ATOMIC) {
+    if (!first_touch<N3>(a, pos, pp)) {
+      fo[0] = f[3 * (size_t)g + 0];
+      fo[1] = f[3 * (size_t)g + 1];
+      fo[2] = f[3 * (size_t)g + 2];
+    }
+  }
+
+  if constexpr (GEO != kStored) {
+    // keep the element's geometry loads ahead of the first barrier (they
+    // would otherwise be sunk past it, onto the element's critical path);
+    // placed after every load, so no load is seen as clobbered by it
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    if (m >= nr) break;  // uniform over the block
-    PointIn& cur = P[m & 1];
-    PointIn& nxt = P[(m + 1) & 1];
-    if (m > 0) __syncthreads();  // the previous element has finished reading s_q / s_u
-    if (act) {
-      s_u[pp] = cur.u[0];
-      s_u[N3 + pp] = cur.u[1];
-      s_u[2 * N3 + pp] = cur.u[2];
-    }
-    if (m + 1 < nr) {
-      load_point<NG, GEO, ATOMIC>(a, mat, u, f, P0 + m + 1, pp, g_next, nxt);
-      if (m + 2 < nr) g_next = node_of<NG, AFF>(a, P0 + m + 2, pp, i, j, k);
-    }
-    __syncthreads();
+    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) asm volatile("" ::"s"(eg.v[d]));
+  }
+  if (p < ND + NG) s_D[p] = tab;
+  if (act) {
+    s_u[pp] = u0;
+    s_u[N3 + pp] = u1;
+    s_u[2 * N3 + pp] = u2;
+  }
+  __syncthreads();
 
-    float du[3][3];
-    ref_grad<NG>(s_u, s_D, i, j, k, du);
-    float Mg[9], scale, det;
-    geom_map<GEO>(a, P0 + m, cur.G, rx, ry, rz, Mg, scale, det);
-    float gr[3][3];
-    apply_map(du, Mg, gr);
-    stress_flux(gr, cur.lw, cur.mw, scale, Mg, s_q, N3, pp, act);
-    __syncthreads();
+  float rx = 0.f, ry = 0.f, rz = 0.f;  // reference coordinates (trilinear path)
+  if constexpr (GEO == kTrilinear) {
+    rx = s_D[ND + i];
+    ry = s_D[ND + j];
+    rz = s_D[ND + k];
+  }
+  float du[3][3];
+  ref_grad<NG>(s_u, s_D, i, j, k, du);
+  float Mg[9], scale, det;
+  geom_map_from<GEO>(eg.v, G, rx, ry, rz, Mg, scale, det);
+  float gr[3][3];
+  apply_map(du, Mg, gr);
+  stress_flux(gr, lw, mw, scale, Mg, s_q, N3, pp, act);
+  __syncthreads();
 
-    float F[3];
-    ref_div<NG>(s_q, s_D, i, j, k, F);
-    if (act) {
-      float* fg = f + 3 * (size_t)cur.g;
-      if constexpr (ATOMIC) {
-        unsafeAtomicAdd(fg + 0, F[0]);
-        unsafeAtomicAdd(fg + 1, F[1]);
-        unsafeAtomicAdd(fg + 2, F[2]);
-      } else {
-        fg[0] = cur.f[0] + F[0];
-        fg[1] = cur.f[1] + F[1];
-        fg[2] = cur.f[2] + F[2];
-      }
+  float F[3];
+  ref_div<NG>(s_q, s_D, i, j, k, F);
+  if (act) {
+    float* fg = f + 3 * (size_t)g;
+    if constexpr (ATOMIC) {
+      unsafeAtomicAdd(fg + 0, F[0]);
+      unsafeAtomicAdd(fg + 1, F[1]);
+      unsafeAtomicAdd(fg + 2, F[2]);
+    } else {
+      fg[0] = fo[0] + F[0];
+      fg[1] = fo[1] + F[1];
+      fg[2] = fo[2] + F[2];
     }
   }
 }
 
-#ifndef SEMX_F32_ELEMS_PER_BLOCK
-#define SEMX_F32_ELEMS_PER_BLOCK 1
-#endif
-
 template <int NG, int GEO, bool ATOMIC, bool AFF>
 hipError_t launch_one(const ForceArgs& a, hipStream_t s) {
-  constexpr int R = SEMX_F32_ELEMS_PER_BLOCK;
-  const int64_t ngrp = (a.count + R - 1) / R;
-  const int64_t nb = ((ngrp + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
-  force_f32_kernel<NG, GEO, ATOMIC, R, AFF><<<grid, block, 0, s>>>(a);
+  force_f32_kernel<NG, GEO, ATOMIC, AFF><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -198,12 +232,12 @@ hipError_t launch_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   }
 }
 
-// Memory skeleton of force_f32_kernel (coloured assembly, one element per
-// workgroup): the same grid, block mapping and per-lane loads and stores
-// (node number, geometry, material, u, first-touch bit, f read unless first,
-// f store), without the contractions and the pointwise arithmetic.  Its
-// duration is the floor that the kernel's access pattern alone sets on the
-// memory system.  f receives meaningless values.
+// Memory skeleton of force_f32_kernel (coloured assembly): the same grid,
+// block mapping and per-lane loads and stores (node number, geometry,
+// material, u, first-touch bit, f read unless first, f store), without the
+// contractions and the pointwise arithmetic.  Its duration is the floor that
+// the kernel's access pattern alone sets on the memory system.  f receives
+// meaningless values.
 template <int NG, int GEO, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
@@ -217,28 +251,36 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArg
   const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
   float* f = a.f + (size_t)model * a.nglob * 3;
   const float* __restrict__ mat = a.mat + (size_t)model * a.nspec * 2 * N3;
-  PointIn P;
-  load_point<NG, GEO, false>(a, mat, u, f, pos, p, node_of<NG, AFF>(a, pos, p, p % NG, (p / NG) % NG, p / (NG * NG)),
-                             P);
-  float s = P.lw + P.mw;
+  float s = 0.0f;
   if constexpr (GEO == kStored) {
+    const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + p;
 #pragma unroll
-    for (int d = 0; d < 9; ++d) s += P.G[d];
+    for (int d = 0; d < 9; ++d) s += ldnt(gp + d * N3);
   } else {
     constexpr int NS = GEO == kRegular ? 9 : 24;
     const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
 #pragma unroll
     for (int d = 0; d < NS; ++d) s += src[d];
   }
-  float* fg = f + 3 * (size_t)P.g;
-  fg[0] = P.f[0] + s * P.u[0];
-  fg[1] = P.f[1] + s * P.u[1];
-  fg[2] = P.f[2] + s * P.u[2];
+  const int g = node_of<NG, AFF>(a, pos, p, p % NG, (p / NG) % NG, p / (NG * NG));
+  s += ldnt(mat + (size_t)pos * 2 * N3 + p) + ldnt(mat + (size_t)pos * 2 * N3 + N3 + p);
+  const float u0 = u[3 * (size_t)g + 0], u1 = u[3 * (size_t)g + 1], u2 = u[3 * (size_t)g + 2];
+  float fo[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (AFF) {
+    prior_force_affine<NG>(f, a.aff + (size_t)pos * 4, g, first_touch<N3>(a, pos, p), fo);
+  } else if (!first_touch<N3>(a, pos, p)) {
+    fo[0] = f[3 * (size_t)g + 0];
+    fo[1] = f[3 * (size_t)g + 1];
+    fo[2] = f[3 * (size_t)g + 2];
+  }
+  float* fg = f + 3 * (size_t)g;
+  fg[0] = fo[0] + s * u0;
+  fg[1] = fo[1] + s * u1;
+  fg[2] = fo[2] + s * u2;
 }
 
 template <int NG, bool AFF>
 hipError_t launch_skeleton_n(int geo, const ForceArgs& a, hipStream_t s) {
-  static_assert(SEMX_F32_ELEMS_PER_BLOCK == 1, "the skeleton mirrors one element per workgroup");
   if (a.count <= 0) return hipSuccess;
   const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);

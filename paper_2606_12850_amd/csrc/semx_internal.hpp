@@ -14,6 +14,10 @@ namespace semx {
 constexpr int kMaxN = 16;     // largest supported NGLL
 constexpr int kMaxNLow = 10;  // largest NGLL of the one-point-per-lane kernels (FP64 storage, adjoint)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, round-robin block dispatch
+// Word 3 of a raw buffer resource on gfx9-family devices (gfx950): 32-bit
+// data format, no swizzle, range-checked against num_records (out-of-range
+// lanes read zeros and fetch nothing).
+constexpr int kBufferWord3 = 0x00020000;
 
 // geometry path of a force launch
 constexpr int kRegular = 0;    // affine element: one Gamma per element
