@@ -97,7 +97,9 @@ __device__ __forceinline__ void geom_map_from(const float* src, const float* G, 
     Mg[0] = C00; Mg[1] = C10; Mg[2] = C20;
     Mg[3] = C01; Mg[4] = C11; Mg[5] = C21;
     Mg[6] = C02; Mg[7] = C12; Mg[8] = C22;
-    const float id = 1.0f / det;
+    // hardware reciprocal (1 ulp): the weighting needs no correctly rounded
+    // quotient, and the IEEE division sequence costs ten instructions a point
+    const float id = __builtin_amdgcn_rcpf(det);
     scale = id * id;
   }
 }
@@ -125,18 +127,16 @@ __device__ __forceinline__ void apply_map(const float du[3][3], const float Mg[9
 // `scale`, and fluxes Phi[c][d] = sum_b sigma[c][b] Mg[d][b] written to s_q.
 __device__ __forceinline__ void stress_flux(const float gr[3][3], float lamw, float muw, float scale,
                                             const float Mg[9], float* s_q, int N3, int pp, bool act) {
-  const float ltr = lamw * (gr[0][0] + gr[1][1] + gr[2][2]);
+  // the weight `scale` is folded into the two moduli before the stress
+  const float ls = lamw * scale, ms = muw * scale, ms2 = 2.0f * ms;
+  const float ltr = ls * (gr[0][0] + gr[1][1] + gr[2][2]);
   float sg[3][3];
-  sg[0][0] = ltr + 2.0f * muw * gr[0][0];
-  sg[1][1] = ltr + 2.0f * muw * gr[1][1];
-  sg[2][2] = ltr + 2.0f * muw * gr[2][2];
-  sg[0][1] = sg[1][0] = muw * (gr[0][1] + gr[1][0]);
-  sg[0][2] = sg[2][0] = muw * (gr[0][2] + gr[2][0]);
-  sg[1][2] = sg[2][1] = muw * (gr[1][2] + gr[2][1]);
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) sg[c][b] *= scale;
+  sg[0][0] = ltr + ms2 * gr[0][0];
+  sg[1][1] = ltr + ms2 * gr[1][1];
+  sg[2][2] = ltr + ms2 * gr[2][2];
+  sg[0][1] = sg[1][0] = ms * (gr[0][1] + gr[1][0]);
+  sg[0][2] = sg[2][0] = ms * (gr[0][2] + gr[2][0]);
+  sg[1][2] = sg[2][1] = ms * (gr[1][2] + gr[2][1]);
   if (act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)

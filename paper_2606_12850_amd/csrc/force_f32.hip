@@ -31,65 +31,87 @@
 namespace semx {
 namespace {
 
-// First-touch bit of local point pp of the element at launch position pos
-// (coloured assembly): the element's NW = ceil(n^3/32) words are uniform over
-// the workgroup, so for NW <= 8 they come through the scalar cache and each
-// lane picks its word with a select chain; the f read that depends on the
-// bit then waits for a scalar load, not for a vector-memory round trip.
+// First-touch bit of the lane's point (coloured assembly).  Point p's bit is
+// bit p & 31 of word p >> 5 of the element's bitmask, so the 64 lanes of wave
+// w read words 2w and 2w + 1: the pair is uniform over the wave, comes
+// through the scalar cache, and turns into the lane's bit with one select on
+// the 64-bit mask.  The f read that depends on the bit then waits for a
+// scalar load, not for a vector-memory round trip.  Lanes past the element's
+// points (p >= n^3) see bits of a zero word or of no point; they store nothing.
 template <int N3>
-__device__ __forceinline__ bool first_touch(const ForceArgs& a, int pos, int pp) {
+__device__ __forceinline__ bool first_touch(const ForceArgs& a, int pos) {
   constexpr int NW = (N3 + 31) / 32;
   if (!a.first) return false;
   const uint32_t* w = a.first + (size_t)pos * a.first_words;
-  if constexpr (NW <= 8) {
-    uint32_t word = w[0];
-#pragma unroll
-    for (int c = 1; c < NW; ++c) {
-      const uint32_t wc = w[c];
-      word = (pp >> 5) == c ? wc : word;
-    }
-    return (word >> (pp & 31)) & 1u;
-  } else {
-    return (w[pp >> 5] >> (pp & 31)) & 1u;
-  }
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const uint64_t lo = wave * 2 < NW ? w[wave * 2] : 0u;
+  const uint64_t hi = wave * 2 + 1 < NW ? w[wave * 2 + 1] : 0u;
+  return __builtin_amdgcn_inverse_ballot_w64(lo | (hi << 32));
 }
 
 // Node number of local point (i, j, k) of the element at launch position
-// `pos`: from the ibool stream, or (AFF) from the element's affine numbering
-// g0 + i sx + j sy + k sz (four scalar loads per element, no per-point stream
-// and no dependent round trip before the gather).
-template <int NG, bool AFF>
-__device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp, int i, int j, int k) {
-  if constexpr (AFF) {
-    const int* r = a.aff + (size_t)pos * 4;
-    return r[0] + i * r[1] + j * r[2] + k * r[3];
-  } else {
-    return ldnt(a.ibool + (size_t)pos * Shape<NG>::N3 + pp);
-  }
+// `pos` from the ibool stream (elements without an affine numbering).
+template <int NG>
+__device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp) {
+  return ldnt(a.ibool + (size_t)pos * Shape<NG>::N3 + pp);
 }
 
-// Read of the prior force at node g for a coloured, affine-numbered element
-// (coloured assembly with first-touch bits): a raw buffer load over the
-// element's node span, with the offset pushed out of range at first-touch
-// points, so the hardware returns zeros there and fetches nothing, and the
-// load is a plain unconditional instruction the compiler can count exactly
-// (no branch, so later waits for u do not also wait for f).  The host
-// classifies an element as affine only when its span fits a 31-bit byte
-// offset.
+// The node span of an affine-numbered element (node g = g0 + i sx + j sy +
+// k sz; four scalar loads per element, no per-point stream and no dependent
+// round trip before the gather): raw buffer resources over the element's
+// nodes in u and f, and the lane's byte offset into them.  With 32-bit
+// offsets from a per-element base, the gather, the prior-force read and the
+// store need no 64-bit address arithmetic.  The host classifies an element
+// as affine only when its span fits a 31-bit byte offset.
+struct AffSpan {
+  __amdgpu_buffer_rsrc_t ru, rf;
+  int off;
+};
+
 template <int NG>
-__device__ __forceinline__ void prior_force_affine(const float* f, const int* r, int g, bool first, float fo[3]) {
+__device__ __forceinline__ AffSpan aff_span(const ForceArgs& a, int pos, const float* u, float* f, int i, int j,
+                                            int k) {
+  const int* r = a.aff + (size_t)pos * 4;
   const int sx = r[1], sy = r[2], sz = r[3];
-  const int gmin = r[0] + (NG - 1) * (min(sx, 0) + min(sy, 0) + min(sz, 0));
-  const int span = (NG - 1) * (abs(sx) + abs(sy) + abs(sz)) + 1;
-  __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(f + 3 * (size_t)gmin), (short)0, span * 12, kBufferWord3);
-  typedef unsigned v3u __attribute__((ext_vector_type(3)));
-  // out of range: 2^31 lies past any num_records <= 2^31 - 1, and adding the
-  // 8 bytes of the last dword cannot wrap a 32-bit offset
-  const v3u v = __builtin_amdgcn_raw_buffer_load_b96(rs, first ? INT32_MIN : (g - gmin) * 12, 0, 0);
-  fo[0] = __uint_as_float(v.x);
-  fo[1] = __uint_as_float(v.y);
-  fo[2] = __uint_as_float(v.z);
+  const int lo = (NG - 1) * (min(sx, 0) + min(sy, 0) + min(sz, 0));
+  const int gmin = r[0] + lo;
+  const int bytes = ((NG - 1) * (abs(sx) + abs(sy) + abs(sz)) + 1) * 12;
+  AffSpan s;
+  s.ru = __builtin_amdgcn_make_buffer_rsrc((void*)(u + 3 * (size_t)gmin), (short)0, bytes, kBufferWord3);
+  s.rf = __builtin_amdgcn_make_buffer_rsrc((void*)(f + 3 * (size_t)gmin), (short)0, bytes, kBufferWord3);
+  s.off = (i * sx + j * sy + k * sz - lo) * 12;
+  return s;
+}
+
+typedef unsigned semx_v3u __attribute__((ext_vector_type(3)));
+
+__device__ __forceinline__ void unpack3(semx_v3u v, float x[3]) {
+  x[0] = __uint_as_float(v.x);
+  x[1] = __uint_as_float(v.y);
+  x[2] = __uint_as_float(v.z);
+}
+
+// u at the lane's node of an affine element.
+__device__ __forceinline__ void gather_affine(const AffSpan& s, float x[3]) {
+  unpack3(__builtin_amdgcn_raw_buffer_load_b96(s.ru, s.off, 0, 0), x);
+}
+
+// Prior force at the lane's node of an affine element: at first-touch points
+// the offset is pushed out of range, so the hardware returns zeros and
+// fetches nothing, and the read stays one unconditional instruction that the
+// compiler counts exactly (no branch, so the wait for u does not also wait
+// for f).  2^31 lies past any num_records <= 2^31 - 1, and adding the 8 bytes
+// of the last dword cannot wrap a 32-bit offset.
+__device__ __forceinline__ void prior_force_affine(const AffSpan& s, bool first, float x[3]) {
+  unpack3(__builtin_amdgcn_raw_buffer_load_b96(s.rf, first ? INT32_MIN : s.off, 0, 0), x);
+}
+
+__device__ __forceinline__ void store_affine(const AffSpan& s, const float x[3]) {
+  semx_v3u v;
+  v.x = __float_as_uint(x[0]);
+  v.y = __float_as_uint(x[1]);
+  v.z = __float_as_uint(x[2]);
+  __builtin_amdgcn_raw_buffer_store_b96(v, s.rf, s.off, 0, 0);
 }
 
 // Per-element geometry that is uniform over the workgroup: Gamma (kRegular,
@@ -100,12 +122,13 @@ struct ElemGeom {
   float v[NS];
 };
 
-// One workgroup owns one element (one lane per GLL point).  Every load an
-// element needs is issued before its first wait: the constant tables (D and
-// the GLL nodes, L2-resident), the per-element scalars (node-numbering
-// coefficients, geometry, first-touch words), the material and the u gather.
-// The f read depends only on the first-touch bit (a scalar load) and is
-// consumed at the very end, so its latency runs under the contractions.
+// One workgroup owns one element (one lane per GLL point).  Every load the
+// element's first half needs is issued before its first wait: the constant
+// tables (D and the GLL nodes, L2-resident), the per-element scalars
+// (node-numbering coefficients, geometry, first-touch words), the material
+// and the u gather.  The prior-force read depends only on the first-touch bit
+// (a scalar load) and is consumed at the very end, so its latency runs under
+// the transpose contractions.
 template <int NG, int GEO, bool ATOMIC, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
@@ -146,20 +169,32 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     for (int d = 0; d < 9; ++d) G[d] = ldnt(gp + d * N3);
   }
 
-  const int g = node_of<NG, AFF>(a, pos, pp, i, j, k);
   const float lw = ldnt(mat + (size_t)pos * 2 * N3 + pp);
   const float mw = ldnt(mat + (size_t)pos * 2 * N3 + N3 + pp);
-  const float u0 = u[3 * (size_t)g + 0];
-  const float u1 = u[3 * (size_t)g + 1];
-  const float u2 = u[3 * (size_t)g + 2];
-  float fo[3] = {0.0f, 0.0f, 0.0f};
-  if constexpr (!ATOMIC && AFF) {
-    prior_force_affine<NG>(f, a.aff + (size_t)pos * 4, g, first_touch<N3>(a, pos, pp), fo);
-  } else if constexpr (!ATOMIC) {
-    if (!first_touch<N3>(a, pos, pp)) {
-      fo[0] = f[3 * (size_t)g + 0];
-      fo[1] = f[3 * (size_t)g + 1];
-      fo[2] = f[3 * (size_t)g + 2];
+  float uo[3], fo[3] = {0.0f, 0.0f, 0.0f};
+  AffSpan sp;
+  int g = 0;
+  bool first = false;
+  if constexpr (AFF) {
+    sp = aff_span<NG>(a, pos, u, f, i, j, k);
+    gather_affine(sp, uo);
+    if constexpr (ATOMIC) {
+      const int* r = a.aff + (size_t)pos * 4;
+      g = r[0] + i * r[1] + j * r[2] + k * r[3];
+    } else {
+      first = first_touch<N3>(a, pos);
+    }
+  } else {
+    g = node_of<NG>(a, pos, pp);
+    uo[0] = u[3 * (size_t)g + 0];
+    uo[1] = u[3 * (size_t)g + 1];
+    uo[2] = u[3 * (size_t)g + 2];
+    if constexpr (!ATOMIC) {
+      if (!first_touch<N3>(a, pos)) {
+        fo[0] = f[3 * (size_t)g + 0];
+        fo[1] = f[3 * (size_t)g + 1];
+        fo[2] = f[3 * (size_t)g + 2];
+      }
     }
   }
 
@@ -172,9 +207,9 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   }
   if (p < ND + NG) s_D[p] = tab;
   if (act) {
-    s_u[pp] = u0;
-    s_u[N3 + pp] = u1;
-    s_u[2 * N3 + pp] = u2;
+    s_u[pp] = uo[0];
+    s_u[N3 + pp] = uo[1];
+    s_u[2 * N3 + pp] = uo[2];
   }
   __syncthreads();
 
@@ -191,20 +226,31 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   float gr[3][3];
   apply_map(du, Mg, gr);
   stress_flux(gr, lw, mw, scale, Mg, s_q, N3, pp, act);
+  // the prior force of an affine element is read here: it is needed only
+  // after the transpose contractions, and issuing it earlier keeps three
+  // more registers live through the stress (65 instead of 63, 7 waves per
+  // SIMD instead of 8)
+  if constexpr (AFF && !ATOMIC) prior_force_affine(sp, first, fo);
   __syncthreads();
 
   float F[3];
   ref_div<NG>(s_q, s_D, i, j, k, F);
   if (act) {
-    float* fg = f + 3 * (size_t)g;
     if constexpr (ATOMIC) {
+      float* fg = f + 3 * (size_t)g;
       unsafeAtomicAdd(fg + 0, F[0]);
       unsafeAtomicAdd(fg + 1, F[1]);
       unsafeAtomicAdd(fg + 2, F[2]);
     } else {
-      fg[0] = fo[0] + F[0];
-      fg[1] = fo[1] + F[1];
-      fg[2] = fo[2] + F[2];
+      const float out[3] = {fo[0] + F[0], fo[1] + F[1], fo[2] + F[2]};
+      if constexpr (AFF) {
+        store_affine(sp, out);
+      } else {
+        float* fg = f + 3 * (size_t)g;
+        fg[0] = out[0];
+        fg[1] = out[1];
+        fg[2] = out[2];
+      }
     }
   }
 }
@@ -262,21 +308,29 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArg
 #pragma unroll
     for (int d = 0; d < NS; ++d) s += src[d];
   }
-  const int g = node_of<NG, AFF>(a, pos, p, p % NG, (p / NG) % NG, p / (NG * NG));
   s += ldnt(mat + (size_t)pos * 2 * N3 + p) + ldnt(mat + (size_t)pos * 2 * N3 + N3 + p);
-  const float u0 = u[3 * (size_t)g + 0], u1 = u[3 * (size_t)g + 1], u2 = u[3 * (size_t)g + 2];
-  float fo[3] = {0.0f, 0.0f, 0.0f};
+  float uo[3], fo[3] = {0.0f, 0.0f, 0.0f};
   if constexpr (AFF) {
-    prior_force_affine<NG>(f, a.aff + (size_t)pos * 4, g, first_touch<N3>(a, pos, p), fo);
-  } else if (!first_touch<N3>(a, pos, p)) {
-    fo[0] = f[3 * (size_t)g + 0];
-    fo[1] = f[3 * (size_t)g + 1];
-    fo[2] = f[3 * (size_t)g + 2];
+    const AffSpan sp = aff_span<NG>(a, pos, u, f, p % NG, (p / NG) % NG, p / (NG * NG));
+    gather_affine(sp, uo);
+    prior_force_affine(sp, first_touch<N3>(a, pos), fo);
+    const float out[3] = {fo[0] + s * uo[0], fo[1] + s * uo[1], fo[2] + s * uo[2]};
+    store_affine(sp, out);
+  } else {
+    const int g = node_of<NG>(a, pos, p);
+    uo[0] = u[3 * (size_t)g + 0];
+    uo[1] = u[3 * (size_t)g + 1];
+    uo[2] = u[3 * (size_t)g + 2];
+    if (!first_touch<N3>(a, pos)) {
+      fo[0] = f[3 * (size_t)g + 0];
+      fo[1] = f[3 * (size_t)g + 1];
+      fo[2] = f[3 * (size_t)g + 2];
+    }
+    float* fg = f + 3 * (size_t)g;
+    fg[0] = fo[0] + s * uo[0];
+    fg[1] = fo[1] + s * uo[1];
+    fg[2] = fo[2] + s * uo[2];
   }
-  float* fg = f + 3 * (size_t)g;
-  fg[0] = fo[0] + s * u0;
-  fg[1] = fo[1] + s * u1;
-  fg[2] = fo[2] + s * u2;
 }
 
 template <int NG, bool AFF>
