@@ -102,7 +102,7 @@ def write_traffic(run_dir: str):
                     agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
             cp = [v for k, vs in agg.items() if "copyBuffer" in k for v in vs][-3:]
             scale = copy_bytes / (sum(cp) / len(cp) * 1024.0)
-            for tag, pat in (("kernel", f"force_f32_kernel<5, {gid}, false, 1, true>"),
+            for tag, pat in (("kernel", f"force_f32_kernel<5, {gid}, false, true>"),
                              ("skeleton", f"force_skeleton_kernel<5, {gid}, true>")):
                 kv = [v for k, vs in agg.items() if pat in k for v in vs]
                 if kv:
@@ -460,12 +460,13 @@ def order_sweep_leg(reps: int = 20, orders=None):
         row["dt_cfl"] = dt
         row["hmin_over_h"] = dt * vp_max / 0.4 / h  # smallest GLL spacing over the element size
         # contraction modes: FP32 everywhere; the matrix-core modes where they
-        # exist (NGLL 4..8 and 16; at 16 the FP32 path is the FP32-operand
-        # matrix-core kernel itself, so mf32 is not listed again).  Timed in
-        # interleaved rounds (median), so that clock state favours no mode.
+        # exist (NGLL 4..8 and 11..16; from 13 the FP32 path is the
+        # FP32-operand matrix-core kernel itself, so mf32 is not listed
+        # there).  Timed in interleaved rounds (median), so that clock state
+        # favours no mode.
         modes = [(c, m) for c, m in (("f32", P.SEMX_C_F32), ("mf32", P.SEMX_C_MFMA_F32), ("bf16", P.SEMX_C_BF16),
                                      ("f16", P.SEMX_C_F16))
-                 if c == "f32" or (4 <= n <= 8) or (n == 16 and c != "mf32")]
+                 if c == "f32" or (4 <= n <= 8) or (11 <= n <= 16 and not (n >= 13 and c == "mf32"))]
         ref = None
         for cname, cmode in modes:
             P.semx_set_mode(s.ctx, cmode, P.SEMX_ASM_COLORED)
@@ -1058,7 +1059,7 @@ def main():
         out["adjoint"] = adjoint_leg()
     if not args.no_order_sweep:
         full = args.order_sweep_full
-        out["order_sweep"] = order_sweep_leg(orders=None if full else (4, 5, 6, 7, 8, 9, 16))
+        out["order_sweep"] = order_sweep_leg(orders=None if full else (4, 5, 6, 7, 8, 9, 12, 16))
         progress("order sweep done")
         if full:
             out["iso_accuracy"] = [iso_accuracy_summary(out["order_sweep"], e) for e in (1e-4, 1e-5)]

@@ -122,7 +122,7 @@ int semx_upload_model(semx_ctx *ctx, int nmodels, const double *lambda, const do
 
 /* Select the contraction arithmetic and the assembly (constants above).
  * The matrix-core contractions (SEMX_C_BF16, SEMX_C_F16, SEMX_C_MFMA_F32)
- * need 4 <= NGLL <= 8 or 13 <= NGLL <= 16 (where SEMX_C_MFMA_F32 is the
+ * need 4 <= NGLL <= 8 or 11 <= NGLL <= 16 (at 13..16 SEMX_C_MFMA_F32 is the
  * FP32 path itself); SEMX_EINVAL otherwise, or for an unknown value, or for
  * coloured assembly on a mesh whose elements repeat a node. */
 int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);

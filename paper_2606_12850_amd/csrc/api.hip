@@ -591,6 +591,19 @@ int build_layout(semx_ctx* c) {
     for (int64_t g = 0; g < c->nglob && c->elem_cover; ++g) c->elem_cover = touched[g] != 0;
     c->first_words = fw;
   }
+  // element-interior points that are the only reference to their node
+  {
+    std::vector<uint8_t> refs(c->nglob, 0);
+    for (int64_t t = 0; t < nspec * n3; ++t) refs[ib[t]] = refs[ib[t]] < 2 ? refs[ib[t]] + 1 : 2;
+    bool excl = n > 2;
+    for (int64_t pos = 0; pos < nspec && excl; ++pos)
+      for (int q = 0; q < n3 && excl; ++q) {
+        const int qi = q % n, qj = (q / n) % n, qk = q / (n * n);
+        const bool interior = qi > 0 && qi < n - 1 && qj > 0 && qj < n - 1 && qk > 0 && qk < n - 1;
+        if (interior) excl = refs[ib[pos * n3 + q]] == 1;
+      }
+    c->interior_exclusive = excl;
+  }
   int rc = dev_alloc(c, c->d_order, sizeof(int32_t) * nspec);
   if (!rc && !first.empty()) rc = dev_alloc(c, c->d_first, sizeof(uint32_t) * first.size());
   if (!rc && first.empty()) dev_free(c->d_first);
@@ -665,9 +678,12 @@ ForceArgs force_args(const semx_ctx* c, const float* u, float* f, bool first_tou
   return a;
 }
 
-int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false) {
+// `f_zero`: f holds zeros on entry, so with atomic assembly the points that
+// are their node's only reference may store instead of adding.
+int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false, bool f_zero = false) {
   ForceArgs a = force_args(c, u, f, first_touch);
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
+  a.excl_interior = atomic && f_zero && c->interior_exclusive ? 1 : 0;
   const auto& launches = atomic ? c->atomic_launches : c->colored_launches;
   hipEvent_t e1 = nullptr;
   if (!launches.empty() && c->timing_stride > 0 && (c->timing_seq++ % c->timing_stride) == 0) {
@@ -681,7 +697,7 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     const int geo = L.irregular ? c->irregular_geo : kRegular;
     if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, a, c->stream);
-    else if (c->n >= kTileMinN)
+    else if (c->n >= kTileMinN || (c->n >= kTileMinNMixed && c->contraction != SEMX_C_F32))
       e = launch_force_tile16(c->n, c->contraction, geo, atomic, L.naff, a, c->stream);
     else if (c->contraction == SEMX_C_F32 && c->n > kMaxNLow)
       e = launch_force_high(c->n, geo, atomic, a, c->stream);
@@ -734,7 +750,7 @@ int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
     int rc = zero_f32(c, f, state_len(c));
     if (rc) return rc;
   }
-  return force_accumulate(c, u, f, force_overwrites(c));
+  return force_accumulate(c, u, f, force_overwrites(c), !force_overwrites(c));
 }
 
 
@@ -1353,7 +1369,7 @@ int semx_set_mode(semx_ctx* c, int contraction, int assembly) {
   if (assembly != SEMX_ASM_COLORED && assembly != SEMX_ASM_ATOMIC)
     return fail(c, SEMX_EINVAL, "set_mode: unknown assembly");
   if (contraction != SEMX_C_F32 && !mfma_supported(c->n, contraction))
-    return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8 or 13 <= NGLL <= 16");
+    return fail(c, SEMX_EINVAL, "set_mode: MFMA contractions need 4 <= NGLL <= 8 or 11 <= NGLL <= 16");
   if (contraction != SEMX_C_F32 && c->storage == SEMX_F64)
     return fail(c, SEMX_EINVAL, "set_mode: FP64 storage contracts on the vector units (SEMX_C_F32 only)");
   if (contraction != SEMX_C_F32 && c->physics == SEMX_ACOUSTIC)

@@ -238,9 +238,18 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   if (act) {
     if constexpr (ATOMIC) {
       float* fg = f + 3 * (size_t)g;
-      unsafeAtomicAdd(fg + 0, F[0]);
-      unsafeAtomicAdd(fg + 1, F[1]);
-      unsafeAtomicAdd(fg + 2, F[2]);
+      // an element-interior point is its node's only reference (checked at
+      // upload): its force is the node's whole force, stored without an atomic
+      const bool own = a.excl_interior && i > 0 && i < NG - 1 && j > 0 && j < NG - 1 && k > 0 && k < NG - 1;
+      if (own) {
+        fg[0] = F[0];
+        fg[1] = F[1];
+        fg[2] = F[2];
+      } else {
+        unsafeAtomicAdd(fg + 0, F[0]);
+        unsafeAtomicAdd(fg + 1, F[1]);
+        unsafeAtomicAdd(fg + 2, F[2]);
+      }
     } else {
       const float out[3] = {fo[0] + F[0], fo[1] + F[1], fo[2] + F[2]};
       if constexpr (AFF) {

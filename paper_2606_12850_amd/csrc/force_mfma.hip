@@ -328,7 +328,7 @@ hipError_t launch_mfma_p(int n, int geo, bool atomic, const ForceArgs& a, hipStr
 
 }  // namespace
 
-bool mfma_supported(int n, int) { return (n >= 4 && n <= 8) || (n >= kTileMinN && n <= 16); }
+bool mfma_supported(int n, int) { return (n >= 4 && n <= 8) || (n >= kTileMinNMixed && n <= 16); }
 
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (prec == SEMX_C_BF16) return launch_mfma_p<SEMX_C_BF16>(n, geo, atomic, a, s);

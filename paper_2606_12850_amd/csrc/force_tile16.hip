@@ -1,4 +1,5 @@
-// Element internal-force kernel for NGLL 13..16 on the matrix cores.
+// Element internal-force kernel for NGLL 11..16 on the matrix cores (FP32
+// operands from NGLL 13, 16-bit operands from NGLL 11).
 //
 // The operator is that of force_f32.hip and force_high.hip (Sec. II-B weak
 // form: three forward and three transpose sum-factorised contractions with
@@ -6,7 +7,7 @@
 // stress and weighted flux; Sec. IV-D fused traversal).  At NGLL 16 every
 // contraction is an exact 16 x 16 x 16 matrix product, so all six run as
 // v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation, four K = 4 steps
-// per product) and the vector units keep only the pointwise work.  NGLL 13
+// per product) and the vector units keep only the pointwise work.  NGLL 11
 // to 15 use the same 16-point tile with padding: D is extended by zero rows
 // and columns and u, lambda, mu are zero at the padding points, so every
 // padded product term is zero and the padding points carry zero flux; only
@@ -586,6 +587,8 @@ hipError_t launch_t16_split(int geo, bool atomic, int64_t naff, const ForceArgs&
 template <int PREC>
 hipError_t launch_t16_n(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
   switch (n) {
+    case 11: return launch_t16_split<11, PREC>(geo, atomic, naff, a, s);
+    case 12: return launch_t16_split<12, PREC>(geo, atomic, naff, a, s);
     case 13: return launch_t16_split<13, PREC>(geo, atomic, naff, a, s);
     case 14: return launch_t16_split<14, PREC>(geo, atomic, naff, a, s);
     case 15: return launch_t16_split<15, PREC>(geo, atomic, naff, a, s);

@@ -114,6 +114,10 @@ struct semx_ctx {
   semx::DevBuf d_first;
   int first_words = 0;
   bool elem_cover = false;
+  // every element-interior GLL point (local indices 1..n-2 in all three
+  // directions) is the only reference to its node, as in any conforming mesh:
+  // atomic assembly stores those points' forces without an atomic
+  bool interior_exclusive = false;
 
   // colouring
   int ncolors = 0;
@@ -213,6 +217,7 @@ struct ForceArgs {
   const uint32_t* first; // coloured per-element paths: per-position bitmask of the points that
                          // reach their node first in launch order (store, no read), or null
   int first_words;       // 32-bit words per position in `first`
+  int excl_interior;     // atomic assembly: element-interior points own their nodes (plain store)
   int64_t pos0;          // first launch position of this launch
   int64_t count;
   int64_t nspec, nglob;
@@ -226,15 +231,18 @@ hipError_t launch_force_f32_split(int n, int geo, bool atomic, int64_t naff, con
 hipError_t launch_force_skeleton(int n, int geo, int64_t naff, const ForceArgs& a, hipStream_t s);
 
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
-// force_high.hip: NGLL 11..16 (one lane per (i, j) column; the force pass uses it for 11..12)
+// force_high.hip: NGLL 11..16 (one lane per (i, j) column; the FP32 force pass uses it for 11..12)
 hipError_t launch_force_high(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // Memory skeleton of the coloured launch_force_high (same loads and stores, no arithmetic).
 hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStream_t s);
-// force_tile16.hip: NGLL 13..16 (16-point tiles, padded below 16), all six
+// force_tile16.hip: NGLL 11..16 (16-point tiles, padded below 16), all six
 // contractions on the matrix cores; prec SEMX_C_F32 / SEMX_C_MFMA_F32 (FP32
 // operands), SEMX_C_BF16, SEMX_C_F16 (the launch's first naff elements have
-// an affine numbering)
+// an affine numbering).  FP32 contractions take it from kTileMinN (below,
+// the column kernel is faster: at NGLL 11-12 the padded tile does 2.4-3x the
+// useful matrix work), the matrix-core modes from kTileMinNMixed.
 constexpr int kTileMinN = 13;
+constexpr int kTileMinNMixed = 11;
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)

@@ -33,7 +33,7 @@ def _cprec(P, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16", "mf32"])
-@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 14, 16])
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8, 11, 14, 16])
 @pytest.mark.parametrize("geometry", ["stored", "trilinear"])
 def test_mixed_force_error(orc, n, prec, geometry):
     import paper_2606_12850_amd as P
