@@ -40,12 +40,20 @@ __device__ __forceinline__ bool first_bit(const ForceArgs& a, int pos, int q) {
   return a.first && ((a.first[(size_t)pos * a.first_words + (q >> 5)] >> (q & 31)) & 1u);
 }
 
-template <int NG, int GEO, bool ATOMIC>
+// One workgroup per element, one lane per point.  As in the elastic FP32
+// kernel, every load of the element's first half is issued before its first
+// wait (D and the GLL nodes, the element's geometry scalars, the first-touch
+// words through the scalar cache, the material and the p gather), and an
+// affine-numbered element (AFF) gathers, reads its prior force and stores
+// through buffers over its node span, the prior force as one unconditional
+// request issued after the flux.
+template <int NG, int GEO, bool ATOMIC, bool AFF>
 __global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
   constexpr int N3 = Shape<NG>::N3;
+  constexpr int ND = NG * NG;
   __shared__ float s_p[N3];
   __shared__ float s_q[3 * N3];
-  __shared__ float s_D[NG * NG];
+  __shared__ float s_D[ND + NG];  // D (row-major), then the GLL nodes
 
   const int ngrp = (int)a.count;
   const int grp = xcd_group(ngrp);
@@ -62,7 +70,11 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
   float* f = a.f + (size_t)model * a.nglob;
   const float* __restrict__ mat = a.mat + ((size_t)model * a.nspec + pos) * 2 * N3;
 
-  const int g = ldnt(a.ibool + (size_t)pos * N3 + pp);
+  float tab = 0.0f;
+  if (p < ND) tab = a.D[p];
+  else if (GEO == kTrilinear && p < ND + NG) tab = a.xi[p - ND];
+  ElemGeom<GEO> eg;
+  load_elem_geom<GEO>(a, pos, eg);
   float G[9];
   if constexpr (GEO == kStored) {
     const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
@@ -70,23 +82,32 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
     for (int d = 0; d < 9; ++d) G[d] = ldnt(gp + d * N3);
   }
   const float r = ldnt(mat + pp);
-  const float pv = u[g];
+  float pv, fo = 0.0f;
+  AffSpan sp;
+  int g = 0;
   bool first = false;
-  float fo = 0.0f;
-  if constexpr (!ATOMIC) {
-    first = first_bit(a, pos, pp);
-    if (!first) fo = f[g];
+  if constexpr (AFF) {
+    sp = aff_span<NG, 1>(a, pos, u, f, i, j, k);
+    gather_affine<1>(sp, &pv);
+    if constexpr (ATOMIC) g = aff_node(a, pos, i, j, k);
+    else first = first_touch<N3>(a, pos);
+  } else {
+    g = node_of<NG>(a, pos, pp);
+    pv = u[g];
+    if constexpr (!ATOMIC)
+      if (!first_touch<N3>(a, pos)) fo = f[g];
   }
-  if (p < NG * NG) s_D[p] = a.D[p];
+  pin_elem_geom<GEO>(eg);
+  if (p < ND + NG) s_D[p] = tab;
   if (act) s_p[pp] = pv;
-  float rx = 0.f, ry = 0.f, rz = 0.f;
-  if constexpr (GEO == kTrilinear) {
-    rx = a.xi[i];
-    ry = a.xi[j];
-    rz = a.xi[k];
-  }
   __syncthreads();
 
+  float rx = 0.f, ry = 0.f, rz = 0.f;
+  if constexpr (GEO == kTrilinear) {
+    rx = s_D[ND + i];
+    ry = s_D[ND + j];
+    rz = s_D[ND + k];
+  }
   float d[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
@@ -95,7 +116,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
     d[2] += s_D[k * NG + q] * s_p[i + NG * (j + NG * q)];
   }
   float Mg[9], scale, det;
-  geom_map<GEO>(a, pos, G, rx, ry, rz, Mg, scale, det);
+  geom_map_from<GEO>(eg.v, G, rx, ry, rz, Mg, scale, det);
   float phi[3];
   scalar_flux(d, Mg, r, scale, phi);
   if (act) {
@@ -103,18 +124,27 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_ac_kernel(ForceArgs a) {
     s_q[N3 + pp] = phi[1];
     s_q[2 * N3 + pp] = phi[2];
   }
+  if constexpr (AFF && !ATOMIC) prior_force_affine<1>(sp, first, &fo);
   __syncthreads();
 
-  float s = 0.0f;
+  float sum = 0.0f;
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    s += s_D[q * NG + i] * s_q[q + NG * (j + NG * k)];
-    s += s_D[q * NG + j] * s_q[N3 + i + NG * (q + NG * k)];
-    s += s_D[q * NG + k] * s_q[2 * N3 + i + NG * (j + NG * q)];
+    sum += s_D[q * NG + i] * s_q[q + NG * (j + NG * k)];
+    sum += s_D[q * NG + j] * s_q[N3 + i + NG * (q + NG * k)];
+    sum += s_D[q * NG + k] * s_q[2 * N3 + i + NG * (j + NG * q)];
   }
   if (act) {
-    if constexpr (ATOMIC) unsafeAtomicAdd(f + g, -s);
-    else f[g] = fo - s;
+    if constexpr (ATOMIC) {
+      // element-interior points own their node (checked at upload, f zero on entry)
+      const bool own = a.excl_interior && i > 0 && i < NG - 1 && j > 0 && j < NG - 1 && k > 0 && k < NG - 1;
+      if (own) f[g] = -sum;
+      else unsafeAtomicAdd(f + g, -sum);
+    } else {
+      const float out = fo - sum;
+      if constexpr (AFF) store_affine<1>(sp, &out);
+      else f[g] = out;
+    }
   }
 }
 
@@ -255,12 +285,12 @@ __global__ __launch_bounds__(AcColShape<NG>::BLK) void force_ac_col_kernel(Force
   }
 }
 
-template <int NG, int GEO, bool ATOMIC>
+template <int NG, int GEO, bool ATOMIC, bool AFF>
 hipError_t launch_ac(const ForceArgs& a, hipStream_t s) {
   const int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   if constexpr (NG <= kMaxNLow) {
     dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(Shape<NG>::BLK);
-    force_ac_kernel<NG, GEO, ATOMIC><<<grid, block, 0, s>>>(a);
+    force_ac_kernel<NG, GEO, ATOMIC, AFF><<<grid, block, 0, s>>>(a);
   } else {
     dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(AcColShape<NG>::BLK);
     force_ac_col_kernel<NG, GEO, ATOMIC><<<grid, block, 0, s>>>(a);
@@ -268,42 +298,55 @@ hipError_t launch_ac(const ForceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NG>
-hipError_t launch_ac_n(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+template <int NG, bool AFF>
+hipError_t launch_ac_g(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   switch (geo) {
     case kRegular:
-      return atomic ? launch_ac<NG, kRegular, true>(a, s) : launch_ac<NG, kRegular, false>(a, s);
+      return atomic ? launch_ac<NG, kRegular, true, AFF>(a, s) : launch_ac<NG, kRegular, false, AFF>(a, s);
     case kStored:
-      return atomic ? launch_ac<NG, kStored, true>(a, s) : launch_ac<NG, kStored, false>(a, s);
+      return atomic ? launch_ac<NG, kStored, true, AFF>(a, s) : launch_ac<NG, kStored, false, AFF>(a, s);
     case kTrilinear:
-      return atomic ? launch_ac<NG, kTrilinear, true>(a, s) : launch_ac<NG, kTrilinear, false>(a, s);
+      return atomic ? launch_ac<NG, kTrilinear, true, AFF>(a, s) : launch_ac<NG, kTrilinear, false, AFF>(a, s);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-}  // namespace
+// the column kernel (NGLL 11..16) reads node numbers only
+template <int NG>
+hipError_t launch_ac_n(int geo, bool atomic, bool aff, const ForceArgs& a, hipStream_t s) {
+  if constexpr (NG <= kMaxNLow) {
+    if (aff) return launch_ac_g<NG, true>(geo, atomic, a, s);
+  }
+  return launch_ac_g<NG, false>(geo, atomic, a, s);
+}
 
-hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
+hipError_t launch_ac_any(int n, int geo, bool atomic, bool aff, const ForceArgs& a, hipStream_t s) {
   switch (n) {
-    case 2: return launch_ac_n<2>(geo, atomic, a, s);
-    case 3: return launch_ac_n<3>(geo, atomic, a, s);
-    case 4: return launch_ac_n<4>(geo, atomic, a, s);
-    case 5: return launch_ac_n<5>(geo, atomic, a, s);
-    case 6: return launch_ac_n<6>(geo, atomic, a, s);
-    case 7: return launch_ac_n<7>(geo, atomic, a, s);
-    case 8: return launch_ac_n<8>(geo, atomic, a, s);
-    case 9: return launch_ac_n<9>(geo, atomic, a, s);
-    case 10: return launch_ac_n<10>(geo, atomic, a, s);
-    case 11: return launch_ac_n<11>(geo, atomic, a, s);
-    case 12: return launch_ac_n<12>(geo, atomic, a, s);
-    case 13: return launch_ac_n<13>(geo, atomic, a, s);
-    case 14: return launch_ac_n<14>(geo, atomic, a, s);
-    case 15: return launch_ac_n<15>(geo, atomic, a, s);
-    case 16: return launch_ac_n<16>(geo, atomic, a, s);
+    case 2: return launch_ac_n<2>(geo, atomic, aff, a, s);
+    case 3: return launch_ac_n<3>(geo, atomic, aff, a, s);
+    case 4: return launch_ac_n<4>(geo, atomic, aff, a, s);
+    case 5: return launch_ac_n<5>(geo, atomic, aff, a, s);
+    case 6: return launch_ac_n<6>(geo, atomic, aff, a, s);
+    case 7: return launch_ac_n<7>(geo, atomic, aff, a, s);
+    case 8: return launch_ac_n<8>(geo, atomic, aff, a, s);
+    case 9: return launch_ac_n<9>(geo, atomic, aff, a, s);
+    case 10: return launch_ac_n<10>(geo, atomic, aff, a, s);
+    case 11: return launch_ac_n<11>(geo, atomic, aff, a, s);
+    case 12: return launch_ac_n<12>(geo, atomic, aff, a, s);
+    case 13: return launch_ac_n<13>(geo, atomic, aff, a, s);
+    case 14: return launch_ac_n<14>(geo, atomic, aff, a, s);
+    case 15: return launch_ac_n<15>(geo, atomic, aff, a, s);
+    case 16: return launch_ac_n<16>(geo, atomic, aff, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+}  // namespace
+
+hipError_t launch_force_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
+  return split_affine(naff, a, [&](const ForceArgs& b, bool aff) { return launch_ac_any(n, geo, atomic, aff, b, s); });
 }
 
 }  // namespace semx

@@ -146,6 +146,157 @@ __device__ __forceinline__ void stress_flux(const float gr[3][3], float lamw, fl
   }
 }
 
+// First-touch bit of the lane's point (coloured assembly).  Point p's bit is
+// bit p & 31 of word p >> 5 of the element's bitmask, so the 64 lanes of wave
+// w read words 2w and 2w + 1: the pair is uniform over the wave, comes
+// through the scalar cache, and turns into the lane's bit with one select on
+// the 64-bit mask.  The f read that depends on the bit then waits for a
+// scalar load, not for a vector-memory round trip.  Lanes past the element's
+// points (p >= n^3) see bits of a zero word or of no point; they store nothing.
+template <int N3>
+__device__ __forceinline__ bool first_touch(const ForceArgs& a, int pos) {
+  constexpr int NW = (N3 + 31) / 32;
+  if (!a.first) return false;
+  const uint32_t* w = a.first + (size_t)pos * a.first_words;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const uint64_t lo = wave * 2 < NW ? w[wave * 2] : 0u;
+  const uint64_t hi = wave * 2 + 1 < NW ? w[wave * 2 + 1] : 0u;
+  return __builtin_amdgcn_inverse_ballot_w64(lo | (hi << 32));
+}
+
+// Node number of local point pp of the element at launch position `pos`
+// from the ibool stream (elements without an affine numbering).
+template <int NG>
+__device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp) {
+  return ldnt(a.ibool + (size_t)pos * Shape<NG>::N3 + pp);
+}
+
+// The node span of an affine-numbered element (node g = g0 + i sx + j sy +
+// k sz; four scalar loads per element, no per-point stream and no dependent
+// round trip before the gather): raw buffer resources over the element's
+// nodes in u and f (NC floats per node), and the lane's byte offset into
+// them.  With 32-bit offsets from a per-element base, the gather, the
+// prior-force read and the store need no 64-bit address arithmetic.  The
+// host classifies an element as affine only when its span fits a 31-bit
+// byte offset at three components per node.
+struct AffSpan {
+  __amdgpu_buffer_rsrc_t ru, rf;
+  int off;
+};
+
+template <int NG, int NC>
+__device__ __forceinline__ AffSpan aff_span(const ForceArgs& a, int pos, const float* u, float* f, int i, int j,
+                                            int k) {
+  const int* r = a.aff + (size_t)pos * 4;
+  const int sx = r[1], sy = r[2], sz = r[3];
+  const int lo = (NG - 1) * (min(sx, 0) + min(sy, 0) + min(sz, 0));
+  const int gmin = r[0] + lo;
+  const int bytes = ((NG - 1) * (abs(sx) + abs(sy) + abs(sz)) + 1) * 4 * NC;
+  AffSpan s;
+  s.ru = __builtin_amdgcn_make_buffer_rsrc((void*)(u + NC * (size_t)gmin), (short)0, bytes, kBufferWord3);
+  s.rf = __builtin_amdgcn_make_buffer_rsrc((void*)(f + NC * (size_t)gmin), (short)0, bytes, kBufferWord3);
+  s.off = (i * sx + j * sy + k * sz - lo) * 4 * NC;
+  return s;
+}
+
+// Node number of local point (i, j, k) of an affine-numbered element.
+__device__ __forceinline__ int aff_node(const ForceArgs& a, int pos, int i, int j, int k) {
+  const int* r = a.aff + (size_t)pos * 4;
+  return r[0] + i * r[1] + j * r[2] + k * r[3];
+}
+
+typedef unsigned semx_v3u __attribute__((ext_vector_type(3)));
+
+// The NC values at the lane's node of an affine element, from buffer `r` at
+// byte offset `off` (one request per point).
+template <int NC>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t r, int off, float x[NC]) {
+  if constexpr (NC == 3) {
+    const semx_v3u v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    x[0] = __uint_as_float(v.x);
+    x[1] = __uint_as_float(v.y);
+    x[2] = __uint_as_float(v.z);
+  } else {
+    static_assert(NC == 1, "one or three components per node");
+    x[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+}
+
+// u at the lane's node of an affine element.
+template <int NC>
+__device__ __forceinline__ void gather_affine(const AffSpan& s, float x[NC]) {
+  buf_load<NC>(s.ru, s.off, x);
+}
+
+// Prior force at the lane's node of an affine element: at first-touch points
+// the offset is pushed out of range, so the hardware returns zeros and
+// fetches nothing, and the read stays one unconditional instruction that the
+// compiler counts exactly (no branch, so the wait for u does not also wait
+// for f).  2^31 lies past any num_records <= 2^31 - 1, and adding the 8 bytes
+// of the last dword cannot wrap a 32-bit offset.
+template <int NC>
+__device__ __forceinline__ void prior_force_affine(const AffSpan& s, bool first, float x[NC]) {
+  buf_load<NC>(s.rf, first ? INT32_MIN : s.off, x);
+}
+
+template <int NC>
+__device__ __forceinline__ void store_affine(const AffSpan& s, const float x[NC]) {
+  if constexpr (NC == 3) {
+    semx_v3u v;
+    v.x = __float_as_uint(x[0]);
+    v.y = __float_as_uint(x[1]);
+    v.z = __float_as_uint(x[2]);
+    __builtin_amdgcn_raw_buffer_store_b96(v, s.rf, s.off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[0]), s.rf, s.off, 0, 0);
+  }
+}
+
+// Per-element geometry that is uniform over the workgroup: Gamma (kRegular,
+// 9 floats) or the trilinear coefficients (kTrilinear, 24 floats).
+template <int GEO>
+struct ElemGeom {
+  static constexpr int NS = GEO == kRegular ? 9 : (GEO == kTrilinear ? 24 : 1);
+  float v[NS];
+};
+
+// Loads of the element's uniform geometry (scalar loads), issued where the
+// caller puts them.
+template <int GEO>
+__device__ __forceinline__ void load_elem_geom(const ForceArgs& a, int pos, ElemGeom<GEO>& eg) {
+  if constexpr (GEO != kStored) {
+    const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
+#pragma unroll
+    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) eg.v[d] = src[d];
+  }
+}
+
+// Keeps the element's geometry loads ahead of the caller's first barrier
+// (they would otherwise be sunk past it, onto the element's critical path).
+// Call after every other load of the element: the compiler treats the empty
+// asm statements as possible writers, so loads after them would no longer
+// come through the scalar cache.
+template <int GEO>
+__device__ __forceinline__ void pin_elem_geom(const ElemGeom<GEO>& eg) {
+  if constexpr (GEO != kStored) {
+#pragma unroll
+    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) asm volatile("" ::"s"(eg.v[d]));
+  }
+}
+
+// A launch range whose first `naff` elements are affine-numbered: two launches.
+template <class F>
+inline hipError_t split_affine(int64_t naff, const ForceArgs& a, F launch) {
+  naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
+  ForceArgs b = a;
+  b.count = naff;
+  hipError_t e = naff > 0 ? launch(b, true) : hipSuccess;
+  if (e != hipSuccess || naff == a.count) return e;
+  b.pos0 = a.pos0 + naff;
+  b.count = a.count - naff;
+  return launch(b, false);
+}
+
 // XCD-aware group index: blocks are dispatched round-robin over the XCDs, so
 // block b runs on XCD b % 8; groups are dealt so that each XCD walks one
 // contiguous eighth of the launch range (elements sharing nodes meet in one L2).

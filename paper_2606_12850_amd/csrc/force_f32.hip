@@ -31,97 +31,6 @@
 namespace semx {
 namespace {
 
-// First-touch bit of the lane's point (coloured assembly).  Point p's bit is
-// bit p & 31 of word p >> 5 of the element's bitmask, so the 64 lanes of wave
-// w read words 2w and 2w + 1: the pair is uniform over the wave, comes
-// through the scalar cache, and turns into the lane's bit with one select on
-// the 64-bit mask.  The f read that depends on the bit then waits for a
-// scalar load, not for a vector-memory round trip.  Lanes past the element's
-// points (p >= n^3) see bits of a zero word or of no point; they store nothing.
-template <int N3>
-__device__ __forceinline__ bool first_touch(const ForceArgs& a, int pos) {
-  constexpr int NW = (N3 + 31) / 32;
-  if (!a.first) return false;
-  const uint32_t* w = a.first + (size_t)pos * a.first_words;
-  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const uint64_t lo = wave * 2 < NW ? w[wave * 2] : 0u;
-  const uint64_t hi = wave * 2 + 1 < NW ? w[wave * 2 + 1] : 0u;
-  return __builtin_amdgcn_inverse_ballot_w64(lo | (hi << 32));
-}
-
-// Node number of local point (i, j, k) of the element at launch position
-// `pos` from the ibool stream (elements without an affine numbering).
-template <int NG>
-__device__ __forceinline__ int node_of(const ForceArgs& a, int pos, int pp) {
-  return ldnt(a.ibool + (size_t)pos * Shape<NG>::N3 + pp);
-}
-
-// The node span of an affine-numbered element (node g = g0 + i sx + j sy +
-// k sz; four scalar loads per element, no per-point stream and no dependent
-// round trip before the gather): raw buffer resources over the element's
-// nodes in u and f, and the lane's byte offset into them.  With 32-bit
-// offsets from a per-element base, the gather, the prior-force read and the
-// store need no 64-bit address arithmetic.  The host classifies an element
-// as affine only when its span fits a 31-bit byte offset.
-struct AffSpan {
-  __amdgpu_buffer_rsrc_t ru, rf;
-  int off;
-};
-
-template <int NG>
-__device__ __forceinline__ AffSpan aff_span(const ForceArgs& a, int pos, const float* u, float* f, int i, int j,
-                                            int k) {
-  const int* r = a.aff + (size_t)pos * 4;
-  const int sx = r[1], sy = r[2], sz = r[3];
-  const int lo = (NG - 1) * (min(sx, 0) + min(sy, 0) + min(sz, 0));
-  const int gmin = r[0] + lo;
-  const int bytes = ((NG - 1) * (abs(sx) + abs(sy) + abs(sz)) + 1) * 12;
-  AffSpan s;
-  s.ru = __builtin_amdgcn_make_buffer_rsrc((void*)(u + 3 * (size_t)gmin), (short)0, bytes, kBufferWord3);
-  s.rf = __builtin_amdgcn_make_buffer_rsrc((void*)(f + 3 * (size_t)gmin), (short)0, bytes, kBufferWord3);
-  s.off = (i * sx + j * sy + k * sz - lo) * 12;
-  return s;
-}
-
-typedef unsigned semx_v3u __attribute__((ext_vector_type(3)));
-
-__device__ __forceinline__ void unpack3(semx_v3u v, float x[3]) {
-  x[0] = __uint_as_float(v.x);
-  x[1] = __uint_as_float(v.y);
-  x[2] = __uint_as_float(v.z);
-}
-
-// u at the lane's node of an affine element.
-__device__ __forceinline__ void gather_affine(const AffSpan& s, float x[3]) {
-  unpack3(__builtin_amdgcn_raw_buffer_load_b96(s.ru, s.off, 0, 0), x);
-}
-
-// Prior force at the lane's node of an affine element: at first-touch points
-// the offset is pushed out of range, so the hardware returns zeros and
-// fetches nothing, and the read stays one unconditional instruction that the
-// compiler counts exactly (no branch, so the wait for u does not also wait
-// for f).  2^31 lies past any num_records <= 2^31 - 1, and adding the 8 bytes
-// of the last dword cannot wrap a 32-bit offset.
-__device__ __forceinline__ void prior_force_affine(const AffSpan& s, bool first, float x[3]) {
-  unpack3(__builtin_amdgcn_raw_buffer_load_b96(s.rf, first ? INT32_MIN : s.off, 0, 0), x);
-}
-
-__device__ __forceinline__ void store_affine(const AffSpan& s, const float x[3]) {
-  semx_v3u v;
-  v.x = __float_as_uint(x[0]);
-  v.y = __float_as_uint(x[1]);
-  v.z = __float_as_uint(x[2]);
-  __builtin_amdgcn_raw_buffer_store_b96(v, s.rf, s.off, 0, 0);
-}
-
-// Per-element geometry that is uniform over the workgroup: Gamma (kRegular,
-// 9 floats) or the trilinear coefficients (kTrilinear, 24 floats).
-template <int GEO>
-struct ElemGeom {
-  static constexpr int NS = GEO == kRegular ? 9 : (GEO == kTrilinear ? 24 : 1);
-  float v[NS];
-};
-
 // One workgroup owns one element (one lane per GLL point).  Every load the
 // element's first half needs is issued before its first wait: the constant
 // tables (D and the GLL nodes, L2-resident), the per-element scalars
@@ -157,11 +66,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   else if (GEO == kTrilinear && p < ND + NG) tab = a.xi[p - ND];
 
   ElemGeom<GEO> eg;
-  if constexpr (GEO != kStored) {
-    const float* src = GEO == kRegular ? a.gam_el + (size_t)pos * 9 : a.tri + (size_t)pos * 24;
-#pragma unroll
-    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) eg.v[d] = src[d];
-  }
+  load_elem_geom<GEO>(a, pos, eg);
   float G[9];
   if constexpr (GEO == kStored) {
     const float* gp = a.gam_pt + (size_t)pos * 9 * N3 + pp;
@@ -176,11 +81,10 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   int g = 0;
   bool first = false;
   if constexpr (AFF) {
-    sp = aff_span<NG>(a, pos, u, f, i, j, k);
-    gather_affine(sp, uo);
+    sp = aff_span<NG, 3>(a, pos, u, f, i, j, k);
+    gather_affine<3>(sp, uo);
     if constexpr (ATOMIC) {
-      const int* r = a.aff + (size_t)pos * 4;
-      g = r[0] + i * r[1] + j * r[2] + k * r[3];
+      g = aff_node(a, pos, i, j, k);
     } else {
       first = first_touch<N3>(a, pos);
     }
@@ -198,13 +102,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     }
   }
 
-  if constexpr (GEO != kStored) {
-    // keep the element's geometry loads ahead of the first barrier (they
-    // would otherwise be sunk past it, onto the element's critical path);
-    // placed after every load, so no load is seen as clobbered by it
-#pragma unroll
-    for (int d = 0; d < ElemGeom<GEO>::NS; ++d) asm volatile("" ::"s"(eg.v[d]));
-  }
+  pin_elem_geom<GEO>(eg);
   if (p < ND + NG) s_D[p] = tab;
   if (act) {
     s_u[pp] = uo[0];
@@ -230,7 +128,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
   // after the transpose contractions, and issuing it earlier keeps three
   // more registers live through the stress (65 instead of 63, 7 waves per
   // SIMD instead of 8)
-  if constexpr (AFF && !ATOMIC) prior_force_affine(sp, first, fo);
+  if constexpr (AFF && !ATOMIC) prior_force_affine<3>(sp, first, fo);
   __syncthreads();
 
   float F[3];
@@ -253,7 +151,7 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_f32_kernel(ForceArgs a) 
     } else {
       const float out[3] = {fo[0] + F[0], fo[1] + F[1], fo[2] + F[2]};
       if constexpr (AFF) {
-        store_affine(sp, out);
+        store_affine<3>(sp, out);
       } else {
         float* fg = f + 3 * (size_t)g;
         fg[0] = out[0];
@@ -320,11 +218,11 @@ __global__ __launch_bounds__(Shape<NG>::BLK) void force_skeleton_kernel(ForceArg
   s += ldnt(mat + (size_t)pos * 2 * N3 + p) + ldnt(mat + (size_t)pos * 2 * N3 + N3 + p);
   float uo[3], fo[3] = {0.0f, 0.0f, 0.0f};
   if constexpr (AFF) {
-    const AffSpan sp = aff_span<NG>(a, pos, u, f, p % NG, (p / NG) % NG, p / (NG * NG));
-    gather_affine(sp, uo);
-    prior_force_affine(sp, first_touch<N3>(a, pos), fo);
+    const AffSpan sp = aff_span<NG, 3>(a, pos, u, f, p % NG, (p / NG) % NG, p / (NG * NG));
+    gather_affine<3>(sp, uo);
+    prior_force_affine<3>(sp, first_touch<N3>(a, pos), fo);
     const float out[3] = {fo[0] + s * uo[0], fo[1] + s * uo[1], fo[2] + s * uo[2]};
-    store_affine(sp, out);
+    store_affine<3>(sp, out);
   } else {
     const int g = node_of<NG>(a, pos, p);
     uo[0] = u[3 * (size_t)g + 0];
@@ -354,19 +252,6 @@ hipError_t launch_skeleton_n(int geo, const ForceArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
-}
-
-// A launch range whose first `naff` elements are affine-numbered: two launches.
-template <class F>
-hipError_t split_affine(int64_t naff, const ForceArgs& a, F launch) {
-  naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
-  ForceArgs b = a;
-  b.count = naff;
-  hipError_t e = naff > 0 ? launch(b, true) : hipSuccess;
-  if (e != hipSuccess || naff == a.count) return e;
-  b.pos0 = a.pos0 + naff;
-  b.count = a.count - naff;
-  return launch(b, false);
 }
 
 template <int NG>

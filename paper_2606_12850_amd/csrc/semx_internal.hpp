@@ -245,8 +245,9 @@ constexpr int kTileMinN = 13;
 constexpr int kTileMinNMixed = 11;
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s);
-// acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node)
-hipError_t launch_force_acoustic(int n, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
+// acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node;
+// the launch's first naff elements have an affine numbering)
+hipError_t launch_force_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
 // MFMA contraction modes: NGLL 4..8 and 13..16 (all three precisions).
 bool mfma_supported(int n, int prec);
 
