@@ -121,6 +121,44 @@ def write_traffic(run_dir: str):
     print(json.dumps({k: (v["bytes_per_launch"] if isinstance(v, dict) else v) for k, v in out.items()}))
 
 
+def write_acoustic_traffic(run_dir: str):
+    """profiles/acoustic_traffic.json from the FETCH_SIZE and WRITE_SIZE runs
+    of `bench.py --acoustic-only` (DIR/pmc_ac_<counter>/run_counter_collection.csv):
+    KiB per dispatch of the NGLL 5 coloured acoustic force kernel on each
+    geometry path, scaled by what the same counter reads for the 1 GiB device
+    copies that follow them."""
+    import collections
+    import csv
+    copy_bytes = 1 << 30
+    src = b"".join(open(os.path.join(ROOT, "paper_2606_12850_amd", "csrc", f), "rb").read()
+                   for f in ("acoustic.hip", "elem_common.hpp"))
+    out = {"unit": "bytes per launch",
+           "workload": "layered-cube mesh 64^3 jittered, NGLL 5, homogeneous acoustic medium, colored "
+                       "(8 launches of 32768 elements), affine node numbering",
+           "kernel_source_sha256": hashlib.sha256(src).hexdigest()}
+    agg = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        a = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(run_dir, f"pmc_ac_{ctr}", "run_counter_collection.csv"))):
+            if r["Counter_Name"] == ctr:
+                a[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        agg[ctr] = a
+    for geo, gid in (("trilinear", 2), ("stored", 1)):
+        d = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            cp = [v for k, vs in agg[ctr].items() if "copyBuffer" in k for v in vs][-3:]
+            scale = copy_bytes / (sum(cp) / len(cp) * 1024.0)
+            kv = [v for k, vs in agg[ctr].items() if f"force_ac_kernel<5, {gid}, false, true>" in k for v in vs]
+            d[ctr] = {"kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv),
+                      "copy_kib_per_GiB": sum(cp) / len(cp), "scale": scale,
+                      "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * scale}
+        d["bytes_per_launch"] = d["FETCH_SIZE"]["bytes_per_launch"] + d["WRITE_SIZE"]["bytes_per_launch"]
+        out[geo] = d
+    with open(os.path.join(ROOT, "profiles", "acoustic_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: (v["bytes_per_launch"] if isinstance(v, dict) else v) for k, v in out.items()}))
+
+
 def cpu_baseline(mesh, lam, mu, budget_s: float = 12.0):
     """FP64 oracle force apply on the first 8 element layers of the same mesh."""
     import numpy as np
@@ -264,7 +302,8 @@ def adjoint_leg(ne: int = 32, nt: int = 1000, every: int = 100, fd_dirs: int = 1
 
 
 def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: int = 4096, epochs: int = 300,
-                  members: int = 4, nt: int = 800, nout: int = 512, ne: int = 16, tol: float = 0.05):
+                  members: int = 4, nt: int = 800, nout: int = 512, ne: int = 16, tol: float = 0.05,
+                  hidden=(512, 512, 512), batch: int = 128, dt: float | None = None, val_seed0: int | None = None):
     """Learned surrogate on the 16^3 box: batched SEM data for the 64-mode
     lambda/mu perturbations, an ensemble of MLPs trained by the library's
     kernels, the spread indicator calibrated on validation models, SEM
@@ -281,12 +320,13 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
     basis = W.fourier_modes(mesh)
     model_fn = lambda a: W.perturbed_models(mesh, basis, a)
     # common dt: Courant 0.4 at the fastest admissible model (delta = +10 % everywhere)
-    probe = P.Solver(NGLL)
-    probe.upload_mesh(mesh)
-    lam0, mu0, rho0 = W.homogeneous_model(mesh)
-    probe.upload_model(lam0 * 1.1, mu0 * 1.1, rho0)
-    dt = P.semx_cfl_dt(probe.ctx, 0.4)
-    probe.close()
+    if dt is None:
+        probe = P.Solver(NGLL)
+        probe.upload_mesh(mesh)
+        lam0, mu0, rho0 = W.homogeneous_model(mesh)
+        probe.upload_model(lam0 * 1.1, mu0 * 1.1, rho0)
+        dt = P.semx_cfl_dt(probe.ctx, 0.4)
+        probe.close()
     se, sx = W.center_vertex_source(mesh)
     re, rx = W.top_receivers_grid(mesh, 4)
     stf = W.ricker(f0, 1.2 / f0, dt, nt + 1)[None, :]
@@ -299,7 +339,8 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
         return np.concatenate(out, 0)
 
     A_tr = W.perturbation_coefficients(basis, range(0, ntrain))
-    A_va = W.perturbation_coefficients(basis, range(ntrain, ntrain + nval))
+    v0 = ntrain if val_seed0 is None else val_seed0
+    A_va = W.perturbation_coefficients(basis, range(v0, v0 + nval))
     A_te = W.perturbation_coefficients(basis, range(10000, 10000 + ntest))
     t0 = time.perf_counter()
     Y_tr = run(A_tr)
@@ -313,8 +354,8 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
     t_sem = time.perf_counter() - t0
     log(f"test data (SEM for all {ntest} models) in {t_sem:.1f} s")
     n_out = Y_tr[0].size
-    sur = Surrogate(64, n_out, hidden=(512, 512, 512), members=members, max_batch=4096)
-    t_train = sur.fit(A_tr, Y_tr, epochs=epochs, batch=128, log=log)
+    sur = Surrogate(64, n_out, hidden=tuple(hidden), members=members, max_batch=4096)
+    t_train = sur.fit(A_tr, Y_tr, epochs=epochs, batch=batch, log=log)
     cal = sur.calibrate(A_va, Y_va.reshape(len(A_va), -1), tol=tol)
     log(f"trained in {t_train:.1f} s; calibration {cal}")
     torch.cuda.synchronize()
@@ -334,8 +375,9 @@ def surrogate_leg(f0: float = 10.0, ntrain: int = 4500, nval: int = 500, ntest: 
     precision = float((flag & bad).sum() / max(flag.sum(), 1))
     sur.close(); sem.close()
     return {"workload": f"box {ne}^3 regular, NGLL {NGLL}, 64 cosine modes (lambda, mu x (1 +- 10 %)), Ricker {f0:g} Hz, "
-                        f"{nt} steps -> {nout} samples, 16 receivers; MLP 64-512-512-512-{n_out} x {members}, "
-                        f"{epochs} epochs batch 128; train {ntrain} / val {nval} / test {ntest}",
+                        f"{nt} steps -> {nout} samples, 16 receivers; MLP 64-{'-'.join(str(h) for h in hidden)}-"
+                        f"{n_out} x {members}, {epochs} epochs batch {batch}; train {ntrain} / val {nval} / "
+                        f"test {ntest}",
             "dt": dt, "sem_data_s": round(t_data, 2), "train_s": round(t_train, 2),
             "surrogate_err_mean": float(e_sur.mean()), "surrogate_err_median": float(np.median(e_sur)),
             "surrogate_err_max": float(e_sur.max()), "mean_seismogram_err_mean": float(e_mean.mean()),
@@ -819,9 +861,15 @@ def main():
     ap.add_argument("--write-traffic", metavar="DIR",
                     help="no GPU: read the four rocprofv3 --pmc runs of --profile-force (DIR/pmc_<geometry>_"
                          "<counter>/run_counter_collection.csv) and write profiles/force_traffic.json")
+    ap.add_argument("--write-acoustic-traffic", metavar="DIR",
+                    help="no GPU: read the two rocprofv3 --pmc runs of --acoustic-only (DIR/pmc_ac_<counter>/"
+                         "run_counter_collection.csv) and write profiles/acoustic_traffic.json")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args.write_traffic)
+        return
+    if args.write_acoustic_traffic:
+        write_acoustic_traffic(args.write_acoustic_traffic)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
@@ -1071,6 +1119,14 @@ def main():
                                          ntest=max(64, int(4096 * k)), epochs=max(5, int(300 * k)))
         out["surrogate"]["scale"] = k
         progress("surrogate leg done")
+        if not args.surrogate:
+            # the same pipeline with a source the mesh resolves: the reduced
+            # configuration of the GPU test (8^3 box, 3 Hz Ricker, 200 steps ->
+            # 100 samples, 4096 training models), where most models are accepted
+            out["surrogate_resolved_source"] = surrogate_leg(
+                f0=3.0, ne=8, nt=200, nout=100, ntrain=4096, nval=128, ntest=256, epochs=120, hidden=(256, 256, 256),
+                batch=64, dt=0.01, val_seed0=5000)
+            progress("resolved-source surrogate leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl.lam, wl.mu)
         if "acoustic" in out:
