@@ -140,6 +140,29 @@ int semx_set_mode(semx_ctx *ctx, int contraction, int assembly);
 #define SEMX_GEOM_TRILINEAR 1
 int semx_set_geometry(semx_ctx *ctx, int mode);
 
+/* Element blocks for the coloured FP32 elastic force at NGLL <= 5 (the
+ * colouring of Sec. IV-C taken over 2 x 2 x 2 element blocks, with the
+ * fused traversal of Sec. IV-D inside each): one workgroup per block of
+ * eight face-adjacent elements gathers each of the block's (2 NGLL - 1)^3
+ * nodes once and writes each once, the elements' shared nodes summed in a
+ * fixed order (deterministic).  The library builds the blocks at mesh upload
+ * when every element is affine-numbered with common strides, all elements
+ * share one geometry kind, and the elements pair up into blocks (a
+ * structured box with even element counts per side).  Modes:
+ *   SEMX_BLOCKS_OFF   the per-element kernel;
+ *   SEMX_BLOCKS_AUTO  blocks where they are built and measured faster than
+ *                     the per-element kernel: irregular elements on the
+ *                     stored-Gamma path (the default);
+ *   SEMX_BLOCKS_ON    blocks wherever they are built (every geometry path).
+ * The result equals the per-element pass up to the order of floating-point
+ * summation.  *active (may be null) returns whether the next coloured FP32
+ * force pass of this context, with its current geometry path, uses the
+ * blocks.  SEMX_EINVAL for an unknown mode. */
+#define SEMX_BLOCKS_OFF 0
+#define SEMX_BLOCKS_AUTO 1
+#define SEMX_BLOCKS_ON 2
+int semx_set_blocks(semx_ctx *ctx, int mode, int *active);
+
 /* f = -K u for every model: u_dev, f_dev device FP32 [nmodels][nglob][3].
  * f_dev is overwritten (not accumulated).  u_dev and f_dev must not overlap. */
 int semx_apply_force(semx_ctx *ctx, const float *u_dev, float *f_dev);

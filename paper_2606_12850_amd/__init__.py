@@ -36,6 +36,7 @@ SEMX_ASM_COLORED = 0
 SEMX_ASM_ATOMIC = 1
 SEMX_GEOM_STORED = 0
 SEMX_GEOM_TRILINEAR = 1
+SEMX_BLOCKS_OFF, SEMX_BLOCKS_AUTO, SEMX_BLOCKS_ON = 0, 1, 2
 SEMX_F32 = 0
 SEMX_F64 = 1
 SEMX_ELASTIC = 0
@@ -77,6 +78,7 @@ _SIGS = {
     "semx_energy": [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
     "semx_set_watchdog": [_vp, _i64, _f64],
     "semx_set_geometry": [_vp, _i32],
+    "semx_set_blocks": [_vp, _i32, ctypes.c_void_p],
     "semx_set_checkpointing": [_vp, _i64],
     "semx_adjoint": [_vp, _vp, _i64, _vp, _vp, _vp],
     "semx_mlp_create": [ctypes.POINTER(_vp), _i32, _vp, _i32, _vp],
@@ -360,6 +362,14 @@ def semx_set_watchdog(ctx, interval: int, max_energy: float = 0.0):
 
 def semx_set_geometry(ctx, mode: int):
     return _check(ctx, lib().semx_set_geometry(ctx, int(mode)))
+
+
+def semx_set_blocks(ctx, mode: int) -> bool:
+    """Mode of the 2 x 2 x 2 element-block force kernel (SEMX_BLOCKS_OFF /
+    _AUTO / _ON); returns whether the next coloured FP32 force pass uses it."""
+    active = ctypes.c_int(0)
+    _check(ctx, lib().semx_set_blocks(ctx, int(mode), ctypes.byref(active)))
+    return bool(active.value)
 
 
 def semx_set_checkpointing(ctx, every: int):

@@ -124,6 +124,14 @@ struct semx_ctx {
   std::vector<int32_t> color_ptr, elem_order;
   std::vector<semx::Launch> colored_launches;  // per colour: regular then irregular
   std::vector<semx::Launch> atomic_launches;   // regular list, irregular list
+  // 2 x 2 x 2 element blocks (FP32 elastic force, NGLL <= 5, coloured):
+  // built when every element is affine-numbered with common strides, of one
+  // geometry kind, and belongs to a block; nblocks = 0 otherwise
+  int64_t nblocks = 0;
+  bool blocks_irregular = false;
+  int blocks_mode = 1;                         // semx_set_blocks (SEMX_BLOCKS_AUTO)
+  std::vector<semx::Launch> block_launches;    // per block colour: a range of the block tables
+  semx::DevBuf d_bpos, d_baff, d_bfirst;
 
   // model
   bool have_model = false;
@@ -229,6 +237,23 @@ hipError_t launch_force_f32(int n, int geo, bool atomic, const ForceArgs& a, hip
 hipError_t launch_force_f32_split(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
 // Memory skeleton of the coloured launch_force_f32_split (same loads and stores, no arithmetic).
 hipError_t launch_force_skeleton(int n, int geo, int64_t naff, const ForceArgs& a, hipStream_t s);
+
+// force_block.hip: 2 x 2 x 2 element blocks, NGLL 2..5, coloured assembly.
+// A launch covers blocks beg .. beg + count - 1 of the block tables (one
+// block colour): bpos [nblocks][8] launch positions of the block's elements
+// m = dx + 2 dy + 4 dz; baff [nblocks][4] the block's node numbering
+// G0 + X sx + Y sy + Z sz (X, Y, Z = 0..2n-2); bfirst [nblocks][words] the
+// first-touch bits of its nodes in block launch order (or null: every node
+// reads its prior force).
+struct BlockArgs {
+  const int32_t* bpos;
+  const int32_t* baff;
+  const uint32_t* bfirst;
+  int64_t beg, count;
+};
+hipError_t launch_force_block(int n, int geo, const ForceArgs& a, const BlockArgs& b, hipStream_t s);
+hipError_t launch_force_block_skeleton(int n, int geo, const ForceArgs& a, const BlockArgs& b, hipStream_t s);
+constexpr int kBlockMaxN = 5;  // eight elements of n^3 points in one 1024-lane workgroup
 
 hipError_t launch_force_mfma(int n, int prec, int geo, bool atomic, const ForceArgs& a, hipStream_t s);
 // force_high.hip: NGLL 11..16 (one lane per (i, j) column; the FP32 force pass uses it for 11..12)
