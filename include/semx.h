@@ -452,6 +452,25 @@ int semx_mlp_mse(semx_mlp *net, const float *y_dev, const float *t_dev, int64_t 
  * refreshes the BF16 working copy */
 int semx_mlp_adam(semx_mlp *net, float lr, float beta1, float beta2, float eps, int64_t step);
 
+/* Surrogate inference around the network (no counterpart in the paper; the
+ * learned surrogate's input normalisation, ensemble mean and error
+ * indicator), on the network's stream:
+ * semx_mlp_affine: y_dev[r][c] = scale_dev[c] * x_dev[r][c] + shift_dev[c]
+ *   for r < rows, c < cols (device FP32, row-major; x_dev and y_dev may be
+ *   the same buffer).  Normalises inputs ((x - mean) / std as scale 1/std,
+ *   shift -mean/std) and maps normalised outputs back to physical units. */
+int semx_mlp_affine(semx_mlp *net, const float *x_dev, int64_t rows, int cols, const float *scale_dev,
+                    const float *shift_dev, float *y_dev);
+/* semx_mlp_ensemble: preds_dev [members][rows][cols] are the members'
+ *   normalised predictions.  mean_dev [rows][cols] = scale * (mean over the
+ *   members) + shift (physical units); indicator_dev [rows] = || scale * s ||
+ *   / || mean_dev row || with s the unbiased standard deviation over the
+ *   members (0 for one member), norms over the row accumulated in FP64 in a
+ *   fixed order.  The indicator is the surrogate's fallback criterion.
+ *   SEMX_EINVAL for a null pointer, members < 1 or cols < 1. */
+int semx_mlp_ensemble(semx_mlp *net, const float *preds_dev, int members, int64_t rows, int cols,
+                      const float *scale_dev, const float *shift_dev, float *mean_dev, float *indicator_dev);
+
 #ifdef __cplusplus
 }
 #endif

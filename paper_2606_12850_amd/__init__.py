@@ -93,6 +93,8 @@ _SIGS = {
     "semx_mlp_backward": [_vp, _vp, _i32],
     "semx_mlp_mse": [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_f64)],
     "semx_mlp_adam": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64],
+    "semx_mlp_affine": [_vp, _vp, _i64, _i32, _vp, _vp, _vp],
+    "semx_mlp_ensemble": [_vp, _vp, _i32, _i64, _i32, _vp, _vp, _vp, _vp],
     "semx_set_storage": [_vp, _i32],
     "semx_apply_force_f64": [_vp, _vp, _vp],
     "semx_set_sources_f64": [_vp, _i32, _vp, _vp, _vp, _i64, _vp],
@@ -446,6 +448,17 @@ def semx_mlp_mse(net, y, t, n: int, dy=None, want_loss: bool = True):
 
 def semx_mlp_adam(net, lr: float, beta1: float, beta2: float, eps: float, step: int):
     return _mcheck(net, lib().semx_mlp_adam(net, float(lr), float(beta1), float(beta2), float(eps), int(step)))
+
+
+def semx_mlp_affine(net, x, rows: int, cols: int, scale, shift, y):
+    """y[r][c] = scale[c] x[r][c] + shift[c] on device FP32 buffers (x may be y)."""
+    return _mcheck(net, lib().semx_mlp_affine(net, _ptr(x), int(rows), int(cols), _ptr(scale), _ptr(shift), _ptr(y)))
+
+
+def semx_mlp_ensemble(net, preds, members: int, rows: int, cols: int, scale, shift, mean, indicator):
+    """Ensemble mean (physical units) and spread indicator of preds [members][rows][cols]."""
+    return _mcheck(net, lib().semx_mlp_ensemble(net, _ptr(preds), int(members), int(rows), int(cols), _ptr(scale),
+                                                _ptr(shift), _ptr(mean), _ptr(indicator)))
 
 
 def semx_set_timing(ctx, stride=1):

@@ -287,6 +287,57 @@ __global__ void mse_kernel(int64_t n, const float* __restrict__ y, const float* 
   if (threadIdx.x == 0) atomicAdd(loss, red[0] / (double)n);
 }
 
+// y[r][c] = a[c] x[r][c] + b[c] (column-wise affine map; x and y may alias)
+__global__ void affine_cols_kernel(int64_t n, int cols, const float* x, const float* __restrict__ a,
+                                   const float* __restrict__ b, float* y) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % cols);
+    y[t] = a[c] * x[t] + b[c];
+  }
+}
+
+// Ensemble statistics of one row per block: members' predictions P[k][r][c]
+// (normalised units), mean over members mapped back through a[c] m + b[c],
+// and the spread indicator || a * std || / || mean (physical) || with the
+// unbiased standard deviation over the members (zero for one member); the
+// two norms are FP64 block reductions in a fixed order.
+__global__ void ensemble_kernel(int members, int64_t rows, int cols, const float* __restrict__ P,
+                                const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ mean,
+                                float* __restrict__ ind) {
+  __shared__ double red[2][256];
+  const int64_t r = blockIdx.x;
+  if (r >= rows) return;
+  double s_sp = 0.0, s_mn = 0.0;
+  const float inv_m = 1.0f / (float)members;
+  const float inv_m1 = members > 1 ? 1.0f / (float)(members - 1) : 0.0f;
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) {
+    float sum = 0.0f;
+    for (int k = 0; k < members; ++k) sum += P[((int64_t)k * rows + r) * cols + c];
+    const float mu = sum * inv_m;
+    float ss = 0.0f;
+    for (int k = 0; k < members; ++k) {
+      const float d = P[((int64_t)k * rows + r) * cols + c] - mu;
+      ss += d * d;
+    }
+    const float sd = a[c] * sqrtf(ss * inv_m1);
+    const float mp = a[c] * mu + b[c];
+    mean[r * cols + c] = mp;
+    s_sp += (double)sd * sd;
+    s_mn += (double)mp * mp;
+  }
+  red[0][threadIdx.x] = s_sp;
+  red[1][threadIdx.x] = s_mn;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ind[r] = (float)(sqrt(red[0][0]) / fmax(sqrt(red[1][0]), 1e-30));
+}
+
 __global__ void adam_kernel(int64_t n, float lr, float b1, float b2, float eps, float c1, float c2,
                             const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
                             float* __restrict__ th, __bf16* __restrict__ thb) {
@@ -551,6 +602,29 @@ int semx_mlp_adam(semx_mlp* p, float lr, float beta1, float beta2, float eps, in
   adam_kernel<<<g1(p->nparam), 256, 0, p->stream>>>(p->nparam, lr, beta1, beta2, eps, c1, c2, p->grad.as<float>(),
                                                     p->m.as<float>(), p->v.as<float>(), p->theta.as<float>(),
                                                     p->theta_bf.as<__bf16>());
+  MLP_HIP(p, hipGetLastError());
+  return SEMX_OK;
+}
+
+int semx_mlp_affine(semx_mlp* p, const float* x_dev, int64_t rows, int cols, const float* scale_dev,
+                    const float* shift_dev, float* y_dev) {
+  if (!p || !x_dev || !y_dev || !scale_dev || !shift_dev || rows < 0 || cols < 1) return SEMX_EINVAL;
+  if (rows == 0) return SEMX_OK;
+  const int64_t n = rows * (int64_t)cols;
+  affine_cols_kernel<<<g1(n) > 8192 ? 8192 : g1(n), 256, 0, p->stream>>>(n, cols, x_dev, scale_dev, shift_dev, y_dev);
+  MLP_HIP(p, hipGetLastError());
+  return SEMX_OK;
+}
+
+int semx_mlp_ensemble(semx_mlp* p, const float* preds_dev, int members, int64_t rows, int cols,
+                      const float* scale_dev, const float* shift_dev, float* mean_dev, float* indicator_dev) {
+  if (!p || !preds_dev || !scale_dev || !shift_dev || !mean_dev || !indicator_dev || members < 1 || rows < 0 ||
+      cols < 1)
+    return SEMX_EINVAL;
+  if (rows == 0) return SEMX_OK;
+  if (rows > INT32_MAX) return mfail(p, SEMX_EINVAL, "ensemble: too many rows");
+  ensemble_kernel<<<(unsigned)rows, 256, 0, p->stream>>>(members, rows, cols, preds_dev, scale_dev, shift_dev,
+                                                         mean_dev, indicator_dev);
   MLP_HIP(p, hipGetLastError());
   return SEMX_OK;
 }

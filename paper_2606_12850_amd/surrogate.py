@@ -10,7 +10,9 @@ and as the reference for its error.
   the members); inputs whose indicator exceeds a threshold calibrated on
   validation data are sent to the SEM solver instead.
 
-Only marshalling, normalisation and bookkeeping happen in Python.
+Only marshalling, the training-set statistics and bookkeeping happen in
+Python; normalisation, the ensemble statistics and the indicator run in the
+library's kernels.
 """
 from __future__ import annotations
 
@@ -20,9 +22,10 @@ import time
 import numpy as np
 import torch
 
-from . import (Solver, semx_mlp_adam, semx_mlp_backward, semx_mlp_create, semx_mlp_destroy, semx_mlp_forward,
-               semx_mlp_get_params, semx_mlp_mse, semx_mlp_num_params, semx_mlp_set_params,
-               semx_read_seismograms, semx_reset, semx_set_dt, semx_set_receivers, semx_set_sources, semx_step)
+from . import (Solver, semx_mlp_adam, semx_mlp_affine, semx_mlp_backward, semx_mlp_create, semx_mlp_destroy,
+               semx_mlp_ensemble, semx_mlp_forward, semx_mlp_get_params, semx_mlp_mse, semx_mlp_num_params,
+               semx_mlp_set_params, semx_read_seismograms, semx_reset, semx_set_dt, semx_set_receivers,
+               semx_set_sources, semx_step)
 
 
 class BatchedSEM:
@@ -171,9 +174,12 @@ class Surrogate:
             sd = Y.std(0) + 1e-30
         self.y_mu = Y.mean(0)
         self.y_sd = sd
-        Xn = torch.from_numpy(((X - self.x_mu) / self.x_sd).astype(np.float32)).to(self.device)
-        Yn = torch.from_numpy(((Y - self.y_mu) / self.y_sd).astype(np.float32)).to(self.device)
         S = X.shape[0]
+        net0 = self.members[0].net
+        Xn = self._dev(X)
+        semx_mlp_affine(net0, Xn, S, X.shape[1], self._dev(1.0 / self.x_sd), self._dev(-self.x_mu / self.x_sd), Xn)
+        Yn = self._dev(Y)
+        semx_mlp_affine(net0, Yn, S, Y.shape[1], self._dev(1.0 / self.y_sd), self._dev(-self.y_mu / self.y_sd), Yn)
         steps_per_epoch = max(1, S // batch)
         total = epochs * steps_per_epoch
         rng = np.random.default_rng(seed)
@@ -191,21 +197,31 @@ class Surrogate:
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    def _dev(self, a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(self.device)
+
     def predict(self, X):
-        """Mean prediction and spread indicator ||std|| / ||mean|| per input."""
-        Xn = torch.from_numpy(((X - self.x_mu) / self.x_sd).astype(np.float32)).to(self.device)
-        preds = []
-        for m in self.members:
-            outs = [m.forward(Xn[b:b + 4096].contiguous()) for b in range(0, Xn.shape[0], 4096)]
-            preds.append(torch.cat(outs, 0))
-        P = torch.stack(preds, 0)  # [members, S, n_out] (normalised)
-        mean = P.mean(0)
-        spread = P.std(0) if len(preds) > 1 else torch.zeros_like(mean)
-        ysd = torch.from_numpy(self.y_sd.astype(np.float32)).to(self.device)
-        ymu = torch.from_numpy(self.y_mu.astype(np.float32)).to(self.device)
-        mean_phys = mean * ysd + ymu
-        ind = torch.linalg.norm(spread * ysd, dim=1) / torch.linalg.norm(mean_phys, dim=1).clamp_min(1e-30)
-        return mean_phys.cpu().numpy(), ind.cpu().numpy()
+        """Mean prediction (physical units) and spread indicator
+        ||std|| / ||mean|| per input.  The input normalisation, the members'
+        forward passes, the ensemble mean, its mapping back to physical
+        units and the indicator all run in the library's kernels."""
+        net0 = self.members[0].net
+        S, n_in = X.shape
+        x = self._dev(X)
+        xs, xb = self._dev(1.0 / self.x_sd), self._dev(-self.x_mu / self.x_sd)
+        semx_mlp_affine(net0, x, S, n_in, xs, xb, x)  # (x - mean) / std in place
+        n_out = self.widths[-1]
+        preds = torch.empty((len(self.members), S, n_out), dtype=torch.float32, device=self.device)
+        for k, m in enumerate(self.members):
+            for b in range(0, S, 4096):
+                nb = min(4096, S - b)
+                semx_mlp_forward(m.net, x[b:b + nb], nb, preds[k, b:b + nb])
+        mean = torch.empty((S, n_out), dtype=torch.float32, device=self.device)
+        ind = torch.empty(S, dtype=torch.float32, device=self.device)
+        semx_mlp_ensemble(net0, preds, len(self.members), S, n_out, self._dev(self.y_sd), self._dev(self.y_mu),
+                          mean, ind)
+        torch.cuda.synchronize(self.device)
+        return mean.cpu().numpy(), ind.cpu().numpy().astype(np.float64)
 
     def calibrate(self, X, Y, tol: float = 0.05):
         """Smallest indicator threshold that flags every validation input whose

@@ -186,3 +186,44 @@ def test_surrogate_pipeline_with_fallback():
     assert e_fin.mean() <= 0.05
     assert t_sur < t_sem                        # the gain, unconditionally
     s.close(); sem.close()
+
+
+def test_affine_and_ensemble_kernels_match_numpy():
+    """The surrogate's normalisation (column-wise affine map) and ensemble
+    statistics (mean in physical units, unbiased spread, the indicator
+    ||scale * std|| / ||mean||) against FP64 numpy on the same data."""
+    import torch
+    import paper_2606_12850_amd as P
+    rng = np.random.default_rng(21)
+    M, S, C = 4, 37, 1000
+    net = P.semx_mlp_create([8, 8], 16, torch.cuda.current_stream())
+    try:
+        x = rng.standard_normal((S, C)).astype(np.float32)
+        a = rng.uniform(0.5, 2.0, C).astype(np.float32)
+        b = rng.standard_normal(C).astype(np.float32)
+        dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+        xd, y = dev(x), torch.empty((S, C), device="cuda")
+        P.semx_mlp_affine(net, xd, S, C, dev(a), dev(b), y)
+        P.semx_mlp_affine(net, xd, S, C, dev(a), dev(b), xd)          # in place
+        ref = a[None].astype(np.float64) * x + b[None]
+        torch.cuda.synchronize()
+        assert np.abs(y.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+        assert np.array_equal(y.cpu().numpy(), xd.cpu().numpy())
+        p = rng.standard_normal((M, S, C)).astype(np.float32)
+        mean, ind = torch.empty((S, C), device="cuda"), torch.empty(S, device="cuda")
+        P.semx_mlp_ensemble(net, dev(p), M, S, C, dev(a), dev(b), mean, ind)
+        torch.cuda.synchronize()
+        p64 = p.astype(np.float64)
+        mref = a * p64.mean(0) + b
+        sref = a * p64.std(0, ddof=1)
+        iref = np.linalg.norm(sref, axis=1) / np.linalg.norm(mref, axis=1)
+        assert np.abs(mean.cpu().numpy() - mref).max() <= 1e-5 * np.abs(mref).max()
+        np.testing.assert_allclose(ind.cpu().numpy(), iref, rtol=1e-5)
+        # one member: zero spread
+        P.semx_mlp_ensemble(net, dev(p[:1]), 1, S, C, dev(a), dev(b), mean, ind)
+        torch.cuda.synchronize()
+        assert np.all(ind.cpu().numpy() == 0.0)
+        with pytest.raises(P.SemxError):
+            P.semx_mlp_ensemble(net, dev(p), 0, S, C, dev(a), dev(b), mean, ind)
+    finally:
+        P.semx_mlp_destroy(net)
