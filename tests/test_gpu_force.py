@@ -371,3 +371,43 @@ def test_zero_steps_and_silent_run():
     for x in (u, v, a):
         assert int(torch.count_nonzero(x)) == 0
     s.close()
+
+
+@pytest.mark.parametrize("renumber", ["reversed", "x_reversed", "scrambled"])
+def test_force_parity_renumbered_nodes(orc, renumber):
+    """Node numberings the affine path must handle: all strides negative
+    (g -> G - 1 - g), one negative stride (x reversed), and a random
+    permutation (no element affine: node numbers streamed).  The force of
+    each must equal the oracle's on the same numbering; a wrong node span in
+    the affine buffer reads would return zeros instead of u or f."""
+    import paper_2606_12850_amd as P
+    n = 5
+    base = W.box_mesh(4, n, 4000.0, jitter=0.1, seed=23)
+    Gx = 4 * (n - 1) + 1
+    g = np.arange(base.nglob)
+    if renumber == "reversed":
+        perm = base.nglob - 1 - g
+    elif renumber == "x_reversed":
+        X, rest = g % Gx, g // Gx
+        perm = (Gx - 1 - X) + Gx * rest
+    else:
+        perm = np.random.default_rng(5).permutation(base.nglob)
+    mesh = base
+    mesh.ibool = perm[base.ibool].astype(np.int32)
+    lam, mu, rho = _hetero_model(mesh, 12)
+    gam, jac, _ = oracle_geometry(orc, mesh)
+    for geometry in ("trilinear", "stored"):
+        for blocks in (P.SEMX_BLOCKS_OFF, P.SEMX_BLOCKS_ON):
+            s = make_solver(n)
+            s.upload_mesh(mesh)
+            s.upload_model(lam, mu, rho)
+            s.set_mode(P.SEMX_C_F32, P.SEMX_ASM_COLORED)
+            P.semx_set_geometry(s.ctx, P.SEMX_GEOM_STORED if geometry == "stored" else P.SEMX_GEOM_TRILINEAR)
+            active = P.semx_set_blocks(s.ctx, blocks)
+            assert active == (blocks == P.SEMX_BLOCKS_ON and renumber != "scrambled")
+            u = np.random.default_rng(8).uniform(-1, 1, (mesh.nglob, 3)).astype(np.float32).astype(np.float64)
+            f_ref = orc.force(n, mesh.ibool, gam, jac, lam, mu, u, mesh.nglob)
+            err = rel_l2(gpu_force(s, u), f_ref)
+            print(f"{renumber} {geometry} blocks={active}: rel L2 = {err:.3e}")
+            assert err <= TOL_F32, err
+            s.close()
