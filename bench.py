@@ -761,6 +761,11 @@ def acoustic_leg(mesh, reps: int = 50, rods: bool = True):
         P.semx_set_receivers(s.ctx, rod.rec_elem, rod.rec_xi, rod.nt)
         s.nrec, s.nt_max = 1, rod.nt
         P.semx_set_dt(s.ctx, rod.dt)
+        # a few hundred elements: the step is bound by kernel launches, which
+        # graph-captured chunks cut at NGLL 5 and 8 (not at 16, where the
+        # element kernels dominate)
+        chunk = 256 if n <= 10 else 0
+        P.semx_set_graphs(s.ctx, chunk)
         P.semx_reset(s.ctx)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -776,7 +781,8 @@ def acoustic_leg(mesh, reps: int = 50, rods: bool = True):
         runs.append({"p": n - 1, "ngll": n, "h_m": round(h, 3), "steps": rod.nt, "nspec": rod.mesh.nspec,
                      "error_ratio": err, "rel_l2_error_pct": round(100 * np.sqrt(err), 4),
                      "oracle_rel_l2_error_pct": round(100 * np.sqrt(o["error_at_h_max"]), 4),
-                     "wall_s": round(wall, 2), "us_per_step": round(wall / rod.nt * 1e6, 2)})
+                     "wall_s": round(wall, 2), "us_per_step": round(wall / rod.nt * 1e6, 2),
+                     "graph_chunk": chunk})
         progress(f"acoustic rod p={n - 1} h={h:.2f}: error {100 * np.sqrt(err):.4f} % in {wall:.1f} s")
     out["equal_accuracy_rod"] = {"x_rec_m": x_rec, "dt": tab["dt"], "bound_rel_l2_pct": 1.0, "runs": runs,
                                  "paper_h_m": {"4": 20.0, "7": 50.0, "15": 130.0}}

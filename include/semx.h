@@ -185,8 +185,11 @@ int semx_max_eigenvalue(semx_ctx *ctx, int iters, double *lambda_max);
  * dir[s][0..2] and time function stf[s][m], m = 0..nstf-1, sample m at
  * t_m = m dt (samples beyond nstf are 0).  It adds
  * stf[s][m] dir[s][c] l_i(xi) l_j(eta) l_k(zeta) to node (i,j,k) of elem[s]
- * (tensor-product interpolation weights, Sec. II-B).  With nmodels > 1 the
- * same sources act on every model.  nsrc = 0 removes all sources. */
+ * (tensor-product interpolation weights, Sec. II-B).  Where several
+ * sources reach one node their terms are summed in source order before the
+ * node's force is updated, so the injection is deterministic.  With
+ * nmodels > 1 the same sources act on every model.  nsrc = 0 removes all
+ * sources. */
 int semx_set_sources(semx_ctx *ctx, int nsrc, const int32_t *elem, const double *xi,
                      const double *dir, int64_t nstf, const float *stf);
 
@@ -205,6 +208,18 @@ int semx_reset(semx_ctx *ctx);
  * Requires mesh, model and dt.  If the watchdog interval is set, checks
  * every that many steps that the state is finite (SEMX_ENUMERIC otherwise). */
 int semx_step(semx_ctx *ctx, int64_t nsteps);
+
+/* Graph-captured time stepping: when chunk > 0, a semx_step() call of at
+ * least 2 chunk + 2 steps with FP32 storage, no force timing, no
+ * checkpoints and no watchdog records `chunk` steps once as a HIP graph and
+ * launches it for the middle of the call (the first step of a fresh run and
+ * the last, energy-tracked, step run directly).  The graph's kernels read
+ * the time index from a device counter that the library sets before each
+ * launch and advances after each step, so the results are bitwise those of
+ * direct stepping; only the per-step launch cost goes.  The graph is built
+ * per call and destroyed at its end.  chunk = 0 (the default) steps
+ * directly.  SEMX_EINVAL outside [0, 4096]. */
+int semx_set_graphs(semx_ctx *ctx, int chunk);
 
 /* Current time index (number of steps taken since reset). */
 int semx_time_index(semx_ctx *ctx, int64_t *it);

@@ -79,6 +79,7 @@ _SIGS = {
     "semx_set_watchdog": [_vp, _i64, _f64],
     "semx_set_geometry": [_vp, _i32],
     "semx_set_blocks": [_vp, _i32, ctypes.c_void_p],
+    "semx_set_graphs": [_vp, _i32],
     "semx_set_checkpointing": [_vp, _i64],
     "semx_adjoint": [_vp, _vp, _i64, _vp, _vp, _vp],
     "semx_mlp_create": [ctypes.POINTER(_vp), _i32, _vp, _i32, _vp],
@@ -372,6 +373,11 @@ def semx_set_blocks(ctx, mode: int) -> bool:
     active = ctypes.c_int(0)
     _check(ctx, lib().semx_set_blocks(ctx, int(mode), ctypes.byref(active)))
     return bool(active.value)
+
+
+def semx_set_graphs(ctx, chunk: int):
+    """Steps per captured HIP graph in semx_step (0: direct launches)."""
+    return _check(ctx, lib().semx_set_graphs(ctx, int(chunk)))
 
 
 def semx_set_checkpointing(ctx, every: int):

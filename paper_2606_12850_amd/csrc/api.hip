@@ -299,33 +299,46 @@ __global__ void accel_kernel(int64_t nnodes, int nc, const float* __restrict__ m
     a[t] = minv[t / nc] * f[t];
 }
 
-// Point sources at sample m: f[node][c] += stf[s][m] * l_q(x_s) dir_c (elastic,
-// nc = 3) or f[node] += stf[s][m] * l_q(x_s) (acoustic, nc = 1), all models.
-__global__ void source_kernel(int nsrc, int n3, int nc, int64_t nstf, int64_t m, int nmodels, int64_t nglob,
-                              const int32_t* __restrict__ nodes, const float* __restrict__ wdir,
+// Point sources at sample m: f[node][c] += sum over the (source s, point q)
+// pairs that reach the node of stf[s][m] * l_q(x_s) dir_c (elastic, nc = 3;
+// acoustic, nc = 1: l_q(x_s)), all models.  One thread per (model, source
+// node, component) sums its pairs in a fixed order (source, then point), so
+// the injection is deterministic even where sources share a node.  The
+// sample is m, or *step + 1 when `step` is given (the device step counter
+// of a graph-captured step: the injection at the end of step n uses sample
+// n + 1).
+__global__ void source_kernel(int nsn, const int32_t* __restrict__ snode, const int32_t* __restrict__ sptr,
+                              const int32_t* __restrict__ sidx, int n3, int nc, int64_t nstf, int64_t m,
+                              const int64_t* step, int nmodels, int64_t nglob, const float* __restrict__ wdir,
                               const float* __restrict__ stf, float* __restrict__ f) {
-  const int64_t total = (int64_t)nmodels * nsrc * n3;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+  if (step) m = *step + 1;
+  const int64_t per = (int64_t)nsn * nc;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nmodels * per;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t sq = t % ((int64_t)nsrc * n3);
-    const int model = (int)(t / ((int64_t)nsrc * n3));
-    const int s = (int)(sq / n3);
-    const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)s * nstf + m] : 0.0f;
-    if (amp == 0.0f) continue;
-    float* fg = f + ((int64_t)model * nglob + nodes[sq]) * nc;
-    for (int cc = 0; cc < nc; ++cc) {
-      const float wv = wdir[nc * sq + cc];
-      if (wv != 0.0f) unsafeAtomicAdd(fg + cc, amp * wv);  // a source on a node has one nonzero weight
+    const int64_t r = t % per;
+    const int i = (int)(r / nc), cc = (int)(r % nc);
+    float acc = 0.0f;
+    for (int k = sptr[i]; k < sptr[i + 1]; ++k) {
+      const int p = sidx[k];
+      const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)(p / n3) * nstf + m] : 0.0f;
+      acc += amp * wdir[(int64_t)nc * p + cc];
     }
+    const int64_t idx = ((t / per) * nglob + snode[i]) * nc + cc;
+    f[idx] += acc;
   }
 }
 
 // Receivers: one block per (model, receiver); sum_q l_q(x_r) u[node_q] per
 // component (nc = 3 elastic, 1 acoustic).
+// The sample is it, or *step when `step` is given (graph-captured steps);
+// samples outside [0, nt_max) are not recorded.
 __global__ void receiver_kernel(int nrec, int n3, int nc, int64_t nglob, int64_t nt_max, int64_t it,
-                                const int32_t* __restrict__ nodes, const float* __restrict__ wts,
-                                const float* __restrict__ u, float* __restrict__ seis) {
+                                const int64_t* step, const int32_t* __restrict__ nodes,
+                                const float* __restrict__ wts, const float* __restrict__ u,
+                                float* __restrict__ seis) {
   __shared__ float red[3][256];
+  if (step) it = *step;
+  if (it < 0 || it >= nt_max) return;  // uniform over the block
   const int r = blockIdx.x, model = blockIdx.y;
   const float* um = u + (int64_t)model * nglob * nc;
   float s[3] = {0.f, 0.f, 0.f};
@@ -346,6 +359,11 @@ __global__ void receiver_kernel(int nrec, int n3, int nc, int64_t nglob, int64_t
   if ((int)threadIdx.x < nc)
     seis[(((int64_t)model * nrec + r) * nc + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
 }
+
+// Device step counter of graph-captured steps: set before a replay, advanced
+// at the end of every captured step.
+__global__ void step_set_kernel(int64_t* step, int64_t v) { *step = v; }
+__global__ void step_incr_kernel(int64_t* step) { *step += 1; }
 
 // FP64 block reductions accumulated with a double atomic into out[slot].
 __device__ inline void block_sum_to(double v, double* out) {
@@ -820,6 +838,54 @@ ForceArgs force_args(const semx_ctx* c, const float* u, float* f, bool first_tou
 
 // `f_zero`: f holds zeros on entry, so with atomic assembly the points that
 // are their node's only reference may store instead of adding.
+// nchunks x G steps through one captured graph of G steps: the steps are
+// recorded once on the capture stream (with the device step counter in place
+// of the host step index in the source, receiver and source-work kernels,
+// and the counter advanced at the end of each step), then the graph is
+// launched nchunks times on the context's stream, the counter set from the
+// host index before each launch.  The captured steps are the ones
+// step_once would launch directly: bitwise the same results.
+int run_graph_chunks(semx_ctx* c, int64_t nchunks, int64_t G) {
+  int rc = SEMX_OK;
+  if (!c->d_step.p) rc = dev_alloc(c, c->d_step, sizeof(int64_t));
+  if (rc) return rc;
+  if (!c->cap_stream) SEMX_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  int64_t* dstep = c->d_step.as<int64_t>();
+  const int64_t it0 = c->it;
+  const bool pend0 = c->pending_correct;
+  hipStream_t home = c->stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  c->stream = c->cap_stream;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  for (int64_t s = 0; s < G && e == hipSuccess && !rc; ++s) {
+    c->track_energy = false;
+    rc = step_once(c, true, nullptr, nullptr, dstep);
+  }
+  const hipError_t e_end = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &graph) : e;
+  c->stream = home;
+  c->it = it0;  // the capture ran nothing
+  c->pending_correct = pend0;
+  if (rc || e_end != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return rc ? rc : hip_fail(c, e_end, "time-loop graph capture");
+  }
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(c, e, "time-loop graph instantiate");
+  for (int64_t k = 0; k < nchunks && e == hipSuccess; ++k) {
+    step_set_kernel<<<1, 1, 0, c->stream>>>(dstep, c->it);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
+    c->it += G;
+  }
+  c->pending_correct = true;
+  const hipError_t e_destroy = hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return hip_fail(c, e, "time-loop graph launch");
+  if (e_destroy != hipSuccess) return hip_fail(c, e_destroy, "time-loop graph destroy");
+  return SEMX_OK;
+}
+
 // True when the FP32 elastic coloured force runs on 2 x 2 x 2 element blocks.
 // In the automatic mode only where the block kernel measured faster than the
 // per-element kernel: the stored-Gamma path, which streams 36 B of Gamma per
@@ -926,12 +992,13 @@ int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
 }
 
 
-int inject_sources(semx_ctx* c, int64_t m, float* f) {
-  if (c->src.nsrc == 0) return SEMX_OK;
-  const int64_t total = (int64_t)c->nmodels * c->src.nsrc * c->n3;
+int inject_sources(semx_ctx* c, int64_t m, float* f, const int64_t* dstep = nullptr) {
+  if (c->src.nsrc == 0 || c->src.nsn == 0) return SEMX_OK;
+  const SourceSet& S = c->src;
+  const int64_t total = (int64_t)c->nmodels * S.nsn * c->ncomp;
   source_kernel<<<grid_for(total), kThreads, 0, c->stream>>>(
-      c->src.nsrc, c->n3, c->ncomp, c->src.nstf, m, c->nmodels, c->nglob, c->src.nodes.as<int32_t>(),
-      c->src.wdir.as<float>(), c->src.stf.as<float>(), f);
+      S.nsn, S.snode.as<int32_t>(), S.sptr.as<int32_t>(), S.sidx.as<int32_t>(), c->n3, c->ncomp, S.nstf, m, dstep,
+      c->nmodels, c->nglob, S.wdir.as<float>(), S.stf.as<float>(), f);
   SEMX_HIP(c, hipGetLastError());
   return SEMX_OK;
 }
@@ -979,10 +1046,10 @@ int do_reset(semx_ctx* c) {
   return rc;
 }
 
-int record_receivers(semx_ctx* c, int64_t idx) {
-  if (c->rec.nrec == 0 || idx < 0 || idx >= c->rec.nt_max) return SEMX_OK;
+int record_receivers(semx_ctx* c, int64_t idx, const int64_t* dstep = nullptr) {
+  if (c->rec.nrec == 0 || (!dstep && (idx < 0 || idx >= c->rec.nt_max))) return SEMX_OK;
   dim3 grid(c->rec.nrec, c->nmodels);
-  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, idx,
+  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, idx, dstep,
                                                c->rec.nodes.as<int32_t>(), c->rec.wts.as<float>(),
                                                c->d_u.as<float>(), c->rec.seis.as<float>());
   SEMX_HIP(c, hipGetLastError());
@@ -1010,7 +1077,7 @@ int check_finite(semx_ctx* c, bool* ok) {
 
 // One explicit Newmark step (correct the pending step, predict, force,
 // sources; optionally record receivers).  Leaves f = -K u + f_src pending.
-int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
+int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a, const int64_t* dstep) {
   if (c->storage == SEMX_F64) return f64_step_once(c, record);
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
   const float dt = (float)c->dt;
@@ -1042,14 +1109,18 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a) {
     int rc = energy_track(c, f_pe, src_in_f);
     if (rc) return rc;
   }
-  int rc = energy_source_step(c, c->it, track && src_in_f);
+  int rc = energy_source_step(c, c->it, track && src_in_f, dstep);
   if (rc) return rc;
   // f is zero here only if the Newmark pass cleared it (untracked step on a
   // mesh the force pass does not overwrite)
   rc = force_into(c, u, f, !track && !force_overwrites(c));
-  if (!rc) rc = inject_sources(c, c->it + 1, f);
-  if (!rc && record) rc = record_receivers(c, c->it);
+  if (!rc) rc = inject_sources(c, c->it + 1, f, dstep);
+  if (!rc && record) rc = record_receivers(c, c->it, dstep);
   if (rc) return rc;
+  if (dstep) {
+    step_incr_kernel<<<1, 1, 0, c->stream>>>(const_cast<int64_t*>(dstep));
+    SEMX_HIP(c, hipGetLastError());
+  }
   c->it++;
   c->pending_correct = true;
   if (track) c->energy_it = c->it;
@@ -1068,6 +1139,7 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
   if (nsrc < 0) return fail(c, SEMX_EINVAL, "set_sources: nsrc < 0");
   if (nsrc == 0) {
     c->src.nsrc = 0;
+    c->src.nsn = 0;
     c->run_gen++;
     c->ckpt_count = 0;
     return c->have_model && c->d_u.p ? energy_reset(c) : SEMX_OK;
@@ -1116,7 +1188,27 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
     if (nz) pts.push_back((int32_t)p);
   }
   if (pts.empty()) pts.push_back(0);
+  // the nodes that receive a source force in FP32, each with its (source,
+  // point) pairs in order: the injection's per-node sums
+  std::vector<std::pair<int32_t, int32_t>> np_pairs;  // (node, s n3 + q)
+  for (size_t p = 0; p < (size_t)nsrc * n3; ++p) {
+    bool nz = false;
+    for (int d = 0; d < nc; ++d) nz |= wdir[p * nc + d] != 0.0f;
+    if (nz) np_pairs.push_back({nodes[p], (int32_t)p});
+  }
+  std::sort(np_pairs.begin(), np_pairs.end());
+  std::vector<int32_t> sptr(1, 0), sidx, snode;
+  for (size_t k = 0; k < np_pairs.size(); ++k) {
+    if (k > 0 && np_pairs[k].first != np_pairs[k - 1].first) sptr.push_back((int32_t)k);
+    if (k == 0 || np_pairs[k].first != np_pairs[k - 1].first) snode.push_back(np_pairs[k].first);
+    sidx.push_back(np_pairs[k].second);
+  }
+  sptr.push_back((int32_t)np_pairs.size());
+  if (sidx.empty()) sidx.push_back(0);
   int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
+  if (!rc) rc = dev_alloc(c, c->src.snode, sizeof(int32_t) * std::max<size_t>(1, snode.size()));
+  if (!rc) rc = dev_alloc(c, c->src.sptr, sizeof(int32_t) * sptr.size());
+  if (!rc) rc = dev_alloc(c, c->src.sidx, sizeof(int32_t) * sidx.size());
   if (!rc) rc = dev_alloc(c, c->src.pts, pts.size() * sizeof(int32_t));
   if (!rc) rc = dev_alloc(c, c->src.wdir, wdir.size() * sizeof(float));
   if (!rc) rc = dev_alloc(c, c->src.stf, sizeof(float) * ns);
@@ -1124,6 +1216,11 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
   if (!rc) rc = dev_alloc(c, c->src.stf64, sizeof(double) * ns);
   if (rc) return rc;
   SEMX_HIP(c, hipMemcpy(c->src.nodes.p, nodes.data(), nodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!snode.empty())
+    SEMX_HIP(c, hipMemcpy(c->src.snode.p, snode.data(), sizeof(int32_t) * snode.size(), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.sptr.p, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice));
+  SEMX_HIP(c, hipMemcpy(c->src.sidx.p, sidx.data(), sizeof(int32_t) * sidx.size(), hipMemcpyHostToDevice));
+  c->src.nsn = (int)snode.size();
   SEMX_HIP(c, hipMemcpy(c->src.pts.p, pts.data(), pts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   c->src.npts = (int)pts.size();
   SEMX_HIP(c, hipMemcpy(c->src.wdir.p, wdir.data(), wdir.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -1195,11 +1292,14 @@ int semx_destroy(semx_ctx* c) {
   else (void)hipDeviceSynchronize();
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   for (DevBuf& b : c->ckpts) dev_free(b);
-  for (DevBuf* b : {&c->d_bpos, &c->d_baff, &c->d_bfirst}) dev_free(*b);
+  for (DevBuf* b : {&c->d_bpos, &c->d_baff, &c->d_bfirst, &c->d_step}) dev_free(*b);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
                     &c->d_mass64, &c->d_wrho, &c->d_u, &c->d_v, &c->d_a, &c->d_f, &c->d_work, &c->d_scratch,
-                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->src.pts, &c->rec.nodes, &c->rec.wts,
+                    &c->src.nodes, &c->src.wdir, &c->src.stf, &c->src.pts, &c->src.snode, &c->src.sptr,
+                    &c->src.sidx, &c->rec.nodes, &c->rec.wts,
                     &c->rec.seis,
                     &c->src.wdir64, &c->src.stf64, &c->rec.wts64, &c->rec.seis64, &c->d_gam64, &c->d_mat64,
                     &c->d_minv64, &c->d_D64,
@@ -1612,6 +1712,8 @@ int semx_force_skeleton(semx_ctx* c, const float* u_dev, float* f_dev, int reps,
   return SEMX_OK;
 }
 
+
+
 int semx_set_dt(semx_ctx* c, double dt) {
   if (!c) return SEMX_EINVAL;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SEMX_EINVAL, "set_dt: dt must be positive");
@@ -1744,6 +1846,32 @@ int semx_step(semx_ctx* c, int64_t nsteps) {
   if (!c->have_mesh || !c->have_model) return fail(c, SEMX_ESTATE, "step: mesh and model required");
   if (!c->have_dt) return fail(c, SEMX_ESTATE, "step: dt not set");
   if (nsteps < 0) return fail(c, SEMX_EINVAL, "step: nsteps < 0");
+  // Graph-captured chunks for the untracked middle of a long call: FP32
+  // storage, no force timing, no checkpoints, no watchdog; the first step
+  // (if no corrector is pending) and the last (energy tracking) run directly.
+  const int64_t G = c->graph_chunk;
+  if (G > 0 && c->storage == SEMX_F32 && c->timing_stride == 0 && c->ckpt_every == 0 &&
+      c->watchdog_every == 0 && nsteps >= 2 * G + 2) {
+    int64_t done = 0;
+    if (!c->pending_correct) {
+      c->track_energy = false;
+      int rc = step_once(c, true);
+      if (rc) return rc;
+      ++done;
+    }
+    const int64_t nchunks = (nsteps - done - 1) / G;
+    if (nchunks >= 2) {
+      int rc = run_graph_chunks(c, nchunks, G);
+      if (rc) return rc;
+      done += nchunks * G;
+    }
+    for (int64_t s = done; s < nsteps; ++s) {
+      c->track_energy = s + 1 == nsteps;
+      int rc = step_once(c, true);
+      if (rc) return rc;
+    }
+    return SEMX_OK;
+  }
   for (int64_t s = 0; s < nsteps; ++s) {
     // the discrete energy is tracked on the last step of the call and on the
     // watchdog's steps that check it
@@ -1839,6 +1967,13 @@ int semx_set_geometry(semx_ctx* c, int mode) {
   if (mode == SEMX_GEOM_STORED) c->irregular_geo = kStored;
   else if (mode == SEMX_GEOM_TRILINEAR) c->irregular_geo = kTrilinear;
   else return fail(c, SEMX_EINVAL, "set_geometry: unknown mode");
+  return SEMX_OK;
+}
+
+int semx_set_graphs(semx_ctx* c, int chunk) {
+  if (!c) return SEMX_EINVAL;
+  if (chunk < 0 || chunk > 4096) return fail(c, SEMX_EINVAL, "set_graphs: chunk outside [0, 4096]");
+  c->graph_chunk = chunk;
   return SEMX_OK;
 }
 

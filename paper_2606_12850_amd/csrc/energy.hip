@@ -83,15 +83,23 @@ __global__ void energy_reduce_kernel(int nblk, const double* __restrict__ part, 
 // stf[s][n] * wdir[(s n3 + q) nc + c]; hist is indexed by k.
 // work: acc[3] += 1/2 sum (u^{n+1} - u^{n-1}) . f_src^n (with_work);
 // corr: acc[2] = sum u^{n+1} . f_src^n; then hist[slot_new] = u^{n+1}.
+// The step is n, or *step when `step` is given (graph-captured steps); the
+// history slot of u^{n-1} (written two steps ago, overwritten with u^{n+1})
+// and whether u^{n-1} is known (n > it0) follow from it.
 template <class T>
 __global__ __launch_bounds__(kT) void source_energy_kernel(int npt, int n3, int nc, int64_t nstf, int64_t n,
+                                                           const int64_t* step, int64_t it0,
                                                            const int32_t* __restrict__ pts,
                                                            const int32_t* __restrict__ nodes,
                                                            const T* __restrict__ wdir, const T* __restrict__ stf,
-                                                           const T* __restrict__ u, const T* hist_old,
-                                                           T* hist_new, int with_work, int with_corr,
-                                                           double* __restrict__ acc) {
+                                                           const T* __restrict__ u, T* hist, size_t per,
+                                                           int with_corr, double* __restrict__ acc) {
   __shared__ double red[kT];
+  if (step) n = *step;
+  T* slot = hist + (size_t)((n + 1) & 1) * per;
+  const T* hist_old = slot;
+  T* hist_new = slot;
+  const int with_work = n > it0 ? 1 : 0;
   double work = 0.0, corr = 0.0;
   for (int k = threadIdx.x; k < npt; k += blockDim.x) {
     const int p = pts[k];
@@ -128,20 +136,19 @@ __global__ void zero_doubles_kernel(double* __restrict__ p, int n) {
 }
 
 template <class T>
-int source_step_t(semx_ctx* c, int64_t n, bool with_corr) {
+int source_step_t(semx_ctx* c, int64_t n, bool with_corr, const int64_t* dstep) {
   const int npt = c->src.npts;
   const size_t per = (size_t)npt * c->ncomp;
   T* hist = c->d_ehist.as<T>();
   const bool f64 = c->storage == SEMX_F64;
   const T* wdir = f64 ? (const T*)c->src.wdir64.p : (const T*)c->src.wdir.p;
   const T* stf = f64 ? (const T*)c->src.stf64.p : (const T*)c->src.stf.p;
-  // slot of u^{n-1} (stored two steps ago) is the slot u^{n+1} goes to
-  T* slot = hist + (size_t)((n + 1) & 1) * per;
-  const int with_work = n > c->energy_it0 ? 1 : 0;  // u^{n-1} is known from the second step on
-  source_energy_kernel<T><<<1, kT, 0, c->stream>>>(npt, c->n3, c->ncomp, c->src.nstf, n, c->src.pts.as<int32_t>(),
-                                                   c->src.nodes.as<int32_t>(),
-                                                   wdir, stf, c->d_u.as<T>(), slot, slot, with_work,
-                                                   with_corr ? 1 : 0, c->d_eacc.as<double>());
+  // the slot of u^{n-1} (stored two steps ago) is the slot u^{n+1} goes to;
+  // u^{n-1} is known from the second step on (n > energy_it0)
+  source_energy_kernel<T><<<1, kT, 0, c->stream>>>(npt, c->n3, c->ncomp, c->src.nstf, n, dstep, c->energy_it0,
+                                                   c->src.pts.as<int32_t>(), c->src.nodes.as<int32_t>(), wdir, stf,
+                                                   c->d_u.as<T>(), hist, per, with_corr ? 1 : 0,
+                                                   c->d_eacc.as<double>());
   SEMX_HIP(c, hipGetLastError());
   return SEMX_OK;
 }
@@ -181,9 +188,10 @@ int energy_reset(semx_ctx* c) {
   return SEMX_OK;
 }
 
-int energy_source_step(semx_ctx* c, int64_t n, bool with_corr) {
+int energy_source_step(semx_ctx* c, int64_t n, bool with_corr, const int64_t* dstep) {
   if (c->src.nsrc == 0 || !c->d_ehist.p) return SEMX_OK;
-  return c->storage == SEMX_F64 ? source_step_t<double>(c, n, with_corr) : source_step_t<float>(c, n, with_corr);
+  return c->storage == SEMX_F64 ? source_step_t<double>(c, n, with_corr, dstep)
+                                : source_step_t<float>(c, n, with_corr, dstep);
 }
 
 int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f) {

@@ -50,6 +50,10 @@ struct SourceSet {
   DevBuf stf64;
   DevBuf pts;     // int32 [npts]: the points (s n3 + q) with a nonzero weight (energy bookkeeping)
   int npts = 0;
+  // the nodes that receive a source force (FP32 weights), ascending, and for
+  // node i its points sidx[sptr[i] .. sptr[i + 1]) (s n3 + q, ascending)
+  DevBuf snode, sptr, sidx;
+  int nsn = 0;
 };
 
 struct ReceiverSet {
@@ -67,6 +71,12 @@ struct ReceiverSet {
 struct semx_ctx {
   int n = 0, n3 = 0;
   hipStream_t stream = nullptr;
+  // graph-captured time loop (semx_set_graphs): steps per captured chunk
+  // (0: every step launched directly), the device step counter the captured
+  // steps read, and the stream the capture is recorded on
+  int graph_chunk = 0;
+  semx::DevBuf d_step;
+  hipStream_t cap_stream = nullptr;
   int device = 0;
   int num_cu = 256;
   std::string err;
@@ -280,7 +290,10 @@ bool mfma_supported(int n, int prec);
 // One explicit step.  seg_u / seg_a (the adjoint's forward recomputation,
 // may be null): the Newmark pass also stores the predicted u and, when it
 // corrects the previous step, that step's acceleration, into them.
-int step_once(semx_ctx* c, bool record, float* seg_u = nullptr, float* seg_a = nullptr);
+// dstep: the device step counter when the step is captured into a graph
+// (the step-indexed kernels read it; the step advances it), else null.
+int step_once(semx_ctx* c, bool record, float* seg_u = nullptr, float* seg_a = nullptr,
+              const int64_t* dstep = nullptr);
 int apply_force_accumulate(semx_ctx* c, const float* u, float* f);
 int fill_zero(semx_ctx* c, float* p, int64_t n);
 // Apply the pending correction (a = M^{-1} f, v += dt/2 a); seg_a, if given,
@@ -300,7 +313,7 @@ int energy_reset(semx_ctx* c);
 // source_in_f, else -K u^n)
 int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f);
 // every step n after the Newmark pass (u holds u^{n+1})
-int energy_source_step(semx_ctx* c, int64_t n, bool with_corr);
+int energy_source_step(semx_ctx* c, int64_t n, bool with_corr, const int64_t* dstep = nullptr);
 int energy_read(semx_ctx* c, double* kin, double* pot, double* work);
 
 // fp64.hip: the FP64 storage path (state buffers hold doubles)
