@@ -22,7 +22,8 @@ def _net(widths, batch, seed=0):
     return MLP(widths, batch, seed)
 
 
-@pytest.mark.parametrize("widths,batch", [([64, 128, 96, 200], 37), ([5, 70, 3], 1), ([64, 512, 512, 512, 24576], 128)])
+@pytest.mark.parametrize("widths,batch", [([64, 128, 96, 200], 37), ([5, 70, 3], 1), ([64, 512, 512, 512, 24576], 128),
+                                          ([64, 512, 20000], 520)])
 def test_forward_backward_vs_fp64(widths, batch):
     import torch
     rng = np.random.default_rng(1)
