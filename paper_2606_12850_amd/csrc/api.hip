@@ -251,31 +251,114 @@ __global__ void fill_f64(double* __restrict__ p, int64_t n, double v) {
 // predicted u to seg_u, the segment buffers, in the same pass.
 constexpr int kCorrect = 1, kPredict = 2, kStoreA = 4, kKeepF = 8, kSeg = 16;
 
-// NC: field components per node (3 elastic, 1 acoustic).
+// One entry (node, component) of the update: m = M^{-1} at the node, ff
+// and aa its f and a; uu and vv are updated in place, the acceleration used
+// is returned.  Both kernels below apply exactly this.
+template <int MODE>
+__device__ __forceinline__ float newmark_entry(float m, float ff, float aa, float dt, float hdt, float hdt2, float& uu,
+                                               float& vv) {
+  float acc;
+  if constexpr ((MODE & kCorrect) != 0) {
+    acc = m * ff;
+    vv = vv + hdt * acc;
+  } else {
+    acc = aa;
+  }
+  if constexpr ((MODE & kPredict) != 0) {
+    uu = uu + dt * vv + hdt2 * acc;
+    vv = vv + hdt * acc;
+  }
+  return acc;
+}
+
+// NC: field components per node (3 elastic, 1 acoustic).  One entry per lane.
 template <int MODE, int NC>
-__global__ void newmark_kernel(int64_t nnodes, int64_t nglob, float dt, const float* __restrict__ minv,
-                               float* __restrict__ u, float* __restrict__ v, float* __restrict__ a,
-                               float* __restrict__ f, float* __restrict__ seg_u, float* __restrict__ seg_a) {
+__global__ void newmark_kernel(int64_t nnodes, float dt, const float* __restrict__ minv, float* __restrict__ u,
+                               float* __restrict__ v, float* __restrict__ a, float* __restrict__ f,
+                               float* __restrict__ seg_u, float* __restrict__ seg_a) {
   const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NC * nnodes;
        t += (int64_t)gridDim.x * blockDim.x) {
-    float acc, vv = v[t];
-    if constexpr ((MODE & kCorrect) != 0) {
-      acc = minv[t / NC] * f[t];
-      vv = vv + hdt * acc;
-      if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
-      if constexpr ((MODE & kSeg) != 0) seg_a[t] = acc;
-    } else {
-      acc = a[t];
-    }
-    if constexpr ((MODE & kPredict) != 0) {
-      const float un = u[t] + dt * vv + hdt2 * acc;
-      u[t] = un;
-      if constexpr ((MODE & kSeg) != 0) seg_u[t] = un;
-      vv = vv + hdt * acc;
+    constexpr bool C = (MODE & kCorrect) != 0, Pr = (MODE & kPredict) != 0;
+    float vv = v[t], uu = Pr ? u[t] : 0.0f;
+    const float acc = newmark_entry<MODE>(C ? minv[t / NC] : 0.0f, C ? f[t] : 0.0f, C ? 0.0f : a[t], dt, hdt, hdt2,
+                                          uu, vv);
+    if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+    if constexpr (C && (MODE & kSeg) != 0) seg_a[t] = acc;
+    if constexpr (Pr) {
+      u[t] = uu;
+      if constexpr ((MODE & kSeg) != 0) seg_u[t] = uu;
       if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0f;
     }
     v[t] = vv;
+  }
+}
+
+// The same update with four consecutive entries per lane (16-byte loads and
+// stores; every array 16-byte aligned).  v and f are streamed with
+// non-temporal loads and v with a non-temporal store, so they do not evict
+// u, which the force pass gathers next.  The last (NC nnodes) % 4 entries
+// go to the first lanes, one each.
+typedef float semx_f4 __attribute__((ext_vector_type(4)));
+template <int MODE, int NC>
+__global__ void newmark4_kernel(int64_t nnodes, float dt, const float* __restrict__ minv, float* __restrict__ u,
+                                float* __restrict__ v, float* __restrict__ a, float* __restrict__ f,
+                                float* __restrict__ seg_u, float* __restrict__ seg_a) {
+  constexpr bool C = (MODE & kCorrect) != 0, Pr = (MODE & kPredict) != 0;
+  const float hdt = 0.5f * dt, hdt2 = 0.5f * dt * dt;
+  const int64_t len = NC * nnodes, len4 = len / 4;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t q = gid; q < len4; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t0 = 4 * q;
+    semx_f4 vv = __builtin_nontemporal_load(reinterpret_cast<const semx_f4*>(v + t0));
+    semx_f4 uu = {0.0f, 0.0f, 0.0f, 0.0f}, ff = uu, aa = uu, acc;
+    if constexpr (Pr) uu = *reinterpret_cast<const semx_f4*>(u + t0);
+    if constexpr (C) ff = __builtin_nontemporal_load(reinterpret_cast<const semx_f4*>(f + t0));
+    else aa = *reinterpret_cast<const semx_f4*>(a + t0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float x = uu[e], y = vv[e];
+      acc[e] = newmark_entry<MODE>(C ? minv[(t0 + e) / NC] : 0.0f, ff[e], aa[e], dt, hdt, hdt2, x, y);
+      uu[e] = x;
+      vv[e] = y;
+    }
+    if constexpr ((MODE & kStoreA) != 0) *reinterpret_cast<semx_f4*>(a + t0) = acc;
+    if constexpr (C && (MODE & kSeg) != 0) *reinterpret_cast<semx_f4*>(seg_a + t0) = acc;
+    if constexpr (Pr) {
+      *reinterpret_cast<semx_f4*>(u + t0) = uu;
+      if constexpr ((MODE & kSeg) != 0) *reinterpret_cast<semx_f4*>(seg_u + t0) = uu;
+      if constexpr ((MODE & kKeepF) == 0) *reinterpret_cast<semx_f4*>(f + t0) = (semx_f4){0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    __builtin_nontemporal_store(vv, reinterpret_cast<semx_f4*>(v + t0));
+  }
+  const int64_t t = 4 * len4 + gid;
+  if (t < len) {
+    float vv = v[t], uu = Pr ? u[t] : 0.0f;
+    const float acc = newmark_entry<MODE>(C ? minv[t / NC] : 0.0f, C ? f[t] : 0.0f, C ? 0.0f : a[t], dt, hdt, hdt2,
+                                          uu, vv);
+    if constexpr ((MODE & kStoreA) != 0) a[t] = acc;
+    if constexpr (C && (MODE & kSeg) != 0) seg_a[t] = acc;
+    if constexpr (Pr) {
+      u[t] = uu;
+      if constexpr ((MODE & kSeg) != 0) seg_u[t] = uu;
+      if constexpr ((MODE & kKeepF) == 0) f[t] = 0.0f;
+    }
+    v[t] = vv;
+  }
+}
+
+bool aligned16(const float* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <int MODE, int NC>
+void launch_newmark_nc(semx_ctx* c, int64_t nn, unsigned gb, float dt, const float* minv, float* u, float* v,
+                       float* a, float* f, float* seg_u, float* seg_a) {
+  const bool vec = aligned16(u) && aligned16(v) && aligned16(a) && aligned16(f) && (!seg_u || aligned16(seg_u)) &&
+                   (!seg_a || aligned16(seg_a));
+  if (vec) {
+    const unsigned g4 = grid_for((NC * nn + 3) / 4, 1 << 30);
+    newmark4_kernel<MODE, NC><<<g4, kThreads, 0, c->stream>>>(nn, dt, minv, u, v, a, f, seg_u, seg_a);
+  } else {
+    newmark_kernel<MODE, NC><<<gb, kThreads, 0, c->stream>>>(nn, dt, minv, u, v, a, f, seg_u, seg_a);
   }
 }
 
@@ -284,11 +367,11 @@ template <int MODE>
 void launch_newmark(semx_ctx* c, int64_t nn, unsigned gb, float dt, const float* minv, float* u, float* v, float* a,
                     float* f, float* seg_u, float* seg_a) {
   if (c->ncomp == 1)
-    newmark_kernel<MODE, 1><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
+    launch_newmark_nc<MODE, 1>(c, nn, gb, dt, minv, u, v, a, f, nullptr, nullptr);
   else if (seg_u || seg_a)
-    newmark_kernel<MODE | kSeg, 3><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, seg_u, seg_a);
+    launch_newmark_nc<MODE | kSeg, 3>(c, nn, gb, dt, minv, u, v, a, f, seg_u, seg_a);
   else
-    newmark_kernel<MODE, 3><<<gb, kThreads, 0, c->stream>>>(nn, c->nglob, dt, minv, u, v, a, f, nullptr, nullptr);
+    launch_newmark_nc<MODE, 3>(c, nn, gb, dt, minv, u, v, a, f, nullptr, nullptr);
 }
 
 // a = M^{-1} f without touching v (initial acceleration).
