@@ -411,38 +411,6 @@ __global__ void source_kernel(int nsn, const int32_t* __restrict__ snode, const 
   }
 }
 
-// Receivers: one block per (model, receiver); sum_q l_q(x_r) u[node_q] per
-// component (nc = 3 elastic, 1 acoustic).
-// The sample is it, or *step when `step` is given (graph-captured steps);
-// samples outside [0, nt_max) are not recorded.
-__global__ void receiver_kernel(int nrec, int n3, int nc, int64_t nglob, int64_t nt_max, int64_t it,
-                                const int64_t* step, const int32_t* __restrict__ nodes,
-                                const float* __restrict__ wts, const float* __restrict__ u,
-                                float* __restrict__ seis) {
-  __shared__ float red[3][256];
-  if (step) it = *step;
-  if (it < 0 || it >= nt_max) return;  // uniform over the block
-  const int r = blockIdx.x, model = blockIdx.y;
-  const float* um = u + (int64_t)model * nglob * nc;
-  float s[3] = {0.f, 0.f, 0.f};
-  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
-    const float wq = wts[(int64_t)r * n3 + q];
-    const int64_t g = nodes[(int64_t)r * n3 + q];
-    for (int c = 0; c < nc; ++c) s[c] += wq * um[nc * g + c];
-  }
-  red[0][threadIdx.x] = s[0];
-  red[1][threadIdx.x] = s[1];
-  red[2][threadIdx.x] = s[2];
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
-    __syncthreads();
-  }
-  if ((int)threadIdx.x < nc)
-    seis[(((int64_t)model * nrec + r) * nc + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
-}
-
 // Device step counter of graph-captured steps: set before a replay, advanced
 // at the end of every captured step.
 __global__ void step_set_kernel(int64_t* step, int64_t v) { *step = v; }
@@ -1129,17 +1097,6 @@ int do_reset(semx_ctx* c) {
   return rc;
 }
 
-int record_receivers(semx_ctx* c, int64_t idx, const int64_t* dstep = nullptr) {
-  if (c->rec.nrec == 0 || (!dstep && (idx < 0 || idx >= c->rec.nt_max))) return SEMX_OK;
-  dim3 grid(c->rec.nrec, c->nmodels);
-  receiver_kernel<<<grid, 256, 0, c->stream>>>(c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, idx, dstep,
-                                               c->rec.nodes.as<int32_t>(), c->rec.wts.as<float>(),
-                                               c->d_u.as<float>(), c->rec.seis.as<float>());
-  SEMX_HIP(c, hipGetLastError());
-  return SEMX_OK;
-}
-
-
 int check_finite(semx_ctx* c, bool* ok) {
   if (c->storage == SEMX_F64) return f64_check_finite(c, ok);
   int* flag = scratch_i(c);
@@ -1192,13 +1149,13 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a, const int64_
     int rc = energy_track(c, f_pe, src_in_f);
     if (rc) return rc;
   }
-  int rc = energy_source_step(c, c->it, track && src_in_f, dstep);
+  // source work and receivers read u^{n+1}, which the force pass leaves alone
+  int rc = step_aux(c, c->it, track && src_in_f, record, dstep);
   if (rc) return rc;
   // f is zero here only if the Newmark pass cleared it (untracked step on a
   // mesh the force pass does not overwrite)
   rc = force_into(c, u, f, !track && !force_overwrites(c));
   if (!rc) rc = inject_sources(c, c->it + 1, f, dstep);
-  if (!rc && record) rc = record_receivers(c, c->it, dstep);
   if (rc) return rc;
   if (dstep) {
     step_incr_kernel<<<1, 1, 0, c->stream>>>(const_cast<int64_t*>(dstep));

@@ -87,14 +87,12 @@ __global__ void energy_reduce_kernel(int nblk, const double* __restrict__ part, 
 // history slot of u^{n-1} (written two steps ago, overwritten with u^{n+1})
 // and whether u^{n-1} is known (n > it0) follow from it.
 template <class T>
-__global__ __launch_bounds__(kT) void source_energy_kernel(int npt, int n3, int nc, int64_t nstf, int64_t n,
-                                                           const int64_t* step, int64_t it0,
-                                                           const int32_t* __restrict__ pts,
-                                                           const int32_t* __restrict__ nodes,
-                                                           const T* __restrict__ wdir, const T* __restrict__ stf,
-                                                           const T* __restrict__ u, T* hist, size_t per,
-                                                           int with_corr, double* __restrict__ acc) {
-  __shared__ double red[kT];
+__device__ __forceinline__ void source_energy_block(int npt, int n3, int nc, int64_t nstf, int64_t n,
+                                                    const int64_t* step, int64_t it0, const int32_t* __restrict__ pts,
+                                                    const int32_t* __restrict__ nodes, const T* __restrict__ wdir,
+                                                    const T* __restrict__ stf, const T* __restrict__ u, T* hist,
+                                                    size_t per, int with_corr, double* __restrict__ acc,
+                                                    double* red) {
   if (step) n = *step;
   T* slot = hist + (size_t)((n + 1) & 1) * per;
   const T* hist_old = slot;
@@ -120,6 +118,74 @@ __global__ __launch_bounds__(kT) void source_energy_kernel(int npt, int n3, int 
     if (with_work) acc[3] += work;
     if (with_corr) acc[2] = corr;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kT) void source_energy_kernel(int npt, int n3, int nc, int64_t nstf, int64_t n,
+                                                           const int64_t* step, int64_t it0,
+                                                           const int32_t* __restrict__ pts,
+                                                           const int32_t* __restrict__ nodes,
+                                                           const T* __restrict__ wdir, const T* __restrict__ stf,
+                                                           const T* __restrict__ u, T* hist, size_t per,
+                                                           int with_corr, double* __restrict__ acc) {
+  __shared__ double red[kT];
+  source_energy_block<T>(npt, n3, nc, nstf, n, step, it0, pts, nodes, wdir, stf, u, hist, per, with_corr, acc, red);
+}
+
+// Receivers (FP32 storage): receiver r of model `model` is
+// sum_q l_q(x_r) u[node_q] per component (nc = 3 elastic, 1 acoustic),
+// stored as sample `it` of seis [nmodels][nrec][nc][nt_max].  One block of
+// kT lanes; the caller keeps samples outside [0, nt_max) away.
+__device__ __forceinline__ void receiver_block(int r, int model, int nrec, int n3, int nc, int64_t nglob,
+                                               int64_t nt_max, int64_t it, const int32_t* __restrict__ nodes,
+                                               const float* __restrict__ wts, const float* __restrict__ u,
+                                               float* __restrict__ seis, float (*red)[kT]) {
+  const float* um = u + (int64_t)model * nglob * nc;
+  float s[3] = {0.f, 0.f, 0.f};
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    const float wq = wts[(int64_t)r * n3 + q];
+    const int64_t g = nodes[(int64_t)r * n3 + q];
+    for (int c = 0; c < nc; ++c) s[c] += wq * um[nc * g + c];
+  }
+  red[0][threadIdx.x] = s[0];
+  red[1][threadIdx.x] = s[1];
+  red[2][threadIdx.x] = s[2];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + st];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < nc)
+    seis[(((int64_t)model * nrec + r) * nc + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
+}
+
+// The per-step bookkeeping that reads u^{n+1} (FP32 storage), one launch
+// after the Newmark pass: blocks x < nrec_blocks record receiver x of model
+// y (sample it, or *step for graph-captured steps; nothing outside
+// [0, nt_max)); block x = nrec_blocks of row y = 0, when `src` is set, is
+// source_energy_block.  The force pass that follows writes only f.
+__global__ __launch_bounds__(kT) void step_aux_kernel(int nrec_blocks, int nrec, int n3, int nc, int64_t nglob,
+                                                      int64_t nt_max, int64_t it, const int64_t* step,
+                                                      const int32_t* __restrict__ rnodes,
+                                                      const float* __restrict__ rwts, float* __restrict__ seis,
+                                                      int src, int npt, int64_t nstf, int64_t it0,
+                                                      const int32_t* __restrict__ pts,
+                                                      const int32_t* __restrict__ snodes,
+                                                      const float* __restrict__ wdir, const float* __restrict__ stf,
+                                                      float* hist, size_t per, int with_corr,
+                                                      double* __restrict__ acc, const float* __restrict__ u) {
+  __shared__ float rred[3][kT];
+  __shared__ double ered[kT];
+  if ((int)blockIdx.x < nrec_blocks) {
+    if (step) it = *step;
+    if (it < 0 || it >= nt_max) return;  // uniform over the block
+    receiver_block(blockIdx.x, blockIdx.y, nrec, n3, nc, nglob, nt_max, it, rnodes, rwts, u, seis, rred);
+    return;
+  }
+  if (!src || blockIdx.y != 0) return;
+  source_energy_block<float>(npt, n3, nc, nstf, it, step, it0, pts, snodes, wdir, stf, u, hist, per, with_corr, acc,
+                             ered);
 }
 
 // u at the source points (model 0) into hist (at a reset or a new state).
@@ -184,6 +250,22 @@ int energy_reset(semx_ctx* c) {
     source_gather_kernel<float><<<nb, kT, 0, c->stream>>>(npt, c->ncomp, c->src.pts.as<int32_t>(),
                                                           c->src.nodes.as<int32_t>(),
                                                           c->d_u.as<float>(), c->d_ehist.as<float>() + slot);
+  SEMX_HIP(c, hipGetLastError());
+  return SEMX_OK;
+}
+
+int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep) {
+  const bool src = c->src.nsrc > 0 && c->d_ehist.p != nullptr;
+  const bool rec = record && c->rec.nrec > 0 && (dstep || (n >= 0 && n < c->rec.nt_max));
+  if (!src && !rec) return SEMX_OK;
+  const int nrb = rec ? c->rec.nrec : 0;
+  dim3 grid(nrb + (src ? 1 : 0), rec ? c->nmodels : 1);
+  const size_t per = (size_t)c->src.npts * c->ncomp;
+  step_aux_kernel<<<grid, kT, 0, c->stream>>>(
+      nrb, c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, n, dstep, c->rec.nodes.as<int32_t>(),
+      c->rec.wts.as<float>(), c->rec.seis.as<float>(), src ? 1 : 0, c->src.npts, c->src.nstf, c->energy_it0,
+      c->src.pts.as<int32_t>(), c->src.nodes.as<int32_t>(), c->src.wdir.as<float>(), c->src.stf.as<float>(),
+      c->d_ehist.as<float>(), per, with_corr ? 1 : 0, c->d_eacc.as<double>(), c->d_u.as<float>());
   SEMX_HIP(c, hipGetLastError());
   return SEMX_OK;
 }

@@ -314,6 +314,10 @@ int energy_reset(semx_ctx* c);
 int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f);
 // every step n after the Newmark pass (u holds u^{n+1})
 int energy_source_step(semx_ctx* c, int64_t n, bool with_corr, const int64_t* dstep = nullptr);
+// FP32 storage: energy_source_step and, with `record`, the receivers' sample
+// n (u^{n+1}), in one launch before the force pass (dstep: the device step
+// counter of graph-captured steps, else null).
+int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep = nullptr);
 int energy_read(semx_ctx* c, double* kin, double* pot, double* work);
 
 // fp64.hip: the FP64 storage path (state buffers hold doubles)
