@@ -242,7 +242,7 @@ def test_lame_mode_rayleigh_quotient(orc, n, tol):
     rq = -np.sum(u * f) / np.sum(M[:, None] * u * u)
     w2 = 2 * a * a * mu.flat[0] / rho.flat[0]
     assert abs(rq / w2 - 1.0) < tol
-    # frequency of cfg1's first Lame mode: m vs/(sqrt(2) L)
+    # frequency of the first Lame mode of the 4 km homogeneous cube: vs / (sqrt(2) L)
     assert abs(np.sqrt(w2) / (2 * np.pi) - 1732.0 / (np.sqrt(2) * L)) < 1e-12
 
 
