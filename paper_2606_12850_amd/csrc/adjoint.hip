@@ -422,12 +422,43 @@ __global__ void adj_source_kernel(int nrec, int n3, int64_t nt_max, int64_t m, i
 }
 
 // psi^m = 2 psi^{m+1} - psi^{m+2} + dt^2 M^{-1} fb;  fb = 0
+__device__ __forceinline__ float adj_entry(float p1, float p0, float dt2, float m, float f) {
+  return 2.0f * p1 - p0 + dt2 * m * f;
+}
+
 __global__ void adj_update_kernel(int64_t nnodes, float dt2, const float* __restrict__ minv,
                                   const float* __restrict__ p1, const float* __restrict__ p0,
                                   float* __restrict__ p2, float* __restrict__ fb) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 3 * nnodes;
        t += (int64_t)gridDim.x * blockDim.x) {
-    p2[t] = 2.0f * p1[t] - p0[t] + dt2 * minv[t / 3] * fb[t];
+    p2[t] = adj_entry(p1[t], p0[t], dt2, minv[t / 3], fb[t]);
+    fb[t] = 0.0f;
+  }
+}
+
+// The same with four consecutive entries per lane (16-byte accesses; every
+// array 16-byte aligned).  The last (3 nnodes) % 4 entries go to the first
+// lanes.
+typedef float adj_f4 __attribute__((ext_vector_type(4)));
+__global__ void adj_update4_kernel(int64_t nnodes, float dt2, const float* __restrict__ minv,
+                                   const float* __restrict__ p1, const float* __restrict__ p0,
+                                   float* __restrict__ p2, float* __restrict__ fb) {
+  const int64_t len = 3 * nnodes, len4 = len / 4;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t q = gid; q < len4; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t0 = 4 * q;
+    const adj_f4 a = *reinterpret_cast<const adj_f4*>(p1 + t0);
+    const adj_f4 b = *reinterpret_cast<const adj_f4*>(p0 + t0);
+    const adj_f4 f = *reinterpret_cast<const adj_f4*>(fb + t0);
+    adj_f4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = adj_entry(a[e], b[e], dt2, minv[(t0 + e) / 3], f[e]);
+    *reinterpret_cast<adj_f4*>(p2 + t0) = r;
+    *reinterpret_cast<adj_f4*>(fb + t0) = (adj_f4){0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  const int64_t t = 4 * len4 + gid;
+  if (t < len) {
+    p2[t] = adj_entry(p1[t], p0[t], dt2, minv[t / 3], fb[t]);
     fb[t] = 0.0f;
   }
 }
@@ -573,6 +604,10 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
                                       "model, sources or state)");
   const int64_t npt = (int64_t)c->nmodels * c->nspec * c->n3;
   const int64_t nn = (int64_t)c->nmodels * c->nglob;
+  // slots of the segment and psi buffers start on 16-byte boundaries (the
+  // update kernels' four-entry form); the padding stays zero
+  const int64_t lenp = (len + 3) / 4 * 4;
+  const size_t vbp = sizeof(float) * lenp;
 
   // buffers
   DevBuf saved, segu, sega, psi, fb, acc;
@@ -580,9 +615,9 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
     for (DevBuf* b : {&saved, &segu, &sega, &psi, &fb, &acc}) dev_free(*b);
   };
   int rc = dev_alloc(c, saved, 4 * vb);
-  if (!rc) rc = dev_alloc(c, segu, (K + 1) * vb);
-  if (!rc) rc = dev_alloc(c, sega, (K + 1) * vb);
-  if (!rc) rc = dev_alloc(c, psi, 3 * vb);
+  if (!rc) rc = dev_alloc(c, segu, (K + 1) * vbp);
+  if (!rc) rc = dev_alloc(c, sega, (K + 1) * vbp);
+  if (!rc) rc = dev_alloc(c, psi, 3 * vbp);
   if (!rc) rc = dev_alloc(c, fb, vb);
   if (!rc) rc = dev_alloc(c, acc, 3 * sizeof(double) * npt);
   if (rc) { cleanup(); return rc; }
@@ -594,11 +629,12 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
   if (!rc) rc = d2d(c, sv + vb, c->d_v.p, vb);
   if (!rc) rc = d2d(c, sv + 2 * vb, c->d_a.p, vb);
   if (!rc) rc = d2d(c, sv + 3 * vb, c->d_f.p, vb);
-  float* p[3] = {psi.as<float>(), psi.as<float>() + len, psi.as<float>() + 2 * len};
+  float* p[3] = {psi.as<float>(), psi.as<float>() + lenp, psi.as<float>() + 2 * lenp};
   double* kl = acc.as<double>();
   double* km = kl + npt;
   double* kr = km + npt;
-  if (!rc) rc = fill_zero(c, psi.as<float>(), 3 * len);
+  if (!rc) rc = fill_zero(c, psi.as<float>(), 3 * lenp);
+  if (!rc) rc = fill_zero(c, segu.as<float>(), (K + 1) * lenp);
   if (!rc) rc = fill_zero(c, fb.as<float>(), len);
   if (!rc) rc = fill_zero(c, acc.as<float>(), 6 * npt);  // 3 * npt doubles of zero bits
   if (rc) { cleanup(); return rc; }
@@ -653,12 +689,12 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
     float* su0 = segu.as<float>();
     float* sa0 = sega.as<float>();
     for (int64_t s = 1; s <= n1 - n0 && !rc; ++s)
-      rc = step_once(c, false, su0 + s * len, s >= 2 ? sa0 + (s - 1) * len : nullptr);
-    if (!rc) rc = complete_step(c, sa0 + (n1 - n0) * len);
+      rc = step_once(c, false, su0 + s * lenp, s >= 2 ? sa0 + (s - 1) * lenp : nullptr);
+    if (!rc) rc = complete_step(c, sa0 + (n1 - n0) * lenp);
     // normaliser of this segment's forward field
     if (!rc) {
       float umax = 0.0f;
-      rc = max_abs(c, segu.as<float>(), (n1 - n0 + 1) * len, dword, &umax);
+      rc = max_abs(c, segu.as<float>(), (n1 - n0 + 1) * lenp, dword, &umax);
       if (!rc) rc = fill_zero(c, fb.as<float>(), len);
       su = pow2_normaliser(umax);
       A.uscale = su;
@@ -668,8 +704,8 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
     for (int64_t m = n1; m >= n0 + 1 && !rc; --m) {
       if (m <= nt - 1) {
         A.fa.u = p[i1];
-        A.um = segu.as<float>() + (m - n0) * len;
-        A.am = sega.as<float>() + (m - n0) * len;
+        A.um = segu.as<float>() + (m - n0) * lenp;
+        A.am = sega.as<float>() + (m - n0) * lenp;
         for (const auto& L : launches) {
           A.fa.pos0 = L.pos0;
           A.fa.count = L.count;
@@ -683,8 +719,8 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
       adj_source_kernel<<<grid_1d(total), 256, 0, c->stream>>>(
           c->rec.nrec, c->n3, c->rec.nt_max, m - 1, c->nmodels, c->nglob, sg / (dt * dt),
           c->rec.nodes.as<int32_t>(), c->rec.wts.as<float>(), gseis_dev, fb.as<float>());
-      adj_update_kernel<<<grid_1d(3 * nn), 256, 0, c->stream>>>(nn, dt * dt, c->d_minv.as<float>(), p[i1], p[i0],
-                                                                p[i2], fb.as<float>());
+      adj_update4_kernel<<<grid_1d((3 * nn + 3) / 4), 256, 0, c->stream>>>(nn, dt * dt, c->d_minv.as<float>(),
+                                                                           p[i1], p[i0], p[i2], fb.as<float>());
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) { rc = hip_fail(c, e, "adjoint update"); break; }
       const int t = i0;
@@ -697,7 +733,7 @@ int semx_adjoint(semx_ctx* c, const float* gseis_dev, int64_t nt, double* g_lamb
     // start-up term with psi^1 (p[i1]) and u^1 (segment 0, slot 1)
     adj_rho_start_kernel<<<grid_1d(npt), 256, 0, c->stream>>>(c->n3, c->nspec, c->nmodels, c->nglob,
                                                               c->d_ibool.as<int32_t>(), c->d_wdet.as<double>(),
-                                                              p[i1], segu.as<float>() + len, su, 1.0 / (double)su, kr);
+                                                              p[i1], segu.as<float>() + lenp, su, 1.0 / (double)su, kr);
     unpermute_kernel<<<grid_1d(npt), 256, 0, c->stream>>>(c->n3, c->nspec, c->nmodels, c->d_order.as<int32_t>(), kl,
                                                           1.0 / (double)sg, g_lambda_dev);
     unpermute_kernel<<<grid_1d(npt), 256, 0, c->stream>>>(c->n3, c->nspec, c->nmodels, c->d_order.as<int32_t>(), km,
