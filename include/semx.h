@@ -93,7 +93,8 @@ const char *semx_last_error(const semx_ctx *ctx);
  * (affine map: Gamma constant) or irregular, and colours the elements by
  * greedy first-fit in element order so that no two elements of a colour share
  * a global node.  Returns SEMX_EGEOM if det J <= 0 anywhere.  Invalidates any
- * uploaded model and time-loop state. */
+ * uploaded model and time-loop state, and removes the sources and receivers
+ * (they are placed in elements of the previous mesh). */
 int semx_upload_mesh(semx_ctx *ctx, int64_t nspec, int64_t nglob, const int32_t *ibool,
                      int64_t nvert, const double *vert_xyz, const int32_t *elem_vert);
 

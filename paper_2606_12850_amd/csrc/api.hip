@@ -577,6 +577,8 @@ int build_blocks(semx_ctx* c, const std::vector<int32_t>& pos_of, const std::vec
   c->nblocks = 0;
   c->block_launches.clear();
   for (DevBuf* b : {&c->d_bpos, &c->d_baff, &c->d_bfirst}) dev_free(*b);
+  c->h_baff.clear();
+  c->h_bfirst.clear();
   const int n = c->n;
   const int64_t nspec = c->nspec;
   if (n < 2 || n > kBlockMaxN || c->ncolors == 0 || nspec % 8 != 0) return SEMX_OK;
@@ -691,6 +693,8 @@ int build_blocks(semx_ctx* c, const std::vector<int32_t>& pos_of, const std::vec
   SEMX_HIP(c, hipMemcpy(c->d_bpos.p, bpos.data(), sizeof(int32_t) * bpos.size(), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_baff.p, baff.data(), sizeof(int32_t) * baff.size(), hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_bfirst.p, bfirst.data(), sizeof(uint32_t) * bfirst.size(), hipMemcpyHostToDevice));
+  c->h_baff = std::move(baff);
+  c->h_bfirst = std::move(bfirst);
   c->nblocks = nb;
   c->blocks_irregular = c->h_regular[0] == 0;
   return SEMX_OK;
@@ -839,6 +843,8 @@ int build_layout(semx_ctx* c) {
   SEMX_HIP(c, hipMemcpy(c->d_aff.p, affpos.data(), sizeof(int32_t) * 4 * nspec, hipMemcpyHostToDevice));
   if (!first.empty())
     SEMX_HIP(c, hipMemcpy(c->d_first.p, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
+  c->h_first = std::move(first);
+  c->first_tl_dirty = true;
   SEMX_HIP(c, hipMemcpy(c->d_gam_el.p, gel.data(), sizeof(float) * 9 * nspec, hipMemcpyHostToDevice));
   SEMX_HIP(c, hipMemcpy(c->d_tri.p, tri.data(), sizeof(float) * 24 * nspec, hipMemcpyHostToDevice));
   {
@@ -912,9 +918,14 @@ ForceArgs force_args(const semx_ctx* c, const float* u, float* f, bool first_tou
 // launched nchunks times on the context's stream, the counter set from the
 // host index before each launch.  The captured steps are the ones
 // step_once would launch directly: bitwise the same results.
+bool prestores(const semx_ctx* c);
+int build_first_tl(semx_ctx* c);
+
 int run_graph_chunks(semx_ctx* c, int64_t nchunks, int64_t G) {
   int rc = SEMX_OK;
-  if (!c->d_step.p) rc = dev_alloc(c, c->d_step, sizeof(int64_t));
+  // nothing may allocate or copy synchronously inside the capture
+  if (prestores(c) && c->first_tl_dirty) rc = build_first_tl(c);
+  if (!rc && !c->d_step.p) rc = dev_alloc(c, c->d_step, sizeof(int64_t));
   if (rc) return rc;
   if (!c->cap_stream) SEMX_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   int64_t* dstep = c->d_step.as<int64_t>();
@@ -934,11 +945,11 @@ int run_graph_chunks(semx_ctx* c, int64_t nchunks, int64_t G) {
   c->it = it0;  // the capture ran nothing
   c->pending_correct = pend0;
   if (rc || e_end != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc ? rc : hip_fail(c, e_end, "time-loop graph capture");
   }
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_fail(c, e, "time-loop graph instantiate");
   for (int64_t k = 0; k < nchunks && e == hipSuccess; ++k) {
     step_set_kernel<<<1, 1, 0, c->stream>>>(dstep, c->it);
@@ -969,8 +980,12 @@ bool blocks_active(const semx_ctx* c) {
   return c->blocks_mode == SEMX_BLOCKS_ON || (c->blocks_irregular && c->irregular_geo == kStored);
 }
 
-int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false, bool f_zero = false) {
+// `tl`: the time loop's pass after the source force was stored into f
+// (prestores()): the first-touch bits with the source nodes cleared.
+int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = false, bool f_zero = false,
+                     bool tl = false) {
   ForceArgs a = force_args(c, u, f, first_touch);
+  if (tl && a.first) a.first = c->d_first_tl.as<uint32_t>();
   const bool atomic = c->assembly == SEMX_ASM_ATOMIC;
   a.excl_interior = atomic && f_zero && c->interior_exclusive ? 1 : 0;
   if (blocks_active(c)) {
@@ -981,8 +996,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     }
     const int geo = c->blocks_irregular ? c->irregular_geo : kRegular;
     for (const auto& L : c->block_launches) {
-      const BlockArgs b{c->d_bpos.as<int32_t>(), c->d_baff.as<int32_t>(),
-                        first_touch ? c->d_bfirst.as<uint32_t>() : nullptr, L.pos0, L.count};
+      const uint32_t* bf = !first_touch ? nullptr : tl ? c->d_bfirst_tl.as<uint32_t>() : c->d_bfirst.as<uint32_t>();
+      const BlockArgs b{c->d_bpos.as<int32_t>(), c->d_baff.as<int32_t>(), bf, L.pos0, L.count};
       const hipError_t e = launch_force_block(c->n, geo, a, b, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
     }
@@ -1049,13 +1064,65 @@ bool force_overwrites(const semx_ctx* c) {
   return c->assembly == SEMX_ASM_COLORED && c->elem_cover && c->d_first.p != nullptr;
 }
 
-// f = -K u.  `f_zeroed`: f already holds zeros.
-int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed) {
+// f = -K u.  `f_zeroed`: f already holds zeros.  `tl`: see force_accumulate.
+int force_into(semx_ctx* c, const float* u, float* f, bool f_zeroed, bool tl = false) {
   if (!f_zeroed && !force_overwrites(c)) {
     int rc = zero_f32(c, f, state_len(c));
     if (rc) return rc;
   }
-  return force_accumulate(c, u, f, force_overwrites(c), !force_overwrites(c));
+  return force_accumulate(c, u, f, force_overwrites(c), !force_overwrites(c), tl);
+}
+
+// The time loop stores the source force into f before the force pass (in
+// the bookkeeping launch) when the pass overwrites every node with
+// first-touch stores: the source nodes' first touch then reads and adds to
+// it, and no injection launch follows the pass.
+bool prestores(const semx_ctx* c) { return c->src.nsrc > 0 && c->src.nsn > 0 && force_overwrites(c); }
+
+// The time loop's first-touch bits: the bit of each source node's first
+// touch (in launch order) cleared, per element and per block.
+int build_first_tl(semx_ctx* c) {
+  std::vector<uint8_t> src(c->nglob, 0);
+  for (int32_t g : c->h_src_nodes)
+    if (g < 0 || g >= c->nglob) return fail(c, SEMX_ESTATE, "sources do not belong to the current mesh");
+  const int n3 = c->n3, fw = c->first_words;
+  if (!c->h_first.empty()) {
+    for (int32_t g : c->h_src_nodes) src[g] = 1;
+    std::vector<uint32_t> bits = c->h_first;
+    for (const auto& L : c->colored_launches)
+      for (int64_t pos = L.pos0; pos < L.pos0 + L.count; ++pos) {
+        const int32_t* ib = &c->h_ibool[(size_t)c->h_order[pos] * n3];
+        for (int q = 0; q < n3; ++q)
+          if (src[ib[q]] == 1) {
+            src[ib[q]] = 0;
+            bits[pos * fw + q / 32] &= ~(1u << (q % 32));
+          }
+      }
+    int rc = dev_alloc(c, c->d_first_tl, sizeof(uint32_t) * bits.size());
+    if (rc) return rc;
+    SEMX_HIP(c, hipMemcpy(c->d_first_tl.p, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice));
+  }
+  if (c->nblocks > 0 && !c->h_bfirst.empty()) {
+    for (int32_t g : c->h_src_nodes) src[g] = 1;
+    const int nb1 = 2 * c->n - 1, nbn = nb1 * nb1 * nb1, nwb = (nbn + 31) / 32;
+    std::vector<uint32_t> bits = c->h_bfirst;
+    for (int64_t t = 0; t < c->nblocks; ++t) {
+      const int32_t* r = &c->h_baff[t * 4];
+      for (int q = 0; q < nbn; ++q) {
+        const int64_t g = r[0] + (int64_t)(q % nb1) * r[1] + (int64_t)((q / nb1) % nb1) * r[2] +
+                          (int64_t)(q / (nb1 * nb1)) * r[3];
+        if (src[g] == 1) {
+          src[g] = 0;
+          bits[t * nwb + q / 32] &= ~(1u << (q % 32));
+        }
+      }
+    }
+    int rc = dev_alloc(c, c->d_bfirst_tl, sizeof(uint32_t) * bits.size());
+    if (rc) return rc;
+    SEMX_HIP(c, hipMemcpy(c->d_bfirst_tl.p, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice));
+  }
+  c->first_tl_dirty = false;
+  return SEMX_OK;
 }
 
 
@@ -1165,13 +1232,16 @@ int step_once(semx_ctx* c, bool record, float* seg_u, float* seg_a, const int64_
     int rc = energy_track(c, f_pe, src_in_f);
     if (rc) return rc;
   }
-  // source work and receivers read u^{n+1}, which the force pass leaves alone
-  int rc = step_aux(c, c->it, track && src_in_f, record, dstep);
+  // source work and receivers read u^{n+1}, which the force pass leaves
+  // alone; with prestores() the same launch stores f_src^{n+1} into f
+  const bool pre = prestores(c);
+  int rc = pre && c->first_tl_dirty ? build_first_tl(c) : SEMX_OK;
+  if (!rc) rc = step_aux(c, c->it, track && src_in_f, record, dstep, pre);
   if (rc) return rc;
   // f is zero here only if the Newmark pass cleared it (untracked step on a
   // mesh the force pass does not overwrite)
-  rc = force_into(c, u, f, !track && !force_overwrites(c));
-  if (!rc) rc = inject_sources(c, c->it + 1, f, dstep);
+  rc = force_into(c, u, f, !track && !force_overwrites(c), pre);
+  if (!rc && !pre) rc = inject_sources(c, c->it + 1, f, dstep);
   if (rc) return rc;
   if (dstep) {
     step_incr_kernel<<<1, 1, 0, c->stream>>>(const_cast<int64_t*>(dstep));
@@ -1196,6 +1266,8 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
   if (nsrc == 0) {
     c->src.nsrc = 0;
     c->src.nsn = 0;
+    c->h_src_nodes.clear();
+    c->first_tl_dirty = true;
     c->run_gen++;
     c->ckpt_count = 0;
     return c->have_model && c->d_u.p ? energy_reset(c) : SEMX_OK;
@@ -1259,6 +1331,8 @@ int set_sources_impl(semx_ctx* c, int nsrc, const int32_t* elem, const double* x
     if (k == 0 || np_pairs[k].first != np_pairs[k - 1].first) snode.push_back(np_pairs[k].first);
     sidx.push_back(np_pairs[k].second);
   }
+  c->h_src_nodes = snode;
+  c->first_tl_dirty = true;
   sptr.push_back((int32_t)np_pairs.size());
   if (sidx.empty()) sidx.push_back(0);
   int rc = dev_alloc(c, c->src.nodes, nodes.size() * sizeof(int32_t));
@@ -1348,8 +1422,8 @@ int semx_destroy(semx_ctx* c) {
   else (void)hipDeviceSynchronize();
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   for (DevBuf& b : c->ckpts) dev_free(b);
-  for (DevBuf* b : {&c->d_bpos, &c->d_baff, &c->d_bfirst, &c->d_step}) dev_free(*b);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (DevBuf* b : {&c->d_bpos, &c->d_baff, &c->d_bfirst, &c->d_step, &c->d_first_tl, &c->d_bfirst_tl}) dev_free(*b);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
   for (DevBuf* b : {&c->d_D, &c->d_Dh, &c->d_xi64, &c->d_w64, &c->d_ibool, &c->d_vert, &c->d_elem_vert,
                     &c->d_gam_pt, &c->d_gam_el, &c->d_tri, &c->d_xi32, &c->d_wdet, &c->d_order, &c->d_mat, &c->d_minv,
@@ -1387,6 +1461,11 @@ int semx_upload_mesh(semx_ctx* c, int64_t nspec, int64_t nglob, const int32_t* i
   int rc = set_device(c);
   if (rc) return rc;
   c->have_mesh = c->have_model = false;
+  // sources and receivers live in elements of the previous mesh
+  c->src.nsrc = 0;
+  c->src.nsn = 0;
+  c->h_src_nodes.clear();
+  c->rec.nrec = 0;
   c->nspec = nspec;
   c->nglob = nglob;
   c->nvert = nvert;

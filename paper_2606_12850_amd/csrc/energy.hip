@@ -160,11 +160,27 @@ __device__ __forceinline__ void receiver_block(int r, int model, int nrec, int n
     seis[(((int64_t)model * nrec + r) * nc + threadIdx.x) * nt_max + it] = red[threadIdx.x][0];
 }
 
-// The per-step bookkeeping that reads u^{n+1} (FP32 storage), one launch
+// The source force of sample m stored at the source nodes (all models): one
+// thread per (model, source node, component) sums the (source, point) pairs
+// that reach the node in a fixed order, as the injection after a force pass
+// does, and stores the sum.
+struct Prestore {
+  int nsn;                    // source nodes; 0: nothing to store
+  const int32_t* snode;       // [nsn] node numbers
+  const int32_t* sptr;        // [nsn + 1]
+  const int32_t* sidx;        // the points s n3 + q of each node
+  float* f;                   // [nmodels][nglob][nc]
+  int nmodels;
+};
+
+// The per-step bookkeeping before the force pass (FP32 storage), one launch
 // after the Newmark pass: blocks x < nrec_blocks record receiver x of model
 // y (sample it, or *step for graph-captured steps; nothing outside
 // [0, nt_max)); block x = nrec_blocks of row y = 0, when `src` is set, is
-// source_energy_block.  The force pass that follows writes only f.
+// source_energy_block; the blocks after it in row 0 store the source force
+// of sample it + 1 (P.nsn > 0).  All of them read u^{n+1}, which the force
+// pass that follows leaves alone; the stores to f touch only source nodes,
+// which nothing else in the launch reads.
 __global__ __launch_bounds__(kT) void step_aux_kernel(int nrec_blocks, int nrec, int n3, int nc, int64_t nglob,
                                                       int64_t nt_max, int64_t it, const int64_t* step,
                                                       const int32_t* __restrict__ rnodes,
@@ -174,7 +190,8 @@ __global__ __launch_bounds__(kT) void step_aux_kernel(int nrec_blocks, int nrec,
                                                       const int32_t* __restrict__ snodes,
                                                       const float* __restrict__ wdir, const float* __restrict__ stf,
                                                       float* hist, size_t per, int with_corr,
-                                                      double* __restrict__ acc, const float* __restrict__ u) {
+                                                      double* __restrict__ acc, const float* __restrict__ u,
+                                                      Prestore P) {
   __shared__ float rred[3][kT];
   __shared__ double ered[kT];
   if ((int)blockIdx.x < nrec_blocks) {
@@ -183,9 +200,25 @@ __global__ __launch_bounds__(kT) void step_aux_kernel(int nrec_blocks, int nrec,
     receiver_block(blockIdx.x, blockIdx.y, nrec, n3, nc, nglob, nt_max, it, rnodes, rwts, u, seis, rred);
     return;
   }
-  if (!src || blockIdx.y != 0) return;
-  source_energy_block<float>(npt, n3, nc, nstf, it, step, it0, pts, snodes, wdir, stf, u, hist, per, with_corr, acc,
-                             ered);
+  if (blockIdx.y != 0) return;
+  if (src && (int)blockIdx.x == nrec_blocks) {
+    source_energy_block<float>(npt, n3, nc, nstf, it, step, it0, pts, snodes, wdir, stf, u, hist, per, with_corr,
+                               acc, ered);
+    return;
+  }
+  const int64_t m = (step ? *step : it) + 1;
+  const int64_t per_m = (int64_t)P.nsn * nc;
+  const int64_t t = ((int64_t)blockIdx.x - nrec_blocks - src) * kT + threadIdx.x;
+  if (t >= P.nmodels * per_m) return;
+  const int64_t r = t % per_m;
+  const int i = (int)(r / nc), cc = (int)(r % nc);
+  float sum = 0.0f;
+  for (int k = P.sptr[i]; k < P.sptr[i + 1]; ++k) {
+    const int p = P.sidx[k];
+    const float amp = (m >= 0 && m < nstf) ? stf[(int64_t)(p / n3) * nstf + m] : 0.0f;
+    sum += amp * wdir[(int64_t)nc * p + cc];
+  }
+  P.f[((t / per_m) * nglob + P.snode[i]) * nc + cc] = sum;
 }
 
 // u at the source points (model 0) into hist (at a reset or a new state).
@@ -254,18 +287,26 @@ int energy_reset(semx_ctx* c) {
   return SEMX_OK;
 }
 
-int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep) {
+int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep, bool prestore) {
   const bool src = c->src.nsrc > 0 && c->d_ehist.p != nullptr;
   const bool rec = record && c->rec.nrec > 0 && (dstep || (n >= 0 && n < c->rec.nt_max));
-  if (!src && !rec) return SEMX_OK;
+  const bool pre = prestore && c->src.nsrc > 0 && c->src.nsn > 0;
+  if (!src && !rec && !pre) return SEMX_OK;
   const int nrb = rec ? c->rec.nrec : 0;
-  dim3 grid(nrb + (src ? 1 : 0), rec ? c->nmodels : 1);
+  Prestore P{};
+  int npb = 0;
+  if (pre) {
+    P = {c->src.nsn, c->src.snode.as<int32_t>(), c->src.sptr.as<int32_t>(), c->src.sidx.as<int32_t>(),
+         c->d_f.as<float>(), c->nmodels};
+    npb = (int)(((int64_t)c->nmodels * c->src.nsn * c->ncomp + kT - 1) / kT);
+  }
+  dim3 grid(nrb + (src ? 1 : 0) + npb, rec ? c->nmodels : 1);
   const size_t per = (size_t)c->src.npts * c->ncomp;
   step_aux_kernel<<<grid, kT, 0, c->stream>>>(
       nrb, c->rec.nrec, c->n3, c->ncomp, c->nglob, c->rec.nt_max, n, dstep, c->rec.nodes.as<int32_t>(),
       c->rec.wts.as<float>(), c->rec.seis.as<float>(), src ? 1 : 0, c->src.npts, c->src.nstf, c->energy_it0,
       c->src.pts.as<int32_t>(), c->src.nodes.as<int32_t>(), c->src.wdir.as<float>(), c->src.stf.as<float>(),
-      c->d_ehist.as<float>(), per, with_corr ? 1 : 0, c->d_eacc.as<double>(), c->d_u.as<float>());
+      c->d_ehist.as<float>(), per, with_corr ? 1 : 0, c->d_eacc.as<double>(), c->d_u.as<float>(), P);
   SEMX_HIP(c, hipGetLastError());
   return SEMX_OK;
 }

@@ -123,6 +123,14 @@ struct semx_ctx {
   // first to reach its node; elem_cover = every node is reached by an element
   semx::DevBuf d_first;
   int first_words = 0;
+  std::vector<uint32_t> h_first;     // host copy of d_first
+  // the time loop's first-touch bits (per element and per block): the same
+  // with the bit of every node that receives a source force cleared, so the
+  // pass adds to the source force stored there before it (built when the
+  // sources or the mesh change)
+  semx::DevBuf d_first_tl, d_bfirst_tl;
+  bool first_tl_dirty = true;
+  std::vector<int32_t> h_src_nodes;  // nodes with a source force (FP32 weights), ascending
   bool elem_cover = false;
   // every element-interior GLL point (local indices 1..n-2 in all three
   // directions) is the only reference to its node, as in any conforming mesh:
@@ -142,6 +150,8 @@ struct semx_ctx {
   int blocks_mode = 1;                         // semx_set_blocks (SEMX_BLOCKS_AUTO)
   std::vector<semx::Launch> block_launches;    // per block colour: a range of the block tables
   semx::DevBuf d_bpos, d_baff, d_bfirst;
+  std::vector<int32_t> h_baff;     // host copies of d_baff and d_bfirst
+  std::vector<uint32_t> h_bfirst;
 
   // model
   bool have_model = false;
@@ -316,8 +326,11 @@ int energy_track(semx_ctx* c, const void* f_pe, bool source_in_f);
 int energy_source_step(semx_ctx* c, int64_t n, bool with_corr, const int64_t* dstep = nullptr);
 // FP32 storage: energy_source_step and, with `record`, the receivers' sample
 // n (u^{n+1}), in one launch before the force pass (dstep: the device step
-// counter of graph-captured steps, else null).
-int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep = nullptr);
+// counter of graph-captured steps, else null).  `prestore`: the same launch
+// also stores the source force of sample n + 1 into f at the source nodes
+// (the force pass then adds to it, through the time-loop first-touch bits).
+int step_aux(semx_ctx* c, int64_t n, bool with_corr, bool record, const int64_t* dstep = nullptr,
+             bool prestore = false);
 int energy_read(semx_ctx* c, double* kin, double* pot, double* work);
 
 // fp64.hip: the FP64 storage path (state buffers hold doubles)
