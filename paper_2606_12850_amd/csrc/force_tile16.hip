@@ -34,6 +34,11 @@
 //
 // Assembly as in the other element kernels: read-modify-write inside a
 // colour (first-touch stores when the launch carries them) or FP32 atomics.
+//
+// NC = 1 runs the scalar (acoustic) operator on the same tiles: one field
+// component (three forward and three transpose products per element), the
+// flux Phi_d = (W / rho) sum_b g_b Gamma_db from the first half of the
+// material table, and a third of the LDS.
 #include <algorithm>
 
 #include "elem_common.hpp"
@@ -172,7 +177,7 @@ __device__ __forceinline__ void load_mat(const ForceArgs& a, int model, int pos,
   }
 }
 
-template <int NG, bool ATOMIC, bool AFF, bool MAT>
+template <int NG, bool ATOMIC, bool AFF, bool MAT, int NC = 3>
 __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __restrict__ u, int model, int pos,
                                            const OwnPts<NG>& P, int g, int c, int w, Ahead& h) {
   constexpr int E3 = NG * NG * NG;
@@ -209,7 +214,7 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
     h.uo[0][t] = h.uo[1][t] = h.uo[2][t] = 0.0f;
     if (P.real(t)) {
 #pragma unroll
-      for (int e = 0; e < 3; ++e) h.uo[e][t] = u[3 * (size_t)h.node[t] + e];
+      for (int e = 0; e < NC; ++e) h.uo[e][t] = u[NC * (size_t)h.node[t] + e];
     }
   }
   if constexpr (MAT) load_mat<NG>(a, model, pos, P, h);
@@ -225,8 +230,9 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
 // one element per workgroup, its loads requested at its start.  Inside a colour the prior f
 // at the element's nodes is read at the start of its arithmetic (no other
 // workgroup of the launch touches those nodes).
-template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC>
+template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
 __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
+  static_assert(NC == 3 || PREC == SEMX_C_F32, "the scalar (acoustic) operator runs in FP32");
   constexpr int E3 = NG * NG * NG;
   // persistent, next element requested ahead (regular path, unpadded tiles)
   constexpr bool AHEAD = GEO == kRegular && NG == kN;
@@ -236,9 +242,9 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   constexpr bool SCALE = PREC == SEMX_C_F16;  // BF16 has the FP32 exponent range
   using L = Low<PREC>;
   using lvec = typename L::vec;
-  __shared__ __attribute__((aligned(16))) float r0[3 * kN3];
-  __shared__ __attribute__((aligned(16))) float r1[3 * kN3];
-  __shared__ __attribute__((aligned(16))) float r2[3 * kN3];
+  __shared__ __attribute__((aligned(16))) float r0[NC * kN3];
+  __shared__ __attribute__((aligned(16))) float r1[NC * kN3];
+  __shared__ __attribute__((aligned(16))) float r2[NC * kN3];
   __shared__ float s_red[2][kWaves];  // FP16: per-wave maxima of the operands
 
   const int ngrp = (int)a.count;
@@ -253,8 +259,8 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   const int l = threadIdx.x & 63;
   const int g = l >> 4, c = l & 15;
   const int model = blockIdx.y;
-  const float* __restrict__ u = a.u + (size_t)model * a.nglob * 3;
-  float* f = a.f + (size_t)model * a.nglob * 3;
+  const float* __restrict__ u = a.u + (size_t)model * a.nglob * NC;
+  float* f = a.f + (size_t)model * a.nglob * NC;
   const OwnPts<NG> P(g, c, w);          // own points (S layout)
   const int sS = lds_at(4 * g, c, w);  // first of the 4 contiguous LDS words of the own points
 
@@ -278,20 +284,19 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   }
 
   Ahead cur;
-  if constexpr (AHEAD) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + grp, P, g, c, w, cur);
+  if constexpr (AHEAD) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD, NC>(a, u, model, (int)a.pos0 + grp, P, g, c, w, cur);
   for (;;) {
     const int pos = (int)a.pos0 + grp;
-    if constexpr (!AHEAD) load_ahead<NG, ATOMIC, AFF, true>(a, u, model, pos, P, g, c, w, cur);
+    if constexpr (!AHEAD) load_ahead<NG, ATOMIC, AFF, true, NC>(a, u, model, pos, P, g, c, w, cur);
     if constexpr (AHEAD && !MAT_AHEAD) load_mat<NG>(a, model, pos, P, cur);
     float fo[3][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       fo[0][t] = fo[1][t] = fo[2][t] = 0.0f;
-      if (!ATOMIC && P.real(t) && !((cur.fw >> t) & 1u)) {  // the point's three values in one request
-        const float* fp = f + 3 * (size_t)cur.node[t];
-        fo[0][t] = fp[0];
-        fo[1][t] = fp[1];
-        fo[2][t] = fp[2];
+      if (!ATOMIC && P.real(t) && !((cur.fw >> t) & 1u)) {  // the point's values in one request
+        const float* fp = f + NC * (size_t)cur.node[t];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) fo[e][t] = fp[e];
       }
     }
     float u0[3] = {0.f, 0.f, 0.f};  // 16-bit operands: u at local point (0,0,0), their offset
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
         for (int t = 0; t < 4; ++t) cur.uo[e][t] = P.real(t) ? cur.uo[e][t] - u0[e] : 0.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e)
+    for (int e = 0; e < NC; ++e)
       st4(r0 + e * kN3 + sS, f32x4{cur.uo[e][0], cur.uo[e][1], cur.uo[e][2], cur.uo[e][3]});
     if constexpr (SCALE) {  // largest |u - u0| of the element, per wave
       float um = 0.0f;
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     __syncthreads();  // B1: u in R0
 
     // ---- forward contractions ----
-    f32x4 dx[3], dy[3];
+    f32x4 dx[NC], dy[NC];
     float su = 1.0f, isu = 1.0f;
     if constexpr (SCALE) {
       float m = 0.0f;
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       isu = uniform(1.0f / su);
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
+    for (int e = 0; e < NC; ++e) {
       f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f}, z = {0.f, 0.f, 0.f, 0.f};
       if constexpr (LOW) {
         // operands (u - u0) su: a rigid translation gives exactly zero
@@ -363,9 +368,9 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       for (int t = 0; t < 4; ++t) r1[e * kN3 + lds_at(c, w, 4 * g + t)] = z[t];
     }
     __syncthreads();  // B2: zeta derivatives in R1; R0 free
-    f32x4 dz[3];
+    f32x4 dz[NC];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) dz[e] = ld4(r1 + e * kN3 + sS);
+    for (int e = 0; e < NC; ++e) dz[e] = ld4(r1 + e * kN3 + sS);
 
     // ---- pointwise: geometry map, stress, weighted fluxes ----
     const float* src = nullptr;
@@ -384,16 +389,9 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
         }
       }
     }
-    f32x4 p0[3], p1[3], p2[3];
+    f32x4 p0[NC], p1[NC], p2[NC];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      float du[3][3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        du[e][0] = dx[e][t];
-        du[e][1] = dy[e][t];
-        du[e][2] = dz[e][t];
-      }
       float G[9];
       if constexpr (GEO == kStored) {
 #pragma unroll
@@ -402,30 +400,50 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       const float rx = (GEO == kTrilinear) ? a.xi[min(4 * g + t, NG - 1)] : 0.f;
       float Mg[9], scale, det;
       geom_map_from<GEO>(src, G, rx, ry, rz, Mg, scale, det);
-      float gr[3][3];
-      apply_map(du, Mg, gr);
-      const float lw = cur.lam4[t], mw = cur.mu4[t];
-      const float ltr = lw * (gr[0][0] + gr[1][1] + gr[2][2]);
-      float sg[3][3];
-      sg[0][0] = ltr + 2.0f * mw * gr[0][0];
-      sg[1][1] = ltr + 2.0f * mw * gr[1][1];
-      sg[2][2] = ltr + 2.0f * mw * gr[2][2];
-      sg[0][1] = sg[1][0] = mw * (gr[0][1] + gr[1][0]);
-      sg[0][2] = sg[2][0] = mw * (gr[0][2] + gr[2][0]);
-      sg[1][2] = sg[2][1] = mw * (gr[1][2] + gr[2][1]);
+      if constexpr (NC == 1) {
+        // scalar operator: physical gradient times det' (Mg), then the
+        // weighted flux phi_d = (W / rho) scale sum_b g_b Mg[d][b]
+        const float dr[3] = {dx[0][t], dy[0][t], dz[0][t]};
+        float gs[3];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        float ph[3];
+        for (int b = 0; b < 3; ++b) gs[b] = dr[0] * Mg[0 * 3 + b] + dr[1] * Mg[1 * 3 + b] + dr[2] * Mg[2 * 3 + b];
+        const float sw = cur.lam4[t] * scale;
+        p0[0][t] = sw * (gs[0] * Mg[0] + gs[1] * Mg[1] + gs[2] * Mg[2]);
+        p1[0][t] = sw * (gs[0] * Mg[3] + gs[1] * Mg[4] + gs[2] * Mg[5]);
+        p2[0][t] = sw * (gs[0] * Mg[6] + gs[1] * Mg[7] + gs[2] * Mg[8]);
+      } else {
+        float du[3][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          ph[d] = scale * (sg[e][0] * Mg[d * 3 + 0] + sg[e][1] * Mg[d * 3 + 1] + sg[e][2] * Mg[d * 3 + 2]);
-        p0[e][t] = ph[0];
-        p1[e][t] = ph[1];
-        p2[e][t] = ph[2];
+        for (int e = 0; e < 3; ++e) {
+          du[e][0] = dx[e][t];
+          du[e][1] = dy[e][t];
+          du[e][2] = dz[e][t];
+        }
+        float gr[3][3];
+        apply_map(du, Mg, gr);
+        const float lw = cur.lam4[t], mw = cur.mu4[t];
+        const float ltr = lw * (gr[0][0] + gr[1][1] + gr[2][2]);
+        float sg[3][3];
+        sg[0][0] = ltr + 2.0f * mw * gr[0][0];
+        sg[1][1] = ltr + 2.0f * mw * gr[1][1];
+        sg[2][2] = ltr + 2.0f * mw * gr[2][2];
+        sg[0][1] = sg[1][0] = mw * (gr[0][1] + gr[1][0]);
+        sg[0][2] = sg[2][0] = mw * (gr[0][2] + gr[2][0]);
+        sg[1][2] = sg[2][1] = mw * (gr[1][2] + gr[2][1]);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          float ph[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            ph[d] = scale * (sg[e][0] * Mg[d * 3 + 0] + sg[e][1] * Mg[d * 3 + 1] + sg[e][2] * Mg[d * 3 + 2]);
+          p0[e][t] = ph[0];
+          p1[e][t] = ph[1];
+          p2[e][t] = ph[2];
+        }
       }
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
+    for (int e = 0; e < NC; ++e) {
       st4(r0 + e * kN3 + sS, p1[e]);
       st4(r2 + e * kN3 + sS, p2[e]);
     }
@@ -434,7 +452,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     // (the eta operand read back from LDS was written by this wave), so
     // 16-bit operands take a per-wave scale there; the zeta operand crosses
     // waves and takes the element's.
-    f32x4 F[3];
+    f32x4 F[NC];
     float sqw = 1.0f, isqw = 1.0f;
     if constexpr (SCALE) {
       float qm = 0.0f, zm = 0.0f;
@@ -451,7 +469,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       if (l == 0) s_red[1][w] = zm;
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
+    for (int e = 0; e < NC; ++e) {
       f32x4 x = {0.f, 0.f, 0.f, 0.f};
       if constexpr (LOW) {
         x = L::mma(Dt16, pack4<PREC>(p0[e][0] * sqw, p0[e][1] * sqw, p0[e][2] * sqw, p0[e][3] * sqw), x);
@@ -465,7 +483,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     const bool more = AHEAD && nxt < xend;  // uniform over the block
     Ahead ahead;
     if constexpr (AHEAD) {
-      if (more) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD>(a, u, model, (int)a.pos0 + nxt, P, g, c, w, ahead);
+      if (more) load_ahead<NG, ATOMIC, AFF, MAT_AHEAD, NC>(a, u, model, (int)a.pos0 + nxt, P, g, c, w, ahead);
     }
     __syncthreads();  // B3: eta fluxes in R0, zeta fluxes in R2; R1 free
     if constexpr (LOW) {
@@ -495,7 +513,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
+      for (int e = 0; e < NC; ++e) {
         f32x4 x = F[e], z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -509,21 +527,17 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     }
     __syncthreads();  // B4: zeta transpose result in R1 (R0, R2 free for the next element)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) F[e] += ld4(r1 + e * kN3 + sS);
+    for (int e = 0; e < NC; ++e) F[e] += ld4(r1 + e * kN3 + sS);
 
     // ---- assembly ----
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (!P.real(t)) continue;
-      float* fg = f + 3 * (size_t)cur.node[t];
-      if constexpr (ATOMIC) {
-        unsafeAtomicAdd(fg + 0, -F[0][t]);
-        unsafeAtomicAdd(fg + 1, -F[1][t]);
-        unsafeAtomicAdd(fg + 2, -F[2][t]);
-      } else {
-        fg[0] = fo[0][t] - F[0][t];
-        fg[1] = fo[1][t] - F[1][t];
-        fg[2] = fo[2][t] - F[2][t];
+      float* fg = f + NC * (size_t)cur.node[t];
+#pragma unroll
+      for (int e = 0; e < NC; ++e) {
+        if constexpr (ATOMIC) unsafeAtomicAdd(fg + e, -F[e][t]);
+        else fg[e] = fo[e][t] - F[e][t];
       }
     }
     if (!AHEAD || !more) break;
@@ -546,66 +560,74 @@ int64_t resident_groups() {
   return cache[dev];
 }
 
-template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC>
+template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
 hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
   int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
   if (GEO == kRegular && NG == kN) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
-  force_tile16_kernel<NG, GEO, ATOMIC, AFF, PREC><<<grid, block, 0, s>>>(a);
+  force_tile16_kernel<NG, GEO, ATOMIC, AFF, PREC, NC><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <int NG, bool AFF, int PREC>
+template <int NG, bool AFF, int PREC, int NC>
 hipError_t launch_t16_geo(int geo, bool atomic, const ForceArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   switch (geo) {
     case kRegular:
-      return atomic ? launch_t16<NG, kRegular, true, AFF, PREC>(a, s) : launch_t16<NG, kRegular, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kRegular, true, AFF, PREC, NC>(a, s)
+                    : launch_t16<NG, kRegular, false, AFF, PREC, NC>(a, s);
     case kStored:
-      return atomic ? launch_t16<NG, kStored, true, AFF, PREC>(a, s) : launch_t16<NG, kStored, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kStored, true, AFF, PREC, NC>(a, s)
+                    : launch_t16<NG, kStored, false, AFF, PREC, NC>(a, s);
     case kTrilinear:
-      return atomic ? launch_t16<NG, kTrilinear, true, AFF, PREC>(a, s)
-                    : launch_t16<NG, kTrilinear, false, AFF, PREC>(a, s);
+      return atomic ? launch_t16<NG, kTrilinear, true, AFF, PREC, NC>(a, s)
+                    : launch_t16<NG, kTrilinear, false, AFF, PREC, NC>(a, s);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-template <int NG, int PREC>
+template <int NG, int PREC, int NC>
 hipError_t launch_t16_split(int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
   // the launch's first naff elements have an affine numbering
   naff = naff < 0 ? 0 : (naff > a.count ? a.count : naff);
   ForceArgs b = a;
   b.count = naff;
-  hipError_t e = launch_t16_geo<NG, true, PREC>(geo, atomic, b, s);
+  hipError_t e = launch_t16_geo<NG, true, PREC, NC>(geo, atomic, b, s);
   if (e != hipSuccess || naff == a.count) return e;
   b.pos0 = a.pos0 + naff;
   b.count = a.count - naff;
-  return launch_t16_geo<NG, false, PREC>(geo, atomic, b, s);
+  return launch_t16_geo<NG, false, PREC, NC>(geo, atomic, b, s);
 }
 
-template <int PREC>
+template <int PREC, int NC>
 hipError_t launch_t16_n(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s) {
   switch (n) {
-    case 11: return launch_t16_split<11, PREC>(geo, atomic, naff, a, s);
-    case 12: return launch_t16_split<12, PREC>(geo, atomic, naff, a, s);
-    case 13: return launch_t16_split<13, PREC>(geo, atomic, naff, a, s);
-    case 14: return launch_t16_split<14, PREC>(geo, atomic, naff, a, s);
-    case 15: return launch_t16_split<15, PREC>(geo, atomic, naff, a, s);
-    case 16: return launch_t16_split<16, PREC>(geo, atomic, naff, a, s);
+    case 11: return launch_t16_split<11, PREC, NC>(geo, atomic, naff, a, s);
+    case 12: return launch_t16_split<12, PREC, NC>(geo, atomic, naff, a, s);
+    case 13: return launch_t16_split<13, PREC, NC>(geo, atomic, naff, a, s);
+    case 14: return launch_t16_split<14, PREC, NC>(geo, atomic, naff, a, s);
+    case 15: return launch_t16_split<15, PREC, NC>(geo, atomic, naff, a, s);
+    case 16: return launch_t16_split<16, PREC, NC>(geo, atomic, naff, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
+hipError_t launch_force_tile16_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a,
+                                        hipStream_t s) {
+  if (n < 13) return hipErrorInvalidValue;
+  return launch_t16_n<SEMX_C_F32, 1>(n, geo, atomic, naff, a, s);
+}
+
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s) {
   switch (prec) {
     case SEMX_C_F32:
-    case SEMX_C_MFMA_F32: return launch_t16_n<SEMX_C_F32>(n, geo, atomic, naff, a, s);
-    case SEMX_C_BF16: return launch_t16_n<SEMX_C_BF16>(n, geo, atomic, naff, a, s);
-    case SEMX_C_F16: return launch_t16_n<SEMX_C_F16>(n, geo, atomic, naff, a, s);
+    case SEMX_C_MFMA_F32: return launch_t16_n<SEMX_C_F32, 3>(n, geo, atomic, naff, a, s);
+    case SEMX_C_BF16: return launch_t16_n<SEMX_C_BF16, 3>(n, geo, atomic, naff, a, s);
+    case SEMX_C_F16: return launch_t16_n<SEMX_C_F16, 3>(n, geo, atomic, naff, a, s);
     default: return hipErrorInvalidValue;
   }
 }

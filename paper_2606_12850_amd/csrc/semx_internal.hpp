@@ -290,6 +290,11 @@ constexpr int kTileMinN = 13;
 constexpr int kTileMinNMixed = 11;
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s);
+// The scalar (acoustic) operator, NGLL 13..16, on the same tiles (FP32; the
+// first half of the material table is W / rho): u and f have one value per
+// node.
+hipError_t launch_force_tile16_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a,
+                                        hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node;
 // the launch's first naff elements have an affine numbering)
 hipError_t launch_force_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a, hipStream_t s);
