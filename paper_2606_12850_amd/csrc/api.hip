@@ -1015,7 +1015,7 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
     a.count = L.count;
     hipError_t e;
     const int geo = L.irregular ? c->irregular_geo : kRegular;
-    if (c->physics == SEMX_ACOUSTIC && c->n >= kTileMinN)
+    if (c->physics == SEMX_ACOUSTIC && c->n >= kTileMinNAcoustic)
       e = launch_force_tile16_acoustic(c->n, geo, atomic, L.naff, a, c->stream);
     else if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, L.naff, a, c->stream);

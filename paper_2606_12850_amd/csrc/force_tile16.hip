@@ -617,7 +617,7 @@ hipError_t launch_t16_n(int n, int geo, bool atomic, int64_t naff, const ForceAr
 
 hipError_t launch_force_tile16_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                         hipStream_t s) {
-  if (n < 13) return hipErrorInvalidValue;
+  if (n < kTileMinNAcoustic) return hipErrorInvalidValue;
   return launch_t16_n<SEMX_C_F32, 1>(n, geo, atomic, naff, a, s);
 }
 

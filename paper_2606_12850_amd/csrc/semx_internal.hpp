@@ -290,9 +290,11 @@ constexpr int kTileMinN = 13;
 constexpr int kTileMinNMixed = 11;
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s);
-// The scalar (acoustic) operator, NGLL 13..16, on the same tiles (FP32; the
+// The scalar (acoustic) operator, NGLL 12..16, on the same tiles (FP32; the
 // first half of the material table is W / rho): u and f have one value per
-// node.
+// node.  Measured against the column kernel at 2e7 nodes: slower at NGLL 11
+// (0.374 / 0.355 ms), faster from 12 (0.348 / 0.383) to 16 (0.195 / 0.383).
+constexpr int kTileMinNAcoustic = 12;
 hipError_t launch_force_tile16_acoustic(int n, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                         hipStream_t s);
 // acoustic.hip: the scalar operator, NGLL 2..16 (u, f hold one value per node;

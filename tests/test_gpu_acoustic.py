@@ -385,12 +385,12 @@ def test_acoustic_batched_time_loop():
         assert err <= TOL_SEIS
 
 
-@pytest.mark.parametrize("n", [2, 5, 10, 11, 13, 16])
+@pytest.mark.parametrize("n", [2, 5, 10, 11, 12, 16])
 def test_acoustic_force_degenerate_meshes(n):
     """Single-element and one-element-wide meshes (one lane per point up to
-    NGLL 10, the column kernel at 11-12, the matrix-core tiles from 13,
-    padded below 16), every assembly and geometry mode, against the
-    acoustic oracle."""
+    NGLL 10, the column kernel at 11, the matrix-core tiles from 12, padded
+    below 16), every assembly and geometry mode, against the acoustic
+    oracle."""
     import paper_2606_12850_amd as P
     from tests.test_gpu_force import _degenerate_meshes
     rng = np.random.default_rng(70 + n)
