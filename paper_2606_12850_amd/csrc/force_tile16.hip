@@ -220,22 +220,35 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
   if constexpr (MAT) load_mat<NG>(a, model, pos, P, h);
 }
 
-// Element loop.  Regular path at NGLL 16: the grid holds one workgroup per compute unit
-// (one fills its LDS) and each walks its share of the launch, dealt XCD by
-// XCD as in xcd_group (the workgroups on XCD x take the x-th eighth of the
-// range, in steps of the number of workgroups there); the next element's node
-// numbers, u and material are requested before the current one's last two
-// barriers, so that their latency hides behind its transpose contractions and
-// assembly.  With per-point geometry or padded tiles the registers are full:
-// one element per workgroup, its loads requested at its start.  Inside a colour the prior f
-// at the element's nodes is read at the start of its arithmetic (no other
-// workgroup of the launch touches those nodes).
+// Element loop.  Regular path (tile_persistent): the grid holds one
+// workgroup per compute unit (one fills its LDS or its registers) and each
+// walks its share of the launch, dealt XCD by XCD as in xcd_group (the
+// workgroups on XCD x take the x-th eighth of the range, in steps of the
+// number of workgroups there); the next element's node numbers and u (and
+// at NGLL 16 with FP32 operands its material) are requested before the
+// current one's last two barriers, so that their latency hides behind its
+// transpose contractions and assembly.  With per-point geometry (and FP16
+// operands on padded tiles) one element per workgroup, its loads requested
+// at its start.  Inside a colour the prior f at the element's nodes is read
+// at the start of its arithmetic (no other workgroup of the launch touches
+// those nodes).
+// The persistent form (the next element requested ahead) on the regular
+// path.  At the padded orders (NGLL < 16) its registers spill (24-40 bytes
+// per lane with FP32 and BF16 operands, 92 with FP16); measured per apply
+// at 2e7 nodes it still gains 4-13 % with FP32 and BF16 operands and for
+// the scalar operator, and loses 20-35 % with FP16, which keeps one element
+// per workgroup there.  The launch sizes the grid by the same rule.
+template <int NG, int GEO, int PREC>
+constexpr bool tile_persistent() {
+  return GEO == kRegular && (NG == kN || PREC != SEMX_C_F16);
+}
+
 template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
 __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   static_assert(NC == 3 || PREC == SEMX_C_F32, "the scalar (acoustic) operator runs in FP32");
   constexpr int E3 = NG * NG * NG;
-  // persistent, next element requested ahead (regular path, unpadded tiles)
-  constexpr bool AHEAD = GEO == kRegular && NG == kN;
+  // persistent, next element requested ahead
+  constexpr bool AHEAD = tile_persistent<NG, GEO, PREC>();
   constexpr bool LOW = PREC == SEMX_C_BF16 || PREC == SEMX_C_F16;
   // 16-bit operands and padded tiles need the registers: material at the start
   constexpr bool MAT_AHEAD = AHEAD && !LOW && NG == kN;
@@ -563,7 +576,7 @@ int64_t resident_groups() {
 template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
 hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
   int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
-  if (GEO == kRegular && NG == kN) nb = std::min<int64_t>(nb, resident_groups());  // the persistent form
+  if (tile_persistent<NG, GEO, PREC>()) nb = std::min<int64_t>(nb, resident_groups());
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
   force_tile16_kernel<NG, GEO, ATOMIC, AFF, PREC, NC><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
