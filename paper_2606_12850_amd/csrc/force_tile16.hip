@@ -232,15 +232,18 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
 // at its start.  Inside a colour the prior f at the element's nodes is read
 // at the start of its arithmetic (no other workgroup of the launch touches
 // those nodes).
-// The persistent form (the next element requested ahead) on the regular
-// path.  At the padded orders (NGLL < 16) its registers spill (24-40 bytes
-// per lane with FP32 and BF16 operands, 92 with FP16); measured per apply
-// at 2e7 nodes it still gains 4-13 % with FP32 and BF16 operands and for
-// the scalar operator, and loses 20-35 % with FP16, which keeps one element
-// per workgroup there.  The launch sizes the grid by the same rule.
-template <int NG, int GEO, int PREC>
+// The persistent form (the next element requested ahead).  Elastic: on the
+// regular path only; at the padded orders (NGLL < 16) its registers spill
+// (24-40 bytes per lane with FP32 and BF16 operands, 92 with FP16) and,
+// measured per apply at 2e7 nodes, it still gains 4-13 % with FP32 and BF16
+// operands and loses 20-35 % with FP16, which keeps one element per
+// workgroup there; with per-point or trilinear geometry it spills 84-176
+// bytes and loses up to 50 %.  The scalar operator (NC = 1) has the room:
+// it gains 5-14 % on every geometry path.  The launch sizes the grid by the
+// same rule.
+template <int NG, int GEO, int PREC, int NC>
 constexpr bool tile_persistent() {
-  return GEO == kRegular && (NG == kN || PREC != SEMX_C_F16);
+  return NC == 1 || (GEO == kRegular && (NG == kN || PREC != SEMX_C_F16));
 }
 
 template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
   static_assert(NC == 3 || PREC == SEMX_C_F32, "the scalar (acoustic) operator runs in FP32");
   constexpr int E3 = NG * NG * NG;
   // persistent, next element requested ahead
-  constexpr bool AHEAD = tile_persistent<NG, GEO, PREC>();
+  constexpr bool AHEAD = tile_persistent<NG, GEO, PREC, NC>();
   constexpr bool LOW = PREC == SEMX_C_BF16 || PREC == SEMX_C_F16;
   // 16-bit operands and padded tiles need the registers: material at the start
   constexpr bool MAT_AHEAD = AHEAD && !LOW && NG == kN;
@@ -576,7 +579,7 @@ int64_t resident_groups() {
 template <int NG, int GEO, bool ATOMIC, bool AFF, int PREC, int NC>
 hipError_t launch_t16(const ForceArgs& a, hipStream_t s) {
   int64_t nb = ((a.count + kNumXcd - 1) / kNumXcd) * kNumXcd;
-  if (tile_persistent<NG, GEO, PREC>()) nb = std::min<int64_t>(nb, resident_groups());
+  if (tile_persistent<NG, GEO, PREC, NC>()) nb = std::min<int64_t>(nb, resident_groups());
   dim3 grid((unsigned)nb, (unsigned)a.nmodels), block(kBlk);
   force_tile16_kernel<NG, GEO, ATOMIC, AFF, PREC, NC><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
