@@ -1019,7 +1019,8 @@ int force_accumulate(semx_ctx* c, const float* u, float* f, bool first_touch = f
       e = launch_force_tile16_acoustic(c->n, geo, atomic, L.naff, a, c->stream);
     else if (c->physics == SEMX_ACOUSTIC)
       e = launch_force_acoustic(c->n, geo, atomic, L.naff, a, c->stream);
-    else if (c->n >= kTileMinN || (c->n >= kTileMinNMixed && c->contraction != SEMX_C_F32))
+    else if (c->n >= kTileMinN || (c->n >= kTileMinNMixed && c->contraction != SEMX_C_F32) ||
+             (c->n == kTileRegularN && geo == kRegular))
       e = launch_force_tile16(c->n, c->contraction, geo, atomic, L.naff, a, c->stream);
     else if (c->contraction == SEMX_C_F32 && c->n > kMaxNLow)
       e = launch_force_high(c->n, geo, atomic, a, c->stream);

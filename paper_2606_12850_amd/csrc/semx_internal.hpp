@@ -288,6 +288,11 @@ hipError_t launch_force_high_skeleton(int n, int geo, const ForceArgs& a, hipStr
 // useful matrix work), the matrix-core modes from kTileMinNMixed.
 constexpr int kTileMinN = 13;
 constexpr int kTileMinNMixed = 11;
+// FP32 at NGLL 12: the tile kernel for launches of regular elements (its
+// persistent form, 0.754 against 0.917 ms per apply for the column kernel
+// at 2e7 nodes); with per-point or trilinear geometry the column kernel
+// stays faster (0.98 against 1.05-1.19 ms), as at NGLL 11 on every path.
+constexpr int kTileRegularN = 12;
 hipError_t launch_force_tile16(int n, int prec, int geo, bool atomic, int64_t naff, const ForceArgs& a,
                                hipStream_t s);
 // The scalar (acoustic) operator, NGLL 12..16, on the same tiles (FP32; the
