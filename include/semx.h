@@ -24,10 +24,13 @@
  *     call that returns data to host memory synchronises that stream.
  *     A context is not thread-safe; use one context per host thread.
  *   - ngll = n = N+1 GLL points per direction, 2 <= n <= 16 (N = polynomial
- *     degree up to 15).  NGLL 11..16 run the FP32 operator, the time loop
- *     and the adjoint on column-per-lane kernels; FP64 storage supports
- *     n <= 10 (SEMX_EINVAL above), the matrix-core contractions 4 <= n <= 8.  Element-local point q = i + n*(j + n*k), i fastest (i
- *     along xi, j along eta, k along zeta).
+ *     degree up to 15).  From NGLL 11 the FP32 operator runs on a
+ *     column-per-lane kernel (NGLL 11, and 12 on irregular elements) or on
+ *     matrix-core tiles (the rest; the acoustic operator from 12), the
+ *     adjoint on column-per-lane kernels; FP64 storage supports n <= 10
+ *     (SEMX_EINVAL above), the 16-bit matrix-core contractions 4 <= n <= 8
+ *     and 11 <= n <= 16.  Element-local point q = i + n*(j + n*k), i fastest
+ *     (i along xi, j along eta, k along zeta).
  *   - Corner v = a + 2b + 4c of an 8-node hexahedron sits at reference
  *     coordinates (xi, eta, zeta) = (2a-1, 2b-1, 2c-1); the geometry is the
  *     trilinear map of the 8 corners.

@@ -1,4 +1,6 @@
-// FP32 element internal-force kernel for high orders (NGLL 11..16).
+// FP32 element internal-force kernel for high orders (NGLL 11..16).  The
+// force pass takes it at NGLL 11 and for irregular elements at 12; the
+// matrix-core tile kernel (force_tile16.hip) is faster elsewhere.
 //
 // Same operator as force_f32.hip (Sec. II-B weak form: three forward and
 // three transpose sum-factorised contractions around the pointwise
