@@ -229,18 +229,22 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
 // current one's last two barriers, so that their latency hides behind its
 // transpose contractions and assembly.  With per-point geometry (and FP16
 // operands on padded tiles) one element per workgroup, its loads requested
-// at its start.  Inside a colour the prior f at the element's nodes is read
-// at the start of its arithmetic (no other workgroup of the launch touches
-// those nodes).
+// at its start.  Inside a colour no other workgroup of the launch touches
+// the element's nodes, so the prior f there may be read at any time before
+// the assembly: at the start of the arithmetic in general, and in the
+// persistent elastic form after the pointwise stage, just before the next
+// element's loads, so that the 12 values are not held through the stress
+// computation (this removed the 8-40 bytes per lane that the padded orders
+// spilled there with FP32 and BF16 operands, and took 4-21 % off an apply
+// at NGLL 12-15).
 // The persistent form (the next element requested ahead).  Elastic: on the
-// regular path only; at the padded orders (NGLL < 16) its registers spill
-// (24-40 bytes per lane with FP32 and BF16 operands, 92 with FP16) and,
-// measured per apply at 2e7 nodes, it still gains 4-13 % with FP32 and BF16
-// operands and loses 20-35 % with FP16, which keeps one element per
-// workgroup there; with per-point or trilinear geometry it spills 84-176
-// bytes and loses up to 50 %.  The scalar operator (NC = 1) has the room:
-// it gains 5-14 % on every geometry path.  The launch sizes the grid by the
-// same rule.
+// regular path only, and with FP16 operands only at NGLL 16; on padded
+// tiles FP16 needs more registers (36-60 bytes per lane spilled) and,
+// measured per apply at 2e7 nodes, loses 20-35 %, so it keeps one element
+// per workgroup there; with per-point or trilinear geometry the persistent
+// form spills 84-176 bytes and loses up to 50 %.  The scalar operator
+// (NC = 1) has the room: it gains 5-14 % on every geometry path.  The launch
+// sizes the grid by the same rule.
 template <int NG, int GEO, int PREC, int NC>
 constexpr bool tile_persistent() {
   return NC == 1 || (GEO == kRegular && (NG == kN || PREC != SEMX_C_F16));
@@ -306,15 +310,18 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
     if constexpr (!AHEAD) load_ahead<NG, ATOMIC, AFF, true, NC>(a, u, model, pos, P, g, c, w, cur);
     if constexpr (AHEAD && !MAT_AHEAD) load_mat<NG>(a, model, pos, P, cur);
     float fo[3][4];
+    auto read_prior = [&]() {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      fo[0][t] = fo[1][t] = fo[2][t] = 0.0f;
-      if (!ATOMIC && P.real(t) && !((cur.fw >> t) & 1u)) {  // the point's values in one request
-        const float* fp = f + NC * (size_t)cur.node[t];
+      for (int t = 0; t < 4; ++t) {
+        fo[0][t] = fo[1][t] = fo[2][t] = 0.0f;
+        if (!ATOMIC && P.real(t) && !((cur.fw >> t) & 1u)) {  // the point's values in one request
+          const float* fp = f + NC * (size_t)cur.node[t];
 #pragma unroll
-        for (int e = 0; e < NC; ++e) fo[e][t] = fp[e];
+          for (int e = 0; e < NC; ++e) fo[e][t] = fp[e];
+        }
       }
-    }
+    };
+    if constexpr (!(AHEAD && NC == 3)) read_prior();
     float u0[3] = {0.f, 0.f, 0.f};  // 16-bit operands: u at local point (0,0,0), their offset
     if constexpr (LOW) {
       const int n0 = AFF ? a.aff[(size_t)pos * 4] : a.ibool[(size_t)pos * E3];
@@ -495,6 +502,7 @@ __global__ __launch_bounds__(kBlk) void force_tile16_kernel(ForceArgs a) {
       }
       F[e] = x;
     }
+    if constexpr (AHEAD && NC == 3) read_prior();
     const int nxt = grp + per_xcd;
     const bool more = AHEAD && nxt < xend;  // uniform over the block
     Ahead ahead;
