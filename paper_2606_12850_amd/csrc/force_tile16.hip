@@ -236,7 +236,7 @@ __device__ __forceinline__ void load_ahead(const ForceArgs& a, const float* __re
 // element's loads, so that the 12 values are not held through the stress
 // computation (this removed the 8-40 bytes per lane that the padded orders
 // spilled there with FP32 and BF16 operands, and took 4-21 % off an apply
-// at NGLL 12-15).
+// at NGLL 11-15).
 // The persistent form (the next element requested ahead).  Elastic: on the
 // regular path only, and with FP16 operands only at NGLL 16; on padded
 // tiles FP16 needs more registers (36-60 bytes per lane spilled) and,
